@@ -1,0 +1,19 @@
+"""FP64 CPU oracle for the boundary-integral water-wave solve.
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+execute anything in this package; only the tests, the smoke check and the
+CPU-baseline leg of the benchmark use it.  It shares no code with the GPU
+path: it is written directly from the paper's formulas in plain PyTorch CPU
+operations in float64/complex128, builds every matrix block literally from
+the kernel table of Sec. 3.2 (and the transposed "dagger" blocks of Sec.
+4.1), applies spectral operators with the FFT, and solves by dense LU.
+Gradients come from PyTorch autograd through these same plain operations.
+"""
+from .bim import (OGeom, assemble_A, A_rows, rhs, solve_phi, solve_gamma, spectral, split,
+                  K_block, G_block, A_block, wall_matrix, psi_on_surface,
+                  psi_mv, u_mv, energy, surface_from_periodic, J_and_grad, dphi_dn_from_omega)
+
+__all__ = ["OGeom", "assemble_A", "A_rows", "rhs", "solve_phi", "solve_gamma", "spectral", "split",
+           "K_block", "G_block", "A_block", "wall_matrix", "psi_on_surface",
+           "psi_mv", "u_mv", "energy", "surface_from_periodic", "J_and_grad",
+           "dphi_dn_from_omega"]

@@ -1,0 +1,377 @@
+"""Plain FP64 CPU oracle of the velocity-potential and vortex-sheet solves.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring): the product path must
+never import this module.
+
+Every function restates one passage of Ambrose, Camassa, Marzuola,
+McLaughlin, Robinson and Wilkening, "Numerical algorithms for water waves
+with background flow over obstacles and topography" (arXiv 2108.01786):
+
+* kernels K_kj and G_kj with their diagonal limits ........ Sec. 3.2, Table 1
+* block operator, rank-(N-1) correction, right-hand side ... Sec. 3.2 (B, A, Aw=b)
+* collocation / trapezoid discretization ................... Sec. 3.3
+* multi-valued potential Phi_mv and its derivative ......... Sec. 3, 3.1
+* normal velocity U (velocity-potential method) ............ Sec. 3.4
+* vortex-sheet wall system and U from gamma ................ Sec. 4.1
+* energy E ................................................. Sec. 5.2
+* spectral derivative and Hilbert transform (FFT symbols) .. Sec. 3.4
+
+Conventions the paper leaves open and that are fixed here: the Nyquist
+coefficient of D, H and |d| is set to zero; the point z_j inside obstacle j
+is supplied with the geometry; the stream-function constant on the bottom is
+zero.  Matrix blocks are written with targets alpha_km along rows and
+sources alpha_jl along columns; the diagonal of a same-boundary block is the
+analytic limit, never the (singular) kernel value.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict, List, Optional, Sequence
+
+import torch
+
+F64 = torch.float64
+C128 = torch.complex128
+
+
+class OGeom:
+    """Per-boundary complex samples z = zeta, d = zeta', e = zeta'' (FP64)."""
+
+    def __init__(self, z: List[torch.Tensor], d: List[torch.Tensor], e: List[torch.Tensor],
+                 zc: torch.Tensor, a: torch.Tensor, V1: float,
+                 psi_wall: Optional[List[torch.Tensor]] = None):
+        self.z, self.d, self.e = z, d, e
+        self.M = [int(t.shape[0]) for t in z]
+        self.nb = len(z)
+        self.alpha = [2.0 * math.pi * torch.arange(m, dtype=F64) / m for m in self.M]
+        self.zc = zc.to(C128)
+        self.a = a.to(F64)
+        self.V1 = float(V1)
+        self.psi_wall = psi_wall
+
+    @classmethod
+    def from_synth(cls, geom) -> "OGeom":
+        t = lambda v: torch.as_tensor(v, dtype=C128)
+        z = [t(c.z) for c in geom.curves]
+        d = [t(c.d) for c in geom.curves]
+        e = [t(c.e) for c in geom.curves]
+        pw = None
+        if geom.psi_wall is not None:
+            pw, off = [], 0
+            for m in geom.M[1:]:
+                pw.append(torch.as_tensor(geom.psi_wall[off:off + m], dtype=F64))
+                off += m
+        return cls(z, d, e, torch.as_tensor(geom.zc), torch.as_tensor(geom.a), geom.V1, pw)
+
+    def with_surface(self, z0, d0, e0) -> "OGeom":
+        """Same walls, new free surface (used for the gradient of J)."""
+        return OGeom([z0] + self.z[1:], [d0] + self.d[1:], [e0] + self.e[1:],
+                     self.zc, self.a, self.V1, self.psi_wall)
+
+
+# ---------------------------------------------------------------------------
+# kernels (Sec. 3.2, Table 1)
+# ---------------------------------------------------------------------------
+
+def half_cot(w: torch.Tensor) -> torch.Tensor:
+    """(1/2) cot(w/2): the periodized Cauchy kernel (Mittag-Leffler sum, Sec. 3)."""
+    return 0.5 / torch.tan(0.5 * w)
+
+
+def _source_pairs(g: OGeom, k: int, j: int, rows: Optional[torch.Tensor]):
+    """zeta_j'(b)/2 cot((zeta_j(b) - zeta_k(a))/2) for a = alpha_km (m in rows), b = alpha_jl.
+
+    Returns (S, regulariser, diag) where for k == j the regulariser is
+    (1/2)cot((b - a)/2) and diag marks the pairs m == l.  On diag the
+    arguments are replaced by a harmless value; callers overwrite those
+    entries with the analytic limit.
+    """
+    if rows is None:
+        rows = torch.arange(g.M[k])
+    zt = g.z[k][rows]
+    at = g.alpha[k][rows]
+    diff = g.z[j][None, :] - zt[:, None]
+    reg, diag = None, None
+    if k == j:
+        diag = rows[:, None] == torch.arange(g.M[j])[None, :]
+        diff = torch.where(diag, torch.ones_like(diff), diff)
+        da = g.alpha[j][None, :] - at[:, None]
+        reg = half_cot(torch.where(diag, torch.ones_like(da), da))
+    S = g.d[j][None, :] * half_cot(diff)
+    return S, reg, diag, rows
+
+
+def self_limit(g: OGeom, k: int) -> torch.Tensor:
+    """zeta''/(2 zeta'): the limit of the regularised self kernel (Sec. 3.2)."""
+    return g.e[k] / (2.0 * g.d[k])
+
+
+def K_block(g: OGeom, k: int, j: int, rows=None) -> torch.Tensor:
+    """K_kj(alpha_km, alpha_jl) = Im{zeta_j'(b)/2 cot((zeta_j(b) - zeta_k(a))/2)}."""
+    S, _, diag, rows = _source_pairs(g, k, j, rows)
+    K = S.imag
+    if diag is not None:
+        lim = self_limit(g, k).imag[rows]
+        K = torch.where(diag, lim[:, None].expand_as(K), K)
+    return K
+
+
+def G_block(g: OGeom, k: int, j: int, rows=None) -> torch.Tensor:
+    """G_kj(alpha_km, alpha_jl) = Re{zeta_j'/2 cot(...) - delta_kj (1/2)cot((b - a)/2)}."""
+    S, reg, diag, rows = _source_pairs(g, k, j, rows)
+    G = S.real
+    if diag is not None:
+        G = G - reg
+        lim = self_limit(g, k).real[rows]
+        G = torch.where(diag, lim[:, None].expand_as(G), G)
+    return G
+
+
+# ---------------------------------------------------------------------------
+# the linear system (Sec. 3.2 and 3.3)
+# ---------------------------------------------------------------------------
+
+def A_block(g: OGeom, k: int, j: int, rows=None) -> torch.Tensor:
+    """Block (k, j) of the collocated, rank-corrected operator A.
+
+    Row blocks: k = 0 gives phi~ on the surface, k >= 1 gives psi~ on wall k.
+    (0,0): -I/2 + K_00/M_0;  (0,j): G_0j/M_j;  (k,0): -G_k0/M_0;
+    (k,j): delta_kj I/2 + K_kj/M_j - delta_kj [k >= 2] E_k, E_k = e e^T / M_k.
+    """
+    if rows is None:
+        rows = torch.arange(g.M[k])
+    Mj = g.M[j]
+    eye = (rows[:, None] == torch.arange(Mj)[None, :]).to(F64) if k == j else None
+    if k == 0 and j == 0:
+        return K_block(g, 0, 0, rows) / Mj - 0.5 * eye
+    if k == 0:
+        return G_block(g, 0, j, rows) / Mj
+    if j == 0:
+        return -G_block(g, k, 0, rows) / Mj
+    B = K_block(g, k, j, rows) / Mj
+    if k == j:
+        B = B + 0.5 * eye
+        if k >= 2:
+            B = B - torch.full_like(B, 1.0 / Mj)
+    return B
+
+
+def _local_rows(g: OGeom, rows: torch.Tensor):
+    off = [0]
+    for m in g.M:
+        off.append(off[-1] + m)
+    out = []
+    for k in range(g.nb):
+        sel = (rows >= off[k]) & (rows < off[k + 1])
+        if bool(sel.any()):
+            out.append((k, torch.nonzero(sel).flatten(), rows[sel] - off[k]))
+    return out
+
+
+def A_rows(g: OGeom, rows: Sequence[int]) -> torch.Tensor:
+    """Selected rows (global node indices) of A, e.g. for sampled checks at large M."""
+    rows = torch.as_tensor(rows, dtype=torch.long)
+    out = torch.zeros(rows.shape[0], sum(g.M), dtype=F64)
+    for k, pos, loc in _local_rows(g, rows):
+        out[pos] = torch.cat([A_block(g, k, j, loc) for j in range(g.nb)], dim=1)
+    return out
+
+
+def assemble_A(g: OGeom) -> torch.Tensor:
+    """The whole M x M matrix of the collocated system (Sec. 3.3)."""
+    return torch.cat([torch.cat([A_block(g, k, j) for j in range(g.nb)], dim=1)
+                      for k in range(g.nb)], dim=0)
+
+
+# ---------------------------------------------------------------------------
+# multi-valued part of the potential (Sec. 3 and 3.1)
+# ---------------------------------------------------------------------------
+
+def dPhi_mv(g: OGeom, z: torch.Tensor) -> torch.Tensor:
+    """Phi_mv'(z) = V1 + sum_j a_j (1/2 - (i/2) cot((z - z_j)/2))."""
+    out = torch.full_like(z, g.V1)
+    for aj, zj in zip(g.a, g.zc):
+        out = out + aj * (0.5 - 1j * half_cot(z - zj))
+    return out
+
+
+def psi_mv(g: OGeom, z: torch.Tensor) -> torch.Tensor:
+    """Im Phi_mv(z) = V1 Im z - sum_j a_j ln|1 - e^{i(z - z_j)}|."""
+    out = g.V1 * z.imag
+    for aj, zj in zip(g.a, g.zc):
+        out = out - aj * torch.log(torch.abs(1.0 - torch.exp(1j * (z - zj))))
+    return out
+
+
+def u_mv(g: OGeom, z: torch.Tensor, d: torch.Tensor) -> torch.Tensor:
+    """s_alpha dphi_mv/dn = Re{Phi_mv'(zeta) i zeta'}  (Sec. 3.4, first line)."""
+    return (dPhi_mv(g, z) * 1j * d).real
+
+
+def rhs(g: OGeom, phi: torch.Tensor) -> torch.Tensor:
+    """b_0 = phi~; b_k = psi_wall_k - psi_mv(zeta_k) for k >= 1 (psi_wall = 0 by default)."""
+    parts = [phi.to(F64)]
+    for k in range(1, g.nb):
+        bk = -psi_mv(g, g.z[k])
+        if g.psi_wall is not None:
+            bk = bk + g.psi_wall[k - 1]
+        parts.append(bk)
+    return torch.cat(parts)
+
+
+# ---------------------------------------------------------------------------
+# spectral operators (Sec. 3.4)
+# ---------------------------------------------------------------------------
+
+def spectral(f: torch.Tensor, op: str) -> torch.Tensor:
+    """FFT-symbol operators on a uniform periodic grid: D (ik), D2 (-k^2),
+    H (-i sgn k) and ABSD (|k|).  The Nyquist coefficient is zeroed."""
+    M = f.shape[-1]
+    k = torch.fft.fftfreq(M, d=1.0 / M).to(F64)
+    nyq = (k == -M / 2)
+    if op == "D":
+        sym = 1j * k
+    elif op == "D2":
+        sym = -(k * k) + 0j
+    elif op == "H":
+        sym = -1j * torch.sign(k)
+    elif op == "ABSD":
+        sym = torch.abs(k) + 0j
+    else:
+        raise ValueError(op)
+    sym = torch.where(nyq, torch.zeros_like(sym), sym)
+    return torch.fft.ifft(sym * torch.fft.fft(f.to(C128))).real
+
+
+def split(g: OGeom, v: torch.Tensor) -> List[torch.Tensor]:
+    return list(torch.split(v, g.M))
+
+
+# ---------------------------------------------------------------------------
+# velocity-potential method (Sec. 3.2 - 3.4)
+# ---------------------------------------------------------------------------
+
+def dphi_dn_from_omega(g: OGeom, omega: List[torch.Tensor]) -> torch.Tensor:
+    """U on the free surface from the densities (Sec. 3.4):
+
+    s U = Re{Phi_mv' i zeta'} - H(omega_0')/2 - (1/M_0) sum_l G_00(b_l, a) omega_0'(b_l)
+          + sum_{j>=1} (1/M_j) sum_l K_j0(b_l, a) omega_j'(b_l).
+    The integration variable sits in the first slot of G_00 and K_j0, so
+    these are the transposes of the blocks G_00 and K_j0.
+    """
+    dw = [spectral(w, "D") for w in omega]
+    s0 = torch.abs(g.d[0])
+    acc = u_mv(g, g.z[0], g.d[0])
+    acc = acc - 0.5 * spectral(dw[0], "H")
+    acc = acc - (G_block(g, 0, 0).T @ dw[0]) / g.M[0]
+    for j in range(1, g.nb):
+        acc = acc + (K_block(g, j, 0).T @ dw[j]) / g.M[j]
+    return acc / s0
+
+
+def solve_phi(g: OGeom, phi: torch.Tensor) -> Dict[str, torch.Tensor]:
+    """Solve A omega = b by dense LU; return omega, psi|_k (k >= 2) and U."""
+    A = assemble_A(g)
+    b = rhs(g, phi)
+    omega = torch.linalg.solve(A, b)
+    parts = split(g, omega)
+    psi_k = torch.stack([p.mean() for p in parts[2:]]) if g.nb > 2 else torch.zeros(0, dtype=F64)
+    U = dphi_dn_from_omega(g, parts)
+    return {"omega": omega, "psi_k": psi_k, "U": U, "A": A, "b": b}
+
+
+# ---------------------------------------------------------------------------
+# vortex-sheet method (Sec. 4.1)
+# ---------------------------------------------------------------------------
+
+def wall_matrix(g: OGeom) -> torch.Tensor:
+    """Row block k, column block j (k, j >= 1): -delta_kj I/2 + K_jk^dagger,
+    (K_jk^dagger)_{ml} = K_jk(alpha_jl, alpha_km)/M_j."""
+    rows = []
+    for k in range(1, g.nb):
+        blocks = []
+        for j in range(1, g.nb):
+            B = K_block(g, j, k).T / g.M[j]
+            if j == k:
+                B = B - 0.5 * torch.eye(g.M[k], dtype=F64)
+            blocks.append(B)
+        rows.append(torch.cat(blocks, dim=1))
+    return torch.cat(rows, dim=0)
+
+
+def solve_gamma(g: OGeom, gamma0: torch.Tensor) -> Dict[str, torch.Tensor]:
+    """Given gamma_0 on the surface, solve the wall system for gamma_1..gamma_N
+    (zero normal velocity on every wall) and return U (Sec. 4.1)."""
+    gamma0 = gamma0.to(F64)
+    rhs_w = []
+    for k in range(1, g.nb):
+        rk = -(G_block(g, 0, k).T @ gamma0) / g.M[0] - u_mv(g, g.z[k], g.d[k])
+        rhs_w.append(rk)
+    W = wall_matrix(g)
+    gw = torch.linalg.solve(W, torch.cat(rhs_w))
+    gparts = split(OGeom(g.z[1:], g.d[1:], g.e[1:], g.zc, g.a, g.V1), gw)
+    s0 = torch.abs(g.d[0])
+    acc = 0.5 * spectral(gamma0, "H") + (G_block(g, 0, 0).T @ gamma0) / g.M[0]
+    for j in range(1, g.nb):
+        acc = acc + (K_block(g, j, 0).T @ gparts[j - 1]) / g.M[j]
+    acc = acc + u_mv(g, g.z[0], g.d[0])
+    return {"U": acc / s0, "gamma_wall": gw, "W": W}
+
+
+# ---------------------------------------------------------------------------
+# energy (Sec. 5.2)
+# ---------------------------------------------------------------------------
+
+def psi_on_surface(g: OGeom, omega: List[torch.Tensor]) -> torch.Tensor:
+    """psi on the fluid side of the surface: psi_mv + Im of the Cauchy integrals.
+
+    By the Plemelj formula the surface's own integral contributes
+    H(omega_0)/2 - (1/M_0) sum_l G_00(a, b_l) omega_0(b_l); each wall j adds
+    (1/M_j) sum_l K_0j(a, b_l) omega_j(b_l).
+    """
+    out = psi_mv(g, g.z[0]) + 0.5 * spectral(omega[0], "H")
+    out = out - (G_block(g, 0, 0) @ omega[0]) / g.M[0]
+    for j in range(1, g.nb):
+        out = out + (K_block(g, 0, j) @ omega[j]) / g.M[j]
+    return out
+
+
+def energy(g: OGeom, phi: torch.Tensor, omega: torch.Tensor, tau: float, grav: float = 1.0) -> float:
+    """E = <tau s + g eta^2 xi_a / 2 + psi|Gamma0 phi_a / 2> + sum_j a_j psi|_j / 2 (rho = 1)."""
+    parts = split(g, omega)
+    z0, d0 = g.z[0], g.d[0]
+    s = torch.abs(d0)
+    phi_a = spectral(phi.to(F64), "D") + (dPhi_mv(g, z0) * d0).real
+    psiG = psi_on_surface(g, parts)
+    E = (tau * s + 0.5 * grav * z0.imag ** 2 * d0.real + 0.5 * psiG * phi_a).mean()
+    for j in range(2, g.nb):
+        E = E + 0.5 * g.a[j - 2] * parts[j].mean()
+    return float(E)
+
+
+# ---------------------------------------------------------------------------
+# surface parameterised by periodic displacements, and the gradient of J
+# ---------------------------------------------------------------------------
+
+def surface_from_periodic(xt: torch.Tensor, yt: torch.Tensor):
+    """zeta = alpha + xt + i yt with spectral zeta', zeta'' (x = alpha + periodic part)."""
+    M = xt.shape[0]
+    al = 2.0 * math.pi * torch.arange(M, dtype=F64) / M
+    z = (al + xt) + 1j * yt
+    d = (1.0 + spectral(xt, "D")) + 1j * spectral(yt, "D")
+    e = spectral(xt, "D2") + 1j * spectral(yt, "D2")
+    return z, d, e
+
+
+def J_and_grad(g_walls: OGeom, xt, yt, phi, weights):
+    """J = sum_m w_m U_m^2 and its gradient w.r.t. (xt, yt, phi) by autograd."""
+    xt = torch.as_tensor(xt, dtype=F64).clone().requires_grad_(True)
+    yt = torch.as_tensor(yt, dtype=F64).clone().requires_grad_(True)
+    ph = torch.as_tensor(phi, dtype=F64).clone().requires_grad_(True)
+    w = torch.as_tensor(weights, dtype=F64)
+    z0, d0, e0 = surface_from_periodic(xt, yt)
+    g = g_walls.with_surface(z0, d0, e0)
+    U = solve_phi(g, ph)["U"]
+    J = (w * U * U).sum()
+    gx, gy, gp = torch.autograd.grad(J, (xt, yt, ph))
+    return float(J.detach()), gx.detach(), gy.detach(), gp.detach(), U.detach()

@@ -1,0 +1,201 @@
+"""Pins of the FP64 CPU oracle to values the paper and the mathematics fix.
+
+Each pin is chosen so that a plausible slip in the oracle (a wrong sign on a
+G block, a dropped E_m correction, a transposed kernel block in U, a wrong
+Hilbert or Nyquist convention, a wrong diagonal limit) fails at least one
+of them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from manufactured import Flow, flat_strip, manufactured_case, manufactured_inputs
+from synth import make_config, paper_problem, ragged_config, tiny_config
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _golden_energy():
+    out = {}
+    with open(os.path.join(GOLDEN, "energy_problems_1_3.txt")) as f:
+        for line in f:
+            line = line.strip()
+            if line and not line.startswith("#"):
+                n, e = line.split()
+                out[int(n)] = float(e)
+    return out
+
+
+@pytest.mark.parametrize("problem", [1, 2, 3])
+def test_energy_matches_printed_E0(problem):
+    """E(0) of problems 1-3 (Sec. 7.3 table; geometry Sec. 7.1) to the 5 printed decimals."""
+    ref = _golden_energy()[problem]
+    cfg = paper_problem(problem)
+    g = O.OGeom.from_synth(cfg["geom"])
+    phi = torch.as_tensor(cfg["phi"])
+    r = O.solve_phi(g, phi)
+    E = O.energy(g, phi, r["omega"], cfg["tau"], cfg["g"])
+    assert abs(E - ref) <= 6e-6, (E, ref)
+
+
+def test_energy_resolution_independent():
+    """The same E(0) at doubled resolution (the discretization is converged)."""
+    cfg1, cfg2 = paper_problem(3), paper_problem(3, 512, 192, 256)
+    Es = []
+    for cfg in (cfg1, cfg2):
+        g = O.OGeom.from_synth(cfg["geom"])
+        phi = torch.as_tensor(cfg["phi"])
+        Es.append(O.energy(g, phi, O.solve_phi(g, phi)["omega"], 0.1))
+    assert abs(Es[0] - Es[1]) < 1e-9
+
+
+@pytest.mark.parametrize("h", [1.0, 3.0])
+@pytest.mark.parametrize("k", [1, 3, 7])
+@pytest.mark.parametrize("V1", [0.0, 1.0])
+def test_flat_strip_dno(h, k, V1):
+    """No obstacles, flat bottom at depth h: U = k tanh(k h) cos(k alpha)."""
+    geom = flat_strip(64, 64, h, V1)
+    al = 2 * np.pi * np.arange(64) / 64
+    g = O.OGeom.from_synth(geom)
+    U = O.solve_phi(g, torch.as_tensor(np.cos(k * al)))["U"].numpy()
+    assert np.abs(U - k * np.tanh(k * h) * np.cos(k * al)).max() < 1e-12
+
+
+def test_manufactured_flow_converges_spectrally():
+    """Exact U and psi|_k of a manufactured periodic flow, with spectral convergence."""
+    errs = []
+    for M0, M1, M2 in [(32, 32, 16), (64, 64, 32), (128, 128, 64), (256, 256, 128)]:
+        geom, phi, U, ck = manufactured_case(M0, M1, M2)
+        g = O.OGeom.from_synth(geom)
+        r = O.solve_phi(g, torch.as_tensor(phi))
+        errs.append(np.abs(r["U"].numpy() - U).max() / np.abs(U).max())
+        if M0 >= 128:
+            assert np.abs(r["psi_k"].numpy() - ck).max() < 1e-13
+    assert errs[0] > 100 * errs[1] > 100 * 100 * errs[2] * 0.1
+    assert errs[2] < 1e-12 and errs[3] < 1e-12
+
+
+def test_mv_term_alone():
+    """w_j = z_j and F = 0: b = 0 so omega = 0 and U = Re{Phi_mv' i zeta'}/s."""
+    cfg = make_config(1)
+    geom = cfg["geom"]
+    flow = Flow(1.0, geom.a, geom.zc)
+    phi, pw, U, _ = manufactured_inputs(geom, flow, [0.0])
+    geom.psi_wall = pw
+    g = O.OGeom.from_synth(geom)
+    r = O.solve_phi(g, torch.as_tensor(phi))
+    assert r["omega"].abs().max() < 1e-13
+    assert np.abs(r["U"].numpy() - U).max() < 1e-13
+
+
+def _indicator(g, m):
+    return torch.cat([torch.full((g.M[k],), 1.0 if k == m else 0.0, dtype=torch.float64)
+                      for k in range(g.nb)])
+
+
+@pytest.mark.parametrize("which", ["c1", "ragged"])
+def test_null_vectors(which):
+    """A 1_0 = -1_0/2; A 1_1 = 1/2 on every wall and 0 on the surface; A 1_m = -1_m (m >= 2)."""
+    geom = make_config(1)["geom"] if which == "c1" else ragged_config()["geom"]
+    g = O.OGeom.from_synth(geom)
+    A = O.assemble_A(g)
+    walls = 1.0 - _indicator(g, 0)
+    tol = 1e-12 if which == "c1" else 1e-10    # identities hold to spectral accuracy
+    assert (A @ _indicator(g, 0) + 0.5 * _indicator(g, 0)).abs().max() < tol
+    assert (A @ _indicator(g, 1) - 0.5 * walls).abs().max() < tol
+    for m in range(2, g.nb):
+        assert (A @ _indicator(g, m) + _indicator(g, m)).abs().max() < tol
+
+
+@pytest.mark.parametrize("which", ["c1", "ragged"])
+def test_zero_net_flux(which):
+    """Incompressibility: sum_m U_m s_m = 0 over one period."""
+    cfg = make_config(1) if which == "c1" else ragged_config()
+    g = O.OGeom.from_synth(cfg["geom"])
+    U = O.solve_phi(g, torch.as_tensor(cfg["phi"]))["U"]
+    assert abs(float((U * g.d[0].abs()).sum())) < 1e-12 * g.M[0]
+
+
+@pytest.mark.parametrize("which", ["c1", "ragged"])
+def test_velocity_potential_equals_vortex_sheet(which):
+    """U from gamma_0 = -omega_0' (Sec. 4.1) equals U of Sec. 3.4; gamma_j = omega_j'."""
+    cfg = make_config(1) if which == "c1" else ragged_config()
+    g = O.OGeom.from_synth(cfg["geom"])
+    r = O.solve_phi(g, torch.as_tensor(cfg["phi"]))
+    parts = O.split(g, r["omega"])
+    rv = O.solve_gamma(g, -O.spectral(parts[0], "D"))
+    assert (rv["U"] - r["U"]).abs().max() < 1e-12
+    gw = torch.cat([O.spectral(p, "D") for p in parts[1:]])
+    # gamma_j and omega_j' agree to the walls' resolution (coarse in the ragged cell)
+    tol = 1e-10 if which == "c1" else 1e-6
+    assert (rv["gamma_wall"] - gw).abs().max() < tol * max(1.0, float(gw.abs().max()))
+
+
+def test_spectral_operators_on_trig_polynomials():
+    M = 48
+    al = torch.as_tensor(2 * np.pi * np.arange(M) / M)
+    for k in (1, 5, 23):
+        c, s = torch.cos(k * al), torch.sin(k * al)
+        assert (O.spectral(c, "D") + k * s).abs().max() < 1e-12
+        assert (O.spectral(s, "D2") + k * k * s).abs().max() < 1e-10
+        assert (O.spectral(c, "H") - s).abs().max() < 1e-13
+        assert (O.spectral(s, "H") + c).abs().max() < 1e-13
+        assert (O.spectral(c, "ABSD") - k * c).abs().max() < 1e-12
+    nyq = torch.cos(M // 2 * al)
+    for op in ("D", "D2", "H", "ABSD"):
+        assert O.spectral(nyq, op).abs().max() < 1e-12
+    assert O.spectral(torch.ones(M, dtype=torch.float64), "H").abs().max() < 1e-14
+
+
+def test_zero_data_gives_zero():
+    cfg = make_config(1)
+    geom = cfg["geom"]
+    geom.V1, geom.a = 0.0, np.zeros_like(geom.a)
+    g = O.OGeom.from_synth(geom)
+    r = O.solve_phi(g, torch.zeros(geom.M[0], dtype=torch.float64))
+    assert r["omega"].abs().max() == 0.0 and r["U"].abs().max() == 0.0
+
+
+def test_linearity_in_data():
+    cfg = make_config(1)
+    g = O.OGeom.from_synth(cfg["geom"])
+    phi = torch.as_tensor(cfg["phi"])
+    r1 = O.solve_phi(g, phi)
+    r2 = O.solve_phi(g, 2.0 * phi)
+    g0 = O.OGeom.from_synth(cfg["geom"])
+    g0.V1, g0.a = 0.0, torch.zeros_like(g0.a)
+    rh = O.solve_phi(g0, phi)          # homogeneous part
+    assert ((r2["omega"] - r1["omega"]) - rh["omega"]).abs().max() < 1e-12
+
+
+def test_gradient_matches_central_differences():
+    """Autograd gradient of J = sum w U^2 vs central differences of the oracle."""
+    t = tiny_config()
+    gw = O.OGeom.from_synth(t["geom"])
+    al = gw.alpha[0]
+    xt, yt = gw.z[0].real - al, gw.z[0].imag
+    ph = torch.as_tensor(t["phi"])
+    wts = torch.as_tensor(np.random.default_rng(3).uniform(0, 1, 32))
+    _, gx, gy, gp, _ = O.J_and_grad(gw, xt, yt, ph, wts)
+    rng = np.random.default_rng(5)
+    for _ in range(3):
+        v = [torch.as_tensor(np.cos(2 * al.numpy() + rng.uniform(0, 6)) * rng.standard_normal())
+             for _c in range(3)]
+        h = 1e-5
+        Jp = O.J_and_grad(gw, xt + h * v[0], yt + h * v[1], ph + h * v[2], wts)[0]
+        Jm = O.J_and_grad(gw, xt - h * v[0], yt - h * v[1], ph - h * v[2], wts)[0]
+        fd = (Jp - Jm) / (2 * h)
+        an = float((gx * v[0]).sum() + (gy * v[1]).sum() + (gp * v[2]).sum())
+        assert abs(fd - an) <= 1e-7 * max(1.0, abs(fd)), (fd, an)
+
+
+def test_sampled_rows_equal_full_matrix():
+    cfg = ragged_config()
+    g = O.OGeom.from_synth(cfg["geom"])
+    A = O.assemble_A(g)
+    rows = [0, 7, 249, 250, 375, 376, 441, 442, 499]
+    assert (O.A_rows(g, rows) - A[rows]).abs().max() == 0.0
