@@ -1,0 +1,225 @@
+/*
+ * wwbi.h -- C ABI of the MI355X boundary-integral water-wave solver.
+ *
+ * The method is the one of Ambrose, Camassa, Marzuola, McLaughlin, Robinson
+ * and Wilkening, "Numerical algorithms for water waves with background flow
+ * over obstacles and topography" (arXiv 2108.01786).  Given the free surface
+ * zeta_0, the bottom zeta_1 and obstacles zeta_2..zeta_N (Sec. 2), the
+ * surface potential phi~ (velocity-potential method, Sec. 3) or the vortex
+ * sheet strength gamma_0 (Sec. 4.1), and the multi-valued flow data V1, a_j,
+ * z_j (Sec. 3, decomposition of Phi), the library returns the normal
+ * velocity U = dphi/dn on the free surface.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Boundary k is sampled at alpha_km = 2 pi m / M_k, m = 0..M_k-1
+ *    (Sec. 3.3).  Node arrays are concatenated boundary by boundary:
+ *    surface (k = 0), bottom (k = 1), obstacles (k = 2..nb-1).
+ *  - The surface and bottom run left to right with
+ *    zeta(alpha + 2 pi) = zeta(alpha) + 2 pi; obstacles are closed curves
+ *    traversed clockwise (fluid on the left, Sec. 2).
+ *  - Pointers marked (device) are HIP device pointers; (host) are host
+ *    pointers.  The caller owns every input and output buffer.  The context
+ *    owns its workspace, which grows to the largest problem seen and is then
+ *    reused (a call on an already-seen size allocates nothing).
+ *  - All work is enqueued on the context's stream; every call returns after
+ *    its results are complete.  A context must not be used by two threads
+ *    at once.
+ *  - Return value: 0 = OK; < 0 = invalid input or runtime failure, outputs
+ *    untouched; > 0 = numerical warning, outputs hold the best iterate.  No
+ *    C++ exception crosses this interface.  The report, when given, is
+ *    always filled.
+ */
+#ifndef WWBI_H
+#define WWBI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define WWBI_OK                   0
+#define WWBI_EINVAL_NULL         -1  /* a required pointer is NULL                     */
+#define WWBI_EINVAL_SIZE         -2  /* nb < 2, nb > WWBI_MAX_BOUNDARIES, M_k odd or < 8 */
+#define WWBI_EINVAL_NONFINITE    -3  /* NaN or Inf in the node data or the potential   */
+#define WWBI_EINVAL_ORIENTATION  -4  /* an obstacle is not clockwise, or the surface or
+                                        bottom does not run left to right             */
+#define WWBI_ECAPACITY           -5  /* workspace allocation failed                    */
+#define WWBI_EHIP                -6  /* a HIP runtime call failed                      */
+#define WWBI_EINVAL_OPTS         -7  /* option out of range                            */
+#define WWBI_NOT_CONVERGED        1  /* iteration budget spent before the tolerance    */
+#define WWBI_STAGNATED            2  /* a restart cycle made no progress               */
+#define WWBI_REFINE_STALLED       3  /* iterative refinement stopped contracting       */
+
+#define WWBI_MAX_BOUNDARIES      64
+
+/* ---- option values ----------------------------------------------------- */
+#define WWBI_FP64                 0  /* FP64 matrix and matvecs                          */
+#define WWBI_FP32_REFINED         1  /* FP32 matrix/matvec (FP32 accumulation) inside
+                                        FP64 iterative refinement                      */
+#define WWBI_MATVEC_AUTO          0  /* stored matrix                                    */
+#define WWBI_MATVEC_STORED        1  /* assemble once, stream the matrix per matvec      */
+#define WWBI_MATVEC_ON_THE_FLY    2  /* recompute entries inside every matvec            */
+#define WWBI_FLAG_PROFILE         1  /* time every launch of the dominant matvec kernel  */
+#define WWBI_FLAG_NO_CORRECTION   2  /* drop the E_m rank-one blocks (singular system;
+                                        for failure-detection tests only)              */
+
+/* spectral operators on one uniform periodic grid (Sec. 3.4), Nyquist mode zeroed */
+#define WWBI_OP_D                 0  /* d/dalpha, symbol i k                             */
+#define WWBI_OP_D2                1  /* d2/dalpha2, symbol -k^2                          */
+#define WWBI_OP_H                 2  /* Hilbert transform, symbol -i sgn k               */
+#define WWBI_OP_ABSD              3  /* |d| = H D, symbol |k|                            */
+
+/* matrices exported by wwbi_debug_matrix */
+#define WWBI_MAT_A                0  /* velocity-potential system (Sec. 3.3)             */
+#define WWBI_MAT_WALL             1  /* vortex-sheet wall system (Sec. 4.1)              */
+
+typedef struct wwbi_ctx wwbi_ctx;
+
+/* Geometry and multi-valued flow data (Sec. 2; Sec. 3 decomposition of Phi). */
+typedef struct {
+    int32_t nb;               /* number of boundaries N+1, 2 <= nb <= 64             */
+    const int32_t *M;         /* (host) nb node counts; each even and >= 8            */
+    const double *x, *y;      /* (device) sum(M): zeta = x + i y                      */
+    const double *dx, *dy;    /* (device) sum(M): zeta'                               */
+    const double *ddx, *ddy;  /* (device) sum(M): zeta''                              */
+    const double *zc;         /* (host) 2*(nb-2): (re, im) of z_j inside obstacle j   */
+    const double *a;          /* (host) nb-2: circulation parameters a_j              */
+    double V1;                /* background-flow strength                             */
+    const double *psi_wall;   /* (device) sum(M)-M_0 stream-function data on the walls,
+                                 or NULL for zero (the paper's problem)               */
+} wwbi_geom;
+
+typedef struct {
+    double tol;          /* stop when ||b - A x||_2 <= tol ||b||_2 (true FP64 residual)   */
+    double inner_tol;    /* FP32_REFINED: relative tolerance of each inner FP32 solve     */
+    int32_t restart;     /* GMRES restart length, 1..WWBI_MAX_RESTART                      */
+    int32_t max_iter;    /* budget of Arnoldi steps (all cycles, all refinement steps)     */
+    int32_t precision;   /* WWBI_FP64 or WWBI_FP32_REFINED                                 */
+    int32_t matvec;      /* WWBI_MATVEC_*                                                  */
+    int32_t poll_every;  /* Arnoldi steps between host reads of the convergence flag       */
+    int32_t max_refine;  /* FP32_REFINED: maximum refinement steps                         */
+    int32_t band;        /* FP32: same-boundary pairs with cyclic |l-m| <= band are
+                            evaluated in FP64 and rounded (near-singular kernel)          */
+    int32_t flags;       /* WWBI_FLAG_*                                                    */
+    const double *x0;    /* (device) sum(M) warm start for omega, or NULL for zero        */
+} wwbi_opts;
+
+#define WWBI_MAX_RESTART 256
+
+typedef struct {
+    int32_t status;
+    int32_t iters;         /* Arnoldi steps taken (all cycles and refinement steps)       */
+    int32_t restarts;      /* restart cycles                                              */
+    int32_t refine_steps;  /* FP32_REFINED: inner solves                                  */
+    double rel_resid;      /* final ||b - A x|| / ||b|| with the FP64 operator            */
+    double ms_prep, ms_assemble, ms_solve, ms_U, ms_total;   /* HIP-event phase times     */
+    int32_t n_matvec;      /* launches of the dominant matvec kernel (FLAG_PROFILE)       */
+    int32_t pad0;
+    double ms_matvec;      /* their summed HIP-event duration (FLAG_PROFILE)              */
+    double bytes_matvec;   /* algorithmic bytes moved by one such launch                  */
+} wwbi_report;
+
+/* Fill *o with defaults: tol 1e-13, inner_tol 1e-6, restart 100, max_iter 2000,
+ * FP64, stored matvec, poll every 4 steps, max_refine 8, band 16, no flags. */
+void wwbi_default_opts(wwbi_opts *o);
+
+/* Human-readable name of a status code (static string). */
+const char *wwbi_status_str(int status);
+
+/* Create a context on HIP device `device` bound to `hip_stream` (a hipStream_t;
+ * NULL = the null stream).  Allocates only small bookkeeping buffers.
+ * Returns WWBI_EHIP if the device cannot be used. */
+int wwbi_create(wwbi_ctx **ctx, int32_t device, void *hip_stream);
+
+/* Rebind the context to another stream (e.g. the caller's current stream). */
+int wwbi_set_stream(wwbi_ctx *ctx, void *hip_stream);
+
+/* Release every buffer and the context itself.  NULL is accepted. */
+int wwbi_destroy(wwbi_ctx *ctx);
+
+/* Pre-size the workspace for up to `max_unknowns` nodes, restart length
+ * `max_restart`, and a stored matrix of the given precision (WWBI_FP64 or
+ * WWBI_FP32_REFINED; -1 = no stored matrix).  Optional: solves grow the
+ * workspace on demand. */
+int wwbi_reserve(wwbi_ctx *ctx, int64_t max_unknowns, int32_t max_restart, int32_t precision);
+
+/* Velocity-potential solve (Sec. 3.2-3.4).
+ *   phi    (device) M_0: surface potential phi~ at the surface nodes.
+ * Assembles A (Sec. 3.3: K, G blocks with weights 1/M_j, -I/2 / +I/2 on the
+ * diagonal blocks, self limits Im{zeta''/(2 zeta')}, rank-one blocks
+ * E_m = e e^T / M_m for m >= 2) and b (b_0 = phi~, b_k = psi_wall - psi_mv),
+ * solves A omega = b by restarted GMRES, and evaluates
+ *   U = [Re{Phi_mv'(zeta) i zeta'} - |d| omega_0 / 2 - G_00^T D omega_0 / M_0
+ *        + sum_j K_j0^T D omega_j / M_j] / |zeta'|                  (Sec. 3.4).
+ * Outputs:
+ *   U      (device) M_0;
+ *   omega  (device) sum(M), or NULL;
+ *   psi_k  (host)   nb-2 stream-function constants psi|_k = mean(omega_k), or NULL.
+ */
+int wwbi_solve_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi, const wwbi_opts *o,
+                   double *U, double *omega, double *psi_k, wwbi_report *rep);
+
+/* Vortex-sheet solve (Sec. 4.1).
+ *   gamma0 (device) M_0: vortex sheet strength gamma_0 = -omega_0'.
+ * Solves the wall system (-I/2 + K^dagger) gamma_w = -G_0k^dagger gamma_0
+ * - s dphi_mv/dn (zero normal velocity on every wall) by GMRES and returns
+ *   U = [H gamma_0 / 2 + G_00^dagger gamma_0 + sum_j K_j0^dagger gamma_j
+ *        + s dphi_mv/dn] / |zeta'|.
+ * Outputs: U (device) M_0; gamma_wall (device) sum(M)-M_0 or NULL. */
+int wwbi_solve_gamma(wwbi_ctx *ctx, const wwbi_geom *g, const double *gamma0, const wwbi_opts *o,
+                     double *U, double *gamma_wall, wwbi_report *rep);
+
+/* Adjoint of the velocity-potential solve.  With omega from wwbi_solve_phi on
+ * the same inputs and dJdU = dJ/dU (device, M_0), returns the gradient of J
+ * with respect to the surface samples (walls held fixed):
+ *   g_phi, g_x, g_y, g_dx, g_dy, g_ddx, g_ddy  (device, M_0 each; overwritten).
+ * Uses one transpose GMRES solve A^T lambda = c with the options' precision
+ * and the derivative of every kernel entry that touches the surface. */
+int wwbi_adjoint_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, const double *dJdU,
+                     const wwbi_opts *o, double *g_phi, double *g_x, double *g_y, double *g_dx,
+                     double *g_dy, double *g_ddx, double *g_ddy, wwbi_report *rep);
+
+/* Several right-hand sides against one matrix: solves A omega_i = rhs_i,
+ * i < n, with the matrix read once per Arnoldi step for all i (matrix-core
+ * product).  rhs, omega: (device) sum(M) x n, column i at offset i*sum(M). */
+int wwbi_solve_phi_multi(wwbi_ctx *ctx, const wwbi_geom *g, const double *rhs, int32_t n,
+                         const wwbi_opts *o, double *omega, wwbi_report *rep);
+
+/* out = alpha * Op(f) + beta * out on one uniform periodic grid of n points
+ * (n even, >= 8); f, out (device) n, may not alias. */
+int wwbi_spectral(wwbi_ctx *ctx, int32_t n, const double *f, int32_t op, double alpha,
+                  double beta, double *out);
+
+/* Surface samples from periodic displacements: zeta = alpha + xt + i yt with
+ * spectral zeta', zeta'' (x = alpha_m + xt_m, x' = 1 + D xt, x'' = D2 xt,
+ * likewise for y).  All pointers (device) n.  The outputs may point into the
+ * concatenated geometry arrays. */
+int wwbi_surface_fill(wwbi_ctx *ctx, int32_t n, const double *xt, const double *yt, double *x,
+                      double *y, double *dx, double *dy, double *ddx, double *ddy);
+
+/* Chain rule of wwbi_surface_fill: g_xt = g_x - D g_dx + D2 g_ddx and likewise
+ * for y (D is antisymmetric, D2 symmetric).  All pointers (device) n. */
+int wwbi_surface_fill_adjoint(wwbi_ctx *ctx, int32_t n, const double *g_x, const double *g_y,
+                              const double *g_dx, const double *g_dy, const double *g_ddx,
+                              const double *g_ddy, double *g_xt, double *g_yt);
+
+/* Export a matrix for inspection: `which` = WWBI_MAT_A (sum(M)^2) or
+ * WWBI_MAT_WALL ((sum(M)-M_0)^2), row-major, FP64 (precision WWBI_FP64) or
+ * FP32 (WWBI_FP32_REFINED, with the FP64 band of width `band`).
+ * out (device) must hold n*n elements of that type. */
+int wwbi_debug_matrix(wwbi_ctx *ctx, const wwbi_geom *g, int32_t which, int32_t precision,
+                      int32_t band, void *out);
+
+/* One product with the velocity-potential matrix: y = A x (transpose = 0) or
+ * y = A^T x (transpose = 1), with the given precision and matvec mode.  x, y
+ * (device) sum(M).  For tests and benchmarks of the matvec kernels. */
+int wwbi_matvec(wwbi_ctx *ctx, const wwbi_geom *g, const double *x, double *y, int32_t precision,
+                int32_t mode, int32_t transpose, int32_t band, wwbi_report *rep);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* WWBI_H */

@@ -1,0 +1,116 @@
+// Host context of libwwbi (shared by the translation units of the host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+
+#include "internal.h"
+
+namespace wwbi {
+
+inline long round_up(long a, long b) { return (a + b - 1) / b * b; }
+
+// Linear operators GMRES can run on.
+enum OpKind {
+    OP_A_S64 = 0,   // velocity-potential A, stored FP64
+    OP_A_S32,       // stored FP32 (FP32 accumulation)
+    OP_A_O64,       // on the fly FP64
+    OP_A_O32,       // on the fly FP32 (FP64 band and limits)
+    OP_AT_S64,      // transposes of the above
+    OP_AT_S32,
+    OP_AT_O64,
+    OP_AT_O32,
+    OP_W_S64,       // vortex-sheet wall operator, stored FP64
+    OP_W_O64,       // on the fly FP64
+};
+
+struct Op {
+    int kind;
+    int n;          // operator size
+    long ld;        // leading dimension of the stored matrix
+    int flags;
+    int band;
+};
+
+struct SolveStats {
+    int iters = 0;
+    int cycles = 0;
+    int refine_steps = 0;
+    double rel_resid = 0.0;
+};
+
+// workspace vectors (each round_up(n, 64) doubles)
+enum VecId { VR = 0, VW, VB, VX, VRR, VD, VG, VHG, VUM, VTMP, VTMP2, VLAM, VMU, VC, kNumVec };
+
+constexpr int kProfPairs = 2048;
+constexpr int kStateSlotOffset = 2048;   // byte offset of the two polled GState copies in hst
+
+struct Ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int restart_cap = 100;
+
+    Layout L{};
+    Flow F{};
+    Nodes N{};
+    const double *psi_wall = nullptr;
+
+    void *A = nullptr;      size_t capA = 0;
+    double *V = nullptr;    size_t capV = 0;
+    float *v32 = nullptr;   size_t capv32 = 0;
+    double *vec[kNumVec] = {};  size_t capvec[kNumVec] = {};
+    double *H = nullptr;    size_t capH = 0;
+    double *cs = nullptr;   size_t capcs = 0;
+    double *sn = nullptr;   size_t capsn = 0;
+    double *gv = nullptr;   size_t capg = 0;
+    double *yv = nullptr;   size_t capy = 0;
+    double *P = nullptr;    size_t capP = 0;
+    double *part = nullptr; size_t cappart = 0;
+    int *bid = nullptr;     size_t capbid = 0;
+    int *loc = nullptr;     size_t caploc = 0;
+    int *Mk = nullptr;      size_t capMk = 0;
+    double *wq = nullptr;   size_t capwq = 0;
+    double *s = nullptr;    size_t caps = 0;
+    double *lre = nullptr;  size_t caplre = 0;
+    double *lim = nullptr;  size_t caplim = 0;
+    double *rowD = nullptr; size_t caprowD = 0;
+    double *rowH = nullptr; size_t caprowH = 0;
+    double *hrow = nullptr; size_t caphrow = 0;     // (1/2) cot(pi n / M_0)
+    double *eR = nullptr;   size_t capeR = 0;       // E = e^{i zeta}
+    double *eI = nullptr;   size_t capeI = 0;
+    double *val = nullptr;  size_t capval = 0;
+    double *apart = nullptr; size_t capapart = 0;   // adjoint partial sums
+    GState *gs = nullptr;
+    void *hst = nullptr;    // pinned host staging (4 KiB)
+
+    hipEvent_t ev[5] = {};
+    hipEvent_t pollev[2] = {};
+    hipEvent_t prof[2 * kProfPairs] = {};
+    bool profiling = false;
+    bool trace = false;     // WWBI_TRACE set: one stderr line per GMRES cycle
+    int nprof = 0;
+
+    int ensure(int n, int restart);
+    int ensure_matrix(size_t bytes);
+    void release();
+    int setup(const wwbi_geom *g, const double *phi, int nphi);
+    void apply(const Op &op, const double *x, const float *x32, const double *c, double *y,
+               const int *active);
+    double op_bytes(const Op &op) const;
+    int read_state(GState &out);
+    void prof_begin();
+    void prof_end();
+    int gmres(const Op &op, const double *b, double *x, bool x_zero, double tol, int restart,
+              int max_iter, int poll, bool fp32_basis, bool verify, SolveStats &st);
+    double device_norm(const double *v, int n);
+    int refine(const Op &op32, const Op &op64, const double *b, double *x, bool x_zero,
+               const wwbi_opts &o, SolveStats &st);
+    void eval_U_from_gamma(const double *gamma, double *U);
+    void gamma_from_omega(const double *omega, double *gamma);
+    static int check_opts(const wwbi_opts *o);
+    void begin_report(bool prof);
+    void finish_report(wwbi_report *rep, int status, const SolveStats &st, double bytes);
+};
+
+}  // namespace wwbi

@@ -1,0 +1,172 @@
+// Kernel entries of the collocated boundary-integral operators (device code).
+//
+// With zeta_p the target node and zeta_q the source node, write
+//   kappa = cot((zeta_q - zeta_p)/2),
+//   S_pq  = (1/2) zeta_q' kappa        (source flavour, Sec. 3.2 table),
+//   R_pq  = -(1/2) zeta_p' kappa       (target flavour: the integration
+//                                       variable sits in the first kernel slot,
+//                                       Sec. 3.4 and Sec. 4.1).
+// The velocity-potential matrix A (Sec. 3.3) takes Im S or Re S block by block,
+// the normal-velocity map and the vortex-sheet wall system take Im R or
+// Re(R + h), h = (1/2) cot((alpha_q - alpha_p)/2) on the surface's own block.
+// On the diagonal every regularised kernel tends to zeta''/(2 zeta').
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "internal.h"
+
+namespace wwbi {
+
+struct Src {               // source node q
+    double ex, ey, dx, dy, w;   // E = e^{i zeta}, zeta', weight 1/M_k
+    int k, loc, M, idx;
+};
+struct Tgt {               // target node p
+    double ex, ey, dx, dy, lre, lim;
+    int k, loc, M, idx;
+};
+
+// Same-boundary pairs closer than this many grid steps take kappa from the
+// difference of the positions (see kappa64).
+constexpr int kNearBand = 16;
+
+__device__ __forceinline__ Src load_src(const Nodes &N, int q) {
+    Src s;
+    s.ex = N.ex[q]; s.ey = N.ey[q]; s.dx = N.dx[q]; s.dy = N.dy[q]; s.w = N.w[q];
+    s.k = N.bid[q]; s.loc = N.loc[q]; s.M = N.Mk[q]; s.idx = q;
+    return s;
+}
+__device__ __forceinline__ Tgt load_tgt(const Nodes &N, int p) {
+    Tgt t;
+    t.ex = N.ex[p]; t.ey = N.ey[p]; t.dx = N.dx[p]; t.dy = N.dy[p];
+    t.lre = N.lre[p]; t.lim = N.lim[p];
+    t.k = N.bid[p]; t.loc = N.loc[p]; t.M = N.Mk[p]; t.idx = p;
+    return t;
+}
+
+// cot((u + i v)/2) = (sin u - i sinh v) / (2 (sin^2(u/2) + sinh^2(v/2))), with
+// half angles so that nearby points lose no digits (cosh v - cos u is never
+// formed).  Used for the multi-valued terms and for near pairs.
+__device__ __forceinline__ void cot_half64(double u, double v, double &cr, double &ci) {
+    double su, cu;
+    sincos(0.5 * u, &su, &cu);
+    const double em = expm1(0.5 * v);        // e^{v/2} - 1, accurate for small v
+    const double ep = em + 1.0;
+    const double ie = 1.0 / ep;
+    const double sh = 0.5 * em * (1.0 + ie); // sinh(v/2)
+    const double ch = 0.5 * (ep + ie);       // cosh(v/2)
+    const double r = 1.0 / (su * su + sh * sh);
+    cr = su * cu * r;
+    ci = -sh * ch * r;
+}
+
+__device__ __forceinline__ int cyc_dist(int a, int b, int M) {
+    int d = a - b;
+    if (d < 0) d = -d;
+    return d < M - d ? d : M - d;
+}
+
+// kappa = cot((zeta_q - zeta_p)/2).  Far pairs use E = e^{i zeta} stored per
+// node: cot(w/2) = i (e^{iw} + 1) / (e^{iw} - 1) with e^{i(zeta_q - zeta_p)} =
+// E_q / E_p, i.e. kappa = i (E_q + E_p) / (E_q - E_p) -- one complex quotient
+// and no transcendental function.  The rounding of E is amplified by
+// 1/|zeta_q - zeta_p| in E_q - E_p, so near pairs (same boundary within
+// kNearBand steps, or |E_q - E_p| < |E_p| / 64) use the half-angle formula on
+// the exact difference of the positions instead.
+__device__ __forceinline__ void kappa64(const Nodes &N, const Tgt &t, const Src &s, double &cr,
+                                        double &ci) {
+    const double dr = s.ex - t.ex, di = s.ey - t.ey;
+    const double den = dr * dr + di * di;
+    const double ee = t.ex * t.ex + t.ey * t.ey;
+    if ((t.k == s.k && cyc_dist(t.loc, s.loc, t.M) <= kNearBand) || den * 4096.0 < ee) {
+        cot_half64(N.x[s.idx] - N.x[t.idx], N.y[s.idx] - N.y[t.idx], cr, ci);
+        return;
+    }
+    const double nr = s.ex + t.ex, ni = s.ey + t.ey;
+    const double inv = 1.0 / den;
+    // N conj(D) / |D|^2 = p; kappa = i p
+    const double pr = (nr * dr + ni * di) * inv;
+    const double pi = (ni * dr - nr * di) * inv;
+    cr = -pi;
+    ci = pr;
+}
+
+// FP32 quotient for far pairs; the sums and differences of E are formed in
+// FP64 first, so the FP32 rounding is not amplified for nearby points.
+__device__ __forceinline__ void kappa32(const Tgt &t, const Src &s, float &cr, float &ci) {
+    const float nr = (float)(s.ex + t.ex), ni = (float)(s.ey + t.ey);
+    const float dr = (float)(s.ex - t.ex), di = (float)(s.ey - t.ey);
+    const float inv = 1.0f / (dr * dr + di * di);
+    const float pr = (nr * dr + ni * di) * inv;
+    const float pi = (ni * dr - nr * di) * inv;
+    cr = -pi;
+    ci = pr;
+}
+
+// h = (1/2) cot(pi n / M_0), n = (l - m) mod M_0, from a table of the surface grid.
+__device__ __forceinline__ double hrow_lookup(const double *hrow, int l, int m, int M) {
+    int n = l - m;
+    if (n < 0) n += M;
+    return hrow[n];
+}
+
+// A(p, q) in FP64 (Sec. 3.3):
+//   k=0,j=0: -delta/2 + w Im S     k=0,j>=1: w Re S
+//   k>=1,j=0: -w Re S              k>=1,j>=1: delta/2 + w Im S - [k=j>=2] w
+// the diagonal of a same-boundary block is the limit Im{zeta''/(2 zeta')}.
+__device__ __forceinline__ double a_val64(const Nodes &N, const Tgt &t, const Src &s, bool corr) {
+    const bool same = (t.k == s.k);
+    const double ecorr = (same && t.k >= 2 && corr) ? s.w : 0.0;
+    if (same && t.loc == s.loc)
+        return (t.k == 0 ? -0.5 : 0.5) + s.w * t.lim - ecorr;
+    double cr, ci;
+    kappa64(N, t, s, cr, ci);
+    const double sr = 0.5 * (s.dx * cr - s.dy * ci);
+    const double si = 0.5 * (s.dx * ci + s.dy * cr);
+    double v = ((t.k == 0) != (s.k == 0)) ? sr : si;
+    if (t.k != 0 && s.k == 0) v = -v;
+    return v * s.w - ecorr;
+}
+
+// A(p, q) stored in FP32.  Differences of positions are always formed in FP64;
+// same-boundary pairs within `band` nodes (cyclically) and the diagonal limits
+// are evaluated entirely in FP64 and rounded once.
+__device__ __forceinline__ float a_val32(const Nodes &N, const Tgt &t, const Src &s, bool corr,
+                                        int band) {
+    const bool same = (t.k == s.k);
+    if (same && cyc_dist(t.loc, s.loc, t.M) <= band) return (float)a_val64(N, t, s, corr);
+    const float ecorr = (same && t.k >= 2 && corr) ? (float)s.w : 0.0f;
+    float cr, ci;
+    kappa32(t, s, cr, ci);
+    const float dx = (float)s.dx, dy = (float)s.dy;
+    const float sr = 0.5f * (dx * cr - dy * ci);
+    const float si = 0.5f * (dx * ci + dy * cr);
+    float v = ((t.k == 0) != (s.k == 0)) ? sr : si;
+    if (t.k != 0 && s.k == 0) v = -v;
+    return v * (float)s.w - ecorr;
+}
+
+// Target-flavour entry T(p, q) = w_q sel(R_pq + [k=j=0] h_pq), sel = Re for a
+// surface source and Im for a wall source; diagonal: w Re L (surface) or
+// w Im L (walls).  Rows on the surface give the normal-velocity map
+// (Sec. 3.4 / Sec. 4.1 formula for U); rows and columns on the walls give
+// the wall operator K^dagger; wall rows with surface sources give G_0k^dagger.
+__device__ __forceinline__ double t_val64(const Nodes &N, const Tgt &t, const Src &s,
+                                         const double *hrow) {
+    if (t.k == s.k && t.loc == s.loc) return s.w * (t.k == 0 ? t.lre : t.lim);
+    double cr, ci;
+    kappa64(N, t, s, cr, ci);
+    const double rr = -0.5 * (t.dx * cr - t.dy * ci);
+    const double ri = -0.5 * (t.dx * ci + t.dy * cr);
+    double v;
+    if (s.k == 0) {
+        v = rr;
+        if (t.k == 0) v += hrow_lookup(hrow, s.loc, t.loc, t.M);
+    } else {
+        v = ri;
+    }
+    return s.w * v;
+}
+
+}  // namespace wwbi

@@ -1,0 +1,157 @@
+// Internal declarations shared by the HIP translation units of libwwbi.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/wwbi.h"
+
+namespace wwbi {
+
+constexpr int kMaxB = WWBI_MAX_BOUNDARIES;
+
+// Boundary layout: node p of boundary k has global index off[k] + m.
+struct Layout {
+    int nb;
+    int n;                 // total nodes sum(M)
+    int off[kMaxB + 1];
+};
+
+// Multi-valued flow data (Sec. 3): V1, a_j and z_j for obstacles j = 2..nb-1.
+struct Flow {
+    double V1;
+    int nobs;
+    double a[kMaxB];
+    double zx[kMaxB], zy[kMaxB];
+};
+
+// Device view of the prepared nodes.  x..dy are the caller's arrays; the rest
+// is derived once per call by k_prep_nodes.
+struct Nodes {
+    const double *x, *y, *dx, *dy, *ddx, *ddy;
+    const double *ex, *ey;   // E = e^{i zeta} = e^{-y} (cos x, sin x)
+    const int *bid;        // boundary index of each node
+    const int *loc;        // index m within its boundary
+    const int *Mk;         // node count M_k of its boundary
+    const double *w;       // quadrature weight 1/M_k of the node's boundary
+    const double *s;       // |zeta'|
+    const double *lre;     // Re{zeta''/(2 zeta')}
+    const double *lim;     // Im{zeta''/(2 zeta')}
+    int n;
+};
+
+// Device-resident GMRES cycle state (one per Krylov solve in flight).
+struct GState {
+    int active;        // 1 while the current restart cycle runs
+    int jdone;         // Arnoldi steps completed in the current cycle
+    int breakdown;
+    int pad;
+    double bnorm;      // ||b||
+    double tol_abs;    // tol * ||b||
+    double beta;       // residual norm at the start of the cycle
+    double resid;      // current residual estimate |g_{j+1}|
+};
+
+// circulant row (1/2) cot(pi n / M) of the Hilbert regulariser h (n != 0)
+constexpr int kOpHalfCot = 100;
+
+struct Ctx;   // host context (api.hip)
+
+// ---- kernels_geom.hip --------------------------------------------------------
+void launch_prep_nodes(const Layout &L, const double *x, const double *y, const double *dx,
+                       const double *dy, const double *ddx, const double *ddy, int *bid,
+                       int *loc, int *Mk, double *w, double *s, double *lre, double *lim,
+                       double *ex, double *ey, hipStream_t st);
+void launch_validate(const Layout &L, const Nodes &N, const double *phi, int nphi,
+                     double *out /* 3*nb+1 */, hipStream_t st);
+void launch_rhs_phi(const Layout &L, const Nodes &N, const Flow &F, const double *phi,
+                    const double *psi_wall, double *b, hipStream_t st);
+void launch_umv(const Nodes &N, const Flow &F, int first, int count, double *out,
+                hipStream_t st);
+void launch_circulant_rows(const Layout &L, int op, double *rows, hipStream_t st);
+void launch_circulant_apply(const Layout &L, const double *rows, const double *f, double *out,
+                            double alpha, double beta, int first_block, int last_block,
+                            hipStream_t st);
+void launch_circ_row1(int M, int op, double *row, hipStream_t st);
+void launch_circ_apply1(int M, const double *row, const double *f, double *out, double alpha,
+                        double beta, hipStream_t st);
+void launch_block_means(const Layout &L, const double *v, double *out, hipStream_t st);
+void launch_U_finalize(int n0, const double *s, const double *umv, const double *hg,
+                       const double *part, int nsplit, double *U, hipStream_t st);
+void launch_wall_rhs_finalize(int nw, const double *umv_w, const double *part, int nsplit,
+                              double *rhs, hipStream_t st);
+void launch_surface_base(int n, const double *xt, const double *yt, double *x, double *y,
+                         hipStream_t st);
+void launch_add_scalar(int n, double *v, double c, hipStream_t st);
+
+// ---- kernels_matrix.hip ------------------------------------------------------
+// `active` (device, may be null): when it points to 0 the product is skipped.
+void launch_assemble64(const Layout &L, const Nodes &N, int flags, double *A, long ld,
+                       hipStream_t st);
+void launch_assemble32(const Layout &L, const Nodes &N, int flags, int band, float *A, long ld,
+                       hipStream_t st);
+void launch_assemble_wall64(const Layout &L, const Nodes &N, const double *hrow, double *W, long ld,
+                            hipStream_t st);
+// y = c - A x, or y = A x when c is null
+void launch_gemv64(const double *A, long ld, int n, const double *x, const double *c, double *y,
+                   const int *active, hipStream_t st);
+void launch_gemv32(const float *A, long ld, int n, const float *x, const double *c, double *y,
+                   const int *active, hipStream_t st);
+void launch_gemv32_x64(const float *A, long ld, int n, const double *x, const double *c,
+                       double *y, const int *active, hipStream_t st);
+void launch_gemvT64(const double *A, long ld, int n, const double *x, const double *c, double *y,
+                    double *part, const int *active, hipStream_t st);
+void launch_gemvT32(const float *A, long ld, int n, const double *x, const double *c, double *y,
+                    double *part, const int *active, hipStream_t st);
+void launch_otf_matvec(const Layout &L, const Nodes &N, int flags, int fp32, int band,
+                       int transpose, const double *x, const double *c, double *y, double *part,
+                       const int *active, hipStream_t st);
+// target-flavour products over rows [r0, r0+nr) and columns [c0, c0+nc):
+// mode 2 = T (normal-velocity map / G^dagger), mode 3 = wall operator T - I/2.
+// Forward: part[s][r] over column chunks; transpose: part[s][c] over row chunks.
+void launch_rflavour(const Layout &L, const Nodes &N, const double *hrow, int mode, int transpose,
+                     int r0, int nr, int c0, int nc, const double *x, double *part,
+                     const int *active, hipStream_t st);
+int rflavour_nsplit(int nsum);
+void launch_reduce_partials(int n, const double *part, int nsplit, const double *c, double scale,
+                            double *y, const int *active, hipStream_t st);
+int otf_chunk(int n);
+int otf_nsplit(int n);
+
+// ---- kernels_adjoint.hip -----------------------------------------------------
+int adjoint_nsplit(int n);
+void launch_adj_c(int n0, const double *Ubar, const double *s, double *c, hipStream_t st);
+void launch_adj_rows(const Nodes &N, const double *hrow, int n0, int n, const double *omega,
+                     const double *gamma, double *part, hipStream_t st);
+void launch_adj_cols(const Nodes &N, int n0, int n, const double *lam, const double *cvec,
+                     double *part, hipStream_t st);
+void launch_adj_finalize(const Nodes &N, const Flow &F, int n0, const double *Ubar,
+                         const double *U, const double *omega, const double *gamma,
+                         const double *lam, const double *prow, int nsr, const double *pcol,
+                         int nsc, double *g_phi, double *g_x, double *g_y, double *g_dx,
+                         double *g_dy, double *g_ddx, double *g_ddy, hipStream_t st);
+
+// ---- kernels_gmres.hip -------------------------------------------------------
+int gmres_nblocks(int n);
+void launch_norm_partial(const double *v, int n, double *P, int G, hipStream_t st);
+void launch_set_tol(const double *P, int G, double tol, GState *gs, hipStream_t st);
+void launch_cycle_start(const double *r, int n, const double *P, int G, double *V, float *v32,
+                        double *g, int ldg, GState *gs, hipStream_t st);
+void launch_cgs_dot(const double *V, long ldv, const double *w, int n, int j, double *P, int ldp,
+                    int G, const GState *gs, hipStream_t st);
+void launch_cgs_update(const double *V, long ldv, double *w, int n, int j, const double *Pin,
+                       double *Pout, int ldp, int G, double *H, int ldh, int pass,
+                       const GState *gs, hipStream_t st);
+void launch_givens_scale(const double *w, int n, int j, const double *P, int G, double *V,
+                         long ldv, float *v32, double *H, int ldh, double *cs, double *sn,
+                         double *g, int restart_len, GState *gs, hipStream_t st);
+void launch_hsolve(const double *H, int ldh, const double *g, double *y, const GState *gs,
+                   hipStream_t st);
+void launch_xupdate(double *x, const double *V, long ldv, int n, const double *y,
+                    const GState *gs, hipStream_t st);
+void launch_axpy(double *x, const double *d, int n, double alpha, hipStream_t st);
+void launch_copy(double *dst, const double *src, int n, hipStream_t st);
+void launch_fill(double *dst, double v, int n, hipStream_t st);
+void launch_to_f32(const double *src, float *dst, int n, hipStream_t st);
+
+}  // namespace wwbi

@@ -1,0 +1,243 @@
+// Derivative contractions of the adjoint of the velocity-potential solve.
+//
+// Forward map (walls fixed, surface samples z, d = z', e = z'' free):
+//   A(z, d, e) omega = b,  b_0 = phi~            (Sec. 3.2-3.3)
+//   gamma = (-D omega_0, D omega_1, ...)
+//   s U = u_mv(z, d) + H gamma_0 / 2 + T(z, d, e) gamma     (Sec. 3.4)
+// With c = Ubar / s and lambda = A^{-T} omegabar, the geometric part of the
+// gradient is
+//   sum_m c_m [d u_mv + dT gamma]_m - sum_m c_m U_m ds_m - lambda^T dA omega.
+// Every kernel entry that involves a surface node contributes through
+//   d kappa / d Delta = -(1 + kappa^2)/2,  kappa = cot((z_q - z_p)/2),
+// so dS/dz_q = -d_q (1 + kappa^2)/4 = -dS/dz_p, dS/dd_q = kappa/2 for the
+// source flavour and dR/dz_q = d_p (1 + kappa^2)/4 = -dR/dz_p, dR/dd_p =
+// -kappa/2 for the target flavour.
+#include "entries.h"
+#include "internal.h"
+
+namespace wwbi {
+
+namespace {
+
+inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+constexpr int kStage = 256;
+
+struct Cx {
+    double re, im;
+};
+__device__ __forceinline__ Cx cmul(Cx a, Cx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ Cx ctimes_i(Cx a) { return {-a.im, a.re}; }
+__device__ __forceinline__ Cx cscale(Cx a, double s) { return {a.re * s, a.im * s}; }
+
+// Row pass: targets r on the surface, all sources q != r.
+//   out[0] = sum_q omega_q dA_rq/dx_r        out[1] = ... /dy_r
+//   out[2] = sum_q gamma_q dT_rq/dx_r        out[3] = ... /dy_r
+//   out[4] = sum_q gamma_q dT_rq/ddx_r       out[5] = ... /ddy_r
+__global__ __launch_bounds__(256) void k_adj_rows(Nodes N, const double *hrow, int n0, int n,
+                                                  int chunk,
+                                                  const double *__restrict__ omega,
+                                                  const double *__restrict__ gamma,
+                                                  double *__restrict__ part) {
+    __shared__ Src ss[kStage];
+    __shared__ double sw[kStage], sg[kStage];
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    const bool live = r < n0;
+    Tgt t;
+    if (live) t = load_tgt(N, r);
+    const int qb = blockIdx.y * chunk, qe = min(n, qb + chunk);
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
+    for (int qq = qb; qq < qe; qq += kStage) {
+        const int q = qq + threadIdx.x;
+        if (q < qe) {
+            ss[threadIdx.x] = load_src(N, q);
+            sw[threadIdx.x] = omega[q];
+            sg[threadIdx.x] = gamma[q];
+        }
+        __syncthreads();
+        const int m = min(kStage, qe - qq);
+        if (live) {
+            for (int i = 0; i < m; ++i) {
+                const Src &s = ss[i];
+                if (s.k == 0 && s.loc == t.loc) continue;
+                double cr, ci;
+                kappa64(N, t, s, cr, ci);
+                const Cx kap{cr, ci};
+                const Cx Q{1.0 + cr * cr - ci * ci, 2.0 * cr * ci};
+                // source flavour, target derivative: dS/dz_r = +d_q Q / 4
+                const Cx dS = cscale(cmul({s.dx, s.dy}, Q), 0.25 * s.w * sw[i]);
+                const Cx dSy = ctimes_i(dS);
+                if (s.k == 0) { a0 += dS.im; a1 += dSy.im; }   // Im block (surface row, surface col)
+                else { a0 += dS.re; a1 += dSy.re; }            // Re block (surface row, wall col)
+                // target flavour: dR/dz_r = -d_r Q / 4, dR/dd_r = -kappa / 2
+                const double gw = s.w * sg[i];
+                const Cx dR = cscale(cmul({t.dx, t.dy}, Q), -0.25 * gw);
+                const Cx dRy = ctimes_i(dR);
+                const Cx dD = cscale(kap, -0.5 * gw);
+                const Cx dDy = ctimes_i(dD);
+                if (s.k == 0) { a2 += dR.re; a3 += dRy.re; a4 += dD.re; a5 += dDy.re; }
+                else { a2 += dR.im; a3 += dRy.im; a4 += dD.im; a5 += dDy.im; }
+            }
+        }
+        __syncthreads();
+    }
+    if (live) {
+        const long st = (long)gridDim.y * n0;
+        double *o = part + (long)blockIdx.y * n0 + r;
+        o[0] = a0; o[st] = a1; o[2 * st] = a2; o[3 * st] = a3; o[4 * st] = a4; o[5 * st] = a5;
+    }
+}
+
+// Column pass: sources r on the surface, all targets p != r.
+//   out[0..3] = sum_p lambda_p dA_pr/d(x_r, y_r, dx_r, dy_r)
+//   out[4..5] = sum_{p on surface} c_p dT_pr/d(x_r, y_r)
+__global__ __launch_bounds__(256) void k_adj_cols(Nodes N, int n0, int n, int chunk,
+                                                  const double *__restrict__ lam,
+                                                  const double *__restrict__ cvec,
+                                                  double *__restrict__ part) {
+    __shared__ Tgt ts[kStage];
+    __shared__ double sl[kStage], sc[kStage];
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    const bool live = r < n0;
+    Src s;
+    if (live) s = load_src(N, r);
+    const int pb = blockIdx.y * chunk, pe = min(n, pb + chunk);
+    double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
+    for (int pp = pb; pp < pe; pp += kStage) {
+        const int p = pp + threadIdx.x;
+        if (p < pe) {
+            ts[threadIdx.x] = load_tgt(N, p);
+            sl[threadIdx.x] = lam[p];
+            sc[threadIdx.x] = p < n0 ? cvec[p] : 0.0;
+        }
+        __syncthreads();
+        const int m = min(kStage, pe - pp);
+        if (live) {
+            for (int i = 0; i < m; ++i) {
+                const Tgt &t = ts[i];
+                if (t.k == 0 && t.loc == s.loc) continue;
+                double cr, ci;
+                kappa64(N, t, s, cr, ci);
+                const Cx kap{cr, ci};
+                const Cx Q{1.0 + cr * cr - ci * ci, 2.0 * cr * ci};
+                // source flavour, source derivative: dS/dz_r = -d_r Q / 4, dS/dd_r = kappa / 2
+                const double lw = s.w * sl[i];
+                const Cx dS = cscale(cmul({s.dx, s.dy}, Q), -0.25 * lw);
+                const Cx dSy = ctimes_i(dS);
+                const Cx dK = cscale(kap, 0.5 * lw);
+                const Cx dKy = ctimes_i(dK);
+                if (t.k == 0) {   // surface row: Im S
+                    a0 += dS.im; a1 += dSy.im; a2 += dK.im; a3 += dKy.im;
+                } else {          // wall row: -Re S
+                    a0 -= dS.re; a1 -= dSy.re; a2 -= dK.re; a3 -= dKy.re;
+                }
+                if (t.k == 0) {
+                    // target flavour, source derivative: dR/dz_r = d_p Q / 4 (surface source: Re)
+                    const Cx dR = cscale(cmul({t.dx, t.dy}, Q), 0.25 * s.w * sc[i]);
+                    a4 += dR.re;
+                    a5 += ctimes_i(dR).re;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (live) {
+        const long st = (long)gridDim.y * n0;
+        double *o = part + (long)blockIdx.y * n0 + r;
+        o[0] = a0; o[st] = a1; o[2 * st] = a2; o[3 * st] = a3; o[4 * st] = a4; o[5 * st] = a5;
+    }
+}
+
+// Combine every term on the surface nodes.
+__global__ void k_adj_finalize(Nodes N, Flow F, int n0, const double *__restrict__ Ubar,
+                               const double *__restrict__ U, const double *__restrict__ omega,
+                               const double *__restrict__ gamma, const double *__restrict__ lam,
+                               const double *__restrict__ prow, int nsr,
+                               const double *__restrict__ pcol, int nsc, double *g_phi,
+                               double *g_x, double *g_y, double *g_dx, double *g_dy, double *g_ddx,
+                               double *g_ddy) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n0) return;
+    double R[6] = {0, 0, 0, 0, 0, 0}, Cc[6] = {0, 0, 0, 0, 0, 0};
+    const long sr = (long)nsr * n0, sc = (long)nsc * n0;
+    for (int k = 0; k < 6; ++k) {
+        for (int b = 0; b < nsr; ++b) R[k] += prow[k * sr + (long)b * n0 + r];
+        for (int b = 0; b < nsc; ++b) Cc[k] += pcol[k * sc + (long)b * n0 + r];
+    }
+    const double x = N.x[r], y = N.y[r], dx = N.dx[r], dy = N.dy[r];
+    const double ex = N.ddx[r], ey = N.ddy[r];
+    const double s = N.s[r], w = N.w[r];
+    const double c = Ubar[r] / s;
+    const double lr = lam[r], wr = omega[r], gr = gamma[r];
+    // u_mv = -(V1 + sum a / 2) y' + sum_j a_j Re{cot((z - z_j)/2) z' / 2}
+    double asum = 0.0;
+    for (int j = 0; j < F.nobs; ++j) asum += F.a[j];
+    double ux = 0, uy = 0, udx = 0, udy = -(F.V1 + 0.5 * asum);
+    for (int j = 0; j < F.nobs; ++j) {
+        double cr, ci;
+        cot_half64(x - F.zx[j], y - F.zy[j], cr, ci);
+        const Cx kap{cr, ci};
+        const Cx Q{1.0 + cr * cr - ci * ci, 2.0 * cr * ci};
+        const Cx dz = cscale(cmul({dx, dy}, Q), -0.25 * F.a[j]);   // d/dz of a kappa z'/2
+        ux += dz.re;
+        uy += ctimes_i(dz).re;
+        udx += 0.5 * F.a[j] * kap.re;
+        udy += 0.5 * F.a[j] * ctimes_i(kap).re;
+    }
+    // diagonal limits L = e/(2d): A_rr = -1/2 + w Im L, T_rr = w Re L
+    const double d2 = dx * dx + dy * dy;
+    const Cx inv_d{dx / d2, -dy / d2};                 // 1/d
+    const Cx L{(ex * dx + ey * dy) / (2.0 * d2), (ey * dx - ex * dy) / (2.0 * d2)};
+    const Cx dLdd = cscale(cmul(L, inv_d), -1.0);      // -e/(2 d^2) = -L/d
+    const Cx dLdd_y = ctimes_i(dLdd);
+    const Cx dLde = cscale(inv_d, 0.5);                // 1/(2d)
+    const Cx dLde_y = ctimes_i(dLde);
+    const double la = -lr * wr * w, tc = c * gr * w;   // weights of Im (A) and Re (T) parts
+    g_phi[r] = lr;
+    g_x[r] = c * ux + c * R[2] + gr * Cc[4] - lr * R[0] - wr * Cc[0];
+    g_y[r] = c * uy + c * R[3] + gr * Cc[5] - lr * R[1] - wr * Cc[1];
+    g_dx[r] = c * udx - c * U[r] * dx / s + c * R[4] - wr * Cc[2] + la * dLdd.im + tc * dLdd.re;
+    g_dy[r] = c * udy - c * U[r] * dy / s + c * R[5] - wr * Cc[3] + la * dLdd_y.im + tc * dLdd_y.re;
+    g_ddx[r] = la * dLde.im + tc * dLde.re;
+    g_ddy[r] = la * dLde_y.im + tc * dLde_y.re;
+}
+
+// c = Ubar / s on the surface
+__global__ void k_adj_c(int n0, const double *Ubar, const double *s, double *c) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < n0) c[r] = Ubar[r] / s[r];
+}
+
+}  // namespace
+
+int adjoint_nsplit(int n) { return cdiv(n, otf_chunk(n)); }
+
+void launch_adj_c(int n0, const double *Ubar, const double *s, double *c, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_c, dim3(cdiv(n0, 256)), dim3(256), 0, st, n0, Ubar, s, c);
+}
+
+void launch_adj_rows(const Nodes &N, const double *hrow, int n0, int n, const double *omega,
+                     const double *gamma, double *part, hipStream_t st) {
+    const int chunk = otf_chunk(n);
+    dim3 grid(cdiv(n0, 256), cdiv(n, chunk));
+    hipLaunchKernelGGL(k_adj_rows, grid, dim3(256), 0, st, N, hrow, n0, n, chunk, omega, gamma,
+                       part);
+}
+
+void launch_adj_cols(const Nodes &N, int n0, int n, const double *lam, const double *cvec,
+                     double *part, hipStream_t st) {
+    const int chunk = otf_chunk(n);
+    dim3 grid(cdiv(n0, 256), cdiv(n, chunk));
+    hipLaunchKernelGGL(k_adj_cols, grid, dim3(256), 0, st, N, n0, n, chunk, lam, cvec, part);
+}
+
+void launch_adj_finalize(const Nodes &N, const Flow &F, int n0, const double *Ubar,
+                         const double *U, const double *omega, const double *gamma,
+                         const double *lam, const double *prow, int nsr, const double *pcol,
+                         int nsc, double *g_phi, double *g_x, double *g_y, double *g_dx,
+                         double *g_dy, double *g_ddx, double *g_ddy, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_finalize, dim3(cdiv(n0, 256)), dim3(256), 0, st, N, F, n0, Ubar, U,
+                       omega, gamma, lam, prow, nsr, pcol, nsc, g_phi, g_x, g_y, g_dx, g_dy,
+                       g_ddx, g_ddy);
+}
+
+}  // namespace wwbi

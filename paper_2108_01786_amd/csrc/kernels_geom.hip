@@ -1,0 +1,325 @@
+// Node preparation, validation, right-hand side, multi-valued terms, spectral
+// circulants and the final assembly of the normal velocity.
+#include "entries.h"
+#include "internal.h"
+
+namespace wwbi {
+
+namespace {
+
+inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+__device__ __forceinline__ int find_block(const Layout &L, int p) {
+    int k = 0;
+    while (k + 1 < L.nb && p >= L.off[k + 1]) ++k;
+    return k;
+}
+
+// Per-node data derived once per call: boundary index, local index, M_k,
+// weight 1/M_k, s = |zeta'| and the self limit zeta''/(2 zeta').
+__global__ void k_prep_nodes(Layout L, const double *x, const double *y, const double *dx,
+                             const double *dy, const double *ddx, const double *ddy, int *bid,
+                             int *loc, int *Mk, double *w, double *s, double *lre, double *lim,
+                             double *eR, double *eI) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= L.n) return;
+    const int k = find_block(L, p);
+    const int M = L.off[k + 1] - L.off[k];
+    bid[p] = k;
+    loc[p] = p - L.off[k];
+    Mk[p] = M;
+    w[p] = 1.0 / (double)M;
+    const double a = dx[p], b = dy[p], ex = ddx[p], ey = ddy[p];
+    const double d2 = a * a + b * b;
+    s[p] = sqrt(d2);
+    // zeta''/(2 zeta') = (ex + i ey)(a - i b) / (2 |zeta'|^2)
+    lre[p] = (ex * a + ey * b) / (2.0 * d2);
+    lim[p] = (ey * a - ex * b) / (2.0 * d2);
+    // E = e^{i zeta} = e^{-y} (cos x + i sin x)
+    double sx, cx;
+    sincos(x[p], &sx, &cx);
+    const double mag = exp(-y[p]);
+    eR[p] = mag * cx;
+    eI[p] = mag * sx;
+}
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) t += sh[i];
+    return t;
+}
+
+// One block per boundary: count of non-finite samples, signed area
+// (1/2) sum (x y' - y x') 2pi/M (negative = clockwise) and the mean of x'.
+// Block nb checks the potential.
+__global__ void k_validate(Layout L, Nodes N, const double *phi, int nphi, double *out) {
+    __shared__ double sh[16];
+    const int k = blockIdx.x;
+    if (k == L.nb) {
+        double bad = 0.0;
+        for (int i = threadIdx.x; i < nphi; i += blockDim.x)
+            bad += isfinite(phi[i]) ? 0.0 : 1.0;
+        bad = block_sum(bad, sh);
+        if (threadIdx.x == 0) out[3 * L.nb] = bad;
+        return;
+    }
+    const int p0 = L.off[k], p1 = L.off[k + 1];
+    const double M = (double)(p1 - p0);
+    double bad = 0.0, area = 0.0, mdx = 0.0;
+    for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
+        const double v[6] = {N.x[p], N.y[p], N.dx[p], N.dy[p], N.ddx[p], N.ddy[p]};
+        bool fin = true;
+        for (int i = 0; i < 6; ++i) fin = fin && isfinite(v[i]);
+        bad += fin ? 0.0 : 1.0;
+        area += 0.5 * (v[0] * v[3] - v[1] * v[2]) * (2.0 * M_PI / M);
+        mdx += v[2] / M;
+    }
+    bad = block_sum(bad, sh);
+    area = block_sum(area, sh);
+    mdx = block_sum(mdx, sh);
+    if (threadIdx.x == 0) {
+        out[3 * k + 0] = bad;
+        out[3 * k + 1] = area;
+        out[3 * k + 2] = mdx;
+    }
+}
+
+// ln|1 - e^{i w}| with |1 - e^{iw}|^2 = expm1(-v)^2 + 4 e^{-v} sin^2(u/2)
+__device__ __forceinline__ double log_abs_1m_eiw(double u, double v) {
+    const double em = expm1(-v);
+    const double su = sin(0.5 * u);
+    return 0.5 * log(em * em + 4.0 * (em + 1.0) * su * su);
+}
+
+// psi_mv(z) = V1 Im z - sum_j a_j ln|1 - e^{i(z - z_j)}|   (Sec. 3, 3.1)
+__device__ __forceinline__ double psi_mv(const Flow &F, double x, double y) {
+    double v = F.V1 * y;
+    for (int j = 0; j < F.nobs; ++j) v -= F.a[j] * log_abs_1m_eiw(x - F.zx[j], y - F.zy[j]);
+    return v;
+}
+
+// b_0 = phi~ on the surface, b_k = psi_wall - psi_mv(zeta_k) on the walls (Sec. 3.2).
+__global__ void k_rhs_phi(Layout L, Nodes N, Flow F, const double *phi, const double *psi_wall,
+                          double *b) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= L.n) return;
+    if (p < L.off[1]) {
+        b[p] = phi[p];
+        return;
+    }
+    const double g = psi_wall ? psi_wall[p - L.off[1]] : 0.0;
+    b[p] = g - psi_mv(F, N.x[p], N.y[p]);
+}
+
+// s dphi_mv/dn = -(V1 + sum a_j / 2) y' + sum_j a_j Re{(1/2) cot((z - z_j)/2) z'}  (Sec. 3.4)
+__global__ void k_umv(Nodes N, Flow F, int first, int count, double *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int p = first + i;
+    const double dx = N.dx[p], dy = N.dy[p];
+    double asum = 0.0;
+    for (int j = 0; j < F.nobs; ++j) asum += F.a[j];
+    double v = -(F.V1 + 0.5 * asum) * dy;
+    for (int j = 0; j < F.nobs; ++j) {
+        double cr, ci;
+        cot_half64(N.x[p] - F.zx[j], N.y[p] - F.zy[j], cr, ci);
+        v += F.a[j] * 0.5 * (cr * dx - ci * dy);
+    }
+    out[i] = v;
+}
+
+// Circulant rows on each boundary's grid (Sec. 3.4 symbols, Nyquist zeroed):
+//   D: c(n) = (1/2)(-1)^n cot(pi n / M), c(0) = 0
+//   H: c(n) = (2/M) cot(pi n / M) for odd n, 0 for even n
+__global__ void k_circ_rows(Layout L, int op, double *rows) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= L.n) return;
+    const int k = find_block(L, p);
+    const int M = L.off[k + 1] - L.off[k];
+    const int nn = p - L.off[k];
+    double v = 0.0;
+    if (nn != 0) {
+        const double th = (double)nn / (double)M;
+        const double ct = cospi(th) / sinpi(th);
+        if (op == WWBI_OP_D)
+            v = (nn & 1) ? -0.5 * ct : 0.5 * ct;
+        else if (nn & 1)
+            v = 2.0 * ct / (double)M;
+    }
+    rows[p] = v;
+}
+
+__global__ void k_circ_row1(int M, int op, double *row) {
+    const int nn = blockIdx.x * blockDim.x + threadIdx.x;
+    if (nn >= M) return;
+    double v = 0.0;
+    if (nn != 0) {
+        const double th = (double)nn / (double)M;
+        const double ct = cospi(th) / sinpi(th);
+        if (op == kOpHalfCot)
+            v = 0.5 * ct;
+        else if (op == WWBI_OP_D)
+            v = (nn & 1) ? -0.5 * ct : 0.5 * ct;
+        else if (nn & 1)
+            v = 2.0 * ct / (double)M;
+    }
+    row[nn] = v;
+}
+
+// Circulant product on one periodic grid of M points:
+//   out_m = alpha sum_l c((m - l) mod M) f_l + beta out_m.
+// Blocks own 256 outputs; f and the 511 row entries a tile of 256 sources
+// needs are staged in LDS, so every thread reads only LDS in the inner loop.
+__global__ __launch_bounds__(256) void k_circ_tile(int M, const double *__restrict__ row,
+                                                   const double *__restrict__ f, double *out,
+                                                   double alpha, double beta) {
+    __shared__ double fs[256];
+    __shared__ double rs[512];
+    const int m0 = blockIdx.x * 256;
+    const int m = m0 + threadIdx.x;
+    double acc = 0.0;
+    for (int l0 = 0; l0 < M; l0 += 256) {
+        const int l = l0 + threadIdx.x;
+        fs[threadIdx.x] = l < M ? f[l] : 0.0;
+        // row index (m - l) for m in [m0, m0+255], l in [l0, l0+255], stored at
+        // (m - l) - (m0 - l0 - 255) in [0, 510]
+        long base = (long)m0 - l0 - 255;
+        for (int t = threadIdx.x; t < 511; t += 256) {
+            long d = (base + t) % M;
+            if (d < 0) d += M;
+            rs[t] = row[d];
+        }
+        __syncthreads();
+        const int cnt = min(256, M - l0);
+        for (int i = 0; i < cnt; ++i) acc += rs[threadIdx.x - i + 255] * fs[i];
+        __syncthreads();
+    }
+    if (m < M) out[m] = alpha * acc + (beta != 0.0 ? beta * out[m] : 0.0);
+}
+
+// psi|_k = (1/M_k) sum_m omega_(k,m) for k >= 2 (Sec. 3.2); one block per boundary.
+__global__ void k_block_means(Layout L, const double *v, double *out) {
+    __shared__ double sh[16];
+    const int k = blockIdx.x + 2;
+    const int p0 = L.off[k], p1 = L.off[k + 1];
+    double acc = 0.0;
+    for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) acc += v[p];
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = acc / (double)(p1 - p0);
+}
+
+// U_m = (u_mv + (1/2) H gamma_0 + sum over split partials of T gamma) / s_m
+__global__ void k_U_finalize(int n0, const double *s, const double *umv, const double *hg,
+                             const double *part, int nsplit, double *U) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n0) return;
+    double acc = 0.0;
+    for (int k = 0; k < nsplit; ++k) acc += part[(long)k * n0 + m];
+    U[m] = (umv[m] + 0.5 * hg[m] + acc) / s[m];
+}
+
+// wall rhs = -(sum of G_0k^dagger gamma_0 partials) - s dphi_mv/dn
+__global__ void k_wall_rhs_finalize(int nw, const double *umv_w, const double *part, int nsplit,
+                                    double *rhs) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nw) return;
+    double acc = 0.0;
+    for (int k = 0; k < nsplit; ++k) acc += part[(long)k * nw + i];
+    rhs[i] = -acc - umv_w[i];
+}
+
+__global__ void k_surface_base(int n, const double *xt, const double *yt, double *x, double *y) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    x[m] = 2.0 * M_PI * (double)m / (double)n + xt[m];
+    y[m] = yt[m];
+}
+
+__global__ void k_add_scalar(int n, double *v, double c) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < n) v[m] += c;
+}
+
+}  // namespace
+
+void launch_prep_nodes(const Layout &L, const double *x, const double *y, const double *dx,
+                       const double *dy, const double *ddx, const double *ddy, int *bid,
+                       int *loc, int *Mk, double *w, double *s, double *lre, double *lim,
+                       double *ex, double *ey, hipStream_t st) {
+    hipLaunchKernelGGL(k_prep_nodes, dim3(cdiv(L.n, 256)), dim3(256), 0, st, L, x, y, dx, dy, ddx,
+                       ddy, bid, loc, Mk, w, s, lre, lim, ex, ey);
+}
+
+void launch_validate(const Layout &L, const Nodes &N, const double *phi, int nphi, double *out,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_validate, dim3(L.nb + 1), dim3(256), 0, st, L, N, phi, nphi, out);
+}
+
+void launch_rhs_phi(const Layout &L, const Nodes &N, const Flow &F, const double *phi,
+                    const double *psi_wall, double *b, hipStream_t st) {
+    hipLaunchKernelGGL(k_rhs_phi, dim3(cdiv(L.n, 256)), dim3(256), 0, st, L, N, F, phi, psi_wall,
+                       b);
+}
+
+void launch_umv(const Nodes &N, const Flow &F, int first, int count, double *out,
+                hipStream_t st) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_umv, dim3(cdiv(count, 256)), dim3(256), 0, st, N, F, first, count, out);
+}
+
+void launch_circulant_rows(const Layout &L, int op, double *rows, hipStream_t st) {
+    hipLaunchKernelGGL(k_circ_rows, dim3(cdiv(L.n, 256)), dim3(256), 0, st, L, op, rows);
+}
+
+void launch_circulant_apply(const Layout &L, const double *rows, const double *f, double *out,
+                            double alpha, double beta, int first_block, int last_block,
+                            hipStream_t st) {
+    for (int k = first_block; k <= last_block; ++k) {
+        const int o = L.off[k], M = L.off[k + 1] - o;
+        hipLaunchKernelGGL(k_circ_tile, dim3(cdiv(M, 256)), dim3(256), 0, st, M, rows + o, f + o,
+                           out + o, alpha, beta);
+    }
+}
+
+void launch_circ_row1(int M, int op, double *row, hipStream_t st) {
+    hipLaunchKernelGGL(k_circ_row1, dim3(cdiv(M, 256)), dim3(256), 0, st, M, op, row);
+}
+
+void launch_circ_apply1(int M, const double *row, const double *f, double *out, double alpha,
+                        double beta, hipStream_t st) {
+    hipLaunchKernelGGL(k_circ_tile, dim3(cdiv(M, 256)), dim3(256), 0, st, M, row, f, out, alpha,
+                       beta);
+}
+
+void launch_block_means(const Layout &L, const double *v, double *out, hipStream_t st) {
+    if (L.nb <= 2) return;
+    hipLaunchKernelGGL(k_block_means, dim3(L.nb - 2), dim3(256), 0, st, L, v, out);
+}
+
+void launch_U_finalize(int n0, const double *s, const double *umv, const double *hg,
+                       const double *part, int nsplit, double *U, hipStream_t st) {
+    hipLaunchKernelGGL(k_U_finalize, dim3(cdiv(n0, 256)), dim3(256), 0, st, n0, s, umv, hg, part,
+                       nsplit, U);
+}
+
+void launch_wall_rhs_finalize(int nw, const double *umv_w, const double *part, int nsplit,
+                              double *rhs, hipStream_t st) {
+    hipLaunchKernelGGL(k_wall_rhs_finalize, dim3(cdiv(nw, 256)), dim3(256), 0, st, nw, umv_w, part,
+                       nsplit, rhs);
+}
+
+void launch_surface_base(int n, const double *xt, const double *yt, double *x, double *y,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_surface_base, dim3(cdiv(n, 256)), dim3(256), 0, st, n, xt, yt, x, y);
+}
+
+void launch_add_scalar(int n, double *v, double c, hipStream_t st) {
+    hipLaunchKernelGGL(k_add_scalar, dim3(cdiv(n, 256)), dim3(256), 0, st, n, v, c);
+}
+
+}  // namespace wwbi

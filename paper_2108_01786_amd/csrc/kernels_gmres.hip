@@ -1,0 +1,344 @@
+// Device-resident restarted GMRES: Arnoldi with classical Gram-Schmidt applied
+// twice (CGS2), Givens rotations on the Hessenberg column, triangular solve and
+// solution update.  Every reduction has a fixed order (partials per block, then
+// a sequential sum over blocks), so results are bitwise reproducible.
+//
+// G blocks each own one contiguous chunk of the vectors.  Every block reduces
+// the G partials itself (in the same order), which avoids a separate launch
+// per reduction.  Kernels of an iteration return at once when the cycle has
+// ended (gs->active == 0), so the host may enqueue several steps between
+// reads of the flag.
+#include "internal.h"
+
+namespace wwbi {
+
+namespace {
+
+constexpr int kT = 256;       // threads per block
+constexpr int kMaxG = 64;     // max blocks of the vector kernels
+
+inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ void chunk_of(int n, int G, int b, int &c0, int &c1) {
+    const int len = (n + G - 1) / G;
+    c0 = b * len;
+    c1 = min(n, c0 + len);
+}
+
+__device__ __forceinline__ double block_sum(double v, double *sh) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[wv] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int i = 0; i < kT / 64; ++i) t += sh[i];
+    return t;
+}
+
+// P[b] = sum over chunk b of v^2
+__global__ __launch_bounds__(kT) void k_norm_partial(const double *v, int n, double *P, int G) {
+    __shared__ double sh[kT / 64];
+    int c0, c1;
+    chunk_of(n, G, blockIdx.x, c0, c1);
+    double a = 0.0;
+    for (int i = c0 + threadIdx.x; i < c1; i += kT) a += v[i] * v[i];
+    a = block_sum(a, sh);
+    if (threadIdx.x == 0) P[blockIdx.x] = a;
+}
+
+__global__ void k_set_tol(const double *P, int G, double tol, GState *gs) {
+    double v = (int)threadIdx.x < G ? P[threadIdx.x] : 0.0;
+    v = wave_sum(v);
+    if (threadIdx.x == 0) {
+        gs->bnorm = sqrt(v);
+        gs->tol_abs = tol * gs->bnorm;
+    }
+}
+
+// v_0 = r / beta (FP64 and FP32 copies), g = (beta, 0, ...), new cycle state.
+__global__ __launch_bounds__(kT) void k_cycle_start(const double *r, int n, const double *P,
+                                                    int G, double *V, float *v32, double *g,
+                                                    int ldg, GState *gs) {
+    __shared__ double sb;
+    if (threadIdx.x < 64) {
+        double v = (int)threadIdx.x < G ? P[threadIdx.x] : 0.0;
+        v = wave_sum(v);
+        if (threadIdx.x == 0) sb = sqrt(v);
+    }
+    __syncthreads();
+    const double beta = sb;
+    const double sc = beta > 0.0 ? 1.0 / beta : 0.0;
+    int c0, c1;
+    chunk_of(n, G, blockIdx.x, c0, c1);
+    for (int i = c0 + threadIdx.x; i < c1; i += kT) {
+        const double v = r[i] * sc;
+        V[i] = v;
+        if (v32) v32[i] = (float)v;
+    }
+    if (blockIdx.x == 0) {
+        for (int i = threadIdx.x; i < ldg; i += kT) g[i] = (i == 0) ? beta : 0.0;
+        if (threadIdx.x == 0) {
+            gs->beta = beta;
+            gs->resid = beta;
+            gs->jdone = 0;
+            gs->breakdown = 0;
+            gs->active = (beta > gs->tol_abs) ? 1 : 0;
+        }
+    }
+}
+
+// P[i*G + b] = <V_i, w> over chunk b, i = 0..j.  Wave wv handles i = wv, wv+4, ...
+__device__ __forceinline__ void chunk_dots(const double *V, long ldv, const double *w, int c0,
+                                           int c1, int j, double *P, int G) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int i = wv; i <= j; i += kT / 64) {
+        const double *vi = V + (long)i * ldv;
+        double a = 0.0;
+        for (int m = c0 + lane; m < c1; m += 64) a += vi[m] * w[m];
+        a = wave_sum(a);
+        if (lane == 0) P[(long)i * G + blockIdx.x] = a;
+    }
+}
+
+// h_i = sum_b P[i*G + b] for i = 0..j into LDS: one wave per i, lanes over b
+// (G <= 64), four coefficients in flight per wave.
+__device__ __forceinline__ void reduce_coeffs(const double *P, int G, int j, double *h) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int i0 = wv; i0 <= j; i0 += 4 * (kT / 64)) {
+        double v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * (kT / 64);
+            v[u] = (i <= j && lane < G) ? P[(long)i * G + lane] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * (kT / 64);
+            const double t = wave_sum(v[u]);
+            if (lane == 0 && i <= j) h[i] = t;
+        }
+    }
+}
+
+__global__ __launch_bounds__(kT) void k_cgs_dot(const double *V, long ldv, const double *w,
+                                                int n, int j, double *P, int ldp, int G,
+                                                const GState *gs) {
+    if (gs->active == 0) return;
+    (void)ldp;
+    int c0, c1;
+    chunk_of(n, G, blockIdx.x, c0, c1);
+    chunk_dots(V, ldv, w, c0, c1, j, P, G);
+}
+
+// h_i = sum_b Pin[i][b] (every block, same order); w -= sum_i h_i V_i on the
+// block's chunk; then partial dots of the new w (pass 0) or its partial
+// squared norm (pass 1).  Block 0 stores h into (pass 0) or adds it to
+// (pass 1) column j of H.
+__global__ __launch_bounds__(kT) void k_cgs_update(const double *V, long ldv, double *w, int n,
+                                                   int j, const double *Pin, double *Pout,
+                                                   int ldp, int G, double *H, int ldh, int pass,
+                                                   const GState *gs) {
+    if (gs->active == 0) return;
+    (void)ldp;
+    __shared__ double h[WWBI_MAX_RESTART + 1];
+    __shared__ double sh[kT / 64];
+    reduce_coeffs(Pin, G, j, h);
+    __syncthreads();
+    if (blockIdx.x == 0) {
+        for (int i = threadIdx.x; i <= j; i += kT) {
+            if (pass == 0)
+                H[(long)j * ldh + i] = h[i];
+            else
+                H[(long)j * ldh + i] += h[i];
+        }
+    }
+    int c0, c1;
+    chunk_of(n, G, blockIdx.x, c0, c1);
+    for (int m = c0 + threadIdx.x; m < c1; m += kT) {
+        double acc = w[m];
+        for (int i = 0; i <= j; ++i) acc -= h[i] * V[(long)i * ldv + m];
+        w[m] = acc;
+    }
+    __syncthreads();
+    if (pass == 0) {
+        chunk_dots(V, ldv, w, c0, c1, j, Pout, G);
+    } else {
+        double a = 0.0;
+        for (int m = c0 + threadIdx.x; m < c1; m += kT) a += w[m] * w[m];
+        a = block_sum(a, sh);
+        if (threadIdx.x == 0) Pout[blockIdx.x] = a;
+    }
+}
+
+// h_{j+1,j} = ||w||; V_{j+1} = w / ||w||; block 0 applies the previous
+// rotations to column j, forms the new one and updates the residual estimate.
+// The column and the rotations are staged in LDS so that the sequential part
+// touches no global memory.
+__global__ __launch_bounds__(kT) void k_givens_scale(const double *w, int n, int j,
+                                                     const double *P, int G, double *V, long ldv,
+                                                     float *v32, double *H, int ldh, double *cs,
+                                                     double *sn, double *g, int restart_len,
+                                                     GState *gs) {
+    if (gs->active == 0) return;
+    __shared__ double snrm;
+    __shared__ double col[WWBI_MAX_RESTART + 2], lc[WWBI_MAX_RESTART], ls[WWBI_MAX_RESTART];
+    if (threadIdx.x < 64) {
+        double v = (int)threadIdx.x < G ? P[threadIdx.x] : 0.0;
+        v = wave_sum(v);
+        if (threadIdx.x == 0) snrm = sqrt(v);
+    }
+    const bool b0 = blockIdx.x == 0;
+    if (b0) {
+        const double *hc = H + (long)j * ldh;
+        for (int i = threadIdx.x; i <= j; i += kT) col[i] = hc[i];
+        for (int i = threadIdx.x; i < j; i += kT) { lc[i] = cs[i]; ls[i] = sn[i]; }
+    }
+    __syncthreads();
+    const double nrm = snrm;
+    const double sc = nrm > 0.0 ? 1.0 / nrm : 0.0;
+    int c0, c1;
+    chunk_of(n, G, blockIdx.x, c0, c1);
+    double *vn = V + (long)(j + 1) * ldv;
+    for (int m = c0 + threadIdx.x; m < c1; m += kT) {
+        const double v = w[m] * sc;
+        vn[m] = v;
+        if (v32) v32[m] = (float)v;
+    }
+    if (!b0) return;
+    if (threadIdx.x == 0) {
+        col[j + 1] = nrm;
+        for (int i = 0; i < j; ++i) {
+            const double a = col[i], b = col[i + 1];
+            col[i] = lc[i] * a + ls[i] * b;
+            col[i + 1] = -ls[i] * a + lc[i] * b;
+        }
+        const double a = col[j], b = col[j + 1];
+        const double r = hypot(a, b);
+        double c = 1.0, s = 0.0;
+        if (r > 0.0) { c = a / r; s = b / r; }
+        cs[j] = c;
+        sn[j] = s;
+        col[j] = r;
+        col[j + 1] = 0.0;
+        const double gj = g[j];
+        g[j] = c * gj;
+        g[j + 1] = -s * gj;
+        const double res = fabs(g[j + 1]);
+        gs->resid = res;
+        gs->jdone = j + 1;
+        const bool brk = !(nrm > 0.0);           // exact invariant subspace, or NaN
+        gs->breakdown = brk ? 1 : 0;
+        if (res <= gs->tol_abs || brk || j + 1 >= restart_len) gs->active = 0;
+    }
+    __syncthreads();
+    double *hc = H + (long)j * ldh;
+    for (int i = threadIdx.x; i <= j + 1; i += kT) hc[i] = col[i];
+}
+
+// y = R^{-1} g for the k x k upper triangle (k = jdone), column-oriented.
+__global__ __launch_bounds__(kT) void k_hsolve(const double *H, int ldh, const double *g,
+                                               double *y, const GState *gs) {
+    __shared__ double rhs[WWBI_MAX_RESTART + 1];
+    const int k = gs->jdone;
+    for (int i = threadIdx.x; i < k; i += kT) rhs[i] = g[i];
+    __syncthreads();
+    for (int l = k - 1; l >= 0; --l) {
+        const double rl = H[(long)l * ldh + l];
+        const double yl = rl != 0.0 ? rhs[l] / rl : 0.0;
+        __syncthreads();
+        if (threadIdx.x == 0) y[l] = yl;
+        for (int i = threadIdx.x; i < l; i += kT) rhs[i] -= H[(long)l * ldh + i] * yl;
+        __syncthreads();
+    }
+}
+
+// x += sum_{i<k} y_i V_i
+__global__ void k_xupdate(double *x, const double *V, long ldv, int n, const double *y,
+                          const GState *gs) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    const int k = gs->jdone;
+    double acc = x[m];
+    for (int i = 0; i < k; ++i) acc += y[i] * V[(long)i * ldv + m];
+    x[m] = acc;
+}
+
+__global__ void k_axpy(double *x, const double *d, int n, double alpha) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < n) x[m] += alpha * d[m];
+}
+__global__ void k_copy(double *dst, const double *src, int n) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < n) dst[m] = src[m];
+}
+__global__ void k_fill(double *dst, double v, int n) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < n) dst[m] = v;
+}
+__global__ void k_to_f32(const double *src, float *dst, int n) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m < n) dst[m] = (float)src[m];
+}
+
+}  // namespace
+
+int gmres_nblocks(int n) {
+    const int g = cdiv(n, kT);
+    return g > kMaxG ? kMaxG : (g < 1 ? 1 : g);
+}
+
+void launch_norm_partial(const double *v, int n, double *P, int G, hipStream_t st) {
+    hipLaunchKernelGGL(k_norm_partial, dim3(G), dim3(kT), 0, st, v, n, P, G);
+}
+void launch_set_tol(const double *P, int G, double tol, GState *gs, hipStream_t st) {
+    hipLaunchKernelGGL(k_set_tol, dim3(1), dim3(64), 0, st, P, G, tol, gs);
+}
+void launch_cycle_start(const double *r, int n, const double *P, int G, double *V, float *v32,
+                        double *g, int ldg, GState *gs, hipStream_t st) {
+    hipLaunchKernelGGL(k_cycle_start, dim3(G), dim3(kT), 0, st, r, n, P, G, V, v32, g, ldg, gs);
+}
+void launch_cgs_dot(const double *V, long ldv, const double *w, int n, int j, double *P, int ldp,
+                    int G, const GState *gs, hipStream_t st) {
+    hipLaunchKernelGGL(k_cgs_dot, dim3(G), dim3(kT), 0, st, V, ldv, w, n, j, P, ldp, G, gs);
+}
+void launch_cgs_update(const double *V, long ldv, double *w, int n, int j, const double *Pin,
+                       double *Pout, int ldp, int G, double *H, int ldh, int pass,
+                       const GState *gs, hipStream_t st) {
+    hipLaunchKernelGGL(k_cgs_update, dim3(G), dim3(kT), 0, st, V, ldv, w, n, j, Pin, Pout, ldp, G,
+                       H, ldh, pass, gs);
+}
+void launch_givens_scale(const double *w, int n, int j, const double *P, int G, double *V,
+                         long ldv, float *v32, double *H, int ldh, double *cs, double *sn,
+                         double *g, int restart_len, GState *gs, hipStream_t st) {
+    hipLaunchKernelGGL(k_givens_scale, dim3(G), dim3(kT), 0, st, w, n, j, P, G, V, ldv, v32, H,
+                       ldh, cs, sn, g, restart_len, gs);
+}
+void launch_hsolve(const double *H, int ldh, const double *g, double *y, const GState *gs,
+                   hipStream_t st) {
+    hipLaunchKernelGGL(k_hsolve, dim3(1), dim3(kT), 0, st, H, ldh, g, y, gs);
+}
+void launch_xupdate(double *x, const double *V, long ldv, int n, const double *y,
+                    const GState *gs, hipStream_t st) {
+    hipLaunchKernelGGL(k_xupdate, dim3(cdiv(n, 256)), dim3(256), 0, st, x, V, ldv, n, y, gs);
+}
+void launch_axpy(double *x, const double *d, int n, double alpha, hipStream_t st) {
+    hipLaunchKernelGGL(k_axpy, dim3(cdiv(n, 256)), dim3(256), 0, st, x, d, n, alpha);
+}
+void launch_copy(double *dst, const double *src, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_copy, dim3(cdiv(n, 256)), dim3(256), 0, st, dst, src, n);
+}
+void launch_fill(double *dst, double v, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill, dim3(cdiv(n, 256)), dim3(256), 0, st, dst, v, n);
+}
+void launch_to_f32(const double *src, float *dst, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_to_f32, dim3(cdiv(n, 256)), dim3(256), 0, st, src, dst, n);
+}
+
+}  // namespace wwbi

@@ -1,0 +1,133 @@
+"""Adjoint of the velocity-potential solve (hand-written transpose solve and
+kernel-derivative contractions) against torch.autograd.gradcheck, central
+differences of the GPU forward, and the oracle's autograd gradient."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from synth import make_config, tiny_config
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ww():
+    from paper_2108_01786_amd import wwbi
+    return wwbi
+
+
+@pytest.fixture(scope="module")
+def ctx(ww):
+    c = ww.Context(0)
+    yield c
+    c.close()
+
+
+def _surface_inputs(geom, phi):
+    z0 = geom.curves[0].z
+    al = 2 * np.pi * np.arange(geom.M[0]) / geom.M[0]
+    return z0.real - al, z0.imag, np.asarray(phi)
+
+
+def _problem(ctx, geom, **opts):
+    from paper_2108_01786_amd.autograd import SurfaceProblem
+    return SurfaceProblem.from_synth(ctx, geom, DEV, **opts)
+
+
+def test_surface_fill_matches_closed_form(ww, ctx):
+    say("case surface_fill tiny")
+    t = tiny_config()
+    geom = t["geom"]
+    xt, yt, _ = _surface_inputs(geom, t["phi"])
+    outs = ctx.surface_fill(torch.as_tensor(xt, device=DEV), torch.as_tensor(yt, device=DEV))
+    c = geom.curves[0]
+    ref = [c.z.real, c.z.imag, c.d.real, c.d.imag, c.e.real, c.e.imag]
+    for o, r in zip(outs, ref):
+        assert np.abs(o.cpu().numpy() - r).max() < 1e-12
+
+
+def test_gradcheck_tiny(ww, ctx):
+    """torch.autograd.gradcheck of U(xt, yt, phi) on a 32/32/16 cell."""
+    say("case gradcheck tiny fp64")
+    from paper_2108_01786_amd.autograd import normal_velocity
+    t = tiny_config()
+    geom = t["geom"]
+    prob = _problem(ctx, geom, tol=1e-14, restart=80)
+    xt, yt, ph = [torch.as_tensor(v, device=DEV).requires_grad_(True)
+                  for v in _surface_inputs(geom, t["phi"])]
+    assert torch.autograd.gradcheck(lambda a, b, c: normal_velocity(a, b, c, prob), (xt, yt, ph),
+                                    eps=1e-6, atol=1e-6, rtol=1e-5)
+
+
+def _gpu_J_grad(ctx, geom, phi, w, **opts):
+    from paper_2108_01786_amd.autograd import normal_velocity
+    prob = _problem(ctx, geom, **opts)
+    xt, yt, ph = [torch.as_tensor(v, device=DEV).requires_grad_(True)
+                  for v in _surface_inputs(geom, phi)]
+    wt = torch.as_tensor(w, device=DEV)
+    U = normal_velocity(xt, yt, ph, prob)
+    J = (wt * U * U).sum()
+    J.backward()
+    return float(J), xt.grad.cpu().numpy(), yt.grad.cpu().numpy(), ph.grad.cpu().numpy(), prob
+
+
+@pytest.mark.parametrize("which", ["c1", "tiny"])
+def test_gradient_matches_oracle_autograd(ww, ctx, which):
+    say(f"case grad vs oracle {which}")
+    cfg = make_config(1) if which == "c1" else tiny_config()
+    geom, phi = cfg["geom"], cfg["phi"]
+    w = np.random.default_rng(4).uniform(0, 1, geom.M[0])
+    J, gx, gy, gp, _ = _gpu_J_grad(ctx, geom, phi, w, tol=1e-14)
+    og = O.OGeom.from_synth(geom)
+    xt, yt, ph = _surface_inputs(geom, phi)
+    Jr, rx, ry, rp, _ = O.J_and_grad(og, xt, yt, ph, w)
+    assert abs(J - Jr) <= 1e-11 * abs(Jr)
+    for a, b in ((gx, rx.numpy()), (gy, ry.numpy()), (gp, rp.numpy())):
+        assert np.abs(a - b).max() <= 1e-9 * np.abs(b).max(), np.abs(a - b).max() / np.abs(b).max()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_adjoint_config4_directions(ww, ctx, prec):
+    """Config 4: J = sum w U^2 on the M = 4608 cell; the gradient along 32 seeded
+    smooth directions against central differences of the GPU forward (h = 1e-6)."""
+    say(f"case adjoint config4 {prec}")
+    from paper_2108_01786_amd.autograd import normal_velocity
+    cfg = make_config(4)
+    geom, phi, w = cfg["geom"], cfg["phi"], cfg["weights"]
+    opts = dict(tol=1e-13, precision=ww.FP64 if prec == "fp64" else ww.FP32_REFINED)
+    J, gx, gy, gp, prob = _gpu_J_grad(ctx, geom, phi, w, **opts)
+    xt, yt, ph = _surface_inputs(geom, phi)
+    wt = torch.as_tensor(w, device=DEV)
+    h = cfg["fd_h"]
+
+    def Jat(dx, dy, dp):
+        U = normal_velocity(torch.as_tensor(xt + dx, device=DEV), torch.as_tensor(yt + dy, device=DEV),
+                            torch.as_tensor(ph + dp, device=DEV), prob)
+        return float((wt * U * U).sum())
+
+    worst = 0.0
+    ndir = 32 if prec == "fp64" else 8
+    for k in range(ndir):
+        d = cfg["directions"][k]
+        fd = (Jat(h * d[0], h * d[1], h * d[2]) - Jat(-h * d[0], -h * d[1], -h * d[2])) / (2 * h)
+        an = float(gx @ d[0] + gy @ d[1] + gp @ d[2])
+        worst = max(worst, abs(fd - an) / max(abs(fd), 1e-3 * abs(J)))
+    say(f"  worst FD mismatch {worst:.2e}")
+    assert worst <= 2e-6
+
+
+def test_adjoint_refined_equals_fp64(ww, ctx):
+    say("case adjoint refined vs fp64 c1")
+    cfg = make_config(1)
+    geom, phi = cfg["geom"], cfg["phi"]
+    w = np.random.default_rng(9).uniform(0, 1, geom.M[0])
+    a = _gpu_J_grad(ctx, geom, phi, w, tol=1e-13)
+    b = _gpu_J_grad(ctx, geom, phi, w, tol=1e-13, precision=ww.FP32_REFINED)
+    for u, v in zip(a[1:4], b[1:4]):
+        assert np.abs(u - v).max() <= 1e-9 * np.abs(u).max()
