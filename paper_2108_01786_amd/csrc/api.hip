@@ -102,6 +102,11 @@ void Ctx::release() {
     for (auto &e : ev) if (e) hipEventDestroy(e);
     for (auto &e : prof) if (e) hipEventDestroy(e);
     for (auto &e : pollev) if (e) hipEventDestroy(e);
+    {
+        MultiWS &m = mw;
+        F(m.V); F(m.v32); F(m.x32); F(m.w); F(m.r); F(m.x); F(m.b); F(m.d); F(m.rr); F(m.P); F(m.H);
+        F(m.cs); F(m.sn); F(m.g); F(m.y); F(m.part); F(m.nrm); F(m.gs);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -223,7 +228,11 @@ int Ctx::read_state(GState &out) {
 }
 
 void Ctx::prof_begin() {
-    if (profiling && nprof < kProfPairs) hipEventRecord(prof[2 * nprof], stream);
+    if (profiling && nprof < kProfPairs) {
+        hipEventRecord(prof[2 * nprof], stream);
+        prof_cycle[nprof] = cur_cycle;
+        prof_step[nprof] = cur_step;
+    }
 }
 void Ctx::prof_end() {
     if (profiling && nprof < kProfPairs) {
@@ -234,9 +243,10 @@ void Ctx::prof_end() {
 
 // Restarted GMRES on op: x <- solution of op x = b.  x must hold the initial
 // guess unless x_zero.  With verify, every cycle starts from the true residual
-// b - op x and convergence is declared only on it; without verify a single
-// cycle runs and its residual estimate is returned (inner solves of the
-// iterative refinement, whose outer loop checks the FP64 residual itself).
+// b - op x and convergence is declared only on it.  Without verify a single
+// cycle runs and the call returns as soon as the update of x is enqueued; the
+// final cycle state is copied asynchronously to host slot 2, which the caller
+// reads after its next synchronisation (inner solves of the refinement).
 //
 // The host enqueues `poll` Arnoldi steps at a time.  After each batch it
 // queues an asynchronous copy of the cycle flag, enqueues the next batch and
@@ -257,33 +267,47 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
     bool first = true;
     double prev_beta = HUGE_VAL;
     int status = WWBI_NOT_CONVERGED;
+    const int its0 = st.iters;
+    int its_seen = 0;          // device step count at the previous cycle start
     GState h{};
     GState *slot = reinterpret_cast<GState *>((char *)hst + kStateSlotOffset);
     for (;;) {
+        cur_cycle = -1;        // the residual product is not an Arnoldi step
         if (first && x_zero)
             launch_copy(r, b, n, stream);
         else
             apply(op, x, nullptr, b, r, nullptr);
         launch_norm_partial(r, n, P3, G, stream);
         launch_cycle_start(r, n, P3, G, V, x32, gv, restart + 1, gs, stream);
-        int rc = read_state(h);
-        if (rc) return rc;
-        st.rel_resid = h.bnorm > 0 ? h.beta / h.bnorm : 0.0;
-        if (trace)
-            std::fprintf(stderr, "wwbi: op %d n %d cycle %d its %d beta/bnorm %.3e\n", op.kind, n,
-                         st.cycles, st.iters, st.rel_resid);
-        if (!h.active) { status = WWBI_OK; break; }
-        if (!std::isfinite(h.beta)) { status = WWBI_STAGNATED; break; }
-        if (st.iters >= max_iter) { status = WWBI_NOT_CONVERGED; break; }
-        if (!first && h.beta > 0.99 * prev_beta) { status = WWBI_STAGNATED; break; }
-        prev_beta = h.beta;
-        const int jmax = std::min(restart, max_iter - st.iters);
+        int jmax = std::min(restart, max_iter - st.iters);
+        if (verify) {
+            int rc = read_state(h);
+            if (rc) return rc;
+            if (!cyc_done.empty() && cyc_done.back() < 0) cyc_done.back() = h.its - its_seen;
+            its_seen = h.its;
+            st.iters = its0 + h.its;
+            st.rel_resid = h.bnorm > 0 ? h.beta / h.bnorm : 0.0;
+            if (trace)
+                std::fprintf(stderr, "wwbi: op %d n %d cycle %d its %d beta/bnorm %.3e\n",
+                             op.kind, n, st.cycles, st.iters, st.rel_resid);
+            if (!h.active) { status = WWBI_OK; break; }
+            if (!std::isfinite(h.beta)) { status = WWBI_STAGNATED; break; }
+            if (st.iters >= max_iter) { status = WWBI_NOT_CONVERGED; break; }
+            if (!first && h.beta > 0.99 * prev_beta) { status = WWBI_STAGNATED; break; }
+            prev_beta = h.beta;
+            jmax = std::min(restart, max_iter - st.iters);
+        }
+        jmax = std::max(jmax, 1);
+        cyc_done.push_back(-1);
+        cur_cycle = (int)cyc_done.size() - 1;
+        last_cycle = cur_cycle;
         int pending = -1;          // slot of the flag copy not yet waited for
         bool ended = false;
         for (int j0 = 0; j0 < jmax && !ended; j0 += poll) {
             const int j1 = std::min(jmax, j0 + poll);
             for (int j = j0; j < j1; ++j) {
                 const double *vj = V + (long)j * ldv;
+                cur_step = j;
                 prof_begin();
                 apply(op, vj, x32, nullptr, w, &gs->active);
                 prof_end();
@@ -304,21 +328,28 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
             }
             pending = cur;
         }
-        if (hipEventSynchronize(pollev[pending]) != hipSuccess) return WWBI_EHIP;
         launch_hsolve(H, restart + 1, gv, yv, gs, stream);
         launch_xupdate(x, V, ldv, n, yv, gs, stream);
-        rc = read_state(h);
-        if (rc) return rc;
-        st.iters += h.jdone;
         st.cycles += 1;
         first = false;
         if (!verify) {
-            st.rel_resid = h.bnorm > 0 ? h.resid / h.bnorm : 0.0;
-            status = h.resid <= h.tol_abs ? WWBI_OK : WWBI_NOT_CONVERGED;
+            if (hipMemcpyAsync(slot + 2, gs, sizeof(GState), hipMemcpyDeviceToHost, stream) !=
+                hipSuccess)
+                return WWBI_EHIP;
+            status = WWBI_OK;
             break;
         }
     }
     return status;
+}
+
+// Tolerance of an inner FP32 solve: o.inner_tol (the contraction the FP32
+// operator supports), loosened when the residual is already close to the
+// target -- a correction only needs to gain the remaining factor (with a 3x
+// margin), which keeps the last refinement step short.
+double inner_tolerance(const wwbi_opts &o, double bnorm, double rnorm) {
+    const double need = rnorm > 0 ? 0.3 * o.tol * bnorm / rnorm : 1.0;
+    return std::min(0.1, std::max(o.inner_tol, need));
 }
 
 double Ctx::device_norm(const double *v, int n) {
@@ -336,16 +367,22 @@ double Ctx::device_norm(const double *v, int n) {
 
 // FP64 iterative refinement around an FP32 inner solve:
 //   r = b - A64 x (FP64 operator); stop at ||r|| <= tol ||b||;
-//   solve A32 d = r by GMRES to inner_tol; x += d.
+//   solve A32 d = r by GMRES to the inner tolerance; x += d.
+// One host synchronisation per step: the norm of the new residual and the
+// final state of the inner solve are read together.
 int Ctx::refine(const Op &op32, const Op &op64, const double *b, double *x, bool x_zero,
                 const wwbi_opts &o, SolveStats &st) {
     const int n = op64.n;
+    const int G = gmres_nblocks(n);
     double *r = vec[VRR], *d = vec[VD];
-    if (x_zero) launch_fill(x, 0.0, n, stream);   // the inner GMRES zeroes d itself
+    double *Pn = P + 2 * 64 * (restart_cap + 1) + 64;   // norm partials (64 doubles)
+    const GState *slot2 = reinterpret_cast<const GState *>((char *)hst + kStateSlotOffset) + 2;
+    if (x_zero) launch_fill(x, 0.0, n, stream);
     const double bn = device_norm(b, n);
     if (!std::isfinite(bn)) return WWBI_EHIP;
     double prev = HUGE_VAL;
     int status = WWBI_NOT_CONVERGED;
+    bool inner_pending = false;
     for (int k = 0;; ++k) {
         double rn;
         if (k == 0 && x_zero) {
@@ -353,19 +390,36 @@ int Ctx::refine(const Op &op32, const Op &op64, const double *b, double *x, bool
             rn = bn;
         } else {
             apply(op64, x, nullptr, b, r, nullptr);
-            rn = device_norm(r, n);
+            launch_norm_partial(r, n, Pn, G, stream);
+            if (hipMemcpyAsync(hst, Pn, sizeof(double) * G, hipMemcpyDeviceToHost, stream) !=
+                hipSuccess)
+                return WWBI_EHIP;
+            if (hipStreamSynchronize(stream) != hipSuccess) return WWBI_EHIP;
+            const double *h = (const double *)hst;
+            double s2 = 0.0;
+            for (int i = 0; i < G; ++i) s2 += h[i];
+            rn = std::sqrt(s2);
+            if (inner_pending) {
+                st.iters += slot2->its;
+                if (last_cycle >= 0 && last_cycle < (int)cyc_done.size())
+                    cyc_done[last_cycle] = slot2->its;
+                inner_pending = false;
+            }
         }
         st.rel_resid = bn > 0 ? rn / bn : 0.0;
+        if (trace)
+            std::fprintf(stderr, "wwbi: refine step %d its %d rel_resid %.3e\n", k, st.iters,
+                         st.rel_resid);
         if (rn <= o.tol * bn) { status = WWBI_OK; break; }
         if (!std::isfinite(rn) || (k > 0 && rn > 0.5 * prev)) { status = WWBI_REFINE_STALLED; break; }
         if (k >= o.max_refine || st.iters >= o.max_iter) { status = WWBI_NOT_CONVERGED; break; }
         prev = rn;
         SolveStats in{};
-        in.iters = st.iters;
-        const int rc = gmres(op32, r, d, true, o.inner_tol, o.restart, o.max_iter, o.poll_every,
-                             op32.kind == OP_A_S32, false, in);
+        const double itol = inner_tolerance(o, bn, rn);
+        const int rc = gmres(op32, r, d, true, itol, o.restart, o.max_iter - st.iters,
+                             o.poll_every, op32.kind == OP_A_S32, false, in);
         if (rc < 0) return rc;
-        st.iters = in.iters;
+        inner_pending = true;
         st.cycles += in.cycles;
         st.refine_steps += 1;
         launch_axpy(x, d, n, 1.0, stream);
@@ -405,6 +459,9 @@ int Ctx::check_opts(const wwbi_opts *o) {
 void Ctx::begin_report(bool prof) {
     profiling = prof;
     nprof = 0;
+    cyc_done.clear();
+    cur_cycle = -1;
+    cur_step = 0;
     hipEventRecord(ev[0], stream);
 }
 
@@ -431,11 +488,257 @@ void Ctx::finish_report(wwbi_report *rep, int status, const SolveStats &st, doub
     rep->ms_solve = ev_ms(ev[2], ev[3]);
     rep->ms_U = ev_ms(ev[3], ev[4]);
     rep->ms_total = ev_ms(ev[0], ev[4]);
-    rep->n_matvec = nprof;
     double t = 0.0;
-    for (int i = 0; i < nprof; ++i) t += ev_ms(prof[2 * i], prof[2 * i + 1]);
+    int cnt = 0;
+    for (int i = 0; i < nprof; ++i) {
+        const int c = prof_cycle[i];
+        const bool real = c < 0 || c >= (int)cyc_done.size() || cyc_done[c] < 0 ||
+                          prof_step[i] < cyc_done[c];
+        if (!real) continue;
+        t += ev_ms(prof[2 * i], prof[2 * i + 1]);
+        ++cnt;
+    }
+    rep->n_matvec = cnt;
     rep->ms_matvec = t;
     rep->bytes_matvec = bytes;
+}
+
+// ---------------------------------------------------------------------------
+// several right-hand sides in lockstep
+// ---------------------------------------------------------------------------
+
+int Ctx::ensure_multi(int n, int nr, int restart) {
+    const size_t ldv = (size_t)round_up(n, 64), rr = (size_t)restart;
+    const size_t ldp = rr + 1;
+    int rc = WWBI_OK;
+    MultiWS &m = mw;
+    auto G = [&](double *&p, size_t &c, size_t w) { if (rc == WWBI_OK) rc = grow(p, c, w); };
+    auto Gf = [&](float *&p, size_t &c, size_t w) { if (rc == WWBI_OK) rc = grow(p, c, w); };
+    G(m.V, m.cV, nr * (rr + 1) * ldv);
+    Gf(m.v32, m.cv32, nr * ldv);
+    Gf(m.x32, m.cx32, nr * ldv);
+    G(m.w, m.cw, nr * ldv);
+    G(m.r, m.cr, nr * ldv);
+    G(m.x, m.cx, nr * ldv);
+    G(m.b, m.cb, nr * ldv);
+    G(m.d, m.cd, nr * ldv);
+    G(m.rr, m.crr, nr * ldv);
+    G(m.P, m.cP, nr * 3 * 64 * ldp);
+    G(m.H, m.cH, nr * ldp * ldp);
+    G(m.cs, m.ccs, nr * (rr + 2));
+    G(m.sn, m.csn, nr * (rr + 2));
+    G(m.g, m.cg, nr * (rr + 2));
+    G(m.y, m.cy, nr * (rr + 2));
+    G(m.part, m.cpart, (size_t)multi_part_size(n, nr) + 64);
+    G(m.nrm, m.cnrm, nr * 64 + 64);
+    if (rc == WWBI_OK && (m.cgs < (size_t)nr || !m.gs)) {
+        if (m.gs) hipFree(m.gs);
+        m.gs = nullptr;
+        m.cgs = 0;
+        if (hipMalloc((void **)&m.gs, sizeof(GState) * nr) != hipSuccess) {
+            (void)hipGetLastError();
+            return WWBI_ECAPACITY;
+        }
+        m.cgs = nr;
+    }
+    return rc;
+}
+
+// Y_s = c_s - A X_s (or A X_s) with the stored matrix of the given kind.
+void Ctx::apply_multi(int kind, int n, long ld, const double *X, const float *X32, long xs, int nr,
+                      const double *c, double *Y) {
+    const long ldv = round_up(n, 64);
+    if (kind == OP_A_S64) {
+        launch_mfma_multi64((const double *)A, ld, n, X, xs, nr, c, ldv, Y, ldv, mw.part, stream);
+    } else {
+        if (!X32) {
+            launch_to_f32_batched(X, xs, mw.x32, ldv, n, nr, stream);
+            X32 = mw.x32;
+            xs = ldv;
+        }
+        launch_mfma_multi32((const float *)A, ld, n, X32, xs, nr, c, ldv, Y, ldv, mw.part, stream);
+    }
+}
+
+int Ctx::read_states(GState *out, int nr) {
+    GState *slot = reinterpret_cast<GState *>((char *)hst + kStateSlotOffset);
+    if (hipMemcpyAsync(slot, mw.gs, sizeof(GState) * nr, hipMemcpyDeviceToHost, stream) !=
+        hipSuccess)
+        return WWBI_EHIP;
+    if (hipStreamSynchronize(stream) != hipSuccess) return WWBI_EHIP;
+    std::memcpy(out, slot, sizeof(GState) * nr);
+    return WWBI_OK;
+}
+
+// nr restarted GMRES solves in lockstep sharing every matrix pass (the matrix
+// is read once per Arnoldi step for all systems).  B and X are batched with
+// stride round_up(n, 64); X starts at zero.
+int Ctx::gmres_multi(int kind, int n, long ld, const double *B, double *X, int nr, double tol,
+                     int restart, int max_iter, int poll, bool verify, SolveStats &st) {
+    const int G = gmres_nblocks(n);
+    const int ldp = restart + 1;
+    const long ldv = round_up(n, 64);
+    MultiWS &m = mw;
+    const Bat bt{nr, (long)(restart + 1) * ldv, ldv, ldv, 3L * 64 * ldp, (long)ldp * ldp,
+                 (long)restart + 2};
+    double *P1 = m.P, *P2 = m.P + 64 * ldp, *P3 = m.P + 2 * 64 * ldp;
+    float *x32 = kind == OP_A_S32 ? m.v32 : nullptr;
+    launch_fill(X, 0.0, (int)(nr * ldv), stream);
+    launch_norm_partial(B, n, P3, G, stream, bt);
+    launch_set_tol(P3, G, tol, m.gs, stream, bt);
+    std::vector<GState> h(nr);
+    bool first = true;
+    double prev = HUGE_VAL;
+    int status = WWBI_NOT_CONVERGED;
+    GState *slot = reinterpret_cast<GState *>((char *)hst + kStateSlotOffset);
+    for (;;) {
+        if (first)
+            launch_copy(m.r, B, (int)(nr * ldv), stream);
+        else
+            apply_multi(kind, n, ld, X, nullptr, ldv, nr, B, m.r);
+        launch_norm_partial(m.r, n, P3, G, stream, bt);
+        launch_cycle_start(m.r, n, P3, G, m.V, x32, m.g, restart + 1, m.gs, stream, bt);
+        int rc = read_states(h.data(), nr);
+        if (rc) return rc;
+        bool any = false;
+        double worst = 0.0, bsum = 0.0;
+        for (int s = 0; s < nr; ++s) {
+            any = any || h[s].active;
+            worst = std::max(worst, h[s].bnorm > 0 ? h[s].beta / h[s].bnorm : 0.0);
+            bsum += h[s].beta;
+        }
+        st.rel_resid = worst;
+        if (!any) { status = WWBI_OK; break; }
+        if (!std::isfinite(bsum)) { status = WWBI_STAGNATED; break; }
+        if (st.iters >= max_iter) { status = WWBI_NOT_CONVERGED; break; }
+        if (!first && bsum > 0.99 * prev) { status = WWBI_STAGNATED; break; }
+        prev = bsum;
+        const int jmax = std::min(restart, max_iter - st.iters);
+        int pending = -1;
+        bool ended = false;
+        for (int j0 = 0; j0 < jmax && !ended; j0 += poll) {
+            const int j1 = std::min(jmax, j0 + poll);
+            for (int j = j0; j < j1; ++j) {
+                prof_begin();
+                apply_multi(kind, n, ld, m.V + (long)j * ldv, x32, x32 ? ldv : bt.v, nr, nullptr,
+                            m.w);
+                prof_end();
+                launch_cgs_dot(m.V, ldv, m.w, n, j, P1, ldp, G, m.gs, stream, bt);
+                launch_cgs_update(m.V, ldv, m.w, n, j, P1, P2, ldp, G, m.H, ldp, 0, m.gs, stream,
+                                  bt);
+                launch_cgs_update(m.V, ldv, m.w, n, j, P2, P3, ldp, G, m.H, ldp, 1, m.gs, stream,
+                                  bt);
+                launch_givens_scale(m.w, n, j, P3, G, m.V, ldv, x32, m.H, ldp, m.cs, m.sn, m.g,
+                                    jmax, m.gs, stream, bt);
+            }
+            const int cur = (j0 / poll) & 1;
+            GState *dst = reinterpret_cast<GState *>((char *)slot + cur * kStateSlotBytes);
+            if (hipMemcpyAsync(dst, m.gs, sizeof(GState) * nr, hipMemcpyDeviceToHost, stream) !=
+                hipSuccess)
+                return WWBI_EHIP;
+            if (hipEventRecord(pollev[cur], stream) != hipSuccess) return WWBI_EHIP;
+            if (pending >= 0) {
+                if (hipEventSynchronize(pollev[pending]) != hipSuccess) return WWBI_EHIP;
+                const GState *ps =
+                    reinterpret_cast<const GState *>((char *)slot + pending * kStateSlotBytes);
+                bool act = false;
+                for (int s = 0; s < nr; ++s) act = act || ps[s].active;
+                if (!act) ended = true;
+            }
+            pending = cur;
+        }
+        if (hipEventSynchronize(pollev[pending]) != hipSuccess) return WWBI_EHIP;
+        launch_hsolve(m.H, ldp, m.g, m.y, m.gs, stream, bt);
+        launch_xupdate(X, m.V, ldv, n, m.y, m.gs, stream, bt);
+        rc = read_states(h.data(), nr);
+        if (rc) return rc;
+        int jd = 0;
+        bool all_ok = true;
+        worst = 0.0;
+        for (int s = 0; s < nr; ++s) {
+            jd = std::max(jd, h[s].jdone);
+            all_ok = all_ok && h[s].resid <= h[s].tol_abs;
+            worst = std::max(worst, h[s].bnorm > 0 ? h[s].resid / h[s].bnorm : 0.0);
+        }
+        st.iters += jd;
+        st.cycles += 1;
+        first = false;
+        if (!verify) {
+            st.rel_resid = worst;
+            status = all_ok ? WWBI_OK : WWBI_NOT_CONVERGED;
+            break;
+        }
+    }
+    return status;
+}
+
+// FP64 refinement of nr systems around batched FP32 inner solves; the FP64
+// residual of each system is formed on the fly.
+int Ctx::refine_multi(int n, long ld, const double *B, double *X, int nr, const wwbi_opts &o,
+                      SolveStats &st) {
+    const long ldv = round_up(n, 64);
+    const int G = gmres_nblocks(n);
+    MultiWS &m = mw;
+    const Bat bn{nr, 0, 0, ldv, 64, 0, 0};
+    launch_fill(X, 0.0, (int)(nr * ldv), stream);
+    auto norms = [&](const double *v, std::vector<double> &out) -> int {
+        launch_norm_partial(v, n, m.nrm, G, stream, bn);
+        double *h = (double *)hst;
+        if (hipMemcpyAsync(h, m.nrm, sizeof(double) * 64 * nr, hipMemcpyDeviceToHost, stream) !=
+            hipSuccess)
+            return WWBI_EHIP;
+        if (hipStreamSynchronize(stream) != hipSuccess) return WWBI_EHIP;
+        out.assign(nr, 0.0);
+        for (int s = 0; s < nr; ++s) {
+            double a = 0.0;
+            for (int b = 0; b < G; ++b) a += h[s * 64 + b];
+            out[s] = std::sqrt(a);
+        }
+        return WWBI_OK;
+    };
+    std::vector<double> bnrm, rn, prev(nr, HUGE_VAL);
+    int rc = norms(B, bnrm);
+    if (rc) return rc;
+    int status = WWBI_NOT_CONVERGED;
+    for (int k = 0;; ++k) {
+        if (k == 0) {
+            launch_copy(m.rr, B, (int)(nr * ldv), stream);
+            rn = bnrm;
+        } else {
+            for (int s = 0; s < nr; ++s)
+                launch_otf_matvec(L, N, o.flags, 0, o.band, 0, X + s * ldv, B + s * ldv,
+                                  m.rr + s * ldv, part, nullptr, stream);
+            rc = norms(m.rr, rn);
+            if (rc) return rc;
+        }
+        double worst = 0.0;
+        bool done = true, stalled = false;
+        for (int s = 0; s < nr; ++s) {
+            const double rel = bnrm[s] > 0 ? rn[s] / bnrm[s] : 0.0;
+            worst = std::max(worst, rel);
+            done = done && rel <= o.tol;
+            stalled = stalled || !std::isfinite(rn[s]) || (k > 0 && rel > o.tol && rn[s] > 0.5 * prev[s]);
+        }
+        st.rel_resid = worst;
+        if (done) { status = WWBI_OK; break; }
+        if (stalled) { status = WWBI_REFINE_STALLED; break; }
+        if (k >= o.max_refine || st.iters >= o.max_iter) { status = WWBI_NOT_CONVERGED; break; }
+        prev = rn;
+        SolveStats in{};
+        in.iters = st.iters;
+        double itol = 0.0;
+        for (int s = 0; s < nr; ++s)
+            if (bnrm[s] > 0 && rn[s] > o.tol * bnrm[s])
+                itol = std::max(itol, inner_tolerance(o, bnrm[s], rn[s]));
+        rc = gmres_multi(OP_A_S32, n, ld, m.rr, m.d, nr, itol > 0 ? itol : o.inner_tol, o.restart,
+                         o.max_iter, o.poll_every, false, in);
+        if (rc < 0) return rc;
+        st.iters = in.iters;
+        st.cycles += in.cycles;
+        st.refine_steps += 1;
+        launch_axpy(X, m.d, (int)(nr * ldv), 1.0, stream);
+    }
+    return status;
 }
 
 }  // namespace wwbi
@@ -489,7 +792,7 @@ int wwbi_create(wwbi_ctx **out, int32_t device, void *stream) {
     c->stream = (hipStream_t)stream;
     int rc = WWBI_OK;
     if (hipMalloc((void **)&c->gs, sizeof(GState)) != hipSuccess) rc = WWBI_ECAPACITY;
-    if (!rc && hipHostMalloc(&c->hst, 4096) != hipSuccess) rc = WWBI_ECAPACITY;
+    if (!rc && hipHostMalloc(&c->hst, kHostStaging) != hipSuccess) rc = WWBI_ECAPACITY;
     for (auto &e : c->ev)
         if (!rc && hipEventCreate(&e) != hipSuccess) rc = WWBI_EHIP;
     for (auto &e : c->prof)
@@ -735,6 +1038,53 @@ int wwbi_adjoint_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, con
     launch_adj_finalize(c->N, c->F, n0, dJdU, U, omega, gam, lam, prow, ns, pcol, ns, g_phi, g_x,
                         g_y, g_dx, g_dy, g_ddx, g_ddy, sm);
     hipEventRecord(c->ev[4], sm);
+    c->finish_report(rep, status, st, bytes);
+    if (hipGetLastError() != hipSuccess) return WWBI_EHIP;
+    return status;
+}
+
+int wwbi_solve_phi_multi(wwbi_ctx *ctx, const wwbi_geom *g, const double *rhs, int32_t nr,
+                         const wwbi_opts *o, double *omega, wwbi_report *rep) {
+    if (!ctx) return WWBI_EINVAL_NULL;
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    SolveStats st{};
+    int rc = Ctx::check_opts(o);
+    if (!rc && (!rhs || !omega)) rc = WWBI_EINVAL_NULL;
+    if (!rc && (nr < 1 || nr > kMaxMulti)) rc = WWBI_EINVAL_OPTS;
+    if (!rc && (o->matvec == WWBI_MATVEC_ON_THE_FLY || o->x0)) rc = WWBI_EINVAL_OPTS;
+    if (!rc) {
+        c->restart_cap = std::max(c->restart_cap, o->restart);
+        c->begin_report((o->flags & WWBI_FLAG_PROFILE) != 0);
+        rc = c->setup(g, nullptr, 0);
+    }
+    if (!rc) rc = c->ensure_multi(c->L.n, nr, o->restart);
+    if (rc) {
+        if (rep) { std::memset(rep, 0, sizeof(*rep)); rep->status = rc; }
+        return rc;
+    }
+    hipStream_t sm = c->stream;
+    const int n = c->L.n;
+    const long ld = round_up(n, 64), ldv = ld;
+    const bool fp32 = o->precision == WWBI_FP32_REFINED;
+    launch_copy_strided(rhs, n, c->mw.b, ldv, n, nr, sm);
+    hipEventRecord(c->ev[1], sm);
+    rc = c->ensure_matrix((size_t)n * ld * (fp32 ? 4 : 8));
+    if (rc) { c->finish_report(rep, rc, st, 0); return rc; }
+    if (fp32)
+        launch_assemble32(c->L, c->N, o->flags, o->band, (float *)c->A, ld, sm);
+    else
+        launch_assemble64(c->L, c->N, o->flags, (double *)c->A, ld, sm);
+    hipEventRecord(c->ev[2], sm);
+    int status;
+    if (!fp32)
+        status = c->gmres_multi(OP_A_S64, n, ld, c->mw.b, c->mw.x, nr, o->tol, o->restart,
+                                o->max_iter, o->poll_every, true, st);
+    else
+        status = c->refine_multi(n, ld, c->mw.b, c->mw.x, nr, *o, st);
+    hipEventRecord(c->ev[3], sm);
+    if (status >= 0) launch_copy_strided(c->mw.x, ldv, omega, n, n, nr, sm);
+    hipEventRecord(c->ev[4], sm);
+    const double bytes = (double)n * n * (fp32 ? 4.0 : 8.0);
     c->finish_report(rep, status, st, bytes);
     if (hipGetLastError() != hipSuccess) return WWBI_EHIP;
     return status;

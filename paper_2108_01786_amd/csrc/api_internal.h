@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <vector>
 
 #include "internal.h"
 
@@ -44,7 +45,28 @@ struct SolveStats {
 enum VecId { VR = 0, VW, VB, VX, VRR, VD, VG, VHG, VUM, VTMP, VTMP2, VLAM, VMU, VC, kNumVec };
 
 constexpr int kProfPairs = 2048;
-constexpr int kStateSlotOffset = 2048;   // byte offset of the two polled GState copies in hst
+constexpr int kStateSlotOffset = 8192;   // byte offset of the two polled GState slots in hst
+constexpr int kStateSlotBytes = 8192;    // bytes per slot (up to kMaxMulti states)
+constexpr int kHostStaging = 32768;      // pinned host staging bytes
+constexpr int kMaxMulti = 32;            // right-hand sides per multi solve
+
+double inner_tolerance(const wwbi_opts &o, double bnorm, double rnorm);
+
+// Batched Krylov workspace of a multi right-hand-side solve.
+struct MultiWS {
+    double *V = nullptr; size_t cV = 0;
+    float *v32 = nullptr; size_t cv32 = 0;
+    float *x32 = nullptr; size_t cx32 = 0;
+    double *w = nullptr, *r = nullptr, *x = nullptr, *b = nullptr, *d = nullptr, *rr = nullptr;
+    size_t cw = 0, cr = 0, cx = 0, cb = 0, cd = 0, crr = 0;
+    double *P = nullptr; size_t cP = 0;
+    double *H = nullptr; size_t cH = 0;
+    double *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;
+    size_t ccs = 0, csn = 0, cg = 0, cy = 0;
+    double *part = nullptr; size_t cpart = 0;
+    double *nrm = nullptr; size_t cnrm = 0;
+    GState *gs = nullptr; size_t cgs = 0;
+};
 
 struct Ctx {
     int device = 0;
@@ -81,6 +103,7 @@ struct Ctx {
     double *eI = nullptr;   size_t capeI = 0;
     double *val = nullptr;  size_t capval = 0;
     double *apart = nullptr; size_t capapart = 0;   // adjoint partial sums
+    MultiWS mw;
     GState *gs = nullptr;
     void *hst = nullptr;    // pinned host staging (4 KiB)
 
@@ -88,6 +111,14 @@ struct Ctx {
     hipEvent_t pollev[2] = {};
     hipEvent_t prof[2 * kProfPairs] = {};
     bool profiling = false;
+    // launch -> (cycle, step) of every profiled matvec; steps at or beyond a
+    // cycle's completed count were no-ops (enqueued ahead of the flag poll)
+    int prof_cycle[kProfPairs] = {};
+    int prof_step[kProfPairs] = {};
+    std::vector<int> cyc_done;   // completed steps per cycle, -1 while unknown
+    int cur_cycle = -1;
+    int cur_step = 0;
+    int last_cycle = -1;
     bool trace = false;     // WWBI_TRACE set: one stderr line per GMRES cycle
     int nprof = 0;
 
@@ -106,6 +137,14 @@ struct Ctx {
     double device_norm(const double *v, int n);
     int refine(const Op &op32, const Op &op64, const double *b, double *x, bool x_zero,
                const wwbi_opts &o, SolveStats &st);
+    int ensure_multi(int n, int nr, int restart);
+    void apply_multi(int kind, int n, long ld, const double *X, const float *X32, long xs, int nr,
+                     const double *c, double *Y);
+    int read_states(GState *out, int nr);
+    int gmres_multi(int kind, int n, long ld, const double *B, double *X, int nr, double tol,
+                    int restart, int max_iter, int poll, bool verify, SolveStats &st);
+    int refine_multi(int n, long ld, const double *B, double *X, int nr, const wwbi_opts &o,
+                     SolveStats &st);
     void eval_U_from_gamma(const double *gamma, double *U);
     void gamma_from_omega(const double *omega, double *gamma);
     static int check_opts(const wwbi_opts *o);

@@ -61,6 +61,16 @@ __device__ __forceinline__ void cot_half64(double u, double v, double &cr, doubl
     ci = -sh * ch * r;
 }
 
+// 1/x from the hardware reciprocal estimate refined by two Newton steps
+// (each step doubles the correct bits; the result is within an ulp of 1/x).
+__device__ __forceinline__ double recip64(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 __device__ __forceinline__ int cyc_dist(int a, int b, int M) {
     int d = a - b;
     if (d < 0) d = -d;
@@ -84,7 +94,7 @@ __device__ __forceinline__ void kappa64(const Nodes &N, const Tgt &t, const Src 
         return;
     }
     const double nr = s.ex + t.ex, ni = s.ey + t.ey;
-    const double inv = 1.0 / den;
+    const double inv = recip64(den);
     // N conj(D) / |D|^2 = p; kappa = i p
     const double pr = (nr * dr + ni * di) * inv;
     const double pi = (ni * dr - nr * di) * inv;

@@ -45,12 +45,25 @@ struct GState {
     int active;        // 1 while the current restart cycle runs
     int jdone;         // Arnoldi steps completed in the current cycle
     int breakdown;
-    int pad;
+    int its;           // Arnoldi steps since the solve began (all cycles)
     double bnorm;      // ||b||
     double tol_abs;    // tol * ||b||
     double beta;       // residual norm at the start of the cycle
     double resid;      // current residual estimate |g_{j+1}|
 };
+
+// Strides of a batch of Krylov solves run in lockstep (system = blockIdx.y).
+// A single solve uses nsys = 1 and zero strides.
+struct Bat {
+    int nsys;
+    long v;      // Krylov basis V (doubles)
+    long v32;    // FP32 copy of the newest basis vector (floats)
+    long vec;    // length-n vectors: x, r, w, b
+    long p;      // partial sums
+    long h;      // Hessenberg matrix
+    long rot;    // Givens cosines/sines, g and y
+};
+constexpr Bat kSingle{1, 0, 0, 0, 0, 0, 0};
 
 // circulant row (1/2) cot(pi n / M) of the Hilbert regulariser h (n != 0)
 constexpr int kOpHalfCot = 100;
@@ -131,24 +144,41 @@ void launch_adj_finalize(const Nodes &N, const Flow &F, int n0, const double *Ub
                          int nsc, double *g_phi, double *g_x, double *g_y, double *g_dx,
                          double *g_dy, double *g_ddx, double *g_ddy, hipStream_t st);
 
+// ---- kernels_multi.hip -------------------------------------------------------
+// Y_s = c_s - A X_s (or A X_s when c is null) for s < nr on the matrix cores.
+void launch_mfma_multi64(const double *A, long ld, int n, const double *X, long xs, int nr,
+                         const double *c, long cs, double *y, long ys, double *part,
+                         hipStream_t st);
+void launch_mfma_multi32(const float *A, long ld, int n, const float *X, long xs, int nr,
+                         const double *c, long cs, double *y, long ys, double *part,
+                         hipStream_t st);
+void launch_to_f32_batched(const double *src, long ss, float *dst, long ds, int n, int nr,
+                           hipStream_t st);
+void launch_copy_strided(const double *src, long ss, double *dst, long ds, int n, int nr,
+                         hipStream_t st);
+int multi_part_size(int n, int nr);
+
 // ---- kernels_gmres.hip -------------------------------------------------------
 int gmres_nblocks(int n);
-void launch_norm_partial(const double *v, int n, double *P, int G, hipStream_t st);
-void launch_set_tol(const double *P, int G, double tol, GState *gs, hipStream_t st);
+void launch_norm_partial(const double *v, int n, double *P, int G, hipStream_t st,
+                         const Bat &bt = kSingle);
+void launch_set_tol(const double *P, int G, double tol, GState *gs, hipStream_t st,
+                    const Bat &bt = kSingle);
 void launch_cycle_start(const double *r, int n, const double *P, int G, double *V, float *v32,
-                        double *g, int ldg, GState *gs, hipStream_t st);
+                        double *g, int ldg, GState *gs, hipStream_t st, const Bat &bt = kSingle);
 void launch_cgs_dot(const double *V, long ldv, const double *w, int n, int j, double *P, int ldp,
-                    int G, const GState *gs, hipStream_t st);
+                    int G, const GState *gs, hipStream_t st, const Bat &bt = kSingle);
 void launch_cgs_update(const double *V, long ldv, double *w, int n, int j, const double *Pin,
                        double *Pout, int ldp, int G, double *H, int ldh, int pass,
-                       const GState *gs, hipStream_t st);
+                       const GState *gs, hipStream_t st, const Bat &bt = kSingle);
 void launch_givens_scale(const double *w, int n, int j, const double *P, int G, double *V,
                          long ldv, float *v32, double *H, int ldh, double *cs, double *sn,
-                         double *g, int restart_len, GState *gs, hipStream_t st);
+                         double *g, int restart_len, GState *gs, hipStream_t st,
+                         const Bat &bt = kSingle);
 void launch_hsolve(const double *H, int ldh, const double *g, double *y, const GState *gs,
-                   hipStream_t st);
+                   hipStream_t st, const Bat &bt = kSingle);
 void launch_xupdate(double *x, const double *V, long ldv, int n, const double *y,
-                    const GState *gs, hipStream_t st);
+                    const GState *gs, hipStream_t st, const Bat &bt = kSingle);
 void launch_axpy(double *x, const double *d, int n, double alpha, hipStream_t st);
 void launch_copy(double *dst, const double *src, int n, hipStream_t st);
 void launch_fill(double *dst, double v, int n, hipStream_t st);

@@ -173,33 +173,56 @@ __global__ void k_circ_row1(int M, int op, double *row) {
 
 // Circulant product on one periodic grid of M points:
 //   out_m = alpha sum_l c((m - l) mod M) f_l + beta out_m.
-// Blocks own 256 outputs; f and the 511 row entries a tile of 256 sources
-// needs are staged in LDS, so every thread reads only LDS in the inner loop.
-__global__ __launch_bounds__(256) void k_circ_tile(int M, const double *__restrict__ row,
-                                                   const double *__restrict__ f, double *out,
-                                                   double alpha, double beta) {
-    __shared__ double fs[256];
-    __shared__ double rs[512];
-    const int m0 = blockIdx.x * 256;
-    const int m = m0 + threadIdx.x;
+// A block owns 64 outputs; its 16 waves split the sources into interleaved
+// tiles of 64, each wave staging its tile of f and the 127 row entries the
+// tile needs in a private LDS region.  All waves run the same number of
+// rounds (so every barrier is reached), and the 16 partial sums are added in
+// a fixed order at the end.
+constexpr int kCT = 64;
+constexpr int kCW = 16;
+__global__ __launch_bounds__(kCT * kCW) void k_circ_tile(int M, const double *__restrict__ row,
+                                                         const double *__restrict__ f,
+                                                         double *out, double alpha,
+                                                         double beta) {
+    __shared__ double fs[kCW][kCT];
+    __shared__ double rs[kCW][2 * kCT];
+    __shared__ double red[kCW][kCT];
+    const int lane = threadIdx.x % kCT, wv = threadIdx.x / kCT;
+    const int m0 = blockIdx.x * kCT;
+    const int ntiles = (M + kCT - 1) / kCT;
+    const int rounds = (ntiles + kCW - 1) / kCW;
     double acc = 0.0;
-    for (int l0 = 0; l0 < M; l0 += 256) {
-        const int l = l0 + threadIdx.x;
-        fs[threadIdx.x] = l < M ? f[l] : 0.0;
-        // row index (m - l) for m in [m0, m0+255], l in [l0, l0+255], stored at
-        // (m - l) - (m0 - l0 - 255) in [0, 510]
-        long base = (long)m0 - l0 - 255;
-        for (int t = threadIdx.x; t < 511; t += 256) {
-            long d = (base + t) % M;
-            if (d < 0) d += M;
-            rs[t] = row[d];
+    for (int rd = 0; rd < rounds; ++rd) {
+        const int tile = rd * kCW + wv;
+        const int l0 = tile * kCT;
+        const bool live = tile < ntiles;
+        if (live) {
+            const int l = l0 + lane;
+            fs[wv][lane] = l < M ? f[l] : 0.0;
+            // row index (m - l) for m in [m0, m0+63], l in [l0, l0+63], stored
+            // at (m - l) - (m0 - l0 - 63) in [0, 126]
+            const long base = (long)m0 - l0 - (kCT - 1);
+            for (int t = lane; t < 2 * kCT - 1; t += kCT) {
+                long d = (base + t) % M;
+                if (d < 0) d += M;
+                rs[wv][t] = row[d];
+            }
         }
         __syncthreads();
-        const int cnt = min(256, M - l0);
-        for (int i = 0; i < cnt; ++i) acc += rs[threadIdx.x - i + 255] * fs[i];
+        if (live) {
+            const int cnt = min(kCT, M - l0);
+            for (int i = 0; i < cnt; ++i) acc += rs[wv][lane - i + kCT - 1] * fs[wv][i];
+        }
         __syncthreads();
     }
-    if (m < M) out[m] = alpha * acc + (beta != 0.0 ? beta * out[m] : 0.0);
+    red[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0) {
+        double s = 0.0;
+        for (int w = 0; w < kCW; ++w) s += red[w][lane];
+        const int m = m0 + lane;
+        if (m < M) out[m] = alpha * s + (beta != 0.0 ? beta * out[m] : 0.0);
+    }
 }
 
 // psi|_k = (1/M_k) sum_m omega_(k,m) for k >= 2 (Sec. 3.2); one block per boundary.
@@ -281,8 +304,8 @@ void launch_circulant_apply(const Layout &L, const double *rows, const double *f
                             hipStream_t st) {
     for (int k = first_block; k <= last_block; ++k) {
         const int o = L.off[k], M = L.off[k + 1] - o;
-        hipLaunchKernelGGL(k_circ_tile, dim3(cdiv(M, 256)), dim3(256), 0, st, M, rows + o, f + o,
-                           out + o, alpha, beta);
+        hipLaunchKernelGGL(k_circ_tile, dim3(cdiv(M, kCT)), dim3(kCT * kCW), 0, st, M, rows + o,
+                           f + o, out + o, alpha, beta);
     }
 }
 
@@ -292,8 +315,8 @@ void launch_circ_row1(int M, int op, double *row, hipStream_t st) {
 
 void launch_circ_apply1(int M, const double *row, const double *f, double *out, double alpha,
                         double beta, hipStream_t st) {
-    hipLaunchKernelGGL(k_circ_tile, dim3(cdiv(M, 256)), dim3(256), 0, st, M, row, f, out, alpha,
-                       beta);
+    hipLaunchKernelGGL(k_circ_tile, dim3(cdiv(M, kCT)), dim3(kCT * kCW), 0, st, M, row, f, out,
+                       alpha, beta);
 }
 
 void launch_block_means(const Layout &L, const double *v, double *out, hipStream_t st) {

@@ -19,6 +19,9 @@ constexpr int kMaxG = 64;     // max blocks of the vector kernels
 
 inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
+// system index of a batched launch (gridDim.y systems in lockstep)
+__device__ __forceinline__ long sys() { return (long)blockIdx.y; }
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -43,8 +46,11 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
 }
 
 // P[b] = sum over chunk b of v^2
-__global__ __launch_bounds__(kT) void k_norm_partial(const double *v, int n, double *P, int G) {
+__global__ __launch_bounds__(kT) void k_norm_partial(const double *v, int n, double *P, int G,
+                                                     Bat bt) {
     __shared__ double sh[kT / 64];
+    v += sys() * bt.vec;
+    P += sys() * bt.p;
     int c0, c1;
     chunk_of(n, G, blockIdx.x, c0, c1);
     double a = 0.0;
@@ -53,20 +59,29 @@ __global__ __launch_bounds__(kT) void k_norm_partial(const double *v, int n, dou
     if (threadIdx.x == 0) P[blockIdx.x] = a;
 }
 
-__global__ void k_set_tol(const double *P, int G, double tol, GState *gs) {
+__global__ void k_set_tol(const double *P, int G, double tol, GState *gs, Bat bt) {
+    P += sys() * bt.p;
+    gs += sys();
     double v = (int)threadIdx.x < G ? P[threadIdx.x] : 0.0;
     v = wave_sum(v);
     if (threadIdx.x == 0) {
         gs->bnorm = sqrt(v);
         gs->tol_abs = tol * gs->bnorm;
+        gs->its = 0;
     }
 }
 
 // v_0 = r / beta (FP64 and FP32 copies), g = (beta, 0, ...), new cycle state.
 __global__ __launch_bounds__(kT) void k_cycle_start(const double *r, int n, const double *P,
                                                     int G, double *V, float *v32, double *g,
-                                                    int ldg, GState *gs) {
+                                                    int ldg, GState *gs, Bat bt) {
     __shared__ double sb;
+    r += sys() * bt.vec;
+    P += sys() * bt.p;
+    V += sys() * bt.v;
+    if (v32) v32 += sys() * bt.v32;
+    g += sys() * bt.rot;
+    gs += sys();
     if (threadIdx.x < 64) {
         double v = (int)threadIdx.x < G ? P[threadIdx.x] : 0.0;
         v = wave_sum(v);
@@ -129,8 +144,12 @@ __device__ __forceinline__ void reduce_coeffs(const double *P, int G, int j, dou
 
 __global__ __launch_bounds__(kT) void k_cgs_dot(const double *V, long ldv, const double *w,
                                                 int n, int j, double *P, int ldp, int G,
-                                                const GState *gs) {
+                                                const GState *gs, Bat bt) {
+    gs += sys();
     if (gs->active == 0) return;
+    V += sys() * bt.v;
+    w += sys() * bt.vec;
+    P += sys() * bt.p;
     (void)ldp;
     int c0, c1;
     chunk_of(n, G, blockIdx.x, c0, c1);
@@ -144,8 +163,14 @@ __global__ __launch_bounds__(kT) void k_cgs_dot(const double *V, long ldv, const
 __global__ __launch_bounds__(kT) void k_cgs_update(const double *V, long ldv, double *w, int n,
                                                    int j, const double *Pin, double *Pout,
                                                    int ldp, int G, double *H, int ldh, int pass,
-                                                   const GState *gs) {
+                                                   const GState *gs, Bat bt) {
+    gs += sys();
     if (gs->active == 0) return;
+    V += sys() * bt.v;
+    w += sys() * bt.vec;
+    Pin += sys() * bt.p;
+    Pout += sys() * bt.p;
+    H += sys() * bt.h;
     (void)ldp;
     __shared__ double h[WWBI_MAX_RESTART + 1];
     __shared__ double sh[kT / 64];
@@ -185,8 +210,17 @@ __global__ __launch_bounds__(kT) void k_givens_scale(const double *w, int n, int
                                                      const double *P, int G, double *V, long ldv,
                                                      float *v32, double *H, int ldh, double *cs,
                                                      double *sn, double *g, int restart_len,
-                                                     GState *gs) {
+                                                     GState *gs, Bat bt) {
+    gs += sys();
     if (gs->active == 0) return;
+    w += sys() * bt.vec;
+    P += sys() * bt.p;
+    V += sys() * bt.v;
+    if (v32) v32 += sys() * bt.v32;
+    H += sys() * bt.h;
+    cs += sys() * bt.rot;
+    sn += sys() * bt.rot;
+    g += sys() * bt.rot;
     __shared__ double snrm;
     __shared__ double col[WWBI_MAX_RESTART + 2], lc[WWBI_MAX_RESTART], ls[WWBI_MAX_RESTART];
     if (threadIdx.x < 64) {
@@ -233,6 +267,7 @@ __global__ __launch_bounds__(kT) void k_givens_scale(const double *w, int n, int
         const double res = fabs(g[j + 1]);
         gs->resid = res;
         gs->jdone = j + 1;
+        gs->its += 1;
         const bool brk = !(nrm > 0.0);           // exact invariant subspace, or NaN
         gs->breakdown = brk ? 1 : 0;
         if (res <= gs->tol_abs || brk || j + 1 >= restart_len) gs->active = 0;
@@ -244,8 +279,12 @@ __global__ __launch_bounds__(kT) void k_givens_scale(const double *w, int n, int
 
 // y = R^{-1} g for the k x k upper triangle (k = jdone), column-oriented.
 __global__ __launch_bounds__(kT) void k_hsolve(const double *H, int ldh, const double *g,
-                                               double *y, const GState *gs) {
+                                               double *y, const GState *gs, Bat bt) {
     __shared__ double rhs[WWBI_MAX_RESTART + 1];
+    H += sys() * bt.h;
+    g += sys() * bt.rot;
+    y += sys() * bt.rot;
+    gs += sys();
     const int k = gs->jdone;
     for (int i = threadIdx.x; i < k; i += kT) rhs[i] = g[i];
     __syncthreads();
@@ -261,7 +300,11 @@ __global__ __launch_bounds__(kT) void k_hsolve(const double *H, int ldh, const d
 
 // x += sum_{i<k} y_i V_i
 __global__ void k_xupdate(double *x, const double *V, long ldv, int n, const double *y,
-                          const GState *gs) {
+                          const GState *gs, Bat bt) {
+    x += sys() * bt.vec;
+    V += sys() * bt.v;
+    y += sys() * bt.rot;
+    gs += sys();
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= n) return;
     const int k = gs->jdone;
@@ -294,39 +337,44 @@ int gmres_nblocks(int n) {
     return g > kMaxG ? kMaxG : (g < 1 ? 1 : g);
 }
 
-void launch_norm_partial(const double *v, int n, double *P, int G, hipStream_t st) {
-    hipLaunchKernelGGL(k_norm_partial, dim3(G), dim3(kT), 0, st, v, n, P, G);
+void launch_norm_partial(const double *v, int n, double *P, int G, hipStream_t st,
+                         const Bat &bt) {
+    hipLaunchKernelGGL(k_norm_partial, dim3(G, bt.nsys), dim3(kT), 0, st, v, n, P, G, bt);
 }
-void launch_set_tol(const double *P, int G, double tol, GState *gs, hipStream_t st) {
-    hipLaunchKernelGGL(k_set_tol, dim3(1), dim3(64), 0, st, P, G, tol, gs);
+void launch_set_tol(const double *P, int G, double tol, GState *gs, hipStream_t st,
+                    const Bat &bt) {
+    hipLaunchKernelGGL(k_set_tol, dim3(1, bt.nsys), dim3(64), 0, st, P, G, tol, gs, bt);
 }
 void launch_cycle_start(const double *r, int n, const double *P, int G, double *V, float *v32,
-                        double *g, int ldg, GState *gs, hipStream_t st) {
-    hipLaunchKernelGGL(k_cycle_start, dim3(G), dim3(kT), 0, st, r, n, P, G, V, v32, g, ldg, gs);
+                        double *g, int ldg, GState *gs, hipStream_t st, const Bat &bt) {
+    hipLaunchKernelGGL(k_cycle_start, dim3(G, bt.nsys), dim3(kT), 0, st, r, n, P, G, V, v32, g,
+                       ldg, gs, bt);
 }
 void launch_cgs_dot(const double *V, long ldv, const double *w, int n, int j, double *P, int ldp,
-                    int G, const GState *gs, hipStream_t st) {
-    hipLaunchKernelGGL(k_cgs_dot, dim3(G), dim3(kT), 0, st, V, ldv, w, n, j, P, ldp, G, gs);
+                    int G, const GState *gs, hipStream_t st, const Bat &bt) {
+    hipLaunchKernelGGL(k_cgs_dot, dim3(G, bt.nsys), dim3(kT), 0, st, V, ldv, w, n, j, P, ldp, G,
+                       gs, bt);
 }
 void launch_cgs_update(const double *V, long ldv, double *w, int n, int j, const double *Pin,
                        double *Pout, int ldp, int G, double *H, int ldh, int pass,
-                       const GState *gs, hipStream_t st) {
-    hipLaunchKernelGGL(k_cgs_update, dim3(G), dim3(kT), 0, st, V, ldv, w, n, j, Pin, Pout, ldp, G,
-                       H, ldh, pass, gs);
+                       const GState *gs, hipStream_t st, const Bat &bt) {
+    hipLaunchKernelGGL(k_cgs_update, dim3(G, bt.nsys), dim3(kT), 0, st, V, ldv, w, n, j, Pin,
+                       Pout, ldp, G, H, ldh, pass, gs, bt);
 }
 void launch_givens_scale(const double *w, int n, int j, const double *P, int G, double *V,
                          long ldv, float *v32, double *H, int ldh, double *cs, double *sn,
-                         double *g, int restart_len, GState *gs, hipStream_t st) {
-    hipLaunchKernelGGL(k_givens_scale, dim3(G), dim3(kT), 0, st, w, n, j, P, G, V, ldv, v32, H,
-                       ldh, cs, sn, g, restart_len, gs);
+                         double *g, int restart_len, GState *gs, hipStream_t st, const Bat &bt) {
+    hipLaunchKernelGGL(k_givens_scale, dim3(G, bt.nsys), dim3(kT), 0, st, w, n, j, P, G, V, ldv,
+                       v32, H, ldh, cs, sn, g, restart_len, gs, bt);
 }
 void launch_hsolve(const double *H, int ldh, const double *g, double *y, const GState *gs,
-                   hipStream_t st) {
-    hipLaunchKernelGGL(k_hsolve, dim3(1), dim3(kT), 0, st, H, ldh, g, y, gs);
+                   hipStream_t st, const Bat &bt) {
+    hipLaunchKernelGGL(k_hsolve, dim3(1, bt.nsys), dim3(kT), 0, st, H, ldh, g, y, gs, bt);
 }
 void launch_xupdate(double *x, const double *V, long ldv, int n, const double *y,
-                    const GState *gs, hipStream_t st) {
-    hipLaunchKernelGGL(k_xupdate, dim3(cdiv(n, 256)), dim3(256), 0, st, x, V, ldv, n, y, gs);
+                    const GState *gs, hipStream_t st, const Bat &bt) {
+    hipLaunchKernelGGL(k_xupdate, dim3(cdiv(n, 256), bt.nsys), dim3(256), 0, st, x, V, ldv, n, y,
+                       gs, bt);
 }
 void launch_axpy(double *x, const double *d, int n, double alpha, hipStream_t st) {
     hipLaunchKernelGGL(k_axpy, dim3(cdiv(n, 256)), dim3(256), 0, st, x, d, n, alpha);

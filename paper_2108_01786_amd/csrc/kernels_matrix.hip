@@ -41,11 +41,13 @@ __global__ __launch_bounds__(256) void k_assemble(Nodes N, const double *hrow, i
                 v = t_val64(N, tg[i], s, hrow);
                 if (tg[i].k == s.k && tg[i].loc == s.loc) v -= 0.5;
             }
-            static_cast<double *>(out)[idx] = v;
+            __builtin_nontemporal_store(v, static_cast<double *>(out) + idx);
         } else if (FP32) {
-            static_cast<float *>(out)[idx] = live ? a_val32(N, tg[i], s, corr != 0, band) : 0.0f;
+            __builtin_nontemporal_store(live ? a_val32(N, tg[i], s, corr != 0, band) : 0.0f,
+                                        static_cast<float *>(out) + idx);
         } else {
-            static_cast<double *>(out)[idx] = live ? a_val64(N, tg[i], s, corr != 0) : 0.0;
+            __builtin_nontemporal_store(live ? a_val64(N, tg[i], s, corr != 0) : 0.0,
+                                        static_cast<double *>(out) + idx);
         }
     }
 }
@@ -61,9 +63,23 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+// 16-byte vectors of the matrix element type, read with a non-temporal hint:
+// the matrix is streamed once per product, and without the hint the stream
+// reaches only about half the HBM bandwidth (measured on MI355X).
 template <typename TA> struct Vec16;
-template <> struct Vec16<float> { using type = float4; static constexpr int n = 4; };
-template <> struct Vec16<double> { using type = double2; static constexpr int n = 2; };
+template <> struct Vec16<float> {
+    typedef float type __attribute__((ext_vector_type(4)));
+    static constexpr int n = 4;
+};
+template <> struct Vec16<double> {
+    typedef double type __attribute__((ext_vector_type(2)));
+    static constexpr int n = 2;
+};
+
+template <typename TA>
+__device__ __forceinline__ typename Vec16<TA>::type stream_load(const TA *p) {
+    return __builtin_nontemporal_load(reinterpret_cast<const typename Vec16<TA>::type *>(p));
+}
 
 template <typename TACC, typename TX, int VW>
 __device__ __forceinline__ void load_x(const TX *x, int col, TACC (&xv)[VW]) {
@@ -71,7 +87,9 @@ __device__ __forceinline__ void load_x(const TX *x, int col, TACC (&xv)[VW]) {
     for (int v = 0; v < VW; ++v) xv[v] = (TACC)x[col + v];
 }
 
-template <typename TA, typename TX, typename TACC, int R>
+// y = c - A x (or A x): each wave owns R rows and walks them in steps of
+// 64 lanes x 16 bytes, U steps in flight; FP32 matrices accumulate in FP32.
+template <typename TA, typename TX, typename TACC, int R, int U>
 __global__ __launch_bounds__(256) void k_gemv(const TA *__restrict__ A, long ld, int n,
                                               const TX *__restrict__ x,
                                               const double *__restrict__ c,
@@ -90,20 +108,37 @@ __global__ __launch_bounds__(256) void k_gemv(const TA *__restrict__ A, long ld,
     TACC acc[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) acc[r] = (TACC)0;
-    const int nfull = (n / STEP) * STEP;
-    for (int c0 = 0; c0 < nfull; c0 += STEP) {
+    const int nbig = (n / (STEP * U)) * (STEP * U);
+    for (int c0 = 0; c0 < nbig; c0 += STEP * U) {
+        V a[U][R];
+        TACC xv[U][VW];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int col = c0 + u * STEP + lane * VW;
+#pragma unroll
+            for (int r = 0; r < R; ++r) a[u][r] = stream_load(rowp[r] + col);
+            load_x<TACC, TX, VW>(x, col, xv[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int v = 0; v < VW; ++v) acc[r] += (TACC)a[u][r][v] * xv[u][v];
+    }
+    const int nstep = (n / STEP) * STEP;
+    for (int c0 = nbig; c0 < nstep; c0 += STEP) {
         const int col = c0 + lane * VW;
         TACC xv[VW];
         load_x<TACC, TX, VW>(x, col, xv);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            const V a = *reinterpret_cast<const V *>(rowp[r] + col);
-            const TA *ae = reinterpret_cast<const TA *>(&a);
+            const V a = stream_load(rowp[r] + col);
 #pragma unroll
-            for (int v = 0; v < VW; ++v) acc[r] += (TACC)ae[v] * xv[v];
+            for (int v = 0; v < VW; ++v) acc[r] += (TACC)a[v] * xv[v];
         }
     }
-    for (int col = nfull + lane; col < n; col += 64) {
+    for (int col = nstep + lane; col < n; col += 64) {
         const TACC xv = (TACC)x[col];
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[r] += (TACC)rowp[r][col] * xv;
@@ -136,10 +171,9 @@ __global__ __launch_bounds__(256) void k_gemvT(const TA *__restrict__ A, long ld
     for (int v = 0; v < VW; ++v) acc[v] = (TACC)0;
     for (int p = p0; p < p1; ++p) {
         const TACC xp = (TACC)x[p];
-        const V a = *reinterpret_cast<const V *>(A + (long)p * ld + col);
-        const TA *ae = reinterpret_cast<const TA *>(&a);
+        const V a = stream_load(A + (long)p * ld + col);
 #pragma unroll
-        for (int v = 0; v < VW; ++v) acc[v] += (TACC)ae[v] * xp;
+        for (int v = 0; v < VW; ++v) acc[v] += (TACC)a[v] * xp;
     }
     double *out = part + (long)blockIdx.y * n;
 #pragma unroll
@@ -178,6 +212,11 @@ __device__ __forceinline__ double entry(const Nodes &N, const Tgt &t, const Src 
     return v;
 }
 
+// Forward product: each thread owns kTPT target rows (rows t, t + 256, ... of
+// the block's 256 * kTPT), so every source staged in LDS is read once for
+// kTPT entries.
+constexpr int kTPT = 2;
+
 template <int MODE, bool ACC32>
 __global__ __launch_bounds__(256) void k_otf_rows(Nodes N, const double *hrow, int r0, int nr,
                                                   int c0, int nc,
@@ -188,14 +227,20 @@ __global__ __launch_bounds__(256) void k_otf_rows(Nodes N, const double *hrow, i
     if (active && *active == 0) return;
     __shared__ Src ss[kStage];
     __shared__ double sx[kStage];
-    const int r = blockIdx.x * 256 + threadIdx.x;
-    const bool live = r < nr;
-    Tgt t;
-    if (live) t = load_tgt(N, r0 + r);
+    Tgt t[kTPT];
+    bool live[kTPT];
+#pragma unroll
+    for (int u = 0; u < kTPT; ++u) {
+        const int r = blockIdx.x * 256 * kTPT + u * 256 + threadIdx.x;
+        live[u] = r < nr;
+        t[u] = load_tgt(N, r0 + (live[u] ? r : 0));
+    }
     const int cb = blockIdx.y * chunk;
     const int ce = min(nc, cb + chunk);
-    double acc = 0.0;
-    float acc32 = 0.0f;
+    double acc[kTPT];
+    float acc32[kTPT];
+#pragma unroll
+    for (int u = 0; u < kTPT; ++u) { acc[u] = 0.0; acc32[u] = 0.0f; }
     for (int cc = cb; cc < ce; cc += kStage) {
         const int q = cc + threadIdx.x;
         if (q < ce) {
@@ -204,17 +249,24 @@ __global__ __launch_bounds__(256) void k_otf_rows(Nodes N, const double *hrow, i
         }
         __syncthreads();
         const int m = min(kStage, ce - cc);
-        if (live) {
-            for (int i = 0; i < m; ++i) {
+        for (int i = 0; i < m; ++i) {
+            const Src s = ss[i];
+            const double xv = sx[i];
+#pragma unroll
+            for (int u = 0; u < kTPT; ++u) {
                 if (ACC32)
-                    acc32 += (float)entry<MODE>(N, t, ss[i], corr != 0, band, hrow) * (float)sx[i];
+                    acc32[u] += (float)entry<MODE>(N, t[u], s, corr != 0, band, hrow) * (float)xv;
                 else
-                    acc += entry<MODE>(N, t, ss[i], corr != 0, band, hrow) * sx[i];
+                    acc[u] += entry<MODE>(N, t[u], s, corr != 0, band, hrow) * xv;
             }
         }
         __syncthreads();
     }
-    if (live) part[(long)blockIdx.y * nr + r] = ACC32 ? (double)acc32 : acc;
+#pragma unroll
+    for (int u = 0; u < kTPT; ++u) {
+        const int r = blockIdx.x * 256 * kTPT + u * 256 + threadIdx.x;
+        if (live[u]) part[(long)blockIdx.y * nr + r] = ACC32 ? (double)acc32[u] : acc[u];
+    }
 }
 
 template <int MODE, bool ACC32>
@@ -297,25 +349,25 @@ void launch_assemble_wall64(const Layout &L, const Nodes &N, const double *hrow,
 
 static int gemv_blocks(int n, int R) { return cdiv(cdiv(n, R), 4); }
 
+constexpr int kGemvR = 2;   // rows per wave
+constexpr int kGemvU = 4;   // 16-byte steps in flight per row
+
 void launch_gemv64(const double *A, long ld, int n, const double *x, const double *c, double *y,
                    const int *active, hipStream_t st) {
-    constexpr int R = 4;
-    hipLaunchKernelGGL((k_gemv<double, double, double, R>), dim3(gemv_blocks(n, R)), dim3(256),
-                       0, st, A, ld, n, x, c, y, active);
+    hipLaunchKernelGGL((k_gemv<double, double, double, kGemvR, kGemvU>),
+                       dim3(gemv_blocks(n, kGemvR)), dim3(256), 0, st, A, ld, n, x, c, y, active);
 }
 
 void launch_gemv32(const float *A, long ld, int n, const float *x, const double *c, double *y,
                    const int *active, hipStream_t st) {
-    constexpr int R = 4;
-    hipLaunchKernelGGL((k_gemv<float, float, float, R>), dim3(gemv_blocks(n, R)), dim3(256), 0,
-                       st, A, ld, n, x, c, y, active);
+    hipLaunchKernelGGL((k_gemv<float, float, float, kGemvR, kGemvU>),
+                       dim3(gemv_blocks(n, kGemvR)), dim3(256), 0, st, A, ld, n, x, c, y, active);
 }
 
 void launch_gemv32_x64(const float *A, long ld, int n, const double *x, const double *c,
                        double *y, const int *active, hipStream_t st) {
-    constexpr int R = 4;
-    hipLaunchKernelGGL((k_gemv<float, double, float, R>), dim3(gemv_blocks(n, R)), dim3(256), 0,
-                       st, A, ld, n, x, c, y, active);
+    hipLaunchKernelGGL((k_gemv<float, double, float, kGemvR, kGemvU>),
+                       dim3(gemv_blocks(n, kGemvR)), dim3(256), 0, st, A, ld, n, x, c, y, active);
 }
 
 void launch_reduce_partials(int n, const double *part, int nsplit, const double *c, double scale,
@@ -355,12 +407,13 @@ void launch_otf_matvec(const Layout &L, const Nodes &N, int flags, int fp32, int
     const int ns = cdiv(n, chunk);
     const int corr = (flags & WWBI_FLAG_NO_CORRECTION) ? 0 : 1;
     dim3 grid(cdiv(n, 256), ns);
+    dim3 gridr(cdiv(n, 256 * kTPT), ns);
     if (!transpose) {
         if (fp32)
-            hipLaunchKernelGGL((k_otf_rows<1, true>), grid, dim3(256), 0, st, N, hrow, 0, n, 0, n, chunk,
-                               corr, band, x, part, active);
+            hipLaunchKernelGGL((k_otf_rows<1, true>), gridr, dim3(256), 0, st, N, hrow, 0, n, 0, n,
+                               chunk, corr, band, x, part, active);
         else
-            hipLaunchKernelGGL((k_otf_rows<0, false>), grid, dim3(256), 0, st, N, hrow, 0, n, 0, n,
+            hipLaunchKernelGGL((k_otf_rows<0, false>), gridr, dim3(256), 0, st, N, hrow, 0, n, 0, n,
                                chunk, corr, band, x, part, active);
     } else {
         if (fp32)
@@ -381,7 +434,7 @@ void launch_rflavour(const Layout &L, const Nodes &N, const double *hrow, int mo
     (void)L;
     if (!transpose) {
         const int chunk = otf_chunk(nc);
-        dim3 grid(cdiv(nr, 256), cdiv(nc, chunk));
+        dim3 grid(cdiv(nr, 256 * kTPT), cdiv(nc, chunk));
         if (mode == 3)
             hipLaunchKernelGGL((k_otf_rows<3, false>), grid, dim3(256), 0, st, N, hrow, r0, nr, c0, nc,
                                chunk, 1, 0, x, part, active);

@@ -1,11 +1,13 @@
 """GPU path (HIP library through the C ABI) against the FP64 CPU oracle.
 
 Error measure: relative max-norm error ||x_gpu - x_ref||_inf / ||x_ref||_inf per
-output.  Bars: 1e-11 for FP64 solves, 1e-10 for refined FP32 solves.  Both
-solve to a relative FP64 residual of 1e-13 (cond_2(A) is a few units, so
-omega is accurate to about 1e-12).  U applies a spectral derivative to omega,
-which amplifies the high modes of the solution error by up to M_0/2, so a
-residual of 1e-12 is not enough for the 1e-10 bar on U at M_0 = 2048.
+output.  Bars: 1e-11 for FP64 solves, 1e-10 for refined FP32 solves.  FP64
+GMRES runs to a relative residual of 1e-13 (cond_2(A) is a few units, so
+omega is accurate to about 1e-12 and its error is smooth).  U applies a
+spectral derivative to omega, which amplifies the high modes of the solution
+error by up to M_0/2.  The last FP32 correction of the refinement carries
+white noise of about 1e-7 of its size, so the refined solves run to 1e-14:
+the final, short step then leaves noise far below the bar on U.
 """
 import numpy as np
 import pytest
@@ -145,11 +147,11 @@ def test_solve_phi_refined_fp32(ww, ctx, name, mode):
     cfg = _cfg(name)
     dg = ww.DeviceGeometry.from_synth(cfg["geom"], DEV)
     U, omega, psi, rep = ctx.solve_phi(
-        dg, torch.as_tensor(cfg["phi"], device=DEV), tol=1e-13, precision=ww.FP32_REFINED,
+        dg, torch.as_tensor(cfg["phi"], device=DEV), tol=1e-14, precision=ww.FP32_REFINED,
         matvec=ww.MATVEC_STORED if mode == "stored" else ww.MATVEC_ON_THE_FLY)
     ref = oracle_solution(name)
     say(f"  iters={rep.iters} refine={rep.refine_steps} resid={rep.rel_resid:.2e}")
-    assert rep.status == 0 and rep.rel_resid <= 1e-13
+    assert rep.status == 0 and rep.rel_resid <= 1e-14
     assert rel(U.cpu().numpy(), ref["U"].numpy()) <= 1e-10
     assert rel(omega.cpu().numpy(), ref["omega"].numpy()) <= 1e-10
 
