@@ -11,9 +11,10 @@ Gradients come from PyTorch autograd through these same plain operations.
 """
 from .bim import (OGeom, assemble_A, A_rows, rhs, solve_phi, solve_gamma, spectral, split,
                   K_block, G_block, A_block, wall_matrix, psi_on_surface,
-                  psi_mv, u_mv, energy, surface_from_periodic, J_and_grad, dphi_dn_from_omega)
+                  psi_mv, u_mv, energy, surface_from_periodic, J_and_grad, dphi_dn_from_omega,
+                  dphi_ds_from_omega)
 
 __all__ = ["OGeom", "assemble_A", "A_rows", "rhs", "solve_phi", "solve_gamma", "spectral", "split",
            "K_block", "G_block", "A_block", "wall_matrix", "psi_on_surface",
            "psi_mv", "u_mv", "energy", "surface_from_periodic", "J_and_grad",
-           "dphi_dn_from_omega"]
+           "dphi_dn_from_omega", "dphi_ds_from_omega"]

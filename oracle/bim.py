@@ -12,6 +12,7 @@ with background flow over obstacles and topography" (arXiv 2108.01786):
 * collocation / trapezoid discretization ................... Sec. 3.3
 * multi-valued potential Phi_mv and its derivative ......... Sec. 3, 3.1
 * normal velocity U (velocity-potential method) ............ Sec. 3.4
+* tangential velocity on every boundary .................... Sec. 5.1
 * vortex-sheet wall system and U from gamma ................ Sec. 4.1
 * energy E ................................................. Sec. 5.2
 * spectral derivative and Hilbert transform (FFT symbols) .. Sec. 3.4
@@ -267,6 +268,33 @@ def dphi_dn_from_omega(g: OGeom, omega: List[torch.Tensor]) -> torch.Tensor:
     for j in range(1, g.nb):
         acc = acc + (K_block(g, j, 0).T @ dw[j]) / g.M[j]
     return acc / s0
+
+
+def dphi_ds_from_omega(g: OGeom, omega: List[torch.Tensor]) -> List[torch.Tensor]:
+    """Tangential derivative dphi/ds on every boundary (Sec. 5.1, the formulas
+    for s dphi/ds_k that accompany the normal ones of Sec. 4.1), with
+    gamma_0 = -omega_0' and gamma_j = omega_j':
+
+    s dphi/ds_k = Re{Phi_mv'(zeta_k) zeta_k'} + [k = 0] gamma_0 / 2
+                  + (1/M_0) sum_l K_0k(b_l, a) gamma_0(b_l)
+                  + sum_{j>=1} ( -[k = j] H(gamma_j)/2 - (1/M_j) sum_l G_jk(b_l, a) gamma_j(b_l) ).
+    The free surface is taken on its fluid (lower) side, where the jump term
+    of gamma_0 enters with a plus sign.  The integration variable sits in
+    the first slot of K_0k and G_jk, so the blocks enter transposed.
+    """
+    gam = [-spectral(omega[0], "D")] + [spectral(w, "D") for w in omega[1:]]
+    out = []
+    for k in range(g.nb):
+        acc = (dPhi_mv(g, g.z[k]) * g.d[k]).real
+        if k == 0:
+            acc = acc + 0.5 * gam[0]
+        acc = acc + (K_block(g, 0, k).T @ gam[0]) / g.M[0]
+        for j in range(1, g.nb):
+            if j == k:
+                acc = acc - 0.5 * spectral(gam[j], "H")
+            acc = acc - (G_block(g, j, k).T @ gam[j]) / g.M[j]
+        out.append(acc / torch.abs(g.d[k]))
+    return out
 
 
 def solve_phi(g: OGeom, phi: torch.Tensor) -> Dict[str, torch.Tensor]:

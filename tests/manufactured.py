@@ -8,7 +8,8 @@ difference Phi_exact - Phi_mv is single-valued in the fluid, so the layer
 potentials can represent it.  Feeding
     phi~ = Re(Phi_exact - Phi_mv) on the surface,
     g_k  = Im Phi_exact - c_k on wall k (c_1 = 0)
-must give U = Re{Phi_exact'(zeta) i zeta'}/|zeta'| and psi|_k = c_k.
+must give U = Re{Phi_exact'(zeta) i zeta'}/|zeta'|, psi|_k = c_k and, on every
+boundary, dphi/ds = Re{Phi_exact'(zeta) zeta'}/|zeta'|.
 
 Flat strip of depth h with no obstacles: phi~ = cos(k alpha) on y = 0 gives
 U = k tanh(k h) cos(k alpha) (the finite-depth Dirichlet-Neumann operator).
@@ -87,18 +88,25 @@ def manufactured_inputs(geom: Geometry, flow: Flow, consts):
     return phi, np.concatenate(walls), U, np.asarray(consts, float)
 
 
+def exact_dphi_ds(geom: Geometry, flow: Flow):
+    """dphi/ds = Re{Phi_exact'(zeta) zeta'}/|zeta'| on every boundary, concatenated."""
+    return np.concatenate([(flow.dPhi(c.z) * c.d).real / np.abs(c.d) for c in geom.curves])
+
+
+CASE_FLOW = Flow(1.0, [0.5], [np.pi + 0.06 - 0.47j], c_cot=0.07, p_cot=np.pi - 0.05 - 0.52j,
+                 c_exp=0.03, c_low=0.2, q_low=0.4 - 1.6j)
+
+
 def manufactured_case(M0=256, M1=256, M2=128, with_psi_wall=True):
     """Config-1-like cell with an off-centre vortex, a cot pole inside the
-    ellipse, e^{-iz} and a log-sin source below the bottom."""
+    ellipse, e^{-iz} and a log-sin source below the bottom (flow CASE_FLOW)."""
     rng = np.random.default_rng(7)
     coeffs = 0.01 * np.exp(-np.arange(2, 8) / 4.0) * (rng.standard_normal(6) + 1j * rng.standard_normal(6))
     surf = fourier_surface(M0, 0.1, coeffs)
     bot = graph_bottom(M1, -1.0, [(1, 0.05)])
     ell = ellipse(M2, np.pi, -0.5, 0.3, 0.15, 0.3)
     geom = Geometry([surf, bot, ell], np.array([np.pi - 0.5j]), np.array([0.5]), 1.0)
-    flow = Flow(1.0, [0.5], [np.pi + 0.06 - 0.47j], c_cot=0.07, p_cot=np.pi - 0.05 - 0.52j,
-                c_exp=0.03, c_low=0.2, q_low=0.4 - 1.6j)
-    phi, pw, U, ck = manufactured_inputs(geom, flow, [0.37])
+    phi, pw, U, ck = manufactured_inputs(geom, CASE_FLOW, [0.37])
     if with_psi_wall:
         geom.psi_wall = pw
     return geom, phi, U, ck

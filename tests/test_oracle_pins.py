@@ -13,7 +13,8 @@ import pytest
 import torch
 
 import oracle as O
-from manufactured import Flow, flat_strip, manufactured_case, manufactured_inputs
+from manufactured import (CASE_FLOW, Flow, exact_dphi_ds, flat_strip, manufactured_case,
+                          manufactured_inputs)
 from synth import make_config, paper_problem, ragged_config, tiny_config
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -63,6 +64,37 @@ def test_flat_strip_dno(h, k, V1):
     g = O.OGeom.from_synth(geom)
     U = O.solve_phi(g, torch.as_tensor(np.cos(k * al)))["U"].numpy()
     assert np.abs(U - k * np.tanh(k * h) * np.cos(k * al)).max() < 1e-12
+
+
+def test_tangential_velocity_manufactured():
+    """dphi/ds on the surface, the bottom and the obstacle (Sec. 5.1 formulas)
+    against Re{Phi'(zeta) zeta'}/|zeta'| of the manufactured flow, converging
+    spectrally; the same formula on the walls of a flow with no obstacles."""
+    errs = []
+    for M0, M1, M2 in [(64, 64, 32), (128, 128, 64), (256, 256, 128)]:
+        geom, phi, _, _ = manufactured_case(M0, M1, M2)
+        g = O.OGeom.from_synth(geom)
+        r = O.solve_phi(g, torch.as_tensor(phi))
+        ds = torch.cat(O.dphi_ds_from_omega(g, O.split(g, r["omega"]))).numpy()
+        ex = exact_dphi_ds(geom, CASE_FLOW)
+        errs.append(np.abs(ds - ex).max() / np.abs(ex).max())
+    assert errs[-1] < 1e-10, errs
+    assert errs[0] > 10 * errs[-1], errs
+
+
+@pytest.mark.parametrize("k", [1, 4])
+def test_tangential_velocity_flat_strip(k):
+    """Flat strip of depth h, phi~ = cos(k alpha): phi = cosh(k(y+h))/cosh(kh) cos(kx),
+    so dphi/ds = -k sin(k alpha) on the surface and -k sin(k alpha)/cosh(kh) on
+    the bottom (whose tangent points in +x)."""
+    h = 1.5
+    geom = flat_strip(64, 64, h)
+    al = 2 * np.pi * np.arange(64) / 64
+    g = O.OGeom.from_synth(geom)
+    r = O.solve_phi(g, torch.as_tensor(np.cos(k * al)))
+    ds = O.dphi_ds_from_omega(g, O.split(g, r["omega"]))
+    assert np.abs(ds[0].numpy() + k * np.sin(k * al)).max() < 1e-12
+    assert np.abs(ds[1].numpy() + k * np.sin(k * al) / np.cosh(k * h)).max() < 1e-12
 
 
 def test_manufactured_flow_converges_spectrally():
