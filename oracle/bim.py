@@ -15,6 +15,7 @@ with background flow over obstacles and topography" (arXiv 2108.01786):
 * tangential velocity on every boundary .................... Sec. 5.1
 * vortex-sheet wall system and U from gamma ................ Sec. 4.1
 * energy E ................................................. Sec. 5.2
+* gamma_t system (time derivative of the sheet strengths) .. Sec. 4.2
 * spectral derivative and Hilbert transform (FFT symbols) .. Sec. 3.4
 
 Conventions the paper leaves open and that are fixed here: the Nyquist
@@ -344,6 +345,106 @@ def solve_gamma(g: OGeom, gamma0: torch.Tensor) -> Dict[str, torch.Tensor]:
         acc = acc + (K_block(g, j, 0).T @ gparts[j - 1]) / g.M[j]
     acc = acc + u_mv(g, g.z[0], g.d[0])
     return {"U": acc / s0, "gamma_wall": gw, "W": W}
+
+
+# ---------------------------------------------------------------------------
+# time derivative of the vortex sheet strengths (Sec. 4.2)
+# ---------------------------------------------------------------------------
+
+def gamma_t_matrix(g: OGeom) -> torch.Tensor:
+    """The collocated operator of the gamma_t system (Sec. 4.2, the gamma_0,t
+    equation stacked on the wall equations), all blocks in the dagger form
+    of Sec. 4.1 (integration variable in the first kernel slot, weight 1/M_j):
+      row 0:  (I/2 + K_00^dagger) gamma_0,t - sum_j G_j0^dagger gamma_j,t
+      row k:  G_0k^dagger gamma_0,t + (-I/2 + K_kk^dagger) gamma_k,t
+              + sum_{j != k} K_jk^dagger gamma_j,t           (k >= 1)."""
+    rows = []
+    for k in range(g.nb):
+        blocks = []
+        for j in range(g.nb):
+            if k == 0 and j == 0:
+                B = K_block(g, 0, 0).T / g.M[0] + 0.5 * torch.eye(g.M[0], dtype=F64)
+            elif k == 0:
+                B = -G_block(g, j, 0).T / g.M[j]
+            elif j == 0:
+                B = G_block(g, 0, k).T / g.M[0]
+            else:
+                B = K_block(g, j, k).T / g.M[j]
+                if j == k:
+                    B = B - 0.5 * torch.eye(g.M[k], dtype=F64)
+            blocks.append(B)
+        rows.append(torch.cat(blocks, dim=1))
+    return torch.cat(rows, dim=0)
+
+
+def F_operators(g: OGeom, gamma0: torch.Tensor, U: torch.Tensor, V: torch.Tensor):
+    """F_00 gamma_0 and F_k0 gamma_0 (k >= 1) in the regularised form that
+    writes zeta_t = (V + i U) zeta' / s (Sec. 4.2):
+      F_00 = -H(U gamma_0 / s)/2 + K_00(V gamma_0 / s) + G_00(U gamma_0 / s),
+      F_k0 = G_k0(V gamma_0 / s) - K_k0(U gamma_0 / s),
+    with K_kj f = (1/M_j) sum_l K_kj(a, b_l) f(b_l) (target in the first slot)."""
+    s0 = torch.abs(g.d[0])
+    fV = V * gamma0 / s0
+    fU = U * gamma0 / s0
+    out = [-0.5 * spectral(fU, "H") + (K_block(g, 0, 0) @ fV + G_block(g, 0, 0) @ fU) / g.M[0]]
+    for k in range(1, g.nb):
+        out.append((G_block(g, k, 0) @ fV - K_block(g, k, 0) @ fU) / g.M[0])
+    return out
+
+
+def gamma_t_rhs(g: OGeom, phi: torch.Tensor, V: torch.Tensor, tau: float,
+                grav: float = 1.0) -> Dict[str, torch.Tensor]:
+    """Right-hand side of the gamma_t system (Sec. 4.2) at the state (zeta, phi~).
+
+    The velocity-potential solve gives omega, U and gamma = (-D omega_0,
+    D omega_j); W is the Birkhoff-Rott velocity plus grad phi_mv on the
+    surface, so that grad phi = W + gamma_0 t / (2 s) on the fluid side:
+    W.t = dphi/ds - gamma_0 / (2 s), W.n = U.
+      surface: d/dalpha( -W.W/2 + (V - W.t) gamma_0 / (2 s) - gamma_0^2 / (8 s^2)
+                         + tau theta_alpha / s - g eta - F_00 gamma_0 ),
+      wall k:  -d/dalpha( F_k0 gamma_0 )."""
+    r = solve_phi(g, phi)
+    parts = split(g, r["omega"])
+    U = r["U"]
+    gamma0 = -spectral(parts[0], "D")
+    s0 = torch.abs(g.d[0])
+    ds = dphi_ds_from_omega(g, parts)[0]
+    Wt = ds - gamma0 / (2.0 * s0)
+    WW = Wt * Wt + U * U
+    theta_a = (g.e[0] / g.d[0]).imag
+    F = F_operators(g, gamma0, U, V.to(F64))
+    surf = (-0.5 * WW + (V - Wt) * gamma0 / (2.0 * s0) - gamma0 ** 2 / (8.0 * s0 ** 2)
+            + tau * theta_a / s0 - grav * g.z[0].imag - F[0])
+    b = [spectral(surf, "D")] + [-spectral(F[k], "D") for k in range(1, g.nb)]
+    return {"b": torch.cat(b), "omega": r["omega"], "U": U, "gamma0": gamma0}
+
+
+def solve_gamma_t(g: OGeom, phi: torch.Tensor, V: torch.Tensor, tau: float,
+                  grav: float = 1.0) -> Dict[str, torch.Tensor]:
+    """gamma_t = (gamma_0,t, gamma_1,t, ...) by dense LU of the Sec. 4.2 system."""
+    r = gamma_t_rhs(g, phi, V, tau, grav)
+    B = gamma_t_matrix(g)
+    r["gamma_t"] = torch.linalg.solve(B, r["b"])
+    r["B"] = B
+    return r
+
+
+def surface_velocity_state(g: OGeom, phi: torch.Tensor, V: torch.Tensor, tau: float,
+                           grav: float = 1.0):
+    """zeta_t = (V + i U) zeta'/s and the phi~ equation of Sec. 3.5 (C = 0):
+    phi~_t = (phi~_alpha / s) V + (U - u_mv / s) U - |grad phi|^2 / 2 - g eta
+             + tau theta_alpha / s, |grad phi|^2 = (phi_alpha / s)^2 + U^2."""
+    r = solve_phi(g, phi)
+    U = r["U"]
+    z, d, e = g.z[0], g.d[0], g.e[0]
+    s0 = torch.abs(d)
+    zt = (V + 1j * U) * d / s0
+    pa_t = spectral(phi.to(F64), "D")
+    pa = pa_t + (dPhi_mv(g, z) * d).real
+    dn_t = U - u_mv(g, z, d) / s0
+    grad2 = (pa / s0) ** 2 + U ** 2
+    phit = pa_t / s0 * V + dn_t * U - 0.5 * grad2 - grav * z.imag + tau * (e / d).imag / s0
+    return zt, phit
 
 
 # ---------------------------------------------------------------------------

@@ -97,6 +97,38 @@ def test_tangential_velocity_flat_strip(k):
     assert np.abs(ds[1].numpy() + k * np.sin(k * al) / np.cosh(k * h)).max() < 1e-12
 
 
+def _gamma_of_state(g, phi):
+    parts = O.split(g, O.solve_phi(g, phi)["omega"])
+    return torch.cat([-O.spectral(parts[0], "D")] + [O.spectral(p, "D") for p in parts[1:]])
+
+
+@pytest.mark.parametrize("tau,vamp", [(0.1, 0.1), (0.0, -0.3)])
+def test_gamma_t_matches_time_derivative(tau, vamp):
+    """The Sec. 4.2 system for gamma_t against the time derivative of the
+    velocity-potential solution: move the surface by zeta_t = (V + iU) zeta'/s
+    and phi~ by its Sec. 3.5 equation, re-solve at t +- dt and difference
+    gamma = (-D omega_0, D omega_j) centrally (config 1, M = 640)."""
+    cfg = make_config(1)
+    g = O.OGeom.from_synth(cfg["geom"])
+    phi = torch.as_tensor(cfg["phi"])
+    M0 = g.M[0]
+    al = 2 * np.pi * torch.arange(M0, dtype=torch.float64) / M0
+    V = vamp * torch.sin(al) + 0.03 * torch.cos(2 * al)
+    gt = O.solve_gamma_t(g, phi, V, tau)["gamma_t"]
+    zt, phit = O.surface_velocity_state(g, phi, V, tau)
+    xt, yt = g.z[0].real - al, g.z[0].imag
+    dt = 1e-4
+    gams = []
+    for sg in (1.0, -1.0):
+        z, d, e = O.surface_from_periodic(xt + sg * dt * zt.real, yt + sg * dt * zt.imag)
+        gams.append(_gamma_of_state(g.with_surface(z, d, e), phi + sg * dt * phit))
+    fd = (gams[0] - gams[1]) / (2 * dt)
+    off = np.cumsum([0] + g.M)
+    for k in range(g.nb):
+        a, b = gt[off[k]:off[k + 1]], fd[off[k]:off[k + 1]]
+        assert float((a - b).abs().max() / a.abs().max()) < 1e-6, k
+
+
 def test_manufactured_flow_converges_spectrally():
     """Exact U and psi|_k of a manufactured periodic flow, with spectral convergence."""
     errs = []
