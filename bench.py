@@ -28,6 +28,26 @@ import numpy as np  # noqa: E402
 import torch  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_k_gemv_fp32_config3_M10240.md")
+
+
+def measured_traffic():
+    """HBM bytes per launch of the stored FP32 matvec from the committed
+    rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by a
+    1 GiB copy), or None when the kernel source changed since it was taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_FILE).read()
+        src = open(os.path.join(ROOT, "paper_2108_01786_amd", "csrc", "kernels_gemv.hip"), "rb").read()
+    except OSError:
+        return None
+    vals = dict(l.split(": ", 1) for l in text.splitlines() if ": " in l and not l.startswith(("*", "#")))
+    if vals.get("kernels_gemv_sha256", "").strip() != hashlib.sha256(src).hexdigest():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def log(msg):
@@ -47,7 +67,20 @@ def parse():
     ap.add_argument("--poll", type=int, default=4)
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (counter calibration)")
+    ap.add_argument("--workload", default="solve", choices=["solve", "large-stages"],
+                    help="solve: the M = 10240 solve (default); large-stages: forward + adjoint "
+                         "stages on the M = 40960 cell")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip timing the diagnostics and the gamma_t stage")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="minimum host time spent on the oracle baseline sample")
     return ap.parse_args()
+
+
+def stats_ms(reps, key="ms_total"):
+    v = np.array([r[key] for r in reps])
+    q1, med, q3 = np.percentile(v, [25, 50, 75])
+    return {"median": float(med), "iqr": float(q3 - q1), "min": float(v.min()), "max": float(v.max())}
 
 
 def timed_solves(ctx, dg, phi, steps, warmup, flags=0, **kw):
@@ -73,11 +106,124 @@ def timed_solves(ctx, dg, phi, steps, warmup, flags=0, **kw):
     return (t1 - t0) / steps, reps, out
 
 
+def time_extras(ctx, dg, geom, phi, a, reps=5):
+    """Per-call times of the diagnostics (tangential velocity on every node and
+    the energy) and of the gamma_t stage (its own velocity-potential solve plus
+    the right-hand side and the n x n FP64 system), on the same cell."""
+    from paper_2108_01786_amd import wwbi
+    M0 = geom.M[0]
+    al = torch.arange(M0, dtype=torch.float64, device=phi.device) * (2 * np.pi / M0)
+    V = 0.1 * torch.sin(al) + 0.03 * torch.cos(2 * al)
+    _, omega, _, _ = ctx.solve_phi(dg, phi, tol=1e-13)
+    out = {}
+    te = []
+    for _ in range(reps + 1):
+        _, _, r = ctx.tangential_energy(dg, omega, phi, tau=0.1, grav=1.0)
+        te.append(r.as_dict())
+    out["tangential_energy_ms"] = stats_ms(te[1:])
+    gt, gp = [], []
+    for _ in range(reps + 1):
+        _, _, r1, r2 = ctx.solve_gamma_t(dg, phi, V, tau=0.1, tol=1e-13, restart=100,
+                                         poll_every=a.poll)
+        gt.append(r2.as_dict())
+        gp.append(r1.as_dict())
+    out["gamma_t_stage_ms"] = stats_ms(gt[1:])
+    out["gamma_t_phi_solve_ms"] = stats_ms(gp[1:])
+    out["gamma_t_iters"] = gt[-1]["iters"]
+    out["gamma_t_phases_ms"] = {k: gt[-1][k] for k in ("ms_prep", "ms_assemble", "ms_solve")}
+    return out
+
+
+def run_large(a):
+    """Forward + adjoint stages on the M = 40960 cell (surface 16384, bottom
+    8192, eight ellipses of 2048): stage s moves the surface and phi by
+    s * 1e-3 times a seeded smooth displacement (degree <= 32), runs the
+    refined-FP32 solve for U warm-started from the previous stage's omega, and
+    the adjoint of J = sum w U^2 (weights ~ U[0, 1]).  One step is one stage."""
+    from paper_2108_01786_amd import wwbi
+    from paper_2108_01786_amd.autograd import SurfaceProblem
+    from synth import make_config
+
+    cfg = make_config(5)
+    geom = cfg["geom"]
+    dev = "cuda:0"
+    ctx = wwbi.Context(0)
+    prob = SurfaceProblem(ctx, geom, dev)
+    M0 = geom.M[0]
+    z0 = geom.curves[0].z
+    al = 2 * np.pi * np.arange(M0) / M0
+    xt0, yt0, ph0 = z0.real - al, z0.imag, np.asarray(cfg["phi"])
+    disp = cfg["stage_disp"]
+    w = torch.as_tensor(np.random.default_rng(178605).uniform(0.0, 1.0, M0), device=dev)
+    ctx.reserve(geom.Mtot, 120, wwbi.FP32_REFINED)
+    opts = dict(precision=wwbi.FP32_REFINED, tol=1e-14, inner_tol=a.inner_tol,
+                matvec=wwbi.MATVEC_STORED, restart=120, poll_every=a.poll)
+    inputs = []
+    for s in range(4):
+        f = s * 1e-3
+        inputs.append([torch.as_tensor(v, device=dev) for v in
+                       (xt0 + f * disp[0], yt0 + f * disp[1], ph0 + f * disp[2])])
+
+    def stage(s, x0, flags=0):
+        xt, yt, ph = inputs[s]
+        g = prob.fill(xt, yt)
+        U, om, _, rf = ctx.solve_phi(g, ph, x0=x0, flags=flags, **opts)
+        grads, ra = ctx.adjoint_phi(g, om, 2.0 * w * U, **opts)
+        ctx.surface_fill_adjoint([grads[k] for k in ("x", "y", "dx", "dy", "ddx", "ddy")])
+        return om, rf.as_dict(), ra.as_dict()
+
+    log(f"bench: large stages M={geom.Mtot}")
+    om = None
+    cold = None
+    for k in range(a.warmup):
+        om, rf, ra = stage(k % 4, om)
+        cold = cold or rf
+    torch.cuda.synchronize()
+    fw, ad = [], []
+    t0 = time.perf_counter()
+    for k in range(a.steps):
+        om, rf, ra = stage((a.warmup + k) % 4, om, wwbi.FLAG_PROFILE if k == 0 else 0)
+        fw.append(rf)
+        ad.append(ra)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / a.steps
+    log(f"bench: {1e3 * t:.2f} ms per stage")
+    p = fw[0]
+    avg = p["ms_matvec"] / max(1, p["n_matvec"])
+    achieved = p["bytes_matvec"] / (avg * 1e-3) / 1e9 if avg > 0 else 0.0
+    line = {
+        "metric": "refined-FP32 forward+adjoint stages/s at 40960 unknowns",
+        "value": 1.0 / t, "unit": "stages/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": 1e3 * t, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 matvec + f64 refinement",
+        "data": "synthetic",
+        "config": {"workload": f"forward+adjoint stages, M={geom.Mtot} (surface {M0}, bottom "
+                               f"{geom.M[1]}, {geom.nb - 2} ellipses of {geom.M[2]})",
+                   "unknowns": geom.Mtot, "matvec": "stored", "tol": 1e-14, "restart": 120,
+                   "warm_start": True},
+        "forward_ms": stats_ms(fw), "adjoint_ms": stats_ms(ad),
+        "forward_iters_warm": [r["iters"] for r in fw],
+        "forward_iters_cold": cold["iters"] if cold else None,
+        "adjoint_iters": [r["iters"] for r in ad],
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_gemv<float,float,float,2,4> (stored FP32 matvec)",
+                     "avg_launch_ms": avg, "launches": p["n_matvec"],
+                     "bytes_per_launch": p["bytes_matvec"]},
+        "cpu_baseline": None,
+        "cpu_baseline_note": "a dense oracle solve at 40960 unknowns does not fit a bounded CPU sample",
+    }
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "one GPU only: the solve runs on a single device; --gpus must be 1"}))
         sys.exit(2)
+    if a.workload == "large-stages":
+        return run_large(a)
     from paper_2108_01786_amd import wwbi
     from synth import make_config, CONFIG_NAMES
 
@@ -103,6 +249,7 @@ def main():
         res["fp64_solves_per_s"] = 1.0 / t64
         res["fp64_ms_per_solve"] = 1e3 * t64
         res["fp64_iters"] = reps64[-1]["iters"]
+        res["fp64_ms_per_solve_stats"] = stats_ms(reps64)
         mv64 = sum(r["ms_matvec"] for r in reps64) / max(1, sum(r["n_matvec"] for r in reps64))
         res["fp64_matvec_ms"] = mv64
         res["fp64_matvec_GBs"] = reps64[-1]["bytes_matvec"] / (mv64 * 1e-3) / 1e9 if mv64 else None
@@ -112,8 +259,9 @@ def main():
     avg = msmv / max(1, nmv)
     bytes_mv = reps32[-1]["bytes_matvec"]
     achieved = bytes_mv / (avg * 1e-3) / 1e9 if avg > 0 else 0.0
+    traffic = measured_traffic() if (a.config == 3 and a.mode == "stored") else None
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "kernel": "k_gemv<float,float,float,2,4> (stored FP32 matvec)",
             "avg_launch_ms": avg, "launches": nmv, "bytes_per_launch": bytes_mv}
 
@@ -121,12 +269,18 @@ def main():
     if not a.no_cpu_baseline:
         import oracle as O
         og = O.OGeom.from_synth(geom)
+        nsol = 0
         t0 = time.perf_counter()
-        ref = O.solve_phi(og, torch.as_tensor(cfg["phi"]))
-        tcpu = time.perf_counter() - t0
-        cpu = {"value": 1.0 / tcpu, "unit": "solves/s", "cores": torch.get_num_threads(),
+        while True:
+            ref = O.solve_phi(og, torch.as_tensor(cfg["phi"]))
+            nsol += 1
+            tcpu = time.perf_counter() - t0
+            if tcpu >= a.cpu_seconds:
+                break
+        cpu = {"value": nsol / tcpu, "unit": "solves/s", "cores": torch.get_num_threads(),
                "kind": "oracle",
-               "sample": f"one full FP64 solve of the same M={geom.Mtot} cell (dense LU)"}
+               "sample": f"{nsol} full FP64 solves of the same M={geom.Mtot} cell (assembly, "
+                         f"dense LU, U), {tcpu:.1f} s"}
         U, omega, psi, _ = out32
         Ur, wr = ref["U"].numpy(), ref["omega"].numpy()
         res["err_vs_oracle_refined"] = {
@@ -140,6 +294,9 @@ def main():
                 "U": float(np.abs(U.cpu().numpy() - Ur).max() / np.abs(Ur).max()),
                 "omega": float(np.abs(omega.cpu().numpy() - wr).max() / np.abs(wr).max()),
             }
+
+    if not a.no_extras:
+        res["extras"] = time_extras(ctx, dg, geom, phi, a)
 
     if a.copy_calib_mb:
         # a device copy of known size for scaling the HBM counters; a 1 GiB
@@ -165,6 +322,7 @@ def main():
                                f"{geom.nb - 2} ellipses of {geom.M[2]})",
                    "unknowns": geom.Mtot, "matvec": a.mode, "tol_refined": 1e-14,
                    "tol_fp64": 1e-13},
+        "ms_per_solve_stats": stats_ms(reps32),
         "iters": last["iters"], "refine_steps": last["refine_steps"],
         "phase_ms": {k: last[k] for k in ("ms_prep", "ms_assemble", "ms_solve", "ms_U")},
         "roofline": roof, "cpu_baseline": cpu,

@@ -172,6 +172,59 @@ int wwbi_solve_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi, const w
 int wwbi_solve_gamma(wwbi_ctx *ctx, const wwbi_geom *g, const double *gamma0, const wwbi_opts *o,
                      double *U, double *gamma_wall, wwbi_report *rep);
 
+/* Tangential velocity on every boundary and the energy, from a
+ * velocity-potential solution (no solve is run).
+ *   phi    (device) M_0: the phi~ passed to wwbi_solve_phi; needed only for
+ *          the energy (may be NULL when energy is NULL).
+ *   omega  (device) sum(M): the densities returned by wwbi_solve_phi.
+ *   tau, grav: surface tension and gravity of the energy (rho = 1).
+ * Outputs (each may be NULL, not both):
+ *   dphids (device) sum(M): the tangential derivative dphi/ds at every node,
+ *          from gamma = (-D omega_0, D omega_j) by the Sec. 5.1 formulas:
+ *          s dphi/ds_k = s dphi_mv/ds_k + [k = 0] gamma_0/2
+ *             + sum_l K_0k(beta_l, alpha) gamma_0,l / M_0
+ *             + sum_{j>=1} ( -[k = j] (H gamma_j)/2 - sum_l G_jk(beta_l, alpha) gamma_j,l / M_j ),
+ *          with the surface on its fluid (lower) side.  With dphi/dn (U on the
+ *          surface, 0 on the walls) it gives the velocity u - i v =
+ *          (dphi/ds - i dphi/dn) |zeta'| / zeta'.
+ *   energy (host) 1: E of Sec. 5.2, the trapezoid mean over the surface of
+ *          tau s + g eta^2 xi' / 2 + psi phi_alpha / 2, plus sum_j a_j psi|_j / 2,
+ *          with psi on the surface from the Plemelj limits of the Cauchy
+ *          integrals and phi_alpha = D phi~ + d phi_mv / d alpha.
+ * Errors: WWBI_EINVAL_NULL (omega, or both outputs, or phi with energy),
+ * WWBI_EINVAL_NONFINITE (tau, grav, geometry or phi), and the geometry
+ * checks of wwbi_solve_phi.  The report carries the timings only. */
+int wwbi_tangential_energy(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi,
+                           const double *omega, double tau, double grav, double *dphids,
+                           double *energy, wwbi_report *rep);
+
+/* Time derivative of the vortex sheet strengths (Sec. 4.2): the gamma_0,t
+ * equation stacked on the wall equations,
+ *   (I/2 + K_00^dagger) gamma_0,t - sum_j G_j0^dagger gamma_j,t = d/dalpha(e_0),
+ *   G_0k^dagger gamma_0,t + (-I/2 + K_kk^dagger) gamma_k,t + sum_{j!=k} K_jk^dagger gamma_j,t
+ *       = -d/dalpha(F_k0 gamma_0)                                   (k >= 1),
+ *   e_0 = -W.W/2 + (V - W.t) gamma_0/(2s) - gamma_0^2/(8 s^2) + tau theta_alpha/s
+ *         - grav eta - F_00 gamma_0,
+ * where gamma = (-D omega_0, D omega_j), U and W (the Birkhoff-Rott velocity
+ * plus grad phi_mv on the surface) come from a velocity-potential solve at
+ * the state (geometry, phi~), and F_00, F_k0 take the regularised form with
+ * zeta_t = (V + iU) zeta'/s.
+ *   phi    (device) M_0: phi~ of the state.
+ *   V      (device) M_0: tangential velocity of the surface parameterisation.
+ *   tau, grav: surface tension and gravity.
+ *   o: tol, restart, max_iter and matvec apply to both solves; precision and
+ *      x0 (an omega warm start) to the velocity-potential solve only; the
+ *      gamma_t system is solved in FP64 (stored or on the fly).
+ * Outputs: gamma_t (device) sum(M), concatenated boundary by boundary;
+ *   U (device) M_0 or NULL: the normal velocity of the state;
+ *   rep_phi / rep (either may be NULL): reports of the velocity-potential
+ *   solve and of the gamma_t stage (right-hand side, assembly, GMRES).
+ * Returns the first error, else the gamma_t solve's warning, else the
+ * velocity-potential solve's. */
+int wwbi_solve_gamma_t(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi, const double *V,
+                       double tau, double grav, const wwbi_opts *o, double *gamma_t, double *U,
+                       wwbi_report *rep_phi, wwbi_report *rep);
+
 /* Adjoint of the velocity-potential solve.  With omega from wwbi_solve_phi on
  * the same inputs and dJdU = dJ/dU (device, M_0), returns the gradient of J
  * with respect to the surface samples (walls held fixed):

@@ -55,7 +55,7 @@ int Ctx::ensure(int n, int restart) {
     G(gv, capg, rr + 1);
     G(yv, capy, rr + 1);
     G(P, capP, 3 * 64 * (rr + 1) + 64);
-    G(part, cappart, 64 * nn + 64);
+    G(part, cappart, 66 * nn + 64);   // up to 64 far slices + the near-band slice
     Gi(bid, capbid, nn);
     Gi(loc, caploc, nn);
     Gi(Mk, capMk, nn);
@@ -146,7 +146,7 @@ int Ctx::setup(const wwbi_geom *g, const double *phi, int nphi) {
     psi_wall = g->psi_wall;
     launch_prep_nodes(L, g->x, g->y, g->dx, g->dy, g->ddx, g->ddy, bid, loc, Mk, wq, s, lre, lim,
                       eR, eI, stream);
-    launch_circ_row1(L.off[1], kOpHalfCot, hrow, stream);
+    launch_circulant_rows(L, kOpHalfCot, hrow, stream);
     launch_validate(L, N, phi, phi ? nphi : 0, val, stream);
     if (hipMemcpyAsync(hst, val, sizeof(double) * (3 * L.nb + 1), hipMemcpyDeviceToHost,
                        stream) != hipSuccess)
@@ -207,13 +207,21 @@ void Ctx::apply(const Op &op, const double *x, const float *x32, const double *c
         launch_reduce_partials(nw, part, rflavour_nsplit(nw), c, 1.0, y, active, stream);
         break;
     }
+    case OP_GT_S64:
+        launch_gemv64((const double *)A, ld, op.n, x, c, y, active, stream);
+        break;
+    case OP_GT_O64:
+        launch_rflavour(L, N, hrow, 8, 0, 0, L.n, 0, L.n, x, part, active, stream);
+        launch_reduce_partials(L.n, part, rflavour_nsplit(L.n), c, 1.0, y, active, stream);
+        break;
     }
 }
 
 double Ctx::op_bytes(const Op &op) const {
     const double n = op.n;
     switch (op.kind) {
-    case OP_A_S64: case OP_AT_S64: case OP_W_S64: return n * n * 8.0 + 2.0 * n * 8.0;
+    case OP_A_S64: case OP_AT_S64: case OP_W_S64: case OP_GT_S64:
+        return n * n * 8.0 + 2.0 * n * 8.0;
     case OP_A_S32: case OP_AT_S32: return n * n * 4.0 + n * 4.0 + n * 8.0;
     default: return 0.0;
     }
@@ -959,6 +967,148 @@ int wwbi_solve_gamma(wwbi_ctx *ctx, const wwbi_geom *g, const double *gamma0, co
     c->finish_report(rep, status, st, c->op_bytes(op));
     if (hipGetLastError() != hipSuccess) return WWBI_EHIP;
     return status;
+}
+
+int wwbi_tangential_energy(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi,
+                           const double *omega, double tau, double grav, double *dphids,
+                           double *energy, wwbi_report *rep) {
+    if (!ctx) return WWBI_EINVAL_NULL;
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    SolveStats st{};
+    int rc = WWBI_OK;
+    if (!omega || (!dphids && !energy) || (energy && !phi)) rc = WWBI_EINVAL_NULL;
+    if (!rc && energy && !(std::isfinite(tau) && std::isfinite(grav))) rc = WWBI_EINVAL_NONFINITE;
+    if (!rc) {
+        c->begin_report(false);
+        rc = c->setup(g, energy ? phi : nullptr, g ? g->M[0] : 0);
+    }
+    if (rc) {
+        if (rep) { std::memset(rep, 0, sizeof(*rep)); rep->status = rc; }
+        return rc;
+    }
+    hipStream_t sm = c->stream;
+    const int n = c->L.n, n0 = c->L.off[1];
+    double *gam = c->vec[VG], *tm = c->vec[VUM], *hg = c->vec[VHG];
+    launch_circulant_rows(c->L, WWBI_OP_D, c->rowD, sm);
+    launch_circulant_rows(c->L, WWBI_OP_H, c->rowH, sm);
+    launch_tmv(c->N, c->F, 0, n, tm, sm);
+    hipEventRecord(c->ev[1], sm);
+    hipEventRecord(c->ev[2], sm);
+    if (dphids) {
+        // s dphi/ds on every boundary from gamma = (-D omega_0, D omega_j)
+        c->gamma_from_omega(omega, gam);
+        if (c->L.nb > 1)
+            launch_circulant_apply(c->L, c->rowH, gam, hg, 1.0, 0.0, 1, c->L.nb - 1, sm);
+        launch_rflavour(c->L, c->N, c->hrow, 5, 0, 0, n, 0, n, gam, c->part, nullptr, sm);
+        launch_tangential_finalize(n, n0, c->s, tm, gam, hg, c->part, rflavour_nsplit(n), dphids,
+                                   sm);
+    }
+    hipEventRecord(c->ev[3], sm);
+    if (energy) {
+        double *hw = c->vec[VTMP], *dphi = c->vec[VTMP2], *e = c->vec[VD];
+        double *means = c->vec[VRR], *E = c->val;
+        launch_circulant_apply(c->L, c->rowH, omega, hw, 1.0, 0.0, 0, 0, sm);
+        launch_circulant_apply(c->L, c->rowD, phi, dphi, 1.0, 0.0, 0, 0, sm);
+        launch_block_means(c->L, omega, means, sm);
+        launch_rflavour(c->L, c->N, c->hrow, 4, 0, 0, n0, 0, n, omega, c->part, nullptr, sm);
+        launch_energy(n0, c->N, c->F, tau, grav, hw, c->part, rflavour_nsplit(n), dphi, tm, means,
+                      e, E, sm);
+        if (hipMemcpyAsync(c->hst, E, sizeof(double), hipMemcpyDeviceToHost, sm) != hipSuccess)
+            return WWBI_EHIP;
+    }
+    hipEventRecord(c->ev[4], sm);
+    c->finish_report(rep, WWBI_OK, st, 0.0);
+    if (energy) std::memcpy(energy, c->hst, sizeof(double));
+    if (hipGetLastError() != hipSuccess) return WWBI_EHIP;
+    return WWBI_OK;
+}
+
+int wwbi_solve_gamma_t(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi, const double *V,
+                       double tau, double grav, const wwbi_opts *o, double *gamma_t, double *U,
+                       wwbi_report *rep_phi, wwbi_report *rep) {
+    if (!ctx) return WWBI_EINVAL_NULL;
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    SolveStats st{};
+    int rc = Ctx::check_opts(o);
+    if (!rc && (!phi || !V || !gamma_t)) rc = WWBI_EINVAL_NULL;
+    if (!rc && !(std::isfinite(tau) && std::isfinite(grav))) rc = WWBI_EINVAL_NONFINITE;
+    if (!rc && (!g || !g->M)) rc = WWBI_EINVAL_NULL;
+    if (!rc && (g->nb < 2 || g->nb > kMaxB)) rc = WWBI_EINVAL_SIZE;
+    long nsum = 0;
+    for (int k = 0; !rc && k < g->nb; ++k) {
+        if (g->M[k] < 8 || (g->M[k] & 1)) rc = WWBI_EINVAL_SIZE;
+        nsum += g->M[k];
+    }
+    if (!rc && nsum > (1L << 28)) rc = WWBI_EINVAL_SIZE;
+    if (!rc) {
+        // size the workspace before the velocity-potential solve: it writes
+        // into workspace vectors, which must not move when the workspace grows
+        c->restart_cap = std::max(c->restart_cap, o->restart);
+        rc = c->ensure((int)nsum, c->restart_cap);
+    }
+    if (rc) {
+        if (rep_phi) { std::memset(rep_phi, 0, sizeof(*rep_phi)); rep_phi->status = rc; }
+        if (rep) { std::memset(rep, 0, sizeof(*rep)); rep->status = rc; }
+        return rc;
+    }
+    // 1. velocity-potential solve at the current state: omega and U
+    wwbi_report r1{};
+    const int s1 = solve_phi_impl(c, g, phi, o, c->vec[VU0], c->vec[VOM], nullptr, &r1);
+    if (rep_phi) *rep_phi = r1;
+    if (s1 < 0) {
+        if (rep) { std::memset(rep, 0, sizeof(*rep)); rep->status = s1; }
+        return s1;
+    }
+    hipStream_t sm = c->stream;
+    const Layout &L = c->L;
+    const int n = L.n, n0 = L.off[1], nw = n - n0;
+    const long ld = round_up(n, 64);
+    double *om = c->vec[VOM], *u0 = c->vec[VU0], *gam = c->vec[VG];
+    double *fV = c->vec[VFV], *fU = c->vec[VFU], *kfv = c->vec[VKF], *gfu = c->vec[VGF];
+    double *hfu = c->vec[VHF], *qg = c->vec[VQG], *tm = c->vec[VTM], *e = c->vec[VE];
+    double *b = c->vec[VB], *x = c->vec[VX];
+    c->begin_report((o->flags & WWBI_FLAG_PROFILE) != 0);
+    // 2. right-hand side (Sec. 4.2)
+    c->gamma_from_omega(om, gam);
+    launch_tmv(c->N, c->F, 0, n0, tm, sm);
+    launch_rflavour(L, c->N, c->hrow, 5, 0, 0, n0, 0, n, gam, c->part, nullptr, sm);
+    launch_reduce_partials(n0, c->part, rflavour_nsplit(n), nullptr, 1.0, qg, nullptr, sm);
+    launch_gt_vectors(n0, V, u0, gam, c->s, fV, fU, sm);
+    launch_circulant_apply(L, c->rowH, fU, hfu, 1.0, 0.0, 0, 0, sm);
+    const int nss = rflavour_nsplit(n0);
+    launch_rflavour(L, c->N, c->hrow, 6, 0, 0, n0, 0, n0, fV, c->part, nullptr, sm);
+    launch_reduce_partials(n0, c->part, nss, nullptr, 1.0, kfv, nullptr, sm);
+    launch_rflavour(L, c->N, c->hrow, 7, 0, 0, n0, 0, n0, fU, c->part, nullptr, sm);
+    launch_reduce_partials(n0, c->part, nss, nullptr, 1.0, gfu, nullptr, sm);
+    launch_gt_surface(n0, c->N, tau, grav, V, u0, gam, tm, qg, 1, hfu, kfv, gfu, e, sm);
+    if (nw > 0) {
+        // wall k: -F_k0 gamma_0 = KS fU - GS fV
+        launch_rflavour(L, c->N, c->hrow, 6, 0, n0, nw, 0, n0, fU, c->part, nullptr, sm);
+        launch_reduce_partials(nw, c->part, nss, nullptr, 1.0, e + n0, nullptr, sm);
+        launch_rflavour(L, c->N, c->hrow, 7, 0, n0, nw, 0, n0, fV, c->part, nullptr, sm);
+        launch_reduce_partials(nw, c->part, nss, e + n0, 1.0, e + n0, nullptr, sm);
+    }
+    launch_circulant_apply(L, c->rowD, e, b, 1.0, 0.0, 0, L.nb - 1, sm);
+    hipEventRecord(c->ev[1], sm);
+    // 3. the gamma_t operator, stored or on the fly, and GMRES in FP64
+    const bool stored = o->matvec != WWBI_MATVEC_ON_THE_FLY;
+    if (stored) {
+        rc = c->ensure_matrix((size_t)n * ld * 8);
+        if (rc) { c->finish_report(rep, rc, st, 0); return rc; }
+        launch_assemble_gt64(L, c->N, (double *)c->A, ld, sm);
+    }
+    hipEventRecord(c->ev[2], sm);
+    Op op{stored ? OP_GT_S64 : OP_GT_O64, n, ld, o->flags, o->band};
+    const int status = c->gmres(op, b, x, true, o->tol, o->restart, o->max_iter, o->poll_every,
+                                false, true, st);
+    hipEventRecord(c->ev[3], sm);
+    if (status < 0) { c->finish_report(rep, status, st, c->op_bytes(op)); return status; }
+    launch_copy(gamma_t, x, n, sm);
+    if (U) launch_copy(U, u0, n0, sm);
+    hipEventRecord(c->ev[4], sm);
+    c->finish_report(rep, status, st, c->op_bytes(op));
+    if (hipGetLastError() != hipSuccess) return WWBI_EHIP;
+    return status != WWBI_OK ? status : s1;
 }
 
 int wwbi_adjoint_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, const double *dJdU,

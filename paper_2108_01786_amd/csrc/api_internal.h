@@ -24,6 +24,8 @@ enum OpKind {
     OP_AT_O32,
     OP_W_S64,       // vortex-sheet wall operator, stored FP64
     OP_W_O64,       // on the fly FP64
+    OP_GT_S64,      // gamma_t operator (Sec. 4.2), stored FP64
+    OP_GT_O64,      // on the fly FP64
 };
 
 struct Op {
@@ -42,7 +44,8 @@ struct SolveStats {
 };
 
 // workspace vectors (each round_up(n, 64) doubles)
-enum VecId { VR = 0, VW, VB, VX, VRR, VD, VG, VHG, VUM, VTMP, VTMP2, VLAM, VMU, VC, kNumVec };
+enum VecId { VR = 0, VW, VB, VX, VRR, VD, VG, VHG, VUM, VTMP, VTMP2, VLAM, VMU, VC,
+             VOM, VU0, VFV, VFU, VKF, VGF, VHF, VQG, VTM, VE, kNumVec };
 
 constexpr int kProfPairs = 2048;
 constexpr int kStateSlotOffset = 8192;   // byte offset of the two polled GState slots in hst

@@ -102,6 +102,18 @@ __device__ __forceinline__ void kappa64(const Nodes &N, const Tgt &t, const Src 
     ci = pr;
 }
 
+// kappa for a pair known to be outside the near band (no near-field branch,
+// so the loops of the on-the-fly products carry no transcendental code).
+__device__ __forceinline__ void kappa64_far(const Tgt &t, const Src &s, double &cr, double &ci) {
+    const double dr = s.ex - t.ex, di = s.ey - t.ey;
+    const double nr = s.ex + t.ex, ni = s.ey + t.ey;
+    const double inv = recip64(dr * dr + di * di);
+    const double pr = (nr * dr + ni * di) * inv;
+    const double pi = (ni * dr - nr * di) * inv;
+    cr = -pi;
+    ci = pr;
+}
+
 // FP32 quotient for far pairs; the sums and differences of E are formed in
 // FP64 first, so the FP32 rounding is not amplified for nearby points.
 __device__ __forceinline__ void kappa32(const Tgt &t, const Src &s, float &cr, float &ci) {
@@ -114,11 +126,18 @@ __device__ __forceinline__ void kappa32(const Tgt &t, const Src &s, float &cr, f
     ci = pr;
 }
 
-// h = (1/2) cot(pi n / M_0), n = (l - m) mod M_0, from a table of the surface grid.
+// h = (1/2) cot(pi n / M), n = (l - m) mod M, from a table of one boundary's grid.
 __device__ __forceinline__ double hrow_lookup(const double *hrow, int l, int m, int M) {
     int n = l - m;
     if (n < 0) n += M;
     return hrow[n];
+}
+
+// h_pq = (1/2) cot((alpha_q - alpha_p)/2) for a same-boundary pair, from the
+// table of every boundary (laid out like the nodes: boundary k's row starts at
+// the node index of its first node).
+__device__ __forceinline__ double h_pair(const double *hall, const Tgt &t, const Src &s) {
+    return hrow_lookup(hall + (t.idx - t.loc), s.loc, t.loc, t.M);
 }
 
 // A(p, q) in FP64 (Sec. 3.3):
@@ -167,6 +186,173 @@ __device__ __forceinline__ double t_val64(const Nodes &N, const Tgt &t, const Sr
     if (t.k == s.k && t.loc == s.loc) return s.w * (t.k == 0 ? t.lre : t.lim);
     double cr, ci;
     kappa64(N, t, s, cr, ci);
+    const double rr = -0.5 * (t.dx * cr - t.dy * ci);
+    const double ri = -0.5 * (t.dx * ci + t.dy * cr);
+    double v;
+    if (s.k == 0) {
+        v = rr;
+        if (t.k == 0) v += hrow_lookup(hrow, s.loc, t.loc, t.M);
+    } else {
+        v = ri;
+    }
+    return s.w * v;
+}
+
+// Stream function on the fluid side of the free surface from the dipole
+// densities (Sec. 5.2 energy; Plemelj limits of the Table 1 integrals):
+//   psi = psi_mv + (1/2) H omega_0 + sum_q P(p, q) omega_q,
+//   P = -w Re(S - h) for a surface source (diagonal -w Re L), w Im S for a
+//   wall source.  Targets are surface nodes only.
+__device__ __forceinline__ double psi_s(const Tgt &t, const Src &s, double cr, double ci,
+                                        const double *hall) {
+    const double sr = 0.5 * (s.dx * cr - s.dy * ci);
+    const double si = 0.5 * (s.dx * ci + s.dy * cr);
+    if (s.k == 0) return -s.w * (sr - h_pair(hall, t, s));
+    return s.w * si;
+}
+__device__ __forceinline__ double psi_val64(const Nodes &N, const Tgt &t, const Src &s,
+                                           const double *hall) {
+    if (t.k == s.k && t.loc == s.loc) return -s.w * t.lre;
+    double cr, ci;
+    kappa64(N, t, s, cr, ci);
+    return psi_s(t, s, cr, ci, hall);
+}
+
+// Tangential derivative on every boundary from gamma (Sec. 5.1, the formula
+// for s dphi/ds_k): the integral terms are sum_q Q(p, q) gamma_q with
+//   Q = w Im R for a surface source (diagonal w Im L),
+//   Q = -w Re(R + [same boundary] h) for a wall source (diagonal -w Re L);
+// the local terms (+gamma_0/2 on the surface, -H gamma_k / 2 on wall k) and
+// the multi-valued part are added separately.
+__device__ __forceinline__ double tan_r(const Tgt &t, const Src &s, double cr, double ci,
+                                        const double *hall) {
+    const double rr = -0.5 * (t.dx * cr - t.dy * ci);
+    const double ri = -0.5 * (t.dx * ci + t.dy * cr);
+    if (s.k == 0) return s.w * ri;
+    const double h = (t.k == s.k) ? h_pair(hall, t, s) : 0.0;
+    return -s.w * (rr + h);
+}
+__device__ __forceinline__ double tan_val64(const Nodes &N, const Tgt &t, const Src &s,
+                                           const double *hall) {
+    if (t.k == s.k && t.loc == s.loc) return s.k == 0 ? s.w * t.lim : -s.w * t.lre;
+    double cr, ci;
+    kappa64(N, t, s, cr, ci);
+    return tan_r(t, s, cr, ci, hall);
+}
+
+// Source-flavour maps of the F operators (Sec. 4.2), sources on the surface:
+//   KS(p, q) = w Im S (diagonal w Im L),  GS(p, q) = w Re(S - [same] h)
+//   (diagonal w Re L); targets anywhere.
+__device__ __forceinline__ double ks_s(const Src &s, double cr, double ci) {
+    return s.w * 0.5 * (s.dx * ci + s.dy * cr);
+}
+__device__ __forceinline__ double gs_s(const Tgt &t, const Src &s, double cr, double ci,
+                                       const double *hall) {
+    const double sr = 0.5 * (s.dx * cr - s.dy * ci);
+    return s.w * (t.k == s.k ? sr - h_pair(hall, t, s) : sr);
+}
+__device__ __forceinline__ double ks_val64(const Nodes &N, const Tgt &t, const Src &s) {
+    if (t.k == s.k && t.loc == s.loc) return s.w * t.lim;
+    double cr, ci;
+    kappa64(N, t, s, cr, ci);
+    return ks_s(s, cr, ci);
+}
+__device__ __forceinline__ double gs_val64(const Nodes &N, const Tgt &t, const Src &s,
+                                          const double *hall) {
+    if (t.k == s.k && t.loc == s.loc) return s.w * t.lre;
+    double cr, ci;
+    kappa64(N, t, s, cr, ci);
+    return gs_s(t, s, cr, ci, hall);
+}
+
+// Operator of the gamma_t system (Sec. 4.2), all blocks in the dagger form:
+//   surface row: I/2 + w Im R (surface source), -w Re R (wall source);
+//   wall row:    w Re R (surface source), -I/2 + w Im R (wall source);
+// diagonals +-1/2 + w Im L.
+__device__ __forceinline__ double gt_r(const Tgt &t, const Src &s, double cr, double ci) {
+    const double rr = -0.5 * (t.dx * cr - t.dy * ci);
+    const double ri = -0.5 * (t.dx * ci + t.dy * cr);
+    if ((t.k == 0) == (s.k == 0)) return s.w * ri;
+    return t.k == 0 ? -s.w * rr : s.w * rr;
+}
+__device__ __forceinline__ double gt_val64(const Nodes &N, const Tgt &t, const Src &s) {
+    if (t.k == s.k && t.loc == s.loc) return (t.k == 0 ? 0.5 : -0.5) + s.w * t.lim;
+    double cr, ci;
+    kappa64(N, t, s, cr, ci);
+    return gt_r(t, s, cr, ci);
+}
+
+// ---------------------------------------------------------------------------
+// split evaluation for the on-the-fly products: the far part skips every
+// same-boundary pair within `nb` grid steps (diagonal included); the near
+// part evaluates exactly those pairs with the full entry functions above.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool in_band(const Tgt &t, const Src &s, int nb) {
+    return t.k == s.k && cyc_dist(t.loc, s.loc, t.M) <= nb;
+}
+
+__device__ __forceinline__ double a_far64(const Tgt &t, const Src &s, bool corr, int nb) {
+    if (in_band(t, s, nb)) return 0.0;
+    const double ecorr = (t.k == s.k && t.k >= 2 && corr) ? s.w : 0.0;
+    double cr, ci;
+    kappa64_far(t, s, cr, ci);
+    const double sr = 0.5 * (s.dx * cr - s.dy * ci);
+    const double si = 0.5 * (s.dx * ci + s.dy * cr);
+    double v = ((t.k == 0) != (s.k == 0)) ? sr : si;
+    if (t.k != 0 && s.k == 0) v = -v;
+    return v * s.w - ecorr;
+}
+
+__device__ __forceinline__ float a_far32(const Tgt &t, const Src &s, bool corr, int nb) {
+    if (in_band(t, s, nb)) return 0.0f;
+    const float ecorr = (t.k == s.k && t.k >= 2 && corr) ? (float)s.w : 0.0f;
+    float cr, ci;
+    kappa32(t, s, cr, ci);
+    const float dx = (float)s.dx, dy = (float)s.dy;
+    const float sr = 0.5f * (dx * cr - dy * ci);
+    const float si = 0.5f * (dx * ci + dy * cr);
+    float v = ((t.k == 0) != (s.k == 0)) ? sr : si;
+    if (t.k != 0 && s.k == 0) v = -v;
+    return v * (float)s.w - ecorr;
+}
+
+__device__ __forceinline__ double psi_far64(const Tgt &t, const Src &s, const double *hall, int nb) {
+    if (in_band(t, s, nb)) return 0.0;
+    double cr, ci;
+    kappa64_far(t, s, cr, ci);
+    return psi_s(t, s, cr, ci, hall);
+}
+
+__device__ __forceinline__ double tan_far64(const Tgt &t, const Src &s, const double *hall, int nb) {
+    if (in_band(t, s, nb)) return 0.0;
+    double cr, ci;
+    kappa64_far(t, s, cr, ci);
+    return tan_r(t, s, cr, ci, hall);
+}
+
+__device__ __forceinline__ double ks_far64(const Tgt &t, const Src &s, int nb) {
+    if (in_band(t, s, nb)) return 0.0;
+    double cr, ci;
+    kappa64_far(t, s, cr, ci);
+    return ks_s(s, cr, ci);
+}
+__device__ __forceinline__ double gs_far64(const Tgt &t, const Src &s, const double *hall, int nb) {
+    if (in_band(t, s, nb)) return 0.0;
+    double cr, ci;
+    kappa64_far(t, s, cr, ci);
+    return gs_s(t, s, cr, ci, hall);
+}
+__device__ __forceinline__ double gt_far64(const Tgt &t, const Src &s, int nb) {
+    if (in_band(t, s, nb)) return 0.0;
+    double cr, ci;
+    kappa64_far(t, s, cr, ci);
+    return gt_r(t, s, cr, ci);
+}
+
+__device__ __forceinline__ double t_far64(const Tgt &t, const Src &s, const double *hrow, int nb) {
+    if (in_band(t, s, nb)) return 0.0;
+    double cr, ci;
+    kappa64_far(t, s, cr, ci);
     const double rr = -0.5 * (t.dx * cr - t.dy * ci);
     const double ri = -0.5 * (t.dx * ci + t.dy * cr);
     double v;

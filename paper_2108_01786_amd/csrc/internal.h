@@ -81,6 +81,25 @@ void launch_rhs_phi(const Layout &L, const Nodes &N, const Flow &F, const double
                     const double *psi_wall, double *b, hipStream_t st);
 void launch_umv(const Nodes &N, const Flow &F, int first, int count, double *out,
                 hipStream_t st);
+void launch_tmv(const Nodes &N, const Flow &F, int first, int count, double *out,
+                hipStream_t st);
+void launch_tangential_finalize(int n, int n0, const double *s, const double *tmv,
+                                const double *gamma, const double *hg, const double *part,
+                                int nsplit, double *out, hipStream_t st);
+// gamma_t right-hand side pieces on the surface: fV = V gamma_0 / s, fU = U gamma_0 / s
+void launch_gt_vectors(int n0, const double *V, const double *U, const double *gamma,
+                       const double *s, double *fV, double *fU, hipStream_t st);
+// surface term e = -W.W/2 + (V - W.t) gamma_0/(2s) - gamma_0^2/(8s^2) + tau theta_a/s - g y - F00
+// with W.t = (tmv + sum of the nsq partials of Q gamma)/s and F00 = -H(fU)/2 + KS fV + GS fU
+void launch_gt_surface(int n0, const Nodes &N, double tau, double grav, const double *V,
+                       const double *U, const double *gamma, const double *tmv,
+                       const double *pq, int nsq, const double *hfu, const double *kfv,
+                       const double *gfu, double *e, hipStream_t st);
+// energy density terms and the fixed-order mean (psi_k: nb-2 obstacle constants)
+void launch_energy(int n0, const Nodes &N, const Flow &F, double tau, double grav,
+                   const double *hw, const double *part, int nsplit, const double *dphi,
+                   const double *tmv, const double *psi_k, double *e, double *E, hipStream_t st);
+// op: WWBI_OP_D, WWBI_OP_H or kOpHalfCot, one row per boundary laid out like the nodes
 void launch_circulant_rows(const Layout &L, int op, double *rows, hipStream_t st);
 void launch_circulant_apply(const Layout &L, const double *rows, const double *f, double *out,
                             double alpha, double beta, int first_block, int last_block,
@@ -103,6 +122,8 @@ void launch_assemble64(const Layout &L, const Nodes &N, int flags, double *A, lo
                        hipStream_t st);
 void launch_assemble32(const Layout &L, const Nodes &N, int flags, int band, float *A, long ld,
                        hipStream_t st);
+// operator of the gamma_t system (Sec. 4.2), n x n FP64
+void launch_assemble_gt64(const Layout &L, const Nodes &N, double *B, long ld, hipStream_t st);
 void launch_assemble_wall64(const Layout &L, const Nodes &N, const double *hrow, double *W, long ld,
                             hipStream_t st);
 // y = c - A x, or y = A x when c is null
@@ -120,7 +141,8 @@ void launch_otf_matvec(const Layout &L, const Nodes &N, int flags, int fp32, int
                        int transpose, const double *x, const double *c, double *y, double *part,
                        const int *active, hipStream_t st);
 // target-flavour products over rows [r0, r0+nr) and columns [c0, c0+nc):
-// mode 2 = T (normal-velocity map / G^dagger), mode 3 = wall operator T - I/2.
+// mode 2 = T (normal-velocity map / G^dagger), mode 3 = wall operator T - I/2,
+// mode 4 = stream-function map P (surface rows), mode 5 = tangential map Q.
 // Forward: part[s][r] over column chunks; transpose: part[s][c] over row chunks.
 void launch_rflavour(const Layout &L, const Nodes &N, const double *hrow, int mode, int transpose,
                      int r0, int nr, int c0, int nc, const double *x, double *part,

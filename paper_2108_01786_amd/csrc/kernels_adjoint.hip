@@ -33,11 +33,62 @@ __device__ __forceinline__ Cx cscale(Cx a, double s) { return {a.re * s, a.im * 
 //   out[0] = sum_q omega_q dA_rq/dx_r        out[1] = ... /dy_r
 //   out[2] = sum_q gamma_q dT_rq/dx_r        out[3] = ... /dy_r
 //   out[4] = sum_q gamma_q dT_rq/ddx_r       out[5] = ... /ddy_r
-__global__ __launch_bounds__(256) void k_adj_rows(Nodes N, const double *hrow, int n0, int n,
-                                                  int chunk,
+__device__ __forceinline__ void row_terms(const Tgt &t, const Src &s, double cr, double ci,
+                                          double wq, double gq, double (&a)[6]) {
+    const Cx kap{cr, ci};
+    const Cx Q{1.0 + cr * cr - ci * ci, 2.0 * cr * ci};
+    // source flavour, target derivative: dS/dz_r = +d_q Q / 4
+    const Cx dS = cscale(cmul({s.dx, s.dy}, Q), 0.25 * s.w * wq);
+    const Cx dSy = ctimes_i(dS);
+    if (s.k == 0) { a[0] += dS.im; a[1] += dSy.im; }   // Im block (surface row, surface col)
+    else { a[0] += dS.re; a[1] += dSy.re; }            // Re block (surface row, wall col)
+    // target flavour: dR/dz_r = -d_r Q / 4, dR/dd_r = -kappa / 2
+    const double gw = s.w * gq;
+    const Cx dR = cscale(cmul({t.dx, t.dy}, Q), -0.25 * gw);
+    const Cx dRy = ctimes_i(dR);
+    const Cx dD = cscale(kap, -0.5 * gw);
+    const Cx dDy = ctimes_i(dD);
+    if (s.k == 0) { a[2] += dR.re; a[3] += dRy.re; a[4] += dD.re; a[5] += dDy.re; }
+    else { a[2] += dR.im; a[3] += dRy.im; a[4] += dD.im; a[5] += dDy.im; }
+}
+
+// Column pass: sources r on the surface, all targets p != r.
+//   out[0..3] = sum_p lambda_p dA_pr/d(x_r, y_r, dx_r, dy_r)
+//   out[4..5] = sum_{p on surface} c_p dT_pr/d(x_r, y_r)
+__device__ __forceinline__ void col_terms(const Tgt &t, const Src &s, double cr, double ci,
+                                          double lp, double cp, double (&a)[6]) {
+    const Cx kap{cr, ci};
+    const Cx Q{1.0 + cr * cr - ci * ci, 2.0 * cr * ci};
+    // source flavour, source derivative: dS/dz_r = -d_r Q / 4, dS/dd_r = kappa / 2
+    const double lw = s.w * lp;
+    const Cx dS = cscale(cmul({s.dx, s.dy}, Q), -0.25 * lw);
+    const Cx dSy = ctimes_i(dS);
+    const Cx dK = cscale(kap, 0.5 * lw);
+    const Cx dKy = ctimes_i(dK);
+    if (t.k == 0) {   // surface row: Im S
+        a[0] += dS.im; a[1] += dSy.im; a[2] += dK.im; a[3] += dKy.im;
+        // target flavour, source derivative: dR/dz_r = d_p Q / 4 (surface source: Re)
+        const Cx dR = cscale(cmul({t.dx, t.dy}, Q), 0.25 * s.w * cp);
+        a[4] += dR.re;
+        a[5] += ctimes_i(dR).re;
+    } else {          // wall row: -Re S
+        a[0] -= dS.re; a[1] -= dSy.re; a[2] -= dK.re; a[3] -= dKy.re;
+    }
+}
+
+__device__ __forceinline__ void store6(double *part, long st, long off, const double (&a)[6]) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) part[k * st + off] = a[k];
+}
+
+// Far part of both passes: every pair except the surface pairs within nb
+// grid steps of r (diagonal included), with kappa from E alone.  Chunk
+// blockIdx.y of the other index, written as slice blockIdx.y of `part`
+// (component stride st).
+__global__ __launch_bounds__(256) void k_adj_rows(Nodes N, int n0, int n, int chunk, int nb,
                                                   const double *__restrict__ omega,
                                                   const double *__restrict__ gamma,
-                                                  double *__restrict__ part) {
+                                                  double *__restrict__ part, long st) {
     __shared__ Src ss[kStage];
     __shared__ double sw[kStage], sg[kStage];
     const int r = blockIdx.x * 256 + threadIdx.x;
@@ -45,7 +96,7 @@ __global__ __launch_bounds__(256) void k_adj_rows(Nodes N, const double *hrow, i
     Tgt t;
     if (live) t = load_tgt(N, r);
     const int qb = blockIdx.y * chunk, qe = min(n, qb + chunk);
-    double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
+    double a[6] = {0, 0, 0, 0, 0, 0};
     for (int qq = qb; qq < qe; qq += kStage) {
         const int q = qq + threadIdx.x;
         if (q < qe) {
@@ -58,42 +109,21 @@ __global__ __launch_bounds__(256) void k_adj_rows(Nodes N, const double *hrow, i
         if (live) {
             for (int i = 0; i < m; ++i) {
                 const Src &s = ss[i];
-                if (s.k == 0 && s.loc == t.loc) continue;
+                if (in_band(t, s, nb)) continue;
                 double cr, ci;
-                kappa64(N, t, s, cr, ci);
-                const Cx kap{cr, ci};
-                const Cx Q{1.0 + cr * cr - ci * ci, 2.0 * cr * ci};
-                // source flavour, target derivative: dS/dz_r = +d_q Q / 4
-                const Cx dS = cscale(cmul({s.dx, s.dy}, Q), 0.25 * s.w * sw[i]);
-                const Cx dSy = ctimes_i(dS);
-                if (s.k == 0) { a0 += dS.im; a1 += dSy.im; }   // Im block (surface row, surface col)
-                else { a0 += dS.re; a1 += dSy.re; }            // Re block (surface row, wall col)
-                // target flavour: dR/dz_r = -d_r Q / 4, dR/dd_r = -kappa / 2
-                const double gw = s.w * sg[i];
-                const Cx dR = cscale(cmul({t.dx, t.dy}, Q), -0.25 * gw);
-                const Cx dRy = ctimes_i(dR);
-                const Cx dD = cscale(kap, -0.5 * gw);
-                const Cx dDy = ctimes_i(dD);
-                if (s.k == 0) { a2 += dR.re; a3 += dRy.re; a4 += dD.re; a5 += dDy.re; }
-                else { a2 += dR.im; a3 += dRy.im; a4 += dD.im; a5 += dDy.im; }
+                kappa64_far(t, s, cr, ci);
+                row_terms(t, s, cr, ci, sw[i], sg[i], a);
             }
         }
         __syncthreads();
     }
-    if (live) {
-        const long st = (long)gridDim.y * n0;
-        double *o = part + (long)blockIdx.y * n0 + r;
-        o[0] = a0; o[st] = a1; o[2 * st] = a2; o[3 * st] = a3; o[4 * st] = a4; o[5 * st] = a5;
-    }
+    if (live) store6(part, st, (long)blockIdx.y * n0 + r, a);
 }
 
-// Column pass: sources r on the surface, all targets p != r.
-//   out[0..3] = sum_p lambda_p dA_pr/d(x_r, y_r, dx_r, dy_r)
-//   out[4..5] = sum_{p on surface} c_p dT_pr/d(x_r, y_r)
-__global__ __launch_bounds__(256) void k_adj_cols(Nodes N, int n0, int n, int chunk,
+__global__ __launch_bounds__(256) void k_adj_cols(Nodes N, int n0, int n, int chunk, int nb,
                                                   const double *__restrict__ lam,
                                                   const double *__restrict__ cvec,
-                                                  double *__restrict__ part) {
+                                                  double *__restrict__ part, long st) {
     __shared__ Tgt ts[kStage];
     __shared__ double sl[kStage], sc[kStage];
     const int r = blockIdx.x * 256 + threadIdx.x;
@@ -101,7 +131,7 @@ __global__ __launch_bounds__(256) void k_adj_cols(Nodes N, int n0, int n, int ch
     Src s;
     if (live) s = load_src(N, r);
     const int pb = blockIdx.y * chunk, pe = min(n, pb + chunk);
-    double a0 = 0, a1 = 0, a2 = 0, a3 = 0, a4 = 0, a5 = 0;
+    double a[6] = {0, 0, 0, 0, 0, 0};
     for (int pp = pb; pp < pe; pp += kStage) {
         const int p = pp + threadIdx.x;
         if (p < pe) {
@@ -114,37 +144,49 @@ __global__ __launch_bounds__(256) void k_adj_cols(Nodes N, int n0, int n, int ch
         if (live) {
             for (int i = 0; i < m; ++i) {
                 const Tgt &t = ts[i];
-                if (t.k == 0 && t.loc == s.loc) continue;
+                if (in_band(t, s, nb)) continue;
                 double cr, ci;
-                kappa64(N, t, s, cr, ci);
-                const Cx kap{cr, ci};
-                const Cx Q{1.0 + cr * cr - ci * ci, 2.0 * cr * ci};
-                // source flavour, source derivative: dS/dz_r = -d_r Q / 4, dS/dd_r = kappa / 2
-                const double lw = s.w * sl[i];
-                const Cx dS = cscale(cmul({s.dx, s.dy}, Q), -0.25 * lw);
-                const Cx dSy = ctimes_i(dS);
-                const Cx dK = cscale(kap, 0.5 * lw);
-                const Cx dKy = ctimes_i(dK);
-                if (t.k == 0) {   // surface row: Im S
-                    a0 += dS.im; a1 += dSy.im; a2 += dK.im; a3 += dKy.im;
-                } else {          // wall row: -Re S
-                    a0 -= dS.re; a1 -= dSy.re; a2 -= dK.re; a3 -= dKy.re;
-                }
-                if (t.k == 0) {
-                    // target flavour, source derivative: dR/dz_r = d_p Q / 4 (surface source: Re)
-                    const Cx dR = cscale(cmul({t.dx, t.dy}, Q), 0.25 * s.w * sc[i]);
-                    a4 += dR.re;
-                    a5 += ctimes_i(dR).re;
-                }
+                kappa64_far(t, s, cr, ci);
+                col_terms(t, s, cr, ci, sl[i], sc[i], a);
             }
         }
         __syncthreads();
     }
-    if (live) {
-        const long st = (long)gridDim.y * n0;
-        double *o = part + (long)blockIdx.y * n0 + r;
-        o[0] = a0; o[st] = a1; o[2 * st] = a2; o[3 * st] = a3; o[4 * st] = a4; o[5 * st] = a5;
+    if (live) store6(part, st, (long)blockIdx.y * n0 + r, a);
+}
+
+// Near part of both passes: the surface partners of r within nb grid steps
+// (the whole surface when it has at most 2 nb + 1 nodes), diagonal excluded,
+// with the exact-difference kappa; written as slice `slice`.
+template <bool COLS>
+__global__ __launch_bounds__(256) void k_adj_near(Nodes N, int n0, int nb,
+                                                  const double *__restrict__ v1,
+                                                  const double *__restrict__ v2,
+                                                  double *__restrict__ part, long st, int slice) {
+    const int r = blockIdx.x * 256 + threadIdx.x;
+    if (r >= n0) return;
+    const bool whole = 2 * nb + 1 >= n0;
+    const int d0 = whole ? -r : -nb, d1 = whole ? n0 - 1 - r : nb;
+    double a[6] = {0, 0, 0, 0, 0, 0};
+    const Tgt tr = load_tgt(N, r);
+    const Src sr = load_src(N, r);
+    for (int d = d0; d <= d1; ++d) {
+        if (d == 0) continue;
+        int l = r + d;
+        if (l < 0) l += n0;
+        if (l >= n0) l -= n0;
+        double cr, ci;
+        if (!COLS) {
+            const Src s = load_src(N, l);
+            kappa64(N, tr, s, cr, ci);
+            row_terms(tr, s, cr, ci, v1[l], v2[l], a);
+        } else {
+            const Tgt t = load_tgt(N, l);
+            kappa64(N, t, sr, cr, ci);
+            col_terms(t, sr, cr, ci, v1[l], v2[l], a);
+        }
     }
+    store6(part, st, (long)slice * n0 + r, a);
 }
 
 // Combine every term on the surface nodes.
@@ -209,7 +251,8 @@ __global__ void k_adj_c(int n0, const double *Ubar, const double *s, double *c) 
 
 }  // namespace
 
-int adjoint_nsplit(int n) { return cdiv(n, otf_chunk(n)); }
+// partial slices per component: far chunks plus the near slice
+int adjoint_nsplit(int n) { return cdiv(n, otf_chunk(n)) + 1; }
 
 void launch_adj_c(int n0, const double *Ubar, const double *s, double *c, hipStream_t st) {
     hipLaunchKernelGGL(k_adj_c, dim3(cdiv(n0, 256)), dim3(256), 0, st, n0, Ubar, s, c);
@@ -217,17 +260,25 @@ void launch_adj_c(int n0, const double *Ubar, const double *s, double *c, hipStr
 
 void launch_adj_rows(const Nodes &N, const double *hrow, int n0, int n, const double *omega,
                      const double *gamma, double *part, hipStream_t st) {
+    (void)hrow;
     const int chunk = otf_chunk(n);
-    dim3 grid(cdiv(n0, 256), cdiv(n, chunk));
-    hipLaunchKernelGGL(k_adj_rows, grid, dim3(256), 0, st, N, hrow, n0, n, chunk, omega, gamma,
-                       part);
+    const int ns = cdiv(n, chunk);
+    const long cs = (long)(ns + 1) * n0;
+    hipLaunchKernelGGL(k_adj_rows, dim3(cdiv(n0, 256), ns), dim3(256), 0, st, N, n0, n, chunk,
+                       kNearBand, omega, gamma, part, cs);
+    hipLaunchKernelGGL((k_adj_near<false>), dim3(cdiv(n0, 256)), dim3(256), 0, st, N, n0,
+                       kNearBand, omega, gamma, part, cs, ns);
 }
 
 void launch_adj_cols(const Nodes &N, int n0, int n, const double *lam, const double *cvec,
                      double *part, hipStream_t st) {
     const int chunk = otf_chunk(n);
-    dim3 grid(cdiv(n0, 256), cdiv(n, chunk));
-    hipLaunchKernelGGL(k_adj_cols, grid, dim3(256), 0, st, N, n0, n, chunk, lam, cvec, part);
+    const int ns = cdiv(n, chunk);
+    const long cs = (long)(ns + 1) * n0;
+    hipLaunchKernelGGL(k_adj_cols, dim3(cdiv(n0, 256), ns), dim3(256), 0, st, N, n0, n, chunk,
+                       kNearBand, lam, cvec, part, cs);
+    hipLaunchKernelGGL((k_adj_near<true>), dim3(cdiv(n0, 256)), dim3(256), 0, st, N, n0,
+                       kNearBand, lam, cvec, part, cs, ns);
 }
 
 void launch_adj_finalize(const Nodes &N, const Flow &F, int n0, const double *Ubar,

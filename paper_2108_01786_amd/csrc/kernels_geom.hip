@@ -136,6 +136,7 @@ __global__ void k_umv(Nodes N, Flow F, int first, int count, double *out) {
 // Circulant rows on each boundary's grid (Sec. 3.4 symbols, Nyquist zeroed):
 //   D: c(n) = (1/2)(-1)^n cot(pi n / M), c(0) = 0
 //   H: c(n) = (2/M) cot(pi n / M) for odd n, 0 for even n
+//   h (the Hilbert regulariser of the kernels): c(n) = (1/2) cot(pi n / M)
 __global__ void k_circ_rows(Layout L, int op, double *rows) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= L.n) return;
@@ -146,7 +147,9 @@ __global__ void k_circ_rows(Layout L, int op, double *rows) {
     if (nn != 0) {
         const double th = (double)nn / (double)M;
         const double ct = cospi(th) / sinpi(th);
-        if (op == WWBI_OP_D)
+        if (op == kOpHalfCot)
+            v = 0.5 * ct;
+        else if (op == WWBI_OP_D)
             v = (nn & 1) ? -0.5 * ct : 0.5 * ct;
         else if (nn & 1)
             v = 2.0 * ct / (double)M;
@@ -256,6 +259,98 @@ __global__ void k_wall_rhs_finalize(int nw, const double *umv_w, const double *p
     rhs[i] = -acc - umv_w[i];
 }
 
+// s dphi_mv/ds = (V1 + sum a_j / 2) x' + sum_j a_j Im{(1/2) cot((z - z_j)/2) z'}
+// on every node (Sec. 5.1, the tangential companion of the normal formula).
+__global__ void k_tmv(Nodes N, Flow F, int first, int count, double *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int p = first + i;
+    const double dx = N.dx[p], dy = N.dy[p];
+    double asum = 0.0;
+    for (int j = 0; j < F.nobs; ++j) asum += F.a[j];
+    double v = (F.V1 + 0.5 * asum) * dx;
+    for (int j = 0; j < F.nobs; ++j) {
+        double cr, ci;
+        cot_half64(N.x[p] - F.zx[j], N.y[p] - F.zy[j], cr, ci);
+        v += F.a[j] * 0.5 * (cr * dy + ci * dx);
+    }
+    out[i] = v;
+}
+
+// dphi/ds = (s dphi_mv/ds + local + sum of the split partials of Q gamma) / s,
+// local = gamma_0 / 2 on the surface and -(H gamma_k)/2 on wall k.
+__global__ void k_tangential_finalize(int n, int n0, const double *s, const double *tmv,
+                                      const double *gamma, const double *hg, const double *part,
+                                      int nsplit, double *out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    double acc = 0.0;
+    for (int k = 0; k < nsplit; ++k) acc += part[(long)k * n + p];
+    const double loc = p < n0 ? 0.5 * gamma[p] : -0.5 * hg[p];
+    out[p] = (tmv[p] + loc + acc) / s[p];
+}
+
+// fV = V gamma_0 / s and fU = U gamma_0 / s on the surface (Sec. 4.2 F operators)
+__global__ void k_gt_vectors(int n0, const double *V, const double *U, const double *gamma,
+                             const double *s, double *fV, double *fU) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n0) return;
+    const double g = gamma[m] / s[m];
+    fV[m] = V[m] * g;
+    fU[m] = U[m] * g;
+}
+
+// The bracket of the gamma_0,t equation (Sec. 4.2) before d/dalpha:
+//   e = -W.W/2 + (V - W.t) gamma_0/(2 s) - gamma_0^2/(8 s^2) + tau theta_a/s - g y - F_00,
+// W.t = (s dphi_mv/ds + sum_q Q gamma)/s (the principal value, without the
+// jump), W.n = U, theta_a = Im(zeta''/zeta') = 2 Im L,
+// F_00 = -H(fU)/2 + KS fV + GS fU.
+__global__ void k_gt_surface(int n0, Nodes N, double tau, double grav, const double *V,
+                             const double *U, const double *gamma, const double *tmv,
+                             const double *pq, int nsq, const double *hfu, const double *kfv,
+                             const double *gfu, double *e) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n0) return;
+    double acc = 0.0;
+    for (int k = 0; k < nsq; ++k) acc += pq[(long)k * n0 + m];
+    const double s = N.s[m], g0 = gamma[m], u = U[m];
+    const double wt = (tmv[m] + acc) / s;
+    const double F00 = -0.5 * hfu[m] + kfv[m] + gfu[m];
+    e[m] = -0.5 * (wt * wt + u * u) + (V[m] - wt) * g0 / (2.0 * s) - g0 * g0 / (8.0 * s * s) +
+           tau * 2.0 * N.lim[m] / s - grav * N.y[m] - F00;
+}
+
+// Per surface node of the energy density (Sec. 5.2, rho = 1):
+//   e = tau s + g y^2 x' / 2 + psi phi_alpha / 2,
+//   psi = psi_mv + (H omega_0)/2 + sum of the split partials of P omega,
+//   phi_alpha = D phi~ + s dphi_mv/ds.
+__global__ void k_energy_terms(int n0, Nodes N, Flow F, double tau, double grav,
+                               const double *hw, const double *part, int nsplit,
+                               const double *dphi, const double *tmv, double *e) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n0) return;
+    double acc = 0.0;
+    for (int k = 0; k < nsplit; ++k) acc += part[(long)k * n0 + m];
+    const double x = N.x[m], y = N.y[m];
+    const double psi = psi_mv(F, x, y) + 0.5 * hw[m] + acc;
+    const double pa = dphi[m] + tmv[m];
+    e[m] = tau * N.s[m] + 0.5 * grav * y * y * N.dx[m] + 0.5 * psi * pa;
+}
+
+// E = mean(e) + sum_{j>=2} a_j psi|_j / 2, one block, fixed summation order.
+__global__ void k_energy_final(int n0, const double *e, Flow F, const double *psi_k,
+                               double *E) {
+    __shared__ double sh[16];
+    double acc = 0.0;
+    for (int m = threadIdx.x; m < n0; m += blockDim.x) acc += e[m];
+    acc = block_sum(acc, sh);
+    if (threadIdx.x == 0) {
+        double v = acc / (double)n0;
+        for (int j = 0; j < F.nobs; ++j) v += 0.5 * F.a[j] * psi_k[j];
+        *E = v;
+    }
+}
+
 __global__ void k_surface_base(int n, const double *xt, const double *yt, double *x, double *y) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= n) return;
@@ -293,6 +388,41 @@ void launch_umv(const Nodes &N, const Flow &F, int first, int count, double *out
                 hipStream_t st) {
     if (count <= 0) return;
     hipLaunchKernelGGL(k_umv, dim3(cdiv(count, 256)), dim3(256), 0, st, N, F, first, count, out);
+}
+
+void launch_tmv(const Nodes &N, const Flow &F, int first, int count, double *out,
+                hipStream_t st) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_tmv, dim3(cdiv(count, 256)), dim3(256), 0, st, N, F, first, count, out);
+}
+
+void launch_tangential_finalize(int n, int n0, const double *s, const double *tmv,
+                                const double *gamma, const double *hg, const double *part,
+                                int nsplit, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_tangential_finalize, dim3(cdiv(n, 256)), dim3(256), 0, st, n, n0, s, tmv,
+                       gamma, hg, part, nsplit, out);
+}
+
+void launch_gt_vectors(int n0, const double *V, const double *U, const double *gamma,
+                       const double *s, double *fV, double *fU, hipStream_t st) {
+    hipLaunchKernelGGL(k_gt_vectors, dim3(cdiv(n0, 256)), dim3(256), 0, st, n0, V, U, gamma, s,
+                       fV, fU);
+}
+
+void launch_gt_surface(int n0, const Nodes &N, double tau, double grav, const double *V,
+                       const double *U, const double *gamma, const double *tmv,
+                       const double *pq, int nsq, const double *hfu, const double *kfv,
+                       const double *gfu, double *e, hipStream_t st) {
+    hipLaunchKernelGGL(k_gt_surface, dim3(cdiv(n0, 256)), dim3(256), 0, st, n0, N, tau, grav, V, U,
+                       gamma, tmv, pq, nsq, hfu, kfv, gfu, e);
+}
+
+void launch_energy(int n0, const Nodes &N, const Flow &F, double tau, double grav,
+                   const double *hw, const double *part, int nsplit, const double *dphi,
+                   const double *tmv, const double *psi_k, double *e, double *E, hipStream_t st) {
+    hipLaunchKernelGGL(k_energy_terms, dim3(cdiv(n0, 256)), dim3(256), 0, st, n0, N, F, tau, grav,
+                       hw, part, nsplit, dphi, tmv, e);
+    hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(1024), 0, st, n0, e, F, psi_k, E);
 }
 
 void launch_circulant_rows(const Layout &L, int op, double *rows, hipStream_t st) {

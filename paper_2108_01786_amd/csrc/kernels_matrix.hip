@@ -16,7 +16,7 @@ constexpr int kRowsPerAsmBlock = 32;
 // assembly: one thread per column (coalesced row writes), a tile of rows per
 // block with the target data staged in LDS (read as broadcasts).
 // ---------------------------------------------------------------------------
-template <bool FP32, bool WALL>
+template <bool FP32, int WALL>
 __global__ __launch_bounds__(256) void k_assemble(Nodes N, const double *hrow, int r0, int nr,
                                                   int c0, int nc, int corr, int band, void *out,
                                                   long ld) {
@@ -35,7 +35,10 @@ __global__ __launch_bounds__(256) void k_assemble(Nodes N, const double *hrow, i
     const int rend = min(kRowsPerAsmBlock, nr - rbase);
     for (int i = 0; i < rend; ++i) {
         const long idx = (long)(rbase + i) * ld + col;
-        if (WALL) {
+        if (WALL == 2) {
+            __builtin_nontemporal_store(live ? gt_val64(N, tg[i], s) : 0.0,
+                                        static_cast<double *>(out) + idx);
+        } else if (WALL) {
             double v = 0.0;
             if (live) {
                 v = t_val64(N, tg[i], s, hrow);
@@ -53,163 +56,100 @@ __global__ __launch_bounds__(256) void k_assemble(Nodes N, const double *hrow, i
 }
 
 // ---------------------------------------------------------------------------
-// stored product y = c - A x (or y = A x): one wave per R rows, 16-byte loads
-// along the row, x converted to the accumulation type, wave-level reduction.
-// ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-// 16-byte vectors of the matrix element type, read with a non-temporal hint:
-// the matrix is streamed once per product, and without the hint the stream
-// reaches only about half the HBM bandwidth (measured on MI355X).
-template <typename TA> struct Vec16;
-template <> struct Vec16<float> {
-    typedef float type __attribute__((ext_vector_type(4)));
-    static constexpr int n = 4;
-};
-template <> struct Vec16<double> {
-    typedef double type __attribute__((ext_vector_type(2)));
-    static constexpr int n = 2;
-};
-
-template <typename TA>
-__device__ __forceinline__ typename Vec16<TA>::type stream_load(const TA *p) {
-    return __builtin_nontemporal_load(reinterpret_cast<const typename Vec16<TA>::type *>(p));
-}
-
-template <typename TACC, typename TX, int VW>
-__device__ __forceinline__ void load_x(const TX *x, int col, TACC (&xv)[VW]) {
-#pragma unroll
-    for (int v = 0; v < VW; ++v) xv[v] = (TACC)x[col + v];
-}
-
-// y = c - A x (or A x): each wave owns R rows and walks them in steps of
-// 64 lanes x 16 bytes, U steps in flight; FP32 matrices accumulate in FP32.
-template <typename TA, typename TX, typename TACC, int R, int U>
-__global__ __launch_bounds__(256) void k_gemv(const TA *__restrict__ A, long ld, int n,
-                                              const TX *__restrict__ x,
-                                              const double *__restrict__ c,
-                                              double *__restrict__ y, const int *active) {
-    if (active && *active == 0) return;
-    using V = typename Vec16<TA>::type;
-    constexpr int VW = Vec16<TA>::n;
-    constexpr int STEP = 64 * VW;
-    const int lane = threadIdx.x & 63;
-    const long wave = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const long r0 = wave * R;
-    if (r0 >= n) return;
-    const TA *rowp[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) rowp[r] = A + (r0 + r < n ? r0 + r : n - 1) * ld;
-    TACC acc[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) acc[r] = (TACC)0;
-    const int nbig = (n / (STEP * U)) * (STEP * U);
-    for (int c0 = 0; c0 < nbig; c0 += STEP * U) {
-        V a[U][R];
-        TACC xv[U][VW];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int col = c0 + u * STEP + lane * VW;
-#pragma unroll
-            for (int r = 0; r < R; ++r) a[u][r] = stream_load(rowp[r] + col);
-            load_x<TACC, TX, VW>(x, col, xv[u]);
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int r = 0; r < R; ++r)
-#pragma unroll
-                for (int v = 0; v < VW; ++v) acc[r] += (TACC)a[u][r][v] * xv[u][v];
-    }
-    const int nstep = (n / STEP) * STEP;
-    for (int c0 = nbig; c0 < nstep; c0 += STEP) {
-        const int col = c0 + lane * VW;
-        TACC xv[VW];
-        load_x<TACC, TX, VW>(x, col, xv);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const V a = stream_load(rowp[r] + col);
-#pragma unroll
-            for (int v = 0; v < VW; ++v) acc[r] += (TACC)a[v] * xv[v];
-        }
-    }
-    for (int col = nstep + lane; col < n; col += 64) {
-        const TACC xv = (TACC)x[col];
-#pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] += (TACC)rowp[r][col] * xv;
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-        const TACC s = wave_sum(acc[r]);
-        if (lane == 0 && r0 + r < n) {
-            const double v = (double)s;
-            y[r0 + r] = c ? c[r0 + r] - v : v;
-        }
-    }
-}
-
-// transpose product, split over row chunks: part[s][q] = sum_{p in chunk s} A[p][q] x[p]
-template <typename TA, typename TACC>
-__global__ __launch_bounds__(256) void k_gemvT(const TA *__restrict__ A, long ld, int n,
-                                               const double *__restrict__ x,
-                                               double *__restrict__ part, int rows_per,
-                                               const int *active) {
-    if (active && *active == 0) return;
-    using V = typename Vec16<TA>::type;
-    constexpr int VW = Vec16<TA>::n;
-    const int col = (blockIdx.x * 256 + threadIdx.x) * VW;
-    const int p0 = blockIdx.y * rows_per;
-    const int p1 = min(n, p0 + rows_per);
-    if (col >= n) return;
-    TACC acc[VW];
-#pragma unroll
-    for (int v = 0; v < VW; ++v) acc[v] = (TACC)0;
-    for (int p = p0; p < p1; ++p) {
-        const TACC xp = (TACC)x[p];
-        const V a = stream_load(A + (long)p * ld + col);
-#pragma unroll
-        for (int v = 0; v < VW; ++v) acc[v] += (TACC)a[v] * xp;
-    }
-    double *out = part + (long)blockIdx.y * n;
-#pragma unroll
-    for (int v = 0; v < VW; ++v)
-        if (col + v < n) out[col + v] = (double)acc[v];
-}
-
-__global__ void k_reduce_partials(int n, const double *__restrict__ part, int nsplit,
-                                  const double *__restrict__ c, double scale,
-                                  double *__restrict__ y, const int *active) {
-    if (active && *active == 0) return;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double s = 0.0;
-    for (int k = 0; k < nsplit; ++k) s += part[(long)k * n + i];
-    s *= scale;
-    y[i] = c ? c[i] - s : s;
-}
-
-// ---------------------------------------------------------------------------
 // on-the-fly products: entries recomputed in registers, never stored.
 // Forward: one thread per target row, a chunk of sources per grid.y staged in
 // LDS.  Transpose: one thread per source column, a chunk of targets staged.
 // Mode selects the entry: 0 = A in FP64, 1 = A in FP32 (with FP64 band),
-// 2 = target-flavour T, 3 = target-flavour wall operator (T - I/2).
+// 2 = target-flavour T, 3 = target-flavour wall operator (T - I/2),
+// 4 = stream-function map P on the surface, 5 = tangential map Q,
+// 6 / 7 = source-flavour maps KS / GS of the F operators, 8 = gamma_t operator.
 // ---------------------------------------------------------------------------
 constexpr int kStage = 256;
 
+// Far part of an entry (zero inside the near band of width nb).
 template <int MODE>
 __device__ __forceinline__ double entry(const Nodes &N, const Tgt &t, const Src &s, bool corr,
-                                        int band, const double *hrow) {
+                                        int nb, const double *hrow) {
+    (void)N;
+    if (MODE == 0) return a_far64(t, s, corr, nb);
+    if (MODE == 1) return (double)a_far32(t, s, corr, nb);
+    if (MODE == 4) return psi_far64(t, s, hrow, nb);
+    if (MODE == 5) return tan_far64(t, s, hrow, nb);
+    if (MODE == 6) return ks_far64(t, s, nb);
+    if (MODE == 7) return gs_far64(t, s, hrow, nb);
+    if (MODE == 8) return gt_far64(t, s, nb);
+    return t_far64(t, s, hrow, nb);
+}
+
+// Full entry (near band pairs), with the FP32 band rule of the stored matrix.
+template <int MODE>
+__device__ __forceinline__ double entry_full(const Nodes &N, const Tgt &t, const Src &s, bool corr,
+                                             int band, const double *hrow) {
     if (MODE == 0) return a_val64(N, t, s, corr);
     if (MODE == 1) return (double)a_val32(N, t, s, corr, band);
+    if (MODE == 4) return psi_val64(N, t, s, hrow);
+    if (MODE == 5) return tan_val64(N, t, s, hrow);
+    if (MODE == 6) return ks_val64(N, t, s);
+    if (MODE == 7) return gs_val64(N, t, s, hrow);
+    if (MODE == 8) return gt_val64(N, t, s);
     double v = t_val64(N, t, s, hrow);
     if (MODE == 3 && t.k == s.k && t.loc == s.loc) v -= 0.5;
     return v;
+}
+
+// Near part: for each output node, the same-boundary partners within nb
+// grid steps, with the exact entry (written as one more partial slice).
+//   rows: out[r] = sum over q near r0+r (q in [c0, c0+nc)) of E(r0+r, q) x[q-c0]
+//   cols: out[c] = sum over p near c0+c (p in [r0, r0+nr)) of E(p, c0+c) x[p-r0]
+// A group of kNearLanes lanes shares one output: lane g takes the partners
+// d0 + g, d0 + g + kNearLanes, ... and the group adds its lanes in a fixed
+// butterfly order.
+constexpr int kNearLanes = 8;
+constexpr int kNearPerBlock = 256 / kNearLanes;
+
+template <int MODE, bool COLS>
+__global__ __launch_bounds__(256) void k_near_band(Nodes N, const double *hrow, int r0, int nr,
+                                                   int c0, int nc, int corr, int band, int nb,
+                                                   const double *__restrict__ x,
+                                                   double *__restrict__ out, const int *active) {
+    if (active && *active == 0) return;
+    const int g = threadIdx.x % kNearLanes;
+    const int i = blockIdx.x * kNearPerBlock + threadIdx.x / kNearLanes;
+    const int nout = COLS ? nc : nr;
+    double acc = 0.0;
+    if (i < nout) {
+        const int me = (COLS ? c0 : r0) + i;
+        const int loc = N.loc[me], M = N.Mk[me];
+        const int base = me - loc;
+        // partners: every node with cyclic distance <= nb, each exactly once
+        // (the whole boundary when it has at most 2 nb + 1 nodes)
+        const bool whole = 2 * nb + 1 >= M;
+        const int d0 = whole ? -loc : -nb, d1 = whole ? M - 1 - loc : nb;
+        if (!COLS) {
+            const Tgt t = load_tgt(N, me);
+            for (int d = d0 + g; d <= d1; d += kNearLanes) {
+                int l = loc + d;
+                if (l < 0) l += M;
+                if (l >= M) l -= M;
+                const int q = base + l;
+                if (q < c0 || q >= c0 + nc) continue;
+                acc += entry_full<MODE>(N, t, load_src(N, q), corr != 0, band, hrow) * x[q - c0];
+            }
+        } else {
+            const Src s = load_src(N, me);
+            for (int d = d0 + g; d <= d1; d += kNearLanes) {
+                int l = loc + d;
+                if (l < 0) l += M;
+                if (l >= M) l -= M;
+                const int p = base + l;
+                if (p < r0 || p >= r0 + nr) continue;
+                acc += entry_full<MODE>(N, load_tgt(N, p), s, corr != 0, band, hrow) * x[p - r0];
+            }
+        }
+    }
+#pragma unroll
+    for (int o = kNearLanes / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (i < nout && g == 0) out[i] = acc;
 }
 
 // Forward product: each thread owns kTPT target rows (rows t, t + 256, ... of
@@ -220,7 +160,7 @@ constexpr int kTPT = 2;
 template <int MODE, bool ACC32>
 __global__ __launch_bounds__(256) void k_otf_rows(Nodes N, const double *hrow, int r0, int nr,
                                                   int c0, int nc,
-                                                  int chunk, int corr, int band,
+                                                  int chunk, int corr, int nb,
                                                   const double *__restrict__ x,
                                                   double *__restrict__ part,
                                                   const int *active) {
@@ -255,9 +195,9 @@ __global__ __launch_bounds__(256) void k_otf_rows(Nodes N, const double *hrow, i
 #pragma unroll
             for (int u = 0; u < kTPT; ++u) {
                 if (ACC32)
-                    acc32[u] += (float)entry<MODE>(N, t[u], s, corr != 0, band, hrow) * (float)xv;
+                    acc32[u] += (float)entry<MODE>(N, t[u], s, corr != 0, nb, hrow) * (float)xv;
                 else
-                    acc[u] += entry<MODE>(N, t[u], s, corr != 0, band, hrow) * xv;
+                    acc[u] += entry<MODE>(N, t[u], s, corr != 0, nb, hrow) * xv;
             }
         }
         __syncthreads();
@@ -272,7 +212,7 @@ __global__ __launch_bounds__(256) void k_otf_rows(Nodes N, const double *hrow, i
 template <int MODE, bool ACC32>
 __global__ __launch_bounds__(256) void k_otf_cols(Nodes N, const double *hrow, int r0, int nr,
                                                   int c0, int nc,
-                                                  int chunk, int corr, int band,
+                                                  int chunk, int corr, int nb,
                                                   const double *__restrict__ x,
                                                   double *__restrict__ part,
                                                   const int *active) {
@@ -298,9 +238,9 @@ __global__ __launch_bounds__(256) void k_otf_cols(Nodes N, const double *hrow, i
         if (live) {
             for (int i = 0; i < m; ++i) {
                 if (ACC32)
-                    acc32 += (float)entry<MODE>(N, ts[i], s, corr != 0, band, hrow) * (float)sx[i];
+                    acc32 += (float)entry<MODE>(N, ts[i], s, corr != 0, nb, hrow) * (float)sx[i];
                 else
-                    acc += entry<MODE>(N, ts[i], s, corr != 0, band, hrow) * sx[i];
+                    acc += entry<MODE>(N, ts[i], s, corr != 0, nb, hrow) * sx[i];
             }
         }
         __syncthreads();
@@ -325,7 +265,7 @@ void launch_assemble64(const Layout &L, const Nodes &N, int flags, double *A, lo
     const int n = L.n;
     dim3 grid(cdiv(ld, 256), cdiv(n, kRowsPerAsmBlock));
     const int corr = (flags & WWBI_FLAG_NO_CORRECTION) ? 0 : 1;
-    hipLaunchKernelGGL((k_assemble<false, false>), grid, dim3(256), 0, st, N, hrow, 0, n, 0, n, corr, 0,
+    hipLaunchKernelGGL((k_assemble<false, 0>), grid, dim3(256), 0, st, N, hrow, 0, n, 0, n, corr, 0,
                        (void *)A, ld);
 }
 
@@ -335,68 +275,26 @@ void launch_assemble32(const Layout &L, const Nodes &N, int flags, int band, flo
     const int n = L.n;
     dim3 grid(cdiv(ld, 256), cdiv(n, kRowsPerAsmBlock));
     const int corr = (flags & WWBI_FLAG_NO_CORRECTION) ? 0 : 1;
-    hipLaunchKernelGGL((k_assemble<true, false>), grid, dim3(256), 0, st, N, hrow, 0, n, 0, n, corr,
+    hipLaunchKernelGGL((k_assemble<true, 0>), grid, dim3(256), 0, st, N, hrow, 0, n, 0, n, corr,
                        band, (void *)A, ld);
+}
+
+void launch_assemble_gt64(const Layout &L, const Nodes &N, double *B, long ld, hipStream_t st) {
+    const int n = L.n;
+    dim3 grid(cdiv(ld, 256), cdiv(n, kRowsPerAsmBlock));
+    hipLaunchKernelGGL((k_assemble<false, 2>), grid, dim3(256), 0, st, N, nullptr, 0, n, 0, n, 1, 0,
+                       (void *)B, ld);
 }
 
 void launch_assemble_wall64(const Layout &L, const Nodes &N, const double *hrow, double *W, long ld,
                             hipStream_t st) {
     const int c0 = L.off[1], nw = L.n - L.off[1];
     dim3 grid(cdiv(ld, 256), cdiv(nw, kRowsPerAsmBlock));
-    hipLaunchKernelGGL((k_assemble<false, true>), grid, dim3(256), 0, st, N, hrow, c0, nw, c0, nw, 1, 0,
+    hipLaunchKernelGGL((k_assemble<false, 1>), grid, dim3(256), 0, st, N, hrow, c0, nw, c0, nw, 1, 0,
                        (void *)W, ld);
 }
 
-static int gemv_blocks(int n, int R) { return cdiv(cdiv(n, R), 4); }
-
-constexpr int kGemvR = 2;   // rows per wave
-constexpr int kGemvU = 4;   // 16-byte steps in flight per row
-
-void launch_gemv64(const double *A, long ld, int n, const double *x, const double *c, double *y,
-                   const int *active, hipStream_t st) {
-    hipLaunchKernelGGL((k_gemv<double, double, double, kGemvR, kGemvU>),
-                       dim3(gemv_blocks(n, kGemvR)), dim3(256), 0, st, A, ld, n, x, c, y, active);
-}
-
-void launch_gemv32(const float *A, long ld, int n, const float *x, const double *c, double *y,
-                   const int *active, hipStream_t st) {
-    hipLaunchKernelGGL((k_gemv<float, float, float, kGemvR, kGemvU>),
-                       dim3(gemv_blocks(n, kGemvR)), dim3(256), 0, st, A, ld, n, x, c, y, active);
-}
-
-void launch_gemv32_x64(const float *A, long ld, int n, const double *x, const double *c,
-                       double *y, const int *active, hipStream_t st) {
-    hipLaunchKernelGGL((k_gemv<float, double, float, kGemvR, kGemvU>),
-                       dim3(gemv_blocks(n, kGemvR)), dim3(256), 0, st, A, ld, n, x, c, y, active);
-}
-
-void launch_reduce_partials(int n, const double *part, int nsplit, const double *c, double scale,
-                            double *y, const int *active, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_partials, dim3(cdiv(n, 256)), dim3(256), 0, st, n, part, nsplit, c,
-                       scale, y, active);
-}
-
-int gemvT_nsplit(int n) { return cdiv(n, 160) > 64 ? 64 : cdiv(n, 160); }
-
-void launch_gemvT64(const double *A, long ld, int n, const double *x, const double *c, double *y,
-                    double *part, const int *active, hipStream_t st) {
-    const int ns = gemvT_nsplit(n);
-    const int rows_per = cdiv(n, ns);
-    dim3 grid(cdiv(n, 256 * 2), ns);
-    hipLaunchKernelGGL((k_gemvT<double, double>), grid, dim3(256), 0, st, A, ld, n, x, part,
-                       rows_per, active);
-    launch_reduce_partials(n, part, ns, c, 1.0, y, active, st);
-}
-
-void launch_gemvT32(const float *A, long ld, int n, const double *x, const double *c, double *y,
-                    double *part, const int *active, hipStream_t st) {
-    const int ns = gemvT_nsplit(n);
-    const int rows_per = cdiv(n, ns);
-    dim3 grid(cdiv(n, 256 * 4), ns);
-    hipLaunchKernelGGL((k_gemvT<float, float>), grid, dim3(256), 0, st, A, ld, n, x, part,
-                       rows_per, active);
-    launch_reduce_partials(n, part, ns, c, 1.0, y, active, st);
-}
+static int near_width(int band) { return band > kNearBand ? band : kNearBand; }
 
 void launch_otf_matvec(const Layout &L, const Nodes &N, int flags, int fp32, int band,
                        int transpose, const double *x, const double *c, double *y, double *part,
@@ -405,51 +303,81 @@ void launch_otf_matvec(const Layout &L, const Nodes &N, int flags, int fp32, int
     const int n = L.n;
     const int chunk = otf_chunk(n);
     const int ns = cdiv(n, chunk);
+    const int nb = near_width(band);
     const int corr = (flags & WWBI_FLAG_NO_CORRECTION) ? 0 : 1;
     dim3 grid(cdiv(n, 256), ns);
     dim3 gridr(cdiv(n, 256 * kTPT), ns);
+    const dim3 gnear(cdiv(n, kNearPerBlock));
+    double *near = part + (long)ns * n;
     if (!transpose) {
-        if (fp32)
+        if (fp32) {
             hipLaunchKernelGGL((k_otf_rows<1, true>), gridr, dim3(256), 0, st, N, hrow, 0, n, 0, n,
-                               chunk, corr, band, x, part, active);
-        else
+                               chunk, corr, nb, x, part, active);
+            hipLaunchKernelGGL((k_near_band<1, false>), gnear, dim3(256), 0, st, N,
+                               hrow, 0, n, 0, n, corr, band, nb, x, near, active);
+        } else {
             hipLaunchKernelGGL((k_otf_rows<0, false>), gridr, dim3(256), 0, st, N, hrow, 0, n, 0, n,
-                               chunk, corr, band, x, part, active);
+                               chunk, corr, nb, x, part, active);
+            hipLaunchKernelGGL((k_near_band<0, false>), gnear, dim3(256), 0, st, N,
+                               hrow, 0, n, 0, n, corr, band, nb, x, near, active);
+        }
     } else {
-        if (fp32)
-            hipLaunchKernelGGL((k_otf_cols<1, true>), grid, dim3(256), 0, st, N, hrow, 0, n, 0, n, chunk,
-                               corr, band, x, part, active);
-        else
+        if (fp32) {
+            hipLaunchKernelGGL((k_otf_cols<1, true>), grid, dim3(256), 0, st, N, hrow, 0, n, 0, n,
+                               chunk, corr, nb, x, part, active);
+            hipLaunchKernelGGL((k_near_band<1, true>), gnear, dim3(256), 0, st, N,
+                               hrow, 0, n, 0, n, corr, band, nb, x, near, active);
+        } else {
             hipLaunchKernelGGL((k_otf_cols<0, false>), grid, dim3(256), 0, st, N, hrow, 0, n, 0, n,
-                               chunk, corr, band, x, part, active);
+                               chunk, corr, nb, x, part, active);
+            hipLaunchKernelGGL((k_near_band<0, true>), gnear, dim3(256), 0, st, N,
+                               hrow, 0, n, 0, n, corr, band, nb, x, near, active);
+        }
     }
-    launch_reduce_partials(n, part, ns, c, 1.0, y, active, st);
+    launch_reduce_partials(n, part, ns + 1, c, 1.0, y, active, st);
 }
 
-int rflavour_nsplit(int nc) { return cdiv(nc, otf_chunk(nc)); }
+// number of partial slices a target-flavour product writes (far chunks + near band)
+int rflavour_nsplit(int nsum) { return cdiv(nsum, otf_chunk(nsum)) + 1; }
+
+template <int MODE>
+static void rflavour_mode(const Nodes &N, const double *hrow, int transpose, int r0, int nr,
+                          int c0, int nc, const double *x, double *part, const int *active,
+                          hipStream_t st) {
+    const int nb = kNearBand;
+    if (!transpose) {
+        const int chunk = otf_chunk(nc);
+        const int ns = cdiv(nc, chunk);
+        dim3 grid(cdiv(nr, 256 * kTPT), ns);
+        hipLaunchKernelGGL((k_otf_rows<MODE, false>), grid, dim3(256), 0, st, N, hrow, r0, nr, c0,
+                           nc, chunk, 1, nb, x, part, active);
+        hipLaunchKernelGGL((k_near_band<MODE, false>), dim3(cdiv(nr, kNearPerBlock)), dim3(256), 0,
+                           st, N, hrow, r0, nr, c0, nc, 1, 0, nb, x, part + (long)ns * nr,
+                           active);
+    } else {
+        const int chunk = otf_chunk(nr);
+        const int ns = cdiv(nr, chunk);
+        dim3 grid(cdiv(nc, 256), ns);
+        hipLaunchKernelGGL((k_otf_cols<MODE, false>), grid, dim3(256), 0, st, N, hrow, r0, nr, c0,
+                           nc, chunk, 1, nb, x, part, active);
+        hipLaunchKernelGGL((k_near_band<MODE, true>), dim3(cdiv(nc, kNearPerBlock)), dim3(256), 0,
+                           st, N, hrow, r0, nr, c0, nc, 1, 0, nb, x, part + (long)ns * nc,
+                           active);
+    }
+}
 
 void launch_rflavour(const Layout &L, const Nodes &N, const double *hrow, int mode, int transpose,
                      int r0, int nr, int c0, int nc, const double *x, double *part,
                      const int *active, hipStream_t st) {
     (void)L;
-    if (!transpose) {
-        const int chunk = otf_chunk(nc);
-        dim3 grid(cdiv(nr, 256 * kTPT), cdiv(nc, chunk));
-        if (mode == 3)
-            hipLaunchKernelGGL((k_otf_rows<3, false>), grid, dim3(256), 0, st, N, hrow, r0, nr, c0, nc,
-                               chunk, 1, 0, x, part, active);
-        else
-            hipLaunchKernelGGL((k_otf_rows<2, false>), grid, dim3(256), 0, st, N, hrow, r0, nr, c0, nc,
-                               chunk, 1, 0, x, part, active);
-    } else {
-        const int chunk = otf_chunk(nr);
-        dim3 grid(cdiv(nc, 256), cdiv(nr, chunk));
-        if (mode == 3)
-            hipLaunchKernelGGL((k_otf_cols<3, false>), grid, dim3(256), 0, st, N, hrow, r0, nr, c0, nc,
-                               chunk, 1, 0, x, part, active);
-        else
-            hipLaunchKernelGGL((k_otf_cols<2, false>), grid, dim3(256), 0, st, N, hrow, r0, nr, c0, nc,
-                               chunk, 1, 0, x, part, active);
+    switch (mode) {
+    case 3: rflavour_mode<3>(N, hrow, transpose, r0, nr, c0, nc, x, part, active, st); break;
+    case 4: rflavour_mode<4>(N, hrow, transpose, r0, nr, c0, nc, x, part, active, st); break;
+    case 5: rflavour_mode<5>(N, hrow, transpose, r0, nr, c0, nc, x, part, active, st); break;
+    case 6: rflavour_mode<6>(N, hrow, transpose, r0, nr, c0, nc, x, part, active, st); break;
+    case 7: rflavour_mode<7>(N, hrow, transpose, r0, nr, c0, nc, x, part, active, st); break;
+    case 8: rflavour_mode<8>(N, hrow, transpose, r0, nr, c0, nc, x, part, active, st); break;
+    default: rflavour_mode<2>(N, hrow, transpose, r0, nr, c0, nc, x, part, active, st); break;
     }
 }
 

@@ -66,6 +66,12 @@ _SIGS = {
                                  C.POINTER(Report)]),
     "wwbi_solve_gamma": (C.c_int, [C.c_void_p, C.POINTER(_Geom), C.c_void_p, C.POINTER(_Opts),
                                    C.c_void_p, C.c_void_p, C.POINTER(Report)]),
+    "wwbi_tangential_energy": (C.c_int, [C.c_void_p, C.POINTER(_Geom), C.c_void_p, C.c_void_p,
+                                         C.c_double, C.c_double, C.c_void_p,
+                                         C.POINTER(C.c_double), C.POINTER(Report)]),
+    "wwbi_solve_gamma_t": (C.c_int, [C.c_void_p, C.POINTER(_Geom), C.c_void_p, C.c_void_p,
+                                     C.c_double, C.c_double, C.POINTER(_Opts), C.c_void_p,
+                                     C.c_void_p, C.POINTER(Report), C.POINTER(Report)]),
     "wwbi_adjoint_phi": (C.c_int, [C.c_void_p, C.POINTER(_Geom), C.c_void_p, C.c_void_p,
                                    C.POINTER(_Opts)] + [C.c_void_p] * 7 + [C.POINTER(Report)]),
     "wwbi_solve_phi_multi": (C.c_int, [C.c_void_p, C.POINTER(_Geom), C.c_void_p, C.c_int32,
@@ -254,6 +260,44 @@ class Context:
         if rc < 0 or (check and rc != OK):
             raise WWBIError(rc, "wwbi_solve_gamma")
         return U, gw, rep
+
+    def tangential_energy(self, geom: DeviceGeometry, omega: torch.Tensor,
+                          phi: Optional[torch.Tensor] = None, tau: float = 0.0, grav: float = 1.0,
+                          want_dphids: bool = True, want_energy: bool = True):
+        """dphi/ds on every node (device, sum(M)) and the energy E (float), from
+        the densities omega of a velocity-potential solve; either may be None."""
+        self._stream()
+        dev = self._dev()
+        omega = _f64(omega, dev)
+        phi = _f64(phi, dev) if phi is not None else None
+        dphids = torch.empty(geom.n, dtype=torch.float64, device=dev) if want_dphids else None
+        E = C.c_double(0.0)
+        rep = Report()
+        g = geom.c_struct()
+        rc = self.lib.wwbi_tangential_energy(self.h, C.byref(g), _ptr(phi), _ptr(omega), tau, grav,
+                                             _ptr(dphids), C.byref(E) if want_energy else None,
+                                             C.byref(rep))
+        if rc != OK:
+            raise WWBIError(rc, "wwbi_tangential_energy")
+        return dphids, (E.value if want_energy else None), rep
+
+    def solve_gamma_t(self, geom: DeviceGeometry, phi: torch.Tensor, V: torch.Tensor,
+                      tau: float = 0.0, grav: float = 1.0, check: bool = True, **kw):
+        """gamma_t (device, sum(M)) of the Sec. 4.2 system at the state (geometry, phi~)
+        with surface tangential velocity V; also U and both reports."""
+        self._stream()
+        dev = self._dev()
+        phi, V = _f64(phi, dev), _f64(V, dev)
+        gt = torch.empty(geom.n, dtype=torch.float64, device=dev)
+        U = torch.empty(geom.M[0], dtype=torch.float64, device=dev)
+        r1, r2 = Report(), Report()
+        g = geom.c_struct()
+        o = make_opts(**kw)
+        rc = self.lib.wwbi_solve_gamma_t(self.h, C.byref(g), _ptr(phi), _ptr(V), tau, grav,
+                                         C.byref(o), _ptr(gt), _ptr(U), C.byref(r1), C.byref(r2))
+        if rc < 0 or (check and rc != OK):
+            raise WWBIError(rc, "wwbi_solve_gamma_t")
+        return gt, U, r1, r2
 
     def adjoint_phi(self, geom: DeviceGeometry, omega: torch.Tensor, dJdU: torch.Tensor,
                     check: bool = True, **kw):
