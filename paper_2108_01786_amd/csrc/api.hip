@@ -320,10 +320,9 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
                 apply(op, vj, x32, nullptr, w, &gs->active);
                 prof_end();
                 launch_cgs_dot(V, ldv, w, n, j, P1, ldp, G, gs, stream);
-                launch_cgs_update(V, ldv, w, n, j, P1, P2, ldp, G, H, restart + 1, 0, gs, stream);
-                launch_cgs_update(V, ldv, w, n, j, P2, P3, ldp, G, H, restart + 1, 1, gs, stream);
-                launch_givens_scale(w, n, j, P3, G, V, ldv, x32, H, restart + 1, cs, sn, gv, jmax,
-                                    gs, stream);
+                launch_cgs_first(V, ldv, w, n, j, P1, P2, P3, G, H, restart + 1, gs, stream);
+                launch_cgs_final(V, ldv, w, n, j, P2, P3, G, x32, H, restart + 1, cs, sn, gv, jmax,
+                                 gs, stream);
             }
             const int cur = (j0 / poll) & 1;
             if (hipMemcpyAsync(slot + cur, gs, sizeof(GState), hipMemcpyDeviceToHost, stream) !=
@@ -632,12 +631,9 @@ int Ctx::gmres_multi(int kind, int n, long ld, const double *B, double *X, int n
                             m.w);
                 prof_end();
                 launch_cgs_dot(m.V, ldv, m.w, n, j, P1, ldp, G, m.gs, stream, bt);
-                launch_cgs_update(m.V, ldv, m.w, n, j, P1, P2, ldp, G, m.H, ldp, 0, m.gs, stream,
-                                  bt);
-                launch_cgs_update(m.V, ldv, m.w, n, j, P2, P3, ldp, G, m.H, ldp, 1, m.gs, stream,
-                                  bt);
-                launch_givens_scale(m.w, n, j, P3, G, m.V, ldv, x32, m.H, ldp, m.cs, m.sn, m.g,
-                                    jmax, m.gs, stream, bt);
+                launch_cgs_first(m.V, ldv, m.w, n, j, P1, P2, P3, G, m.H, ldp, m.gs, stream, bt);
+                launch_cgs_final(m.V, ldv, m.w, n, j, P2, P3, G, x32, m.H, ldp, m.cs, m.sn, m.g,
+                                 jmax, m.gs, stream, bt);
             }
             const int cur = (j0 / poll) & 1;
             GState *dst = reinterpret_cast<GState *>((char *)slot + cur * kStateSlotBytes);

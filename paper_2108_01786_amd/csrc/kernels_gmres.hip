@@ -156,83 +156,88 @@ __global__ __launch_bounds__(kT) void k_cgs_dot(const double *V, long ldv, const
     chunk_dots(V, ldv, w, c0, c1, j, P, G);
 }
 
-// h_i = sum_b Pin[i][b] (every block, same order); w -= sum_i h_i V_i on the
-// block's chunk; then partial dots of the new w (pass 0) or its partial
-// squared norm (pass 1).  Block 0 stores h into (pass 0) or adds it to
-// (pass 1) column j of H.
-__global__ __launch_bounds__(kT) void k_cgs_update(const double *V, long ldv, double *w, int n,
-                                                   int j, const double *Pin, double *Pout,
-                                                   int ldp, int G, double *H, int ldh, int pass,
-                                                   const GState *gs, Bat bt) {
+// First Gram-Schmidt pass: h_i = sum_b P1[i][b] (every block, same order);
+// w' = w - sum_i h_i V_i on the block's chunk; then the partial dots of w'
+// with V (P2) and its partial squared norm (P3).  Block 0 stores h into
+// column j of H.
+__global__ __launch_bounds__(kT) void k_cgs_first(const double *V, long ldv, double *w, int n,
+                                                  int j, const double *P1, double *P2,
+                                                  double *P3, int G, double *H, int ldh,
+                                                  const GState *gs, Bat bt) {
     gs += sys();
     if (gs->active == 0) return;
     V += sys() * bt.v;
     w += sys() * bt.vec;
-    Pin += sys() * bt.p;
-    Pout += sys() * bt.p;
+    P1 += sys() * bt.p;
+    P2 += sys() * bt.p;
+    P3 += sys() * bt.p;
     H += sys() * bt.h;
-    (void)ldp;
     __shared__ double h[WWBI_MAX_RESTART + 1];
     __shared__ double sh[kT / 64];
-    reduce_coeffs(Pin, G, j, h);
+    reduce_coeffs(P1, G, j, h);
     __syncthreads();
-    if (blockIdx.x == 0) {
-        for (int i = threadIdx.x; i <= j; i += kT) {
-            if (pass == 0)
-                H[(long)j * ldh + i] = h[i];
-            else
-                H[(long)j * ldh + i] += h[i];
-        }
-    }
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i <= j; i += kT) H[(long)j * ldh + i] = h[i];
     int c0, c1;
     chunk_of(n, G, blockIdx.x, c0, c1);
+    double nn = 0.0;
     for (int m = c0 + threadIdx.x; m < c1; m += kT) {
         double acc = w[m];
         for (int i = 0; i <= j; ++i) acc -= h[i] * V[(long)i * ldv + m];
         w[m] = acc;
+        nn += acc * acc;
     }
+    nn = block_sum(nn, sh);
+    if (threadIdx.x == 0) P3[blockIdx.x] = nn;
     __syncthreads();
-    if (pass == 0) {
-        chunk_dots(V, ldv, w, c0, c1, j, Pout, G);
-    } else {
-        double a = 0.0;
-        for (int m = c0 + threadIdx.x; m < c1; m += kT) a += w[m] * w[m];
-        a = block_sum(a, sh);
-        if (threadIdx.x == 0) Pout[blockIdx.x] = a;
-    }
+    chunk_dots(V, ldv, w, c0, c1, j, P2, G);
 }
 
-// h_{j+1,j} = ||w||; V_{j+1} = w / ||w||; block 0 applies the previous
-// rotations to column j, forms the new one and updates the residual estimate.
-// The column and the rotations are staged in LDS so that the sequential part
-// touches no global memory.
-__global__ __launch_bounds__(kT) void k_givens_scale(const double *w, int n, int j,
-                                                     const double *P, int G, double *V, long ldv,
-                                                     float *v32, double *H, int ldh, double *cs,
-                                                     double *sn, double *g, int restart_len,
-                                                     GState *gs, Bat bt) {
+// Second (re-orthogonalising) pass fused with the normalisation and the
+// Givens step: h2_i = sum_b P2[i][b]; w'' = w' - sum_i h2_i V_i;
+// ||w''||^2 = ||w'||^2 - ||h2||^2 (the correction is at rounding level, so
+// the difference loses nothing); V_{j+1} = w'' / ||w''|| in FP64 and FP32.
+// Block 0 adds h2 to column j of H, applies the previous rotations, forms the
+// new one and updates the residual estimate, with the column and the
+// rotations staged in LDS.
+__global__ __launch_bounds__(kT) void k_cgs_final(const double *V_, long ldv, const double *w,
+                                                  int n, int j, const double *P2,
+                                                  const double *P3, int G, float *v32,
+                                                  double *H, int ldh, double *cs, double *sn,
+                                                  double *g, int restart_len, GState *gs,
+                                                  Bat bt) {
     gs += sys();
     if (gs->active == 0) return;
+    double *V = const_cast<double *>(V_) + sys() * bt.v;
     w += sys() * bt.vec;
-    P += sys() * bt.p;
-    V += sys() * bt.v;
+    P2 += sys() * bt.p;
+    P3 += sys() * bt.p;
     if (v32) v32 += sys() * bt.v32;
     H += sys() * bt.h;
     cs += sys() * bt.rot;
     sn += sys() * bt.rot;
     g += sys() * bt.rot;
+    __shared__ double h[WWBI_MAX_RESTART + 1];
     __shared__ double snrm;
     __shared__ double col[WWBI_MAX_RESTART + 2], lc[WWBI_MAX_RESTART], ls[WWBI_MAX_RESTART];
-    if (threadIdx.x < 64) {
-        double v = (int)threadIdx.x < G ? P[threadIdx.x] : 0.0;
-        v = wave_sum(v);
-        if (threadIdx.x == 0) snrm = sqrt(v);
-    }
+    reduce_coeffs(P2, G, j, h);
     const bool b0 = blockIdx.x == 0;
+    if (threadIdx.x < 64) {
+        double v = (int)threadIdx.x < G ? P3[threadIdx.x] : 0.0;
+        v = wave_sum(v);
+        if (threadIdx.x == 0) snrm = v;
+    }
     if (b0) {
         const double *hc = H + (long)j * ldh;
         for (int i = threadIdx.x; i <= j; i += kT) col[i] = hc[i];
         for (int i = threadIdx.x; i < j; i += kT) { lc[i] = cs[i]; ls[i] = sn[i]; }
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s2 = 0.0;
+        for (int i = 0; i <= j; ++i) s2 += h[i] * h[i];
+        const double q = snrm - s2;
+        snrm = q > 0.0 ? sqrt(q) : 0.0;
     }
     __syncthreads();
     const double nrm = snrm;
@@ -241,12 +246,15 @@ __global__ __launch_bounds__(kT) void k_givens_scale(const double *w, int n, int
     chunk_of(n, G, blockIdx.x, c0, c1);
     double *vn = V + (long)(j + 1) * ldv;
     for (int m = c0 + threadIdx.x; m < c1; m += kT) {
-        const double v = w[m] * sc;
+        double acc = w[m];
+        for (int i = 0; i <= j; ++i) acc -= h[i] * V[(long)i * ldv + m];
+        const double v = acc * sc;
         vn[m] = v;
         if (v32) v32[m] = (float)v;
     }
     if (!b0) return;
     if (threadIdx.x == 0) {
+        for (int i = 0; i <= j; ++i) col[i] += h[i];
         col[j + 1] = nrm;
         for (int i = 0; i < j; ++i) {
             const double a = col[i], b = col[i + 1];
@@ -355,16 +363,17 @@ void launch_cgs_dot(const double *V, long ldv, const double *w, int n, int j, do
     hipLaunchKernelGGL(k_cgs_dot, dim3(G, bt.nsys), dim3(kT), 0, st, V, ldv, w, n, j, P, ldp, G,
                        gs, bt);
 }
-void launch_cgs_update(const double *V, long ldv, double *w, int n, int j, const double *Pin,
-                       double *Pout, int ldp, int G, double *H, int ldh, int pass,
-                       const GState *gs, hipStream_t st, const Bat &bt) {
-    hipLaunchKernelGGL(k_cgs_update, dim3(G, bt.nsys), dim3(kT), 0, st, V, ldv, w, n, j, Pin,
-                       Pout, ldp, G, H, ldh, pass, gs, bt);
+void launch_cgs_first(const double *V, long ldv, double *w, int n, int j, const double *P1,
+                      double *P2, double *P3, int G, double *H, int ldh, const GState *gs,
+                      hipStream_t st, const Bat &bt) {
+    hipLaunchKernelGGL(k_cgs_first, dim3(G, bt.nsys), dim3(kT), 0, st, V, ldv, w, n, j, P1, P2,
+                       P3, G, H, ldh, gs, bt);
 }
-void launch_givens_scale(const double *w, int n, int j, const double *P, int G, double *V,
-                         long ldv, float *v32, double *H, int ldh, double *cs, double *sn,
-                         double *g, int restart_len, GState *gs, hipStream_t st, const Bat &bt) {
-    hipLaunchKernelGGL(k_givens_scale, dim3(G, bt.nsys), dim3(kT), 0, st, w, n, j, P, G, V, ldv,
+void launch_cgs_final(const double *V, long ldv, const double *w, int n, int j,
+                      const double *P2, const double *P3, int G, float *v32, double *H, int ldh,
+                      double *cs, double *sn, double *g, int restart_len, GState *gs,
+                      hipStream_t st, const Bat &bt) {
+    hipLaunchKernelGGL(k_cgs_final, dim3(G, bt.nsys), dim3(kT), 0, st, V, ldv, w, n, j, P2, P3, G,
                        v32, H, ldh, cs, sn, g, restart_len, gs, bt);
 }
 void launch_hsolve(const double *H, int ldh, const double *g, double *y, const GState *gs,
