@@ -269,10 +269,10 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
     double *r = vec[VR], *w = vec[VW];
     double *P1 = P, *P2 = P + 64 * ldp, *P3 = P + 2 * 64 * ldp;   // P[i*G + b] layout
     float *x32 = fp32_basis ? v32 : nullptr;
-    if (x_zero) launch_fill(x, 0.0, n, stream);
     launch_norm_partial(b, n, P3, G, stream);
     launch_set_tol(P3, G, tol, gs, stream);
     bool first = true;
+    bool x_set = !x_zero;      // a cold start writes x with its first update
     double prev_beta = HUGE_VAL;
     int status = WWBI_NOT_CONVERGED;
     const int its0 = st.iters;
@@ -281,12 +281,14 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
     GState *slot = reinterpret_cast<GState *>((char *)hst + kStateSlotOffset);
     for (;;) {
         cur_cycle = -1;        // the residual product is not an Arnoldi step
-        if (first && x_zero)
-            launch_copy(r, b, n, stream);
-        else
+        const double *r0 = r;
+        if (!x_set) {
+            r0 = b;            // r = b - A 0, whose norm partials are already in P3
+        } else {
             apply(op, x, nullptr, b, r, nullptr);
-        launch_norm_partial(r, n, P3, G, stream);
-        launch_cycle_start(r, n, P3, G, V, x32, gv, restart + 1, gs, stream);
+            launch_norm_partial(r, n, P3, G, stream);
+        }
+        launch_cycle_start(r0, n, P3, G, V, x32, gv, restart + 1, gs, stream);
         int jmax = std::min(restart, max_iter - st.iters);
         if (verify) {
             int rc = read_state(h);
@@ -336,7 +338,8 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
             pending = cur;
         }
         launch_hsolve(H, restart + 1, gv, yv, gs, stream);
-        launch_xupdate(x, V, ldv, n, yv, gs, stream);
+        launch_xupdate(x, V, ldv, n, yv, !x_set, gs, stream);
+        x_set = true;
         st.cycles += 1;
         first = false;
         if (!verify) {
@@ -347,6 +350,7 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
             break;
         }
     }
+    if (!x_set) launch_fill(x, 0.0, n, stream);   // stopped before the first update
     return status;
 }
 
@@ -384,17 +388,22 @@ int Ctx::refine(const Op &op32, const Op &op64, const double *b, double *x, bool
     double *r = vec[VRR], *d = vec[VD];
     double *Pn = P + 2 * 64 * (restart_cap + 1) + 64;   // norm partials (64 doubles)
     const GState *slot2 = reinterpret_cast<const GState *>((char *)hst + kStateSlotOffset) + 2;
-    if (x_zero) launch_fill(x, 0.0, n, stream);
-    const double bn = device_norm(b, n);
-    if (!std::isfinite(bn)) return WWBI_EHIP;
+    // From a cold start the first inner solve takes b itself and writes x;
+    // ||b|| then comes back in that solve's final state, read at the first
+    // synchronisation, so no host round trip precedes it.
+    double bn = -1.0;
+    if (!x_zero) {
+        bn = device_norm(b, n);
+        if (!std::isfinite(bn)) return WWBI_EHIP;
+    }
     double prev = HUGE_VAL;
     int status = WWBI_NOT_CONVERGED;
     bool inner_pending = false;
     for (int k = 0;; ++k) {
         double rn;
-        if (k == 0 && x_zero) {
-            launch_copy(r, b, n, stream);    // r = b - A 0
-            rn = bn;
+        const bool cold = k == 0 && x_zero;
+        if (cold) {
+            rn = -1.0;
         } else {
             apply(op64, x, nullptr, b, r, nullptr);
             launch_norm_partial(r, n, Pn, G, stream);
@@ -411,25 +420,36 @@ int Ctx::refine(const Op &op32, const Op &op64, const double *b, double *x, bool
                 if (last_cycle >= 0 && last_cycle < (int)cyc_done.size())
                     cyc_done[last_cycle] = slot2->its;
                 inner_pending = false;
+                if (bn < 0.0) {
+                    bn = slot2->bnorm;     // the first inner solve's right-hand side was b
+                    prev = bn;
+                }
             }
         }
-        st.rel_resid = bn > 0 ? rn / bn : 0.0;
-        if (trace)
-            std::fprintf(stderr, "wwbi: refine step %d its %d rel_resid %.3e\n", k, st.iters,
-                         st.rel_resid);
-        if (rn <= o.tol * bn) { status = WWBI_OK; break; }
-        if (!std::isfinite(rn) || (k > 0 && rn > 0.5 * prev)) { status = WWBI_REFINE_STALLED; break; }
+        if (!cold) {
+            st.rel_resid = bn > 0 ? rn / bn : 0.0;
+            if (trace)
+                std::fprintf(stderr, "wwbi: refine step %d its %d rel_resid %.3e\n", k,
+                             st.iters, st.rel_resid);
+            if (rn <= o.tol * bn) { status = WWBI_OK; break; }
+            if (!std::isfinite(rn) || (k > 0 && rn > 0.5 * prev)) {
+                status = WWBI_REFINE_STALLED;
+                break;
+            }
+        }
         if (k >= o.max_refine || st.iters >= o.max_iter) { status = WWBI_NOT_CONVERGED; break; }
-        prev = rn;
+        if (!cold) prev = rn;
         SolveStats in{};
-        const double itol = inner_tolerance(o, bn, rn);
-        const int rc = gmres(op32, r, d, true, itol, o.restart, o.max_iter - st.iters,
-                             o.poll_every, op32.kind == OP_A_S32, false, in);
+        // for the cold step rn = ||b||, where the inner tolerance does not depend on ||b||
+        const double itol = cold ? inner_tolerance(o, 1.0, 1.0) : inner_tolerance(o, bn, rn);
+        const int rc = gmres(op32, cold ? b : r, cold ? x : d, true, itol, o.restart,
+                             o.max_iter - st.iters, o.poll_every, op32.kind == OP_A_S32, false,
+                             in);
         if (rc < 0) return rc;
         inner_pending = true;
         st.cycles += in.cycles;
         st.refine_steps += 1;
-        launch_axpy(x, d, n, 1.0, stream);
+        if (!cold) launch_axpy(x, d, n, 1.0, stream);
     }
     return status;
 }
@@ -653,7 +673,7 @@ int Ctx::gmres_multi(int kind, int n, long ld, const double *B, double *X, int n
         }
         if (hipEventSynchronize(pollev[pending]) != hipSuccess) return WWBI_EHIP;
         launch_hsolve(m.H, ldp, m.g, m.y, m.gs, stream, bt);
-        launch_xupdate(X, m.V, ldv, n, m.y, m.gs, stream, bt);
+        launch_xupdate(X, m.V, ldv, n, m.y, false, m.gs, stream, bt);
         rc = read_states(h.data(), nr);
         if (rc) return rc;
         int jd = 0;

@@ -201,8 +201,9 @@ void launch_cgs_final(const double *V, long ldv, const double *w, int n, int j,
                       hipStream_t st, const Bat &bt = kSingle);
 void launch_hsolve(const double *H, int ldh, const double *g, double *y, const GState *gs,
                    hipStream_t st, const Bat &bt = kSingle);
+// x += V y (x = V y when overwrite)
 void launch_xupdate(double *x, const double *V, long ldv, int n, const double *y,
-                    const GState *gs, hipStream_t st, const Bat &bt = kSingle);
+                    bool overwrite, const GState *gs, hipStream_t st, const Bat &bt = kSingle);
 void launch_axpy(double *x, const double *d, int n, double alpha, hipStream_t st);
 void launch_copy(double *dst, const double *src, int n, hipStream_t st);
 void launch_fill(double *dst, double v, int n, hipStream_t st);

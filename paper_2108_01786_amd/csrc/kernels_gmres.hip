@@ -306,9 +306,9 @@ __global__ __launch_bounds__(kT) void k_hsolve(const double *H, int ldh, const d
     }
 }
 
-// x += sum_{i<k} y_i V_i
+// x += sum_{i<k} y_i V_i (x = ... when overwrite is set)
 __global__ void k_xupdate(double *x, const double *V, long ldv, int n, const double *y,
-                          const GState *gs, Bat bt) {
+                          int overwrite, const GState *gs, Bat bt) {
     x += sys() * bt.vec;
     V += sys() * bt.v;
     y += sys() * bt.rot;
@@ -316,7 +316,7 @@ __global__ void k_xupdate(double *x, const double *V, long ldv, int n, const dou
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= n) return;
     const int k = gs->jdone;
-    double acc = x[m];
+    double acc = overwrite ? 0.0 : x[m];
     for (int i = 0; i < k; ++i) acc += y[i] * V[(long)i * ldv + m];
     x[m] = acc;
 }
@@ -381,9 +381,9 @@ void launch_hsolve(const double *H, int ldh, const double *g, double *y, const G
     hipLaunchKernelGGL(k_hsolve, dim3(1, bt.nsys), dim3(kT), 0, st, H, ldh, g, y, gs, bt);
 }
 void launch_xupdate(double *x, const double *V, long ldv, int n, const double *y,
-                    const GState *gs, hipStream_t st, const Bat &bt) {
+                    bool overwrite, const GState *gs, hipStream_t st, const Bat &bt) {
     hipLaunchKernelGGL(k_xupdate, dim3(cdiv(n, 256), bt.nsys), dim3(256), 0, st, x, V, ldv, n, y,
-                       gs, bt);
+                       overwrite ? 1 : 0, gs, bt);
 }
 void launch_axpy(double *x, const double *d, int n, double alpha, hipStream_t st) {
     hipLaunchKernelGGL(k_axpy, dim3(cdiv(n, 256)), dim3(256), 0, st, x, d, n, alpha);

@@ -258,3 +258,38 @@ def test_deterministic(ww, ctx):
     a = ctx.solve_phi(dg, phi, precision=ww.FP32_REFINED)[0].cpu().numpy()
     b = ctx.solve_phi(dg, phi, precision=ww.FP32_REFINED)[0].cpu().numpy()
     assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_zero_right_hand_side(ww, ctx, prec):
+    """b = 0 (flat strip, phi~ = 0, V1 = 0, no obstacles): omega = 0 and U = 0
+    exactly, on both precision paths (the cold start writes x without a fill)."""
+    say(f"case zero rhs {prec}")
+    from manufactured import flat_strip
+    geom = flat_strip(64, 64, 1.0, 0.0)
+    dg = ww.DeviceGeometry.from_synth(geom, DEV)
+    phi = torch.zeros(64, dtype=torch.float64, device=DEV)
+    U, om, _, rep = ctx.solve_phi(dg, phi, tol=1e-13 if prec == "fp64" else 1e-14,
+                                  precision=ww.FP64 if prec == "fp64" else ww.FP32_REFINED)
+    assert rep.status == 0
+    assert float(om.abs().max()) == 0.0 and float(U.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_warm_start(ww, ctx, prec):
+    """x0 = the converged omega: the solve stops at once with the same result;
+    x0 = omega of a nearby state converges in fewer steps to the same answer."""
+    say(f"case warm start {prec}")
+    cfg = make_config(1)
+    dg = ww.DeviceGeometry.from_synth(cfg["geom"], DEV)
+    phi = torch.as_tensor(cfg["phi"], device=DEV)
+    kw = dict(tol=1e-13 if prec == "fp64" else 1e-14,
+              precision=ww.FP64 if prec == "fp64" else ww.FP32_REFINED)
+    U0, om0, _, r0 = ctx.solve_phi(dg, phi, **kw)
+    U1, om1, _, r1 = ctx.solve_phi(dg, phi, x0=om0.clone(), **kw)
+    assert r1.iters == 0 and torch.equal(om1, om0)
+    U2, om2, _, r2 = ctx.solve_phi(dg, phi * 1.001, x0=om0.clone(), **kw)
+    U3, om3, _, r3 = ctx.solve_phi(dg, phi * 1.001, **kw)
+    say(f"  cold iters {r3.iters} warm iters {r2.iters}")
+    assert r2.iters < r3.iters
+    assert float((U2 - U3).abs().max() / U3.abs().max()) <= 1e-11
