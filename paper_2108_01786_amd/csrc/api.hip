@@ -269,6 +269,9 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
     double *r = vec[VR], *w = vec[VW];
     double *P1 = P, *P2 = P + 64 * ldp, *P3 = P + 2 * 64 * ldp;   // P[i*G + b] layout
     float *x32 = fp32_basis ? v32 : nullptr;
+    // the inner solves of the refinement (the only callers without the
+    // true-residual check) orthogonalise once; every other solve twice
+    const bool single_pass = !verify;
     launch_norm_partial(b, n, P3, G, stream);
     launch_set_tol(P3, G, tol, gs, stream);
     bool first = true;
@@ -321,10 +324,15 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
                 prof_begin();
                 apply(op, vj, x32, nullptr, w, &gs->active);
                 prof_end();
-                launch_cgs_dot(V, ldv, w, n, j, P1, ldp, G, gs, stream);
-                launch_cgs_first(V, ldv, w, n, j, P1, P2, P3, G, H, restart + 1, gs, stream);
-                launch_cgs_final(V, ldv, w, n, j, P2, P3, G, x32, H, restart + 1, cs, sn, gv, jmax,
-                                 gs, stream);
+                launch_cgs_dot(V, ldv, w, n, j, P1, P3, G, gs, stream);
+                if (single_pass) {
+                    launch_cgs_final(V, ldv, w, n, j, P1, P3, G, x32, H, restart + 1, false, cs,
+                                     sn, gv, jmax, gs, stream);
+                } else {
+                    launch_cgs_first(V, ldv, w, n, j, P1, P2, P3, G, H, restart + 1, gs, stream);
+                    launch_cgs_final(V, ldv, w, n, j, P2, P3, G, x32, H, restart + 1, true, cs,
+                                     sn, gv, jmax, gs, stream);
+                }
             }
             const int cur = (j0 / poll) & 1;
             if (hipMemcpyAsync(slot + cur, gs, sizeof(GState), hipMemcpyDeviceToHost, stream) !=
@@ -650,10 +658,10 @@ int Ctx::gmres_multi(int kind, int n, long ld, const double *B, double *X, int n
                 apply_multi(kind, n, ld, m.V + (long)j * ldv, x32, x32 ? ldv : bt.v, nr, nullptr,
                             m.w);
                 prof_end();
-                launch_cgs_dot(m.V, ldv, m.w, n, j, P1, ldp, G, m.gs, stream, bt);
+                launch_cgs_dot(m.V, ldv, m.w, n, j, P1, P3, G, m.gs, stream, bt);
                 launch_cgs_first(m.V, ldv, m.w, n, j, P1, P2, P3, G, m.H, ldp, m.gs, stream, bt);
-                launch_cgs_final(m.V, ldv, m.w, n, j, P2, P3, G, x32, m.H, ldp, m.cs, m.sn, m.g,
-                                 jmax, m.gs, stream, bt);
+                launch_cgs_final(m.V, ldv, m.w, n, j, P2, P3, G, x32, m.H, ldp, true, m.cs, m.sn,
+                                 m.g, jmax, m.gs, stream, bt);
             }
             const int cur = (j0 / poll) & 1;
             GState *dst = reinterpret_cast<GState *>((char *)slot + cur * kStateSlotBytes);

@@ -188,16 +188,18 @@ void launch_set_tol(const double *P, int G, double tol, GState *gs, hipStream_t 
                     const Bat &bt = kSingle);
 void launch_cycle_start(const double *r, int n, const double *P, int G, double *V, float *v32,
                         double *g, int ldg, GState *gs, hipStream_t st, const Bat &bt = kSingle);
-void launch_cgs_dot(const double *V, long ldv, const double *w, int n, int j, double *P, int ldp,
-                    int G, const GState *gs, hipStream_t st, const Bat &bt = kSingle);
+// partial dots of w with V_0..V_j into P, partial |w|^2 into P3
+void launch_cgs_dot(const double *V, long ldv, const double *w, int n, int j, double *P,
+                    double *P3, int G, const GState *gs, hipStream_t st, const Bat &bt = kSingle);
 // first Gram-Schmidt pass (w -= V h; dots of V with w into P2, |w|^2 into P3)
 void launch_cgs_first(const double *V, long ldv, double *w, int n, int j, const double *P1,
                       double *P2, double *P3, int G, double *H, int ldh, const GState *gs,
                       hipStream_t st, const Bat &bt = kSingle);
-// second pass fused with normalisation into V_{j+1} and the Givens step
+// last pass fused with normalisation into V_{j+1} and the Givens step
+// (add: column j of H already holds a first pass)
 void launch_cgs_final(const double *V, long ldv, const double *w, int n, int j,
                       const double *P2, const double *P3, int G, float *v32, double *H, int ldh,
-                      double *cs, double *sn, double *g, int restart_len, GState *gs,
+                      bool add, double *cs, double *sn, double *g, int restart_len, GState *gs,
                       hipStream_t st, const Bat &bt = kSingle);
 void launch_hsolve(const double *H, int ldh, const double *g, double *y, const GState *gs,
                    hipStream_t st, const Bat &bt = kSingle);

@@ -142,17 +142,24 @@ __device__ __forceinline__ void reduce_coeffs(const double *P, int G, int j, dou
     }
 }
 
+// Partial dots of w with V_0..V_j (P[i*G + b]) and the partial squared norm
+// of w (P3[b]).
 __global__ __launch_bounds__(kT) void k_cgs_dot(const double *V, long ldv, const double *w,
-                                                int n, int j, double *P, int ldp, int G,
+                                                int n, int j, double *P, double *P3, int G,
                                                 const GState *gs, Bat bt) {
     gs += sys();
     if (gs->active == 0) return;
     V += sys() * bt.v;
     w += sys() * bt.vec;
     P += sys() * bt.p;
-    (void)ldp;
+    P3 += sys() * bt.p;
+    __shared__ double sh[kT / 64];
     int c0, c1;
     chunk_of(n, G, blockIdx.x, c0, c1);
+    double nn = 0.0;
+    for (int m = c0 + threadIdx.x; m < c1; m += kT) nn += w[m] * w[m];
+    nn = block_sum(nn, sh);
+    if (threadIdx.x == 0) P3[blockIdx.x] = nn;
     chunk_dots(V, ldv, w, c0, c1, j, P, G);
 }
 
@@ -193,19 +200,22 @@ __global__ __launch_bounds__(kT) void k_cgs_first(const double *V, long ldv, dou
     chunk_dots(V, ldv, w, c0, c1, j, P2, G);
 }
 
-// Second (re-orthogonalising) pass fused with the normalisation and the
-// Givens step: h2_i = sum_b P2[i][b]; w'' = w' - sum_i h2_i V_i;
-// ||w''||^2 = ||w'||^2 - ||h2||^2 (the correction is at rounding level, so
-// the difference loses nothing); V_{j+1} = w'' / ||w''|| in FP64 and FP32.
-// Block 0 adds h2 to column j of H, applies the previous rotations, forms the
-// new one and updates the residual estimate, with the column and the
-// rotations staged in LDS.
+// Last Gram-Schmidt pass fused with the normalisation and the Givens step:
+// h_i = sum_b P2[i][b]; w'' = w' - sum_i h_i V_i; ||w''||^2 = ||w'||^2 -
+// ||h||^2 with ||w'||^2 from P3; V_{j+1} = w'' / ||w''|| in FP64 and FP32.
+// After a first pass (add = 1) h is the re-orthogonalising correction, at
+// rounding level, so the difference loses nothing; as the only pass (add = 0)
+// the difference is exact to about eps (||w|| / ||w''||)^2, ample for the
+// inner solves of the refinement, whose outer FP64 residual corrects them.
+// Block 0 adds h to (add = 1) or stores it into (add = 0) column j of H,
+// applies the previous rotations, forms the new one and updates the residual
+// estimate, with the column and the rotations staged in LDS.
 __global__ __launch_bounds__(kT) void k_cgs_final(const double *V_, long ldv, const double *w,
                                                   int n, int j, const double *P2,
                                                   const double *P3, int G, float *v32,
-                                                  double *H, int ldh, double *cs, double *sn,
-                                                  double *g, int restart_len, GState *gs,
-                                                  Bat bt) {
+                                                  double *H, int ldh, int add, double *cs,
+                                                  double *sn, double *g, int restart_len,
+                                                  GState *gs, Bat bt) {
     gs += sys();
     if (gs->active == 0) return;
     double *V = const_cast<double *>(V_) + sys() * bt.v;
@@ -229,7 +239,7 @@ __global__ __launch_bounds__(kT) void k_cgs_final(const double *V_, long ldv, co
     }
     if (b0) {
         const double *hc = H + (long)j * ldh;
-        for (int i = threadIdx.x; i <= j; i += kT) col[i] = hc[i];
+        for (int i = threadIdx.x; i <= j; i += kT) col[i] = add ? hc[i] : 0.0;
         for (int i = threadIdx.x; i < j; i += kT) { lc[i] = cs[i]; ls[i] = sn[i]; }
     }
     __syncthreads();
@@ -358,9 +368,9 @@ void launch_cycle_start(const double *r, int n, const double *P, int G, double *
     hipLaunchKernelGGL(k_cycle_start, dim3(G, bt.nsys), dim3(kT), 0, st, r, n, P, G, V, v32, g,
                        ldg, gs, bt);
 }
-void launch_cgs_dot(const double *V, long ldv, const double *w, int n, int j, double *P, int ldp,
-                    int G, const GState *gs, hipStream_t st, const Bat &bt) {
-    hipLaunchKernelGGL(k_cgs_dot, dim3(G, bt.nsys), dim3(kT), 0, st, V, ldv, w, n, j, P, ldp, G,
+void launch_cgs_dot(const double *V, long ldv, const double *w, int n, int j, double *P,
+                    double *P3, int G, const GState *gs, hipStream_t st, const Bat &bt) {
+    hipLaunchKernelGGL(k_cgs_dot, dim3(G, bt.nsys), dim3(kT), 0, st, V, ldv, w, n, j, P, P3, G,
                        gs, bt);
 }
 void launch_cgs_first(const double *V, long ldv, double *w, int n, int j, const double *P1,
@@ -371,10 +381,10 @@ void launch_cgs_first(const double *V, long ldv, double *w, int n, int j, const 
 }
 void launch_cgs_final(const double *V, long ldv, const double *w, int n, int j,
                       const double *P2, const double *P3, int G, float *v32, double *H, int ldh,
-                      double *cs, double *sn, double *g, int restart_len, GState *gs,
+                      bool add, double *cs, double *sn, double *g, int restart_len, GState *gs,
                       hipStream_t st, const Bat &bt) {
     hipLaunchKernelGGL(k_cgs_final, dim3(G, bt.nsys), dim3(kT), 0, st, V, ldv, w, n, j, P2, P3, G,
-                       v32, H, ldh, cs, sn, g, restart_len, gs, bt);
+                       v32, H, ldh, add ? 1 : 0, cs, sn, g, restart_len, gs, bt);
 }
 void launch_hsolve(const double *H, int ldh, const double *g, double *y, const GState *gs,
                    hipStream_t st, const Bat &bt) {
