@@ -55,7 +55,7 @@ int Ctx::ensure(int n, int restart) {
     G(gv, capg, rr + 1);
     G(yv, capy, rr + 1);
     G(P, capP, 3 * 64 * (rr + 1) + 64);
-    G(part, cappart, 66 * nn + 64);   // up to 64 far slices + the near-band slice
+    G(part, cappart, 130 * nn + 64);   // up to 128 far slices + the near-band slice
     Gi(bid, capbid, nn);
     Gi(loc, caploc, nn);
     Gi(Mk, capMk, nn);
@@ -204,7 +204,7 @@ void Ctx::apply(const Op &op, const double *x, const float *x32, const double *c
     case OP_W_O64: {
         const int o1 = L.off[1], nw = L.n - o1;
         launch_rflavour(L, N, hrow, 3, 0, o1, nw, o1, nw, x, part, active, stream);
-        launch_reduce_partials(nw, part, rflavour_nsplit(nw), c, 1.0, y, active, stream);
+        launch_reduce_partials(nw, part, rflavour_nsplit(nw, nw, 0), c, 1.0, y, active, stream);
         break;
     }
     case OP_GT_S64:
@@ -212,7 +212,8 @@ void Ctx::apply(const Op &op, const double *x, const float *x32, const double *c
         break;
     case OP_GT_O64:
         launch_rflavour(L, N, hrow, 8, 0, 0, L.n, 0, L.n, x, part, active, stream);
-        launch_reduce_partials(L.n, part, rflavour_nsplit(L.n), c, 1.0, y, active, stream);
+        launch_reduce_partials(L.n, part, rflavour_nsplit(L.n, L.n, 0), c, 1.0, y, active,
+                               stream);
         break;
     }
 }
@@ -470,7 +471,7 @@ void Ctx::eval_U_from_gamma(const double *gamma, double *U) {
     launch_circulant_apply(L, rowH, gamma, hg, 1.0, 0.0, 0, 0, stream);
     launch_umv(N, F, 0, n0, um, stream);
     launch_rflavour(L, N, hrow, 2, 0, 0, n0, 0, L.n, gamma, part, nullptr, stream);
-    launch_U_finalize(n0, s, um, hg, part, rflavour_nsplit(L.n), U, stream);
+    launch_U_finalize(n0, s, um, hg, part, rflavour_nsplit(n0, L.n, 0), U, stream);
 }
 
 void Ctx::gamma_from_omega(const double *omega, double *gamma) {
@@ -967,7 +968,7 @@ int wwbi_solve_gamma(wwbi_ctx *ctx, const wwbi_geom *g, const double *gamma0, co
     // wall right-hand side: -G_0k^dagger gamma_0 - s dphi_mv/dn on every wall
     launch_umv(c->N, c->F, n0, nw, um, c->stream);
     launch_rflavour(c->L, c->N, c->hrow, 2, 0, n0, nw, 0, n0, gamma0, c->part, nullptr, c->stream);
-    launch_wall_rhs_finalize(nw, um, c->part, rflavour_nsplit(n0), rhs, c->stream);
+    launch_wall_rhs_finalize(nw, um, c->part, rflavour_nsplit(nw, n0, 0), rhs, c->stream);
     hipEventRecord(c->ev[1], c->stream);
     const bool stored = o->matvec != WWBI_MATVEC_ON_THE_FLY;
     if (stored) {
@@ -1024,8 +1025,8 @@ int wwbi_tangential_energy(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi,
         if (c->L.nb > 1)
             launch_circulant_apply(c->L, c->rowH, gam, hg, 1.0, 0.0, 1, c->L.nb - 1, sm);
         launch_rflavour(c->L, c->N, c->hrow, 5, 0, 0, n, 0, n, gam, c->part, nullptr, sm);
-        launch_tangential_finalize(n, n0, c->s, tm, gam, hg, c->part, rflavour_nsplit(n), dphids,
-                                   sm);
+        launch_tangential_finalize(n, n0, c->s, tm, gam, hg, c->part, rflavour_nsplit(n, n, 0),
+                                   dphids, sm);
     }
     hipEventRecord(c->ev[3], sm);
     if (energy) {
@@ -1035,8 +1036,8 @@ int wwbi_tangential_energy(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi,
         launch_circulant_apply(c->L, c->rowD, phi, dphi, 1.0, 0.0, 0, 0, sm);
         launch_block_means(c->L, omega, means, sm);
         launch_rflavour(c->L, c->N, c->hrow, 4, 0, 0, n0, 0, n, omega, c->part, nullptr, sm);
-        launch_energy(n0, c->N, c->F, tau, grav, hw, c->part, rflavour_nsplit(n), dphi, tm, means,
-                      e, E, sm);
+        launch_energy(n0, c->N, c->F, tau, grav, hw, c->part, rflavour_nsplit(n0, n, 0), dphi, tm,
+                      means, e, E, sm);
         if (hipMemcpyAsync(c->hst, E, sizeof(double), hipMemcpyDeviceToHost, sm) != hipSuccess)
             return WWBI_EHIP;
     }
@@ -1096,10 +1097,10 @@ int wwbi_solve_gamma_t(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi, con
     c->gamma_from_omega(om, gam);
     launch_tmv(c->N, c->F, 0, n0, tm, sm);
     launch_rflavour(L, c->N, c->hrow, 5, 0, 0, n0, 0, n, gam, c->part, nullptr, sm);
-    launch_reduce_partials(n0, c->part, rflavour_nsplit(n), nullptr, 1.0, qg, nullptr, sm);
+    launch_reduce_partials(n0, c->part, rflavour_nsplit(n0, n, 0), nullptr, 1.0, qg, nullptr, sm);
     launch_gt_vectors(n0, V, u0, gam, c->s, fV, fU, sm);
     launch_circulant_apply(L, c->rowH, fU, hfu, 1.0, 0.0, 0, 0, sm);
-    const int nss = rflavour_nsplit(n0);
+    const int nss = rflavour_nsplit(n0, n0, 0), nsw = rflavour_nsplit(nw, n0, 0);
     launch_rflavour(L, c->N, c->hrow, 6, 0, 0, n0, 0, n0, fV, c->part, nullptr, sm);
     launch_reduce_partials(n0, c->part, nss, nullptr, 1.0, kfv, nullptr, sm);
     launch_rflavour(L, c->N, c->hrow, 7, 0, 0, n0, 0, n0, fU, c->part, nullptr, sm);
@@ -1108,9 +1109,9 @@ int wwbi_solve_gamma_t(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi, con
     if (nw > 0) {
         // wall k: -F_k0 gamma_0 = KS fU - GS fV
         launch_rflavour(L, c->N, c->hrow, 6, 0, n0, nw, 0, n0, fU, c->part, nullptr, sm);
-        launch_reduce_partials(nw, c->part, nss, nullptr, 1.0, e + n0, nullptr, sm);
+        launch_reduce_partials(nw, c->part, nsw, nullptr, 1.0, e + n0, nullptr, sm);
         launch_rflavour(L, c->N, c->hrow, 7, 0, n0, nw, 0, n0, fV, c->part, nullptr, sm);
-        launch_reduce_partials(nw, c->part, nss, e + n0, 1.0, e + n0, nullptr, sm);
+        launch_reduce_partials(nw, c->part, nsw, e + n0, 1.0, e + n0, nullptr, sm);
     }
     launch_circulant_apply(L, c->rowD, e, b, 1.0, 0.0, 0, L.nb - 1, sm);
     hipEventRecord(c->ev[1], sm);
@@ -1170,7 +1171,7 @@ int wwbi_adjoint_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, con
     // c = Ubar / s;  gammabar = T^T c - H c / 2 (surface block);  mu = Gamma^T gammabar
     launch_adj_c(n0, dJdU, c->s, cv, sm);
     launch_rflavour(c->L, c->N, c->hrow, 2, 1, 0, n0, 0, n, cv, c->part, nullptr, sm);
-    launch_reduce_partials(n, c->part, rflavour_nsplit(n0), nullptr, 1.0, gbar, nullptr, sm);
+    launch_reduce_partials(n, c->part, rflavour_nsplit(n0, n, 1), nullptr, 1.0, gbar, nullptr, sm);
     launch_circulant_apply(c->L, c->rowH, cv, gbar, -0.5, 1.0, 0, 0, sm);
     launch_circulant_apply(c->L, c->rowD, gbar, mu, 1.0, 0.0, 0, 0, sm);
     launch_circulant_apply(c->L, c->rowD, gbar, mu, -1.0, 0.0, 1, c->L.nb - 1, sm);

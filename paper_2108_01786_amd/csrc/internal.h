@@ -41,6 +41,22 @@ struct Nodes {
 };
 
 // Device-resident GMRES cycle state (one per Krylov solve in flight).
+// sum_{k < ns} part[k * stride + i], added in increasing k; eight loads are
+// issued before their additions (the slices are streamed from HBM/L2).
+__device__ __forceinline__ double sum_slices(const double *part, int ns, long stride, long i) {
+    double acc = 0.0;
+    int k = 0;
+    for (; k + 8 <= ns; k += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = part[(long)(k + u) * stride + i];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; k < ns; ++k) acc += part[(long)k * stride + i];
+    return acc;
+}
+
 struct GState {
     int active;        // 1 while the current restart cycle runs
     int jdone;         // Arnoldi steps completed in the current cycle
@@ -147,7 +163,10 @@ void launch_otf_matvec(const Layout &L, const Nodes &N, int flags, int fp32, int
 void launch_rflavour(const Layout &L, const Nodes &N, const double *hrow, int mode, int transpose,
                      int r0, int nr, int c0, int nc, const double *x, double *part,
                      const int *active, hipStream_t st);
-int rflavour_nsplit(int nsum);
+// partial slices (far chunks + the near band) of a product over nr rows and
+// nc columns, forward or transposed; at most 129, each of length nr
+// (forward) or nc (transposed)
+int rflavour_nsplit(int nr, int nc, int transpose);
 void launch_reduce_partials(int n, const double *part, int nsplit, const double *c, double scale,
                             double *y, const int *active, hipStream_t st);
 int otf_chunk(int n);

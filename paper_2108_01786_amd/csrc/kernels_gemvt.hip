@@ -80,8 +80,7 @@ __global__ void k_reduce_partials(int n, const double *__restrict__ part, int ns
     if (active && *active == 0) return;
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double s = 0.0;
-    for (int k = 0; k < nsplit; ++k) s += part[(long)k * n + i];
+    double s = sum_slices(part, nsplit, n, i);
     s *= scale;
     y[i] = c ? c[i] - s : s;
 }
@@ -90,7 +89,7 @@ __global__ void k_reduce_partials(int n, const double *__restrict__ part, int ns
 
 void launch_reduce_partials(int n, const double *part, int nsplit, const double *c, double scale,
                             double *y, const int *active, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_partials, dim3(cdiv(n, 256)), dim3(256), 0, st, n, part, nsplit, c,
+    hipLaunchKernelGGL(k_reduce_partials, dim3(cdiv(n, 64)), dim3(64), 0, st, n, part, nsplit, c,
                        scale, y, active);
 }
 

@@ -244,8 +244,7 @@ __global__ void k_U_finalize(int n0, const double *s, const double *umv, const d
                              const double *part, int nsplit, double *U) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= n0) return;
-    double acc = 0.0;
-    for (int k = 0; k < nsplit; ++k) acc += part[(long)k * n0 + m];
+    const double acc = sum_slices(part, nsplit, n0, m);
     U[m] = (umv[m] + 0.5 * hg[m] + acc) / s[m];
 }
 
@@ -254,8 +253,7 @@ __global__ void k_wall_rhs_finalize(int nw, const double *umv_w, const double *p
                                     double *rhs) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nw) return;
-    double acc = 0.0;
-    for (int k = 0; k < nsplit; ++k) acc += part[(long)k * nw + i];
+    const double acc = sum_slices(part, nsplit, nw, i);
     rhs[i] = -acc - umv_w[i];
 }
 
@@ -284,8 +282,7 @@ __global__ void k_tangential_finalize(int n, int n0, const double *s, const doub
                                       int nsplit, double *out) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
-    double acc = 0.0;
-    for (int k = 0; k < nsplit; ++k) acc += part[(long)k * n + p];
+    const double acc = sum_slices(part, nsplit, n, p);
     const double loc = p < n0 ? 0.5 * gamma[p] : -0.5 * hg[p];
     out[p] = (tmv[p] + loc + acc) / s[p];
 }
@@ -311,8 +308,7 @@ __global__ void k_gt_surface(int n0, Nodes N, double tau, double grav, const dou
                              const double *gfu, double *e) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= n0) return;
-    double acc = 0.0;
-    for (int k = 0; k < nsq; ++k) acc += pq[(long)k * n0 + m];
+    const double acc = sum_slices(pq, nsq, n0, m);
     const double s = N.s[m], g0 = gamma[m], u = U[m];
     const double wt = (tmv[m] + acc) / s;
     const double F00 = -0.5 * hfu[m] + kfv[m] + gfu[m];
@@ -329,8 +325,7 @@ __global__ void k_energy_terms(int n0, Nodes N, Flow F, double tau, double grav,
                                const double *dphi, const double *tmv, double *e) {
     const int m = blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= n0) return;
-    double acc = 0.0;
-    for (int k = 0; k < nsplit; ++k) acc += part[(long)k * n0 + m];
+    const double acc = sum_slices(part, nsplit, n0, m);
     const double x = N.x[m], y = N.y[m];
     const double psi = psi_mv(F, x, y) + 0.5 * hw[m] + acc;
     const double pa = dphi[m] + tmv[m];
@@ -399,7 +394,7 @@ void launch_tmv(const Nodes &N, const Flow &F, int first, int count, double *out
 void launch_tangential_finalize(int n, int n0, const double *s, const double *tmv,
                                 const double *gamma, const double *hg, const double *part,
                                 int nsplit, double *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_tangential_finalize, dim3(cdiv(n, 256)), dim3(256), 0, st, n, n0, s, tmv,
+    hipLaunchKernelGGL(k_tangential_finalize, dim3(cdiv(n, 64)), dim3(64), 0, st, n, n0, s, tmv,
                        gamma, hg, part, nsplit, out);
 }
 
@@ -413,14 +408,14 @@ void launch_gt_surface(int n0, const Nodes &N, double tau, double grav, const do
                        const double *U, const double *gamma, const double *tmv,
                        const double *pq, int nsq, const double *hfu, const double *kfv,
                        const double *gfu, double *e, hipStream_t st) {
-    hipLaunchKernelGGL(k_gt_surface, dim3(cdiv(n0, 256)), dim3(256), 0, st, n0, N, tau, grav, V, U,
+    hipLaunchKernelGGL(k_gt_surface, dim3(cdiv(n0, 64)), dim3(64), 0, st, n0, N, tau, grav, V, U,
                        gamma, tmv, pq, nsq, hfu, kfv, gfu, e);
 }
 
 void launch_energy(int n0, const Nodes &N, const Flow &F, double tau, double grav,
                    const double *hw, const double *part, int nsplit, const double *dphi,
                    const double *tmv, const double *psi_k, double *e, double *E, hipStream_t st) {
-    hipLaunchKernelGGL(k_energy_terms, dim3(cdiv(n0, 256)), dim3(256), 0, st, n0, N, F, tau, grav,
+    hipLaunchKernelGGL(k_energy_terms, dim3(cdiv(n0, 64)), dim3(64), 0, st, n0, N, F, tau, grav,
                        hw, part, nsplit, dphi, tmv, e);
     hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(1024), 0, st, n0, e, F, psi_k, E);
 }
@@ -456,13 +451,13 @@ void launch_block_means(const Layout &L, const double *v, double *out, hipStream
 
 void launch_U_finalize(int n0, const double *s, const double *umv, const double *hg,
                        const double *part, int nsplit, double *U, hipStream_t st) {
-    hipLaunchKernelGGL(k_U_finalize, dim3(cdiv(n0, 256)), dim3(256), 0, st, n0, s, umv, hg, part,
+    hipLaunchKernelGGL(k_U_finalize, dim3(cdiv(n0, 64)), dim3(64), 0, st, n0, s, umv, hg, part,
                        nsplit, U);
 }
 
 void launch_wall_rhs_finalize(int nw, const double *umv_w, const double *part, int nsplit,
                               double *rhs, hipStream_t st) {
-    hipLaunchKernelGGL(k_wall_rhs_finalize, dim3(cdiv(nw, 256)), dim3(256), 0, st, nw, umv_w, part,
+    hipLaunchKernelGGL(k_wall_rhs_finalize, dim3(cdiv(nw, 64)), dim3(64), 0, st, nw, umv_w, part,
                        nsplit, rhs);
 }
 

@@ -65,6 +65,8 @@ __global__ __launch_bounds__(256) void k_assemble(Nodes N, const double *hrow, i
 // 6 / 7 = source-flavour maps KS / GS of the F operators, 8 = gamma_t operator.
 // ---------------------------------------------------------------------------
 constexpr int kStage = 256;
+constexpr int kOtfBlocks = 2048;     // target grid size of an on-the-fly product
+constexpr int kOtfMaxSlices = 128;   // at most this many partial slices (+ the near band)
 
 // Far part of an entry (zero inside the near band of width nb).
 template <int MODE>
@@ -259,6 +261,25 @@ int otf_chunk(int n) {
 }
 int otf_nsplit(int n) { return cdiv(n, otf_chunk(n)); }
 
+// Chunk of the summed index for an on-the-fly product with `nout` outputs
+// (`per_block` of them per block) and `nsum` summed indices: enough chunks
+// for about kOtfBlocks blocks, a multiple of 32 indices, at most
+// kOtfMaxSlices chunks.
+static int split_chunk(int nout, int nsum, int per_block) {
+    const int ob = cdiv(nout, per_block);
+    int ns = cdiv(kOtfBlocks, ob);
+    ns = ns < 1 ? 1 : (ns > kOtfMaxSlices ? kOtfMaxSlices : ns);
+    int c = cdiv(nsum, ns);
+    c = cdiv(c, 32) * 32;
+    return c < 32 ? 32 : c;
+}
+static int rows_chunk(int nr, int nc) { return split_chunk(nr, nc, 256 * kTPT); }
+static int cols_chunk(int nr, int nc) { return split_chunk(nc, nr, 256); }
+
+int rflavour_nsplit(int nr, int nc, int transpose) {
+    return transpose ? cdiv(nr, cols_chunk(nr, nc)) + 1 : cdiv(nc, rows_chunk(nr, nc)) + 1;
+}
+
 void launch_assemble64(const Layout &L, const Nodes &N, int flags, double *A, long ld,
                        hipStream_t st) {
     const double *hrow = nullptr;
@@ -301,7 +322,7 @@ void launch_otf_matvec(const Layout &L, const Nodes &N, int flags, int fp32, int
                        const int *active, hipStream_t st) {
     const double *hrow = nullptr;
     const int n = L.n;
-    const int chunk = otf_chunk(n);
+    const int chunk = transpose ? cols_chunk(n, n) : rows_chunk(n, n);
     const int ns = cdiv(n, chunk);
     const int nb = near_width(band);
     const int corr = (flags & WWBI_FLAG_NO_CORRECTION) ? 0 : 1;
@@ -337,8 +358,6 @@ void launch_otf_matvec(const Layout &L, const Nodes &N, int flags, int fp32, int
     launch_reduce_partials(n, part, ns + 1, c, 1.0, y, active, st);
 }
 
-// number of partial slices a target-flavour product writes (far chunks + near band)
-int rflavour_nsplit(int nsum) { return cdiv(nsum, otf_chunk(nsum)) + 1; }
 
 template <int MODE>
 static void rflavour_mode(const Nodes &N, const double *hrow, int transpose, int r0, int nr,
@@ -346,7 +365,7 @@ static void rflavour_mode(const Nodes &N, const double *hrow, int transpose, int
                           hipStream_t st) {
     const int nb = kNearBand;
     if (!transpose) {
-        const int chunk = otf_chunk(nc);
+        const int chunk = rows_chunk(nr, nc);
         const int ns = cdiv(nc, chunk);
         dim3 grid(cdiv(nr, 256 * kTPT), ns);
         hipLaunchKernelGGL((k_otf_rows<MODE, false>), grid, dim3(256), 0, st, N, hrow, r0, nr, c0,
@@ -355,7 +374,7 @@ static void rflavour_mode(const Nodes &N, const double *hrow, int transpose, int
                            st, N, hrow, r0, nr, c0, nc, 1, 0, nb, x, part + (long)ns * nr,
                            active);
     } else {
-        const int chunk = otf_chunk(nr);
+        const int chunk = cols_chunk(nr, nc);
         const int ns = cdiv(nr, chunk);
         dim3 grid(cdiv(nc, 256), ns);
         hipLaunchKernelGGL((k_otf_cols<MODE, false>), grid, dim3(256), 0, st, N, hrow, r0, nr, c0,
