@@ -16,6 +16,7 @@ with background flow over obstacles and topography" (arXiv 2108.01786):
 * vortex-sheet wall system and U from gamma ................ Sec. 4.1
 * energy E ................................................. Sec. 5.2
 * gamma_t system (time derivative of the sheet strengths) .. Sec. 4.2
+* one Runge-Kutta stage: graph and HLS surfaces, V, filter . Sec. 2, 3.5, 5
 * spectral derivative and Hilbert transform (FFT symbols) .. Sec. 3.4
 
 Conventions the paper leaves open and that are fixed here: the Nyquist
@@ -227,7 +228,8 @@ def rhs(g: OGeom, phi: torch.Tensor) -> torch.Tensor:
 
 def spectral(f: torch.Tensor, op: str) -> torch.Tensor:
     """FFT-symbol operators on a uniform periodic grid: D (ik), D2 (-k^2),
-    H (-i sgn k) and ABSD (|k|).  The Nyquist coefficient is zeroed."""
+    H (-i sgn k), ABSD (|k|), INT (1/(ik), the zero-mean antiderivative) and
+    FILTER (the 36th-order filter).  The Nyquist coefficient is zeroed."""
     M = f.shape[-1]
     k = torch.fft.fftfreq(M, d=1.0 / M).to(F64)
     nyq = (k == -M / 2)
@@ -239,6 +241,12 @@ def spectral(f: torch.Tensor, op: str) -> torch.Tensor:
         sym = -1j * torch.sign(k)
     elif op == "ABSD":
         sym = torch.abs(k) + 0j
+    elif op == "INT":
+        # zero-mean periodic antiderivative: 1/(ik) for k != 0, 0 at k = 0
+        sym = torch.where(k == 0, torch.zeros_like(k), 1.0 / torch.where(k == 0, torch.ones_like(k), k)) / 1j
+    elif op == "FILTER":
+        # the 36th-order filter of Sec. 5: exp(-36 (|k| / kmax)^36), kmax = M/2
+        sym = torch.exp(-36.0 * (torch.abs(k) / (M / 2)) ** 36) + 0j
     else:
         raise ValueError(op)
     sym = torch.where(nyq, torch.zeros_like(sym), sym)
@@ -445,6 +453,104 @@ def surface_velocity_state(g: OGeom, phi: torch.Tensor, V: torch.Tensor, tau: fl
     grad2 = (pa / s0) ** 2 + U ** 2
     phit = pa_t / s0 * V + dn_t * U - 0.5 * grad2 - grav * z.imag + tau * (e / d).imag / s0
     return zt, phit
+
+
+# ---------------------------------------------------------------------------
+# evolution of the free surface: one Runge-Kutta stage (Sec. 2, 3.5, 5)
+# ---------------------------------------------------------------------------
+
+def graph_surface(eta: torch.Tensor):
+    """zeta = alpha + i eta with spectral zeta', zeta'' (Sec. 2.1, xi = alpha)."""
+    M = eta.shape[0]
+    al = 2.0 * math.pi * torch.arange(M, dtype=F64) / M
+    z = al + 1j * eta
+    d = 1.0 + 1j * spectral(eta, "D")
+    e = 1j * spectral(eta, "D2")
+    return z, d, e
+
+
+def hls_reconstruct(Ptheta: torch.Tensor):
+    """The curve from P theta (Sec. 2.2): C, S are the means of cos and sin of
+    P theta, P_0 theta = arg(C - iS), s_alpha = (C^2 + S^2)^(-1/2),
+    zeta' = s_alpha e^{i theta}; xi, eta are zero-mean antiderivatives shifted
+    so that xi(0) = 0 and the mean height <eta> = P_0[eta xi'] = 0."""
+    M = Ptheta.shape[0]
+    al = 2.0 * math.pi * torch.arange(M, dtype=F64) / M
+    C = torch.cos(Ptheta).mean()
+    S = torch.sin(Ptheta).mean()
+    theta = Ptheta + torch.atan2(-S, C)
+    sa = 1.0 / torch.sqrt(C * C + S * S)
+    d = sa * torch.exp(1j * theta)
+    xa = spectral(d.real - 1.0, "INT")
+    ya = spectral(d.imag, "INT")
+    xi = al + xa - xa[0]
+    eta = ya - (ya * d.real).mean()
+    theta_a = spectral(Ptheta, "D")
+    e = 1j * theta_a * d
+    return xi + 1j * eta, d, e, theta, sa
+
+
+def hls_V(theta_a: torch.Tensor, U: torch.Tensor, d: torch.Tensor) -> torch.Tensor:
+    """V = antiderivative of (theta_a U - mean), with V(0) = U(0) eta'(0)/xi'(0)
+    so that xi(0) stays 0 (Sec. 5, the equation for V)."""
+    f = theta_a * U
+    V = spectral(f - f.mean(), "INT")
+    return V - V[0] + U[0] * d[0].imag / d[0].real
+
+
+def stage_rhs(g_walls: OGeom, mode: str, q: torch.Tensor, phi: torch.Tensor, tau: float,
+              grav: float = 1.0):
+    """Time derivatives of the surface variable q and of phi~ at one stage.
+
+    mode "graph": q = eta with xi = alpha; V = eta_alpha U and
+      eta_t = sqrt(1 + eta_alpha^2) U (Sec. 2.1).
+    mode "hls": q = P theta; the curve is reconstructed (Sec. 2.2), V from its
+      equation in Sec. 5 and (P theta)_t = P[(U_alpha + V theta_alpha) / s_alpha].
+    phi~_t follows Sec. 3.5 with C(t) = 0 in both modes."""
+    q = q.to(F64)
+    if mode == "graph":
+        z, d, e = graph_surface(q)
+    else:
+        z, d, e, theta, sa = hls_reconstruct(q)
+    g = g_walls.with_surface(z, d, e)
+    U = solve_phi(g, phi)["U"]
+    if mode == "graph":
+        ea = d.imag
+        V = ea * U
+        qt = torch.sqrt(1.0 + ea * ea) * U
+    else:
+        theta_a = spectral(q, "D")
+        V = hls_V(theta_a, U, d)
+        f = (spectral(U, "D") + V * theta_a) / sa
+        qt = f - f.mean()
+    _, phit = surface_velocity_state(g, phi, V, tau, grav)
+    return qt, phit, {"z": z, "d": d, "e": e, "U": U, "V": V}
+
+
+def rk_step(g_walls: OGeom, mode: str, A, b, h: float, q: torch.Tensor, phi: torch.Tensor,
+            tau: float, grav: float = 1.0, filt: bool = True):
+    """One explicit Runge-Kutta step with tableau (A, b), every stage by
+    stage_rhs; the 36th-order filter (Sec. 5) is applied to q and phi~ at the
+    end of the step when filt is set."""
+    s = len(b)
+    kq, kp = [], []
+    for i in range(s):
+        qi, pi = q.clone(), phi.clone()
+        for j in range(i):
+            if A[i][j] != 0.0:
+                qi = qi + h * A[i][j] * kq[j]
+                pi = pi + h * A[i][j] * kp[j]
+        a1, a2, _ = stage_rhs(g_walls, mode, qi, pi, tau, grav)
+        kq.append(a1)
+        kp.append(a2)
+    qn, pn = q.clone(), phi.clone()
+    for i in range(s):
+        if b[i] != 0.0:
+            qn = qn + h * b[i] * kq[i]
+            pn = pn + h * b[i] * kp[i]
+    if filt:
+        qn, pn = spectral(qn, "FILTER"), spectral(pn, "FILTER")
+    return qn, pn
 
 
 # ---------------------------------------------------------------------------

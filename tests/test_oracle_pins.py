@@ -263,3 +263,103 @@ def test_sampled_rows_equal_full_matrix():
     A = O.assemble_A(g)
     rows = [0, 7, 249, 250, 375, 376, 441, 442, 499]
     assert (O.A_rows(g, rows) - A[rows]).abs().max() == 0.0
+
+
+# ---------------------------------------------------------------------------
+# one Runge-Kutta stage of the free-surface evolution (Sec. 2, 3.5, 5)
+# ---------------------------------------------------------------------------
+
+def _stage_setup():
+    cfg = make_config(1)
+    g = O.OGeom.from_synth(cfg["geom"])
+    M0 = g.M[0]
+    al = 2 * np.pi * torch.arange(M0, dtype=torch.float64) / M0
+    return g, torch.as_tensor(cfg["phi"]), al
+
+
+def test_hls_reconstruction_closes_the_curve():
+    """P theta = 0 gives the flat surface; a general P theta gives a curve with
+    |zeta'| = s_alpha, arg zeta' = theta, zeta' = 1 + D(zeta - alpha), xi(0) = 0
+    and zero mean height (Sec. 2.2)."""
+    _, _, al = _stage_setup()
+    z, d, e, th, sa = O.hls_reconstruct(torch.zeros_like(al))
+    assert float((z - al).abs().max()) < 1e-15 and abs(float(sa) - 1.0) < 1e-15
+    Pt = 0.15 * torch.sin(al) + 0.05 * torch.cos(2 * al) - 0.04 * torch.sin(3 * al)
+    z, d, e, th, sa = O.hls_reconstruct(Pt)
+    assert float((d.abs() - sa).abs().max()) < 1e-14
+    assert float((torch.angle(d) - th).abs().max()) < 1e-14
+    dz = (1.0 + O.spectral(z.real - al, "D")) + 1j * O.spectral(z.imag, "D")
+    assert float((dz - d).abs().max()) < 1e-12
+    assert abs(float(z.real[0])) < 1e-15 and abs(float((z.imag * d.real).mean())) < 1e-15
+    assert abs(complex(d.mean()) - 1.0) < 1e-14
+
+
+@pytest.mark.parametrize("mode", ["graph", "hls"])
+def test_stage_conserves_energy(mode):
+    """Along the stage's time derivatives the energy of Sec. 5.2 is stationary:
+    central differences over +-1e-4 give |dE/dt| below 1e-8, against
+    derivatives of order one (a dropped or mis-signed term of the phi~
+    equation, or a wrong V, moves it by orders of magnitude)."""
+    g, phi, al = _stage_setup()
+    tau = 0.1
+    q = (0.1 * torch.cos(al) + 0.02 * torch.sin(2 * al) if mode == "graph"
+         else 0.15 * torch.sin(al) + 0.05 * torch.cos(2 * al))
+    qt, pt, _ = O.stage_rhs(g, mode, q, phi, tau)
+
+    def E(qq, pp):
+        z, d, e = O.graph_surface(qq) if mode == "graph" else O.hls_reconstruct(qq)[:3]
+        gg = g.with_surface(z, d, e)
+        return O.energy(gg, pp, O.solve_phi(gg, pp)["omega"], tau, 1.0)
+
+    dt = 1e-4
+    dE = (E(q + dt * qt, phi + dt * pt) - E(q - dt * qt, phi - dt * pt)) / (2 * dt)
+    assert float(qt.abs().max()) > 0.1 and float(pt.abs().max()) > 0.1
+    assert abs(dE) < 1e-8, dE
+
+
+def test_hls_kinematics():
+    """The curve reconstructed from P theta +- dt (P theta)_t moves with
+    (V + iU) zeta'/s_alpha (Sec. 2.2 and the HLS appendix): V keeps xi(0) = 0
+    and the mean height fixed."""
+    g, phi, al = _stage_setup()
+    q = 0.15 * torch.sin(al) + 0.05 * torch.cos(2 * al)
+    qt, _, ex = O.stage_rhs(g, "hls", q, phi, 0.1)
+    dt = 1e-4
+    zt = (O.hls_reconstruct(q + dt * qt)[0] - O.hls_reconstruct(q - dt * qt)[0]) / (2 * dt)
+    ref = (ex["V"] + 1j * ex["U"]) * ex["d"] / ex["d"].abs()
+    assert float((zt - ref).abs().max()) < 1e-8
+
+
+def test_rk4_converges_at_fourth_order():
+    """The classical RK4 tableau through rk_step (filter off): halving h
+    divides the error at T = 0.02 by about 16."""
+    g, phi, al = _stage_setup()
+    q0 = 0.1 * torch.cos(al) + 0.02 * torch.sin(2 * al)
+    A = [[0, 0, 0, 0], [0.5, 0, 0, 0], [0, 0.5, 0, 0], [0, 0, 1, 0]]
+    b = [1 / 6, 1 / 3, 1 / 3, 1 / 6]
+
+    def run(h, nsteps):
+        q, p = q0.clone(), phi.clone()
+        for _ in range(nsteps):
+            q, p = O.rk_step(g, "graph", A, b, h, q, p, 0.1, filt=False)
+        return q, p
+
+    qr, pr = run(0.02 / 16, 16)
+    errs = []
+    for k in (2, 4):
+        q, p = run(0.02 / k, k)
+        errs.append(max(float((q - qr).abs().max()), float((p - pr).abs().max())))
+    assert 10.0 < errs[0] / errs[1] < 24.0, errs
+
+
+def test_filter_symbol():
+    """exp(-36 (|k|/kmax)^36): mode kmax/2 is damped by 36 * 2^-36 (5.2e-10),
+    the top mode below Nyquist is cut to exp(-36 ((M/2-1)/(M/2))^36) (Sec. 5)."""
+    M = 64
+    al = 2 * np.pi * torch.arange(M, dtype=torch.float64) / M
+    f = torch.cos(16 * al)
+    want = np.exp(-36.0 * 0.5 ** 36)
+    assert float((O.spectral(f, "FILTER") - want * f).abs().max()) < 1e-13
+    f = torch.cos(31 * al)
+    want = np.exp(-36.0 * (31 / 32) ** 36)
+    assert float((O.spectral(f, "FILTER") - want * f).abs().max()) < 1e-13
