@@ -73,6 +73,10 @@ extern "C" {
 #define WWBI_OP_ABSD              3  /* |d| = H D, symbol |k|                            */
 
 /* matrices exported by wwbi_debug_matrix */
+/* surface representation of an evolution stage (wwbi_stage_rhs, wwbi_rk_step) */
+#define WWBI_SURF_GRAPH           0  /* xi = alpha, state eta (Sec. 2.1)                 */
+#define WWBI_SURF_HLS             1  /* tangent angle, state P theta (Sec. 2.2)          */
+
 #define WWBI_MAT_A                0  /* velocity-potential system (Sec. 3.3)             */
 #define WWBI_MAT_WALL             1  /* vortex-sheet wall system (Sec. 4.1)              */
 
@@ -224,6 +228,43 @@ int wwbi_tangential_energy(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi,
 int wwbi_solve_gamma_t(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi, const double *V,
                        double tau, double grav, const wwbi_opts *o, double *gamma_t, double *U,
                        wwbi_report *rep_phi, wwbi_report *rep);
+
+/* One Runge-Kutta stage of the velocity-potential evolution: the time
+ * derivatives of the surface variable q and of phi~ at the state (q, phi~)
+ * with the walls of g held fixed.
+ *   mode WWBI_SURF_GRAPH: q = eta on xi = alpha (Sec. 2.1); the surface is
+ *     zeta = alpha + i eta with spectral derivatives; V = eta_alpha U and
+ *     q_t = eta_t = sqrt(1 + eta_alpha^2) U.
+ *   mode WWBI_SURF_HLS: q = P theta, the zero-mean tangent angle (Sec. 2.2);
+ *     the curve is reconstructed with C, S = means of cos, sin P theta,
+ *     P_0 theta = arg(C - iS), s_alpha = (C^2 + S^2)^(-1/2), and zero-mean
+ *     antiderivatives shifted to xi(0) = 0 and zero mean height;
+ *     V = antiderivative of theta_alpha U minus its mean with V(0) =
+ *     U(0) eta'(0)/xi'(0) (Sec. 5); q_t = P[(U_alpha + V theta_alpha)/s_alpha].
+ *   In both modes phi~_t = (phi~_alpha/s) V + (dphi~/dn) U - |grad phi|^2/2
+ *     - grav eta + tau theta_alpha/s (Sec. 3.5, C(t) = 0).
+ * g: the first M_0 entries of x, y, dx, dy, ddx, ddy must be writable device
+ *    memory: the surface of the stage is written there (the walls are read).
+ * q, phi (device) M_0: the state.  o: options of the velocity-potential
+ *    solve (precision, tolerance, ...).
+ * Outputs (device, M_0): q_t, phi_t; U and V may be NULL.
+ * rep: the velocity-potential solve's report. */
+int wwbi_stage_rhs(wwbi_ctx *ctx, const wwbi_geom *g, int32_t mode, const double *q,
+                   const double *phi, double tau, double grav, const wwbi_opts *o, double *q_t,
+                   double *phi_t, double *U, double *V, wwbi_report *rep);
+
+/* One explicit Runge-Kutta step of the same evolution with the tableau
+ * A (host, nstage x nstage row-major; entries on and above the diagonal are
+ * ignored) and weights b (host, nstage), 1 <= nstage <= 16:
+ *   stage i: (q_i, phi_i) = (q, phi) + h sum_{j<i} A_ij k_j, k_i = stage_rhs(q_i, phi_i);
+ *   then (q, phi) += h sum_i b_i k_i, followed (filter != 0) by the 36th-order
+ *   filter exp(-36 (|k| / (M_0/2))^36) on both (Sec. 5).
+ * q, phi (device, M_0) are updated in place; g as for wwbi_stage_rhs.
+ * rep: iterations summed over the stages, ms_solve = their solve time,
+ * ms_total = wall time of the step. */
+int wwbi_rk_step(wwbi_ctx *ctx, const wwbi_geom *g, int32_t mode, int32_t nstage,
+                 const double *A, const double *b, double h, double *q, double *phi, double tau,
+                 double grav, int32_t filter, const wwbi_opts *o, wwbi_report *rep);
 
 /* Adjoint of the velocity-potential solve.  With omega from wwbi_solve_phi on
  * the same inputs and dJdU = dJ/dU (device, M_0), returns the gradient of J

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -94,6 +95,7 @@ void Ctx::release() {
     for (int i = 0; i < kNumVec; ++i) F(vec[i]);
     F(H); F(cs); F(sn); F(gv); F(yv); F(P); F(part);
     F(bid); F(loc); F(Mk); F(wq); F(s); F(lre); F(lim); F(rowD); F(rowH); F(val); F(apart);
+    F(evrow); F(ew); F(ek);
     F(hrow); F(eR); F(eI);
     if (gs) hipFree(gs);
     gs = nullptr;
@@ -1134,6 +1136,188 @@ int wwbi_solve_gamma_t(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi, con
     c->finish_report(rep, status, st, c->op_bytes(op));
     if (hipGetLastError() != hipSuccess) return WWBI_EHIP;
     return status != WWBI_OK ? status : s1;
+}
+
+// ---------------------------------------------------------------------------
+// evolution of the free surface: one Runge-Kutta stage and one step
+// (Sec. 2.1, 2.2, 3.5, 5)
+// ---------------------------------------------------------------------------
+
+namespace {
+enum EvVec { EW_U = 0, EW_V, EW_T1, EW_T2, EW_T3, EW_T4, EW_DPHI, EW_SC, kEw };
+}
+
+// Workspace and the D / antiderivative / filter rows of the M_0 grid.
+static int evolve_prepare(Ctx *c, int M0) {
+    const size_t M = (size_t)M0;
+    int rc = grow(c->ew, c->capew, kEw * M + 64);
+    if (!rc && c->ev_M != M0) {
+        rc = grow(c->evrow, c->capevrow, 4 * M + 64);
+        if (!rc) {
+            launch_circ_row1(M0, WWBI_OP_D, c->evrow, c->stream);
+            launch_evolve_rows(M0, c->evrow + 3 * M, c->evrow + M, c->evrow + 2 * M, c->stream);
+            c->ev_M = M0;
+        }
+    }
+    return rc;
+}
+
+static int check_stage_geom(const wwbi_geom *g, int mode) {
+    if (!g || !g->M || !g->x || !g->y || !g->dx || !g->dy || !g->ddx || !g->ddy)
+        return WWBI_EINVAL_NULL;
+    if (g->nb < 2 || g->nb > kMaxB) return WWBI_EINVAL_SIZE;
+    if (g->M[0] < 8 || (g->M[0] & 1)) return WWBI_EINVAL_SIZE;
+    if (mode != WWBI_SURF_GRAPH && mode != WWBI_SURF_HLS) return WWBI_EINVAL_OPTS;
+    return WWBI_OK;
+}
+
+// Surface of the stage state written into the first M_0 entries of the
+// geometry arrays, the velocity-potential solve there, then the rates.
+static int stage_impl(Ctx *c, const wwbi_geom *g, int mode, const double *q, const double *phi,
+                      double tau, double grav, const wwbi_opts *o, double *qt, double *phit,
+                      double *Uout, double *Vout, wwbi_report *rep) {
+    const int M0 = g->M[0];
+    const size_t M = (size_t)M0;
+    int rc = evolve_prepare(c, M0);
+    if (rc) return rc;
+    hipStream_t st = c->stream;
+    double *x = const_cast<double *>(g->x), *y = const_cast<double *>(g->y);
+    double *dx = const_cast<double *>(g->dx), *dy = const_cast<double *>(g->dy);
+    double *ddx = const_cast<double *>(g->ddx), *ddy = const_cast<double *>(g->ddy);
+    const double *rD = c->evrow, *rI = c->evrow + M;
+    double *U = c->ew + EW_U * M, *V = c->ew + EW_V * M;
+    double *t1 = c->ew + EW_T1 * M, *t2 = c->ew + EW_T2 * M, *t3 = c->ew + EW_T3 * M;
+    double *t4 = c->ew + EW_T4 * M, *dphi = c->ew + EW_DPHI * M, *sc = c->ew + EW_SC * M;
+    if (mode == WWBI_SURF_GRAPH) {
+        // zeta = alpha + i eta (Sec. 2.1)
+        launch_graph_base(M0, q, x, y, dx, ddx, st);
+        launch_circ_apply1(M0, rD, q, dy, 1.0, 0.0, st);
+        launch_circ_apply1(M0, rD, dy, ddy, 1.0, 0.0, st);
+    } else {
+        // the curve from P theta (Sec. 2.2)
+        launch_mean_cs(M0, q, sc, st);
+        launch_hls_slope(M0, q, sc, dx, dy, t1, st);
+        launch_circ_apply1(M0, rI, t1, t2, 1.0, 0.0, st);      // xi^aux
+        launch_circ_apply1(M0, rI, dy, t3, 1.0, 0.0, st);      // eta^aux
+        launch_mean_prod(M0, t3, dx, sc + 2, st);
+        launch_hls_xy(M0, t2, t3, sc + 2, x, y, st);
+        launch_circ_apply1(M0, rD, q, t4, 1.0, 0.0, st);       // theta_alpha
+        launch_hls_curv(M0, t4, dx, dy, ddx, ddy, st);
+    }
+    wwbi_report r{};
+    const int s1 = solve_phi_impl(c, g, phi, o, U, nullptr, nullptr, &r);
+    if (rep) *rep = r;
+    if (s1 < 0) return s1;
+    if (mode == WWBI_SURF_GRAPH) {
+        launch_graph_rates(M0, U, dy, V, qt, st);
+    } else {
+        // V (Sec. 5) and (P theta)_t = P[(U_alpha + V theta_alpha) / s_alpha]
+        launch_mul(M0, t4, U, t1, st);
+        launch_circ_apply1(M0, rI, t1, t2, 1.0, 0.0, st);
+        launch_hls_V(M0, t2, U, dx, dy, V, st);
+        launch_circ_apply1(M0, rD, U, t3, 1.0, 0.0, st);
+        launch_hls_f(M0, t3, V, t4, dx, dy, t1, st);
+        launch_mean_prod(M0, t1, nullptr, sc + 3, st);
+        launch_sub_mean(M0, t1, sc + 3, qt, st);
+    }
+    launch_circ_apply1(M0, rD, phi, dphi, 1.0, 0.0, st);
+    launch_phit(M0, c->N, c->F, dphi, U, V, tau, grav, phit, st);
+    if (Uout) launch_copy(Uout, U, M0, st);
+    if (Vout) launch_copy(Vout, V, M0, st);
+    if (hipGetLastError() != hipSuccess) return WWBI_EHIP;
+    return s1;
+}
+
+int wwbi_stage_rhs(wwbi_ctx *ctx, const wwbi_geom *g, int32_t mode, const double *q,
+                   const double *phi, double tau, double grav, const wwbi_opts *o, double *q_t,
+                   double *phi_t, double *U, double *V, wwbi_report *rep) {
+    if (!ctx) return WWBI_EINVAL_NULL;
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    int rc = check_stage_geom(g, mode);
+    if (!rc) rc = Ctx::check_opts(o);
+    if (!rc && (!q || !phi || !q_t || !phi_t)) rc = WWBI_EINVAL_NULL;
+    if (!rc && !(std::isfinite(tau) && std::isfinite(grav))) rc = WWBI_EINVAL_NONFINITE;
+    if (rc) {
+        if (rep) { std::memset(rep, 0, sizeof(*rep)); rep->status = rc; }
+        return rc;
+    }
+    rc = stage_impl(c, g, mode, q, phi, tau, grav, o, q_t, phi_t, U, V, rep);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return WWBI_EHIP;
+    return rc;
+}
+
+int wwbi_rk_step(wwbi_ctx *ctx, const wwbi_geom *g, int32_t mode, int32_t nstage,
+                 const double *A, const double *b, double h, double *q, double *phi, double tau,
+                 double grav, int32_t filter, const wwbi_opts *o, wwbi_report *rep) {
+    if (!ctx) return WWBI_EINVAL_NULL;
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    int rc = check_stage_geom(g, mode);
+    if (!rc) rc = Ctx::check_opts(o);
+    if (!rc && (!A || !b || !q || !phi)) rc = WWBI_EINVAL_NULL;
+    if (!rc && (nstage < 1 || nstage > kMaxStages)) rc = WWBI_EINVAL_OPTS;
+    if (!rc && !(std::isfinite(h) && std::isfinite(tau) && std::isfinite(grav)))
+        rc = WWBI_EINVAL_NONFINITE;
+    for (int i = 0; !rc && i < nstage; ++i) {
+        if (!std::isfinite(b[i])) rc = WWBI_EINVAL_NONFINITE;
+        for (int j = 0; j < i; ++j)
+            if (!std::isfinite(A[i * nstage + j])) rc = WWBI_EINVAL_NONFINITE;
+    }
+    const int M0 = rc ? 0 : g->M[0];
+    const size_t M = (size_t)M0;
+    if (!rc) rc = grow(c->ek, c->capek, (2 * (size_t)nstage + 2) * M + 64);
+    if (rc) {
+        if (rep) { std::memset(rep, 0, sizeof(*rep)); rep->status = rc; }
+        return rc;
+    }
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t st = c->stream;
+    double *Kq = c->ek, *Kp = c->ek + nstage * M;
+    double *qi = c->ek + 2 * nstage * M, *pi = qi + M;
+    wwbi_report total{};
+    int status = WWBI_OK;
+    for (int i = 0; i < nstage; ++i) {
+        RkCoef co{};
+        co.ns = i;
+        co.h = h;
+        for (int j = 0; j < i; ++j) co.c[j] = A[i * nstage + j];
+        launch_rk_combine(M0, q, Kq, (long)M, co, qi, st);
+        launch_rk_combine(M0, phi, Kp, (long)M, co, pi, st);
+        wwbi_report r{};
+        const int s = stage_impl(c, g, mode, qi, pi, tau, grav, o, Kq + i * M, Kp + i * M,
+                                 nullptr, nullptr, &r);
+        total.iters += r.iters;
+        total.restarts += r.restarts;
+        total.refine_steps += r.refine_steps;
+        total.rel_resid = std::max(total.rel_resid, r.rel_resid);
+        total.n_matvec += r.n_matvec;
+        total.ms_matvec += r.ms_matvec;
+        total.ms_solve += r.ms_total;
+        if (s < 0) { status = s; break; }
+        if (s > 0 && status == WWBI_OK) status = s;
+    }
+    if (status >= 0) {
+        RkCoef co{};
+        co.ns = nstage;
+        co.h = h;
+        for (int j = 0; j < nstage; ++j) co.c[j] = b[j];
+        launch_rk_combine(M0, q, Kq, (long)M, co, qi, st);
+        launch_rk_combine(M0, phi, Kp, (long)M, co, pi, st);
+        if (filter) {
+            // the 36th-order filter at the end of the step (Sec. 5)
+            const double *rF = c->evrow + 2 * M;
+            launch_circ_apply1(M0, rF, qi, q, 1.0, 0.0, st);
+            launch_circ_apply1(M0, rF, pi, phi, 1.0, 0.0, st);
+        } else {
+            launch_copy(q, qi, M0, st);
+            launch_copy(phi, pi, M0, st);
+        }
+    }
+    const bool ok = hipStreamSynchronize(st) == hipSuccess && hipGetLastError() == hipSuccess;
+    total.status = ok ? status : WWBI_EHIP;
+    total.ms_total =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (rep) *rep = total;
+    return ok ? status : WWBI_EHIP;
 }
 
 int wwbi_adjoint_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, const double *dJdU,

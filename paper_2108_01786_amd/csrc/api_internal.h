@@ -106,6 +106,13 @@ struct Ctx {
     double *eI = nullptr;   size_t capeI = 0;
     double *val = nullptr;  size_t capval = 0;
     double *apart = nullptr; size_t capapart = 0;   // adjoint partial sums
+    // surface evolution: rows of D, the antiderivative and the filter on the
+    // M_0 grid (recomputed when M_0 changes), stage work vectors and the
+    // Runge-Kutta stage derivatives
+    int ev_M = 0;
+    double *evrow = nullptr; size_t capevrow = 0;    // D | INT | FILTER | sigma
+    double *ew = nullptr;    size_t capew = 0;
+    double *ek = nullptr;    size_t capek = 0;
     MultiWS mw;
     GState *gs = nullptr;
     void *hst = nullptr;    // pinned host staging (4 KiB)

@@ -40,7 +40,6 @@ struct Nodes {
     int n;
 };
 
-// Device-resident GMRES cycle state (one per Krylov solve in flight).
 // sum_{k < ns} part[k * stride + i], added in increasing k; eight loads are
 // issued before their additions (the slices are streamed from HBM/L2).
 __device__ __forceinline__ double sum_slices(const double *part, int ns, long stride, long i) {
@@ -57,6 +56,7 @@ __device__ __forceinline__ double sum_slices(const double *part, int ns, long st
     return acc;
 }
 
+// Device-resident GMRES cycle state (one per Krylov solve in flight).
 struct GState {
     int active;        // 1 while the current restart cycle runs
     int jdone;         // Arnoldi steps completed in the current cycle
@@ -131,6 +131,39 @@ void launch_wall_rhs_finalize(int nw, const double *umv_w, const double *part, i
 void launch_surface_base(int n, const double *xt, const double *yt, double *x, double *y,
                          hipStream_t st);
 void launch_add_scalar(int n, double *v, double c, hipStream_t st);
+
+// ---- kernels_evolve.hip ------------------------------------------------------
+constexpr int kMaxStages = 16;   // Runge-Kutta stages per step
+struct RkCoef {
+    int ns;
+    double h;
+    double c[kMaxStages];
+};
+// filter symbol (sigma, M/2) and the circulant rows of the zero-mean
+// antiderivative and of the 36th-order filter on an M-point grid
+void launch_evolve_rows(int M, double *sigma, double *rint, double *rfil, hipStream_t st);
+void launch_graph_base(int M, const double *eta, double *x, double *y, double *dx, double *ddx,
+                       hipStream_t st);
+void launch_mean_cs(int M, const double *a, double *out, hipStream_t st);
+void launch_mean_prod(int M, const double *a, const double *b, double *out, hipStream_t st);
+void launch_hls_slope(int M, const double *Pt, const double *cs, double *dx, double *dy,
+                      double *xm1, hipStream_t st);
+void launch_hls_xy(int M, const double *xa, const double *ya, const double *mean_yx, double *x,
+                   double *y, hipStream_t st);
+void launch_hls_curv(int M, const double *ta, const double *dx, const double *dy, double *ddx,
+                     double *ddy, hipStream_t st);
+void launch_graph_rates(int M, const double *U, const double *dy, double *V, double *qt,
+                        hipStream_t st);
+void launch_mul(int M, const double *a, const double *b, double *out, hipStream_t st);
+void launch_hls_V(int M, const double *Vi, const double *U, const double *dx, const double *dy,
+                  double *V, hipStream_t st);
+void launch_hls_f(int M, const double *dU, const double *V, const double *ta, const double *dx,
+                  const double *dy, double *f, hipStream_t st);
+void launch_sub_mean(int M, const double *f, const double *mean, double *out, hipStream_t st);
+void launch_phit(int M, const Nodes &N, const Flow &F, const double *dphi, const double *U,
+                 const double *V, double tau, double grav, double *out, hipStream_t st);
+void launch_rk_combine(int M, const double *base, const double *K, long ld, const RkCoef &co,
+                       double *out, hipStream_t st);
 
 // ---- kernels_matrix.hip ------------------------------------------------------
 // `active` (device, may be null): when it points to 0 the product is skipped.

@@ -22,6 +22,7 @@ OK, EINVAL_NULL, EINVAL_SIZE, EINVAL_NONFINITE, EINVAL_ORIENTATION = 0, -1, -2, 
 ECAPACITY, EHIP, EINVAL_OPTS = -5, -6, -7
 NOT_CONVERGED, STAGNATED, REFINE_STALLED = 1, 2, 3
 FP64, FP32_REFINED = 0, 1
+SURF_GRAPH, SURF_HLS = 0, 1
 MATVEC_AUTO, MATVEC_STORED, MATVEC_ON_THE_FLY = 0, 1, 2
 FLAG_PROFILE, FLAG_NO_CORRECTION = 1, 2
 OP_D, OP_D2, OP_H, OP_ABSD = 0, 1, 2, 3
@@ -72,6 +73,13 @@ _SIGS = {
     "wwbi_solve_gamma_t": (C.c_int, [C.c_void_p, C.POINTER(_Geom), C.c_void_p, C.c_void_p,
                                      C.c_double, C.c_double, C.POINTER(_Opts), C.c_void_p,
                                      C.c_void_p, C.POINTER(Report), C.POINTER(Report)]),
+    "wwbi_stage_rhs": (C.c_int, [C.c_void_p, C.POINTER(_Geom), C.c_int32, C.c_void_p, C.c_void_p,
+                                 C.c_double, C.c_double, C.POINTER(_Opts), C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(Report)]),
+    "wwbi_rk_step": (C.c_int, [C.c_void_p, C.POINTER(_Geom), C.c_int32, C.c_int32,
+                               C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double,
+                               C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_int32,
+                               C.POINTER(_Opts), C.POINTER(Report)]),
     "wwbi_adjoint_phi": (C.c_int, [C.c_void_p, C.POINTER(_Geom), C.c_void_p, C.c_void_p,
                                    C.POINTER(_Opts)] + [C.c_void_p] * 7 + [C.POINTER(Report)]),
     "wwbi_solve_phi_multi": (C.c_int, [C.c_void_p, C.POINTER(_Geom), C.c_void_p, C.c_int32,
@@ -298,6 +306,48 @@ class Context:
         if rc < 0 or (check and rc != OK):
             raise WWBIError(rc, "wwbi_solve_gamma_t")
         return gt, U, r1, r2
+
+    def stage_rhs(self, geom: DeviceGeometry, mode: int, q: torch.Tensor, phi: torch.Tensor,
+                  tau: float = 0.0, grav: float = 1.0, check: bool = True, **kw):
+        """(q_t, phi_t, U, V, report) of one evolution stage; the stage's surface
+        is written into the first M_0 entries of the geometry arrays."""
+        self._stream()
+        dev = self._dev()
+        q, phi = _f64(q, dev), _f64(phi, dev)
+        out = [torch.empty(geom.M[0], dtype=torch.float64, device=dev) for _ in range(4)]
+        rep = Report()
+        g = geom.c_struct()
+        o = make_opts(**kw)
+        rc = self.lib.wwbi_stage_rhs(self.h, C.byref(g), mode, _ptr(q), _ptr(phi), tau, grav,
+                                     C.byref(o), *[_ptr(t) for t in out], C.byref(rep))
+        if rc < 0 or (check and rc != OK):
+            raise WWBIError(rc, "wwbi_stage_rhs")
+        return out[0], out[1], out[2], out[3], rep
+
+    def rk_step(self, geom: DeviceGeometry, mode: int, A, b, h: float, q: torch.Tensor,
+                phi: torch.Tensor, tau: float = 0.0, grav: float = 1.0, filt: bool = True,
+                check: bool = True, **kw):
+        """One explicit Runge-Kutta step with tableau (A, b); q and phi (device,
+        contiguous FP64) are updated in place.  Returns the report."""
+        self._stream()
+        A = np.ascontiguousarray(np.asarray(A, dtype=np.float64))
+        b = np.ascontiguousarray(np.asarray(b, dtype=np.float64))
+        ns = int(b.shape[0])
+        if A.shape != (ns, ns):
+            raise ValueError("A must be nstage x nstage")
+        for t in (q, phi):
+            if t.dtype != torch.float64 or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError("q and phi must be contiguous FP64 device tensors")
+        rep = Report()
+        g = geom.c_struct()
+        o = make_opts(**kw)
+        Ac = A.ctypes.data_as(C.POINTER(C.c_double))
+        bc = b.ctypes.data_as(C.POINTER(C.c_double))
+        rc = self.lib.wwbi_rk_step(self.h, C.byref(g), mode, ns, Ac, bc, h, _ptr(q), _ptr(phi),
+                                   tau, grav, 1 if filt else 0, C.byref(o), C.byref(rep))
+        if rc < 0 or (check and rc != OK):
+            raise WWBIError(rc, "wwbi_rk_step")
+        return rep
 
     def adjoint_phi(self, geom: DeviceGeometry, omega: torch.Tensor, dJdU: torch.Tensor,
                     check: bool = True, **kw):
