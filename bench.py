@@ -131,6 +131,30 @@ def time_extras(ctx, dg, geom, phi, a, reps=5):
     out["gamma_t_phi_solve_ms"] = stats_ms(gp[1:])
     out["gamma_t_iters"] = gt[-1]["iters"]
     out["gamma_t_phases_ms"] = {k: gt[-1][k] for k in ("ms_prep", "ms_assemble", "ms_solve")}
+    # one evolution stage (HLS surface, refined FP32 solve) and one DOP853 step
+    # (tableau read from scipy) on the same walls; the stage's surface is
+    # written into a copy of the geometry
+    dg2 = wwbi.DeviceGeometry.from_synth(geom, phi.device)
+    Pt = (0.15 * torch.sin(al) + 0.05 * torch.cos(2 * al)).contiguous()
+    kw = dict(precision=wwbi.FP32_REFINED, tol=1e-14, inner_tol=a.inner_tol, restart=100,
+              poll_every=a.poll)
+    st_ms = []
+    for _ in range(reps + 1):
+        t0 = time.perf_counter()
+        ctx.stage_rhs(dg2, wwbi.SURF_HLS, Pt, phi, tau=0.1, **kw)
+        torch.cuda.synchronize()
+        st_ms.append(1e3 * (time.perf_counter() - t0))
+    out["stage_hls_ms"] = float(np.median(st_ms[1:]))
+    try:
+        from scipy.integrate._ivp import dop853_coefficients as d
+        A = np.array(d.A[:d.N_STAGES, :d.N_STAGES], dtype=np.float64)
+        b = np.array(d.B[:d.N_STAGES], dtype=np.float64)
+        q, p = Pt.clone(), phi.clone().contiguous()
+        rep = ctx.rk_step(dg2, wwbi.SURF_HLS, A, b, 1e-3, q, p, tau=0.1, **kw)
+        out["dop853_step_ms"] = rep.ms_total
+        out["dop853_step_iters"] = rep.iters
+    except ImportError:
+        pass
     return out
 
 

@@ -17,6 +17,7 @@ with background flow over obstacles and topography" (arXiv 2108.01786):
 * energy E ................................................. Sec. 5.2
 * gamma_t system (time derivative of the sheet strengths) .. Sec. 4.2
 * one Runge-Kutta stage: graph and HLS surfaces, V, filter . Sec. 2, 3.5, 5
+* velocity inside the fluid (Helsing-Ojala rule) ........... Sec. 5.1, appendix
 * spectral derivative and Hilbert transform (FFT symbols) .. Sec. 3.4
 
 Conventions the paper leaves open and that are fixed here: the Nyquist
@@ -551,6 +552,71 @@ def rk_step(g_walls: OGeom, mode: str, A, b, h: float, q: torch.Tensor, phi: tor
     if filt:
         qn, pn = spectral(qn, "FILTER"), spectral(pn, "FILTER")
     return qn, pn
+
+
+# ---------------------------------------------------------------------------
+# values inside the fluid (Sec. 5.1 and the Helsing-Ojala appendix)
+# ---------------------------------------------------------------------------
+
+def dphi_dn_all(g: OGeom, omega: List[torch.Tensor]) -> List[torch.Tensor]:
+    """Normal derivative dphi/dn on every boundary (Sec. 4.1, the formulas for
+    s dphi/dn_k), gamma_0 = -omega_0', gamma_j = omega_j':
+      s dphi/dn_k = Re{Phi_mv'(zeta_k) i zeta_k'} + [k = 0] H(gamma_0)/2
+                    + (1/M_0) sum_l G_0k(b_l, a) gamma_0(b_l)
+                    + sum_{j>=1} ( -[k = j] gamma_j/2 + (1/M_j) sum_l K_jk(b_l, a) gamma_j(b_l) ).
+    On the surface this is U; on the walls it vanishes for the physical
+    problem (psi constant there) up to the discretization error."""
+    gam = [-spectral(omega[0], "D")] + [spectral(w, "D") for w in omega[1:]]
+    out = []
+    for k in range(g.nb):
+        acc = u_mv(g, g.z[k], g.d[k])
+        if k == 0:
+            acc = acc + 0.5 * spectral(gam[0], "H")
+        acc = acc + (G_block(g, 0, k).T @ gam[0]) / g.M[0]
+        for j in range(1, g.nb):
+            if j == k:
+                acc = acc - 0.5 * gam[j]
+            acc = acc + (K_block(g, j, k).T @ gam[j]) / g.M[j]
+        out.append(acc / torch.abs(g.d[k]))
+    return out
+
+
+def boundary_dPhi(g: OGeom, omega: List[torch.Tensor]) -> List[torch.Tensor]:
+    """Phi'(zeta) = u - i v = (dphi/ds - i dphi/dn) |zeta'| / zeta' on every
+    boundary (Sec. 5.1)."""
+    ds = dphi_ds_from_omega(g, omega)
+    dn = dphi_dn_all(g, omega)
+    return [(ds[k] - 1j * dn[k]) * torch.abs(g.d[k]) / g.d[k] for k in range(g.nb)]
+
+
+def helsing_ojala(g: OGeom, fvals: List[torch.Tensor], z: torch.Tensor) -> torch.Tensor:
+    """f(z) for z in the fluid from the boundary values of a periodic function
+    analytic there (the Helsing-Ojala rule):
+      f(z) = sum lam_km f_km / sum lam_km,
+      lam_km = sigma_k / M_k * (1/2) cot((zeta_km - z)/2) zeta'_km.
+    The trapezoid sums approximate contour integrals over the positively
+    oriented boundary of the fluid, which runs along the free surface against
+    its parameter (sigma_0 = -1) and along the bottom and the clockwise
+    obstacles with it (sigma_k = +1).  A point on a node takes that node's value."""
+    z = z.to(C128)
+    num = torch.zeros_like(z)
+    den = torch.zeros_like(z)
+    hit = torch.full(z.shape, -1, dtype=torch.long)
+    hitv = torch.zeros_like(z)
+    for k in range(g.nb):
+        sig = -1.0 if k == 0 else 1.0
+        diff = g.z[k][None, :] - z[:, None]
+        on = diff == 0
+        lam = sig / g.M[k] * half_cot(torch.where(on, torch.ones_like(diff), diff)) * g.d[k][None, :]
+        lam = torch.where(on, torch.zeros_like(lam), lam)
+        num = num + (lam * fvals[k].to(C128)[None, :]).sum(1)
+        den = den + lam.sum(1)
+        rows = on.any(1)
+        if bool(rows.any()):
+            idx = on.float().argmax(1)
+            hitv = torch.where(rows, fvals[k].to(C128)[idx], hitv)
+            hit = torch.where(rows, torch.full_like(hit, k), hit)
+    return torch.where(hit >= 0, hitv, num / den)
 
 
 # ---------------------------------------------------------------------------

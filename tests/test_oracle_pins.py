@@ -363,3 +363,62 @@ def test_filter_symbol():
     f = torch.cos(31 * al)
     want = np.exp(-36.0 * (31 / 32) ** 36)
     assert float((O.spectral(f, "FILTER") - want * f).abs().max()) < 1e-13
+
+
+# ---------------------------------------------------------------------------
+# values inside the fluid (Sec. 5.1, Helsing-Ojala appendix)
+# ---------------------------------------------------------------------------
+
+def _inward_points(g, dists=(1e-1, 1e-2, 1e-4, 1e-7), stride=7):
+    """Points pushed into the fluid from every stride-th node: along -i zeta'/s
+    below the surface, along +i zeta'/s off the bottom and the clockwise obstacles."""
+    pts = []
+    for k in range(g.nb):
+        nrm = (-1j if k == 0 else 1j) * g.d[k] / torch.abs(g.d[k])
+        for dist in dists:
+            pts.append(g.z[k][::stride] + dist * nrm[::stride])
+    return torch.cat(pts)
+
+
+def test_helsing_ojala_analytic_function():
+    """e^{-iz} + 0.15 cot((z - p)/2) with p inside the obstacle, from its boundary
+    values, at points down to 1e-7 from every boundary: spectrally accurate (1e-14);
+    the same sum with the surface taken along its parameter fails."""
+    geom, _, _, _ = manufactured_case(256, 256, 128)
+    g = O.OGeom.from_synth(geom)
+    z = _inward_points(g)
+    f = lambda w: torch.exp(-1j * w) + 0.15 / torch.tan(0.5 * (w - (np.pi - 0.5j)))
+    val = O.helsing_ojala(g, [f(zz) for zz in g.z], z)
+    assert float((val - f(z)).abs().max() / f(z).abs().max()) < 1e-14
+    flipped = O.OGeom([g.z[0].flip(0)] + g.z[1:], [-g.d[0].flip(0)] + g.d[1:],
+                      [g.e[0].flip(0)] + g.e[1:], g.zc, g.a, g.V1)
+    bad = O.helsing_ojala(flipped, [f(zz) for zz in flipped.z], z)
+    assert float((bad - f(z)).abs().max() / f(z).abs().max()) > 1e-3
+
+
+def test_boundary_and_interior_velocity_manufactured():
+    """Phi' = u - iv of the manufactured flow: on all boundaries from the
+    solve's densities (dphi/ds and dphi/dn of every boundary) and inside the
+    fluid by the Helsing-Ojala rule, down to 1e-7 from the boundary."""
+    geom, phi, _, _ = manufactured_case(256, 256, 128)
+    g = O.OGeom.from_synth(geom)
+    om = O.split(g, O.solve_phi(g, torch.as_tensor(phi))["omega"])
+    bd = O.boundary_dPhi(g, om)
+    for k, c in enumerate(geom.curves):
+        ex = torch.as_tensor(CASE_FLOW.dPhi(c.z))
+        assert float((bd[k] - ex).abs().max()) < 1e-10, k
+    z = _inward_points(g)
+    exz = torch.as_tensor(CASE_FLOW.dPhi(z.numpy()))
+    assert float((O.helsing_ojala(g, bd, z) - exz).abs().max() / exz.abs().max()) < 1e-11
+
+
+def test_walls_are_streamlines():
+    """For the physical problem (psi_wall = 0) dphi/dn vanishes on every wall up
+    to the discretization error, and equals U on the surface."""
+    cfg = make_config(1)
+    g = O.OGeom.from_synth(cfg["geom"])
+    r = O.solve_phi(g, torch.as_tensor(cfg["phi"]))
+    dn = O.dphi_dn_all(g, O.split(g, r["omega"]))
+    assert float((dn[0] - r["U"]).abs().max()) < 1e-14
+    for v in dn[1:]:
+        assert float(v.abs().max()) < 1e-10
