@@ -266,6 +266,38 @@ int wwbi_rk_step(wwbi_ctx *ctx, const wwbi_geom *g, int32_t mode, int32_t nstage
                  const double *A, const double *b, double h, double *q, double *phi, double tau,
                  double grav, int32_t filter, const wwbi_opts *o, wwbi_report *rep);
 
+/* Velocity on every boundary node from the densities omega of a
+ * velocity-potential solve: u and v (device, sum(M)) with
+ *   u - i v = (dphi/ds - i dphi/dn) |zeta'| / zeta'     (Sec. 5.1),
+ * dphi/ds from the Sec. 5.1 formulas and dphi/dn from the Sec. 4.1 formulas
+ * for every boundary (U on the surface; zero on the walls of the physical
+ * problem up to the discretization error). */
+int wwbi_boundary_velocity(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, double *u,
+                           double *v);
+
+/* Values inside the fluid of a periodic function analytic there, from its
+ * values on every boundary node (the Helsing-Ojala rule of the appendix to
+ * Sec. 5.1):
+ *   f(z) = sum_km lam_km f_km / sum_km lam_km,
+ *   lam_km = sigma_k / M_k * (1/2) cot((zeta_km - z)/2) zeta'_km,
+ * sigma_0 = -1 (the positively oriented boundary runs along the free surface
+ * against its parameter), sigma_k = +1 for the bottom and the obstacles.
+ * Spectrally accurate up to and on the boundary; a point equal to a node
+ * (or a period image of one) takes that node's value.
+ *   f_re, f_im (device) sum(M); zx, zy (device) npts points inside the fluid;
+ *   out_re, out_im (device) npts. */
+int wwbi_interior_eval(wwbi_ctx *ctx, const wwbi_geom *g, const double *f_re,
+                       const double *f_im, int32_t npts, const double *zx, const double *zy,
+                       double *out_re, double *out_im);
+
+/* Fluid velocity (u, v) at npts points inside the fluid from the densities
+ * omega: the boundary values of u - i v (wwbi_boundary_velocity), which is
+ * analytic and periodic in the fluid, carried inside by the Helsing-Ojala rule.
+ *   zx, zy, u, v (device) npts. */
+int wwbi_interior_velocity(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega,
+                           int32_t npts, const double *zx, const double *zy, double *u,
+                           double *v);
+
 /* Adjoint of the velocity-potential solve.  With omega from wwbi_solve_phi on
  * the same inputs and dJdU = dJ/dU (device, M_0), returns the gradient of J
  * with respect to the surface samples (walls held fixed):

@@ -95,7 +95,7 @@ void Ctx::release() {
     for (int i = 0; i < kNumVec; ++i) F(vec[i]);
     F(H); F(cs); F(sn); F(gv); F(yv); F(P); F(part);
     F(bid); F(loc); F(Mk); F(wq); F(s); F(lre); F(lim); F(rowD); F(rowH); F(val); F(apart);
-    F(evrow); F(ew); F(ek);
+    F(evrow); F(ew); F(ek); F(hop); F(hoi);
     F(hrow); F(eR); F(eI);
     if (gs) hipFree(gs);
     gs = nullptr;
@@ -1318,6 +1318,87 @@ int wwbi_rk_step(wwbi_ctx *ctx, const wwbi_geom *g, int32_t mode, int32_t nstage
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (rep) *rep = total;
     return ok ? status : WWBI_EHIP;
+}
+
+// ---------------------------------------------------------------------------
+// velocity on the boundaries and inside the fluid (Sec. 4.1, 5.1 and the
+// Helsing-Ojala appendix)
+// ---------------------------------------------------------------------------
+
+// s dphi/ds and s dphi/dn on every node from the densities omega
+static void boundary_derivs(Ctx *c, const double *omega, double *sds, double *sdn) {
+    hipStream_t sm = c->stream;
+    const Layout &L = c->L;
+    const int n = L.n, n0 = L.off[1];
+    double *gam = c->vec[VG], *hg = c->vec[VHG], *tm = c->vec[VTM], *um = c->vec[VUM];
+    launch_circulant_rows(L, WWBI_OP_D, c->rowD, sm);
+    launch_circulant_rows(L, WWBI_OP_H, c->rowH, sm);
+    c->gamma_from_omega(omega, gam);
+    launch_circulant_apply(L, c->rowH, gam, hg, 1.0, 0.0, 0, L.nb - 1, sm);
+    launch_tmv(c->N, c->F, 0, n, tm, sm);
+    launch_umv(c->N, c->F, 0, n, um, sm);
+    const int ns = rflavour_nsplit(n, n, 0);
+    launch_rflavour(L, c->N, c->hrow, 5, 0, 0, n, 0, n, gam, c->part, nullptr, sm);
+    launch_tangential_finalize(n, n0, nullptr, tm, gam, hg, c->part, ns, sds, sm);
+    launch_rflavour(L, c->N, c->hrow, 2, 0, 0, n, 0, n, gam, c->part, nullptr, sm);
+    launch_normal_finalize(n, n0, um, gam, hg, c->part, ns, sdn, sm);
+}
+
+static int interior_common(Ctx *c, const wwbi_geom *g, int32_t npts, const double *zx,
+                           const double *zy) {
+    if (!zx || !zy) return WWBI_EINVAL_NULL;
+    if (npts < 1 || npts > (1 << 26)) return WWBI_EINVAL_SIZE;
+    int rc = c->setup(g, nullptr, 0);
+    if (rc) return rc;
+    const size_t ns = (size_t)ho_slices(npts, c->L.n);
+    rc = grow(c->hop, c->caphop, 4 * ns * npts + 64);
+    if (!rc) rc = grow(c->hoi, c->caphoi, ns * npts + 64);
+    return rc;
+}
+
+int wwbi_boundary_velocity(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, double *u,
+                           double *v) {
+    if (!ctx) return WWBI_EINVAL_NULL;
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    if (!omega || !u || !v) return WWBI_EINVAL_NULL;
+    int rc = c->setup(g, nullptr, 0);
+    if (rc) return rc;
+    double *sds = c->vec[VE], *sdn = c->vec[VQG];
+    boundary_derivs(c, omega, sds, sdn);
+    launch_boundary_velocity(c->L.n, g->dx, g->dy, sds, sdn, false, u, v, c->stream);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return WWBI_EHIP;
+    return hip_ok(hipGetLastError());
+}
+
+int wwbi_interior_eval(wwbi_ctx *ctx, const wwbi_geom *g, const double *f_re,
+                       const double *f_im, int32_t npts, const double *zx, const double *zy,
+                       double *out_re, double *out_im) {
+    if (!ctx) return WWBI_EINVAL_NULL;
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    if (!f_re || !f_im || !out_re || !out_im) return WWBI_EINVAL_NULL;
+    int rc = interior_common(c, g, npts, zx, zy);
+    if (rc) return rc;
+    launch_helsing_ojala(c->N, c->L.n, c->L.off[1], npts, zx, zy, f_re, f_im, c->hop, c->hoi,
+                         false, out_re, out_im, c->stream);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return WWBI_EHIP;
+    return hip_ok(hipGetLastError());
+}
+
+int wwbi_interior_velocity(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega,
+                           int32_t npts, const double *zx, const double *zy, double *u,
+                           double *v) {
+    if (!ctx) return WWBI_EINVAL_NULL;
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    if (!omega || !u || !v) return WWBI_EINVAL_NULL;
+    int rc = interior_common(c, g, npts, zx, zy);
+    if (rc) return rc;
+    double *sds = c->vec[VE], *sdn = c->vec[VQG], *fr = c->vec[VFV], *fi = c->vec[VFU];
+    boundary_derivs(c, omega, sds, sdn);
+    launch_boundary_velocity(c->L.n, g->dx, g->dy, sds, sdn, true, fr, fi, c->stream);
+    launch_helsing_ojala(c->N, c->L.n, c->L.off[1], npts, zx, zy, fr, fi, c->hop, c->hoi, true,
+                         u, v, c->stream);
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return WWBI_EHIP;
+    return hip_ok(hipGetLastError());
 }
 
 int wwbi_adjoint_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, const double *dJdU,

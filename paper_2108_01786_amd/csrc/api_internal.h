@@ -113,6 +113,8 @@ struct Ctx {
     double *evrow = nullptr; size_t capevrow = 0;    // D | INT | FILTER | sigma
     double *ew = nullptr;    size_t capew = 0;
     double *ek = nullptr;    size_t capek = 0;
+    double *hop = nullptr;   size_t caphop = 0;      // interior evaluation partials
+    int *hoi = nullptr;      size_t caphoi = 0;
     MultiWS mw;
     GState *gs = nullptr;
     void *hst = nullptr;    // pinned host staging (4 KiB)

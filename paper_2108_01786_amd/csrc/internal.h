@@ -165,6 +165,22 @@ void launch_phit(int M, const Nodes &N, const Flow &F, const double *dphi, const
 void launch_rk_combine(int M, const double *base, const double *K, long ld, const RkCoef &co,
                        double *out, hipStream_t st);
 
+// ---- kernels_interior.hip ----------------------------------------------------
+// Helsing-Ojala rule at P points from boundary values f (partial slices in
+// part: 4 * ho_slices * P doubles; hit: ho_slices * P ints)
+int ho_slices(int P, int n);
+void launch_helsing_ojala(const Nodes &N, int n, int n0, int P, const double *zx,
+                          const double *zy, const double *fr, const double *fi, double *part,
+                          int *hit, bool neg_im, double *outr, double *outi, hipStream_t st);
+void launch_boundary_velocity(int n, const double *dx, const double *dy, const double *sds,
+                              const double *sdn, bool phi_prime, double *u, double *v,
+                              hipStream_t st);
+// s dphi/dn = s dphi_mv/dn + local + T gamma partials (local: H gamma_0/2 on
+// the surface, -gamma_k/2 on wall k)
+void launch_normal_finalize(int n, int n0, const double *umv, const double *gamma,
+                            const double *hg, const double *part, int nsplit, double *out,
+                            hipStream_t st);
+
 // ---- kernels_matrix.hip ------------------------------------------------------
 // `active` (device, may be null): when it points to 0 the product is skipped.
 void launch_assemble64(const Layout &L, const Nodes &N, int flags, double *A, long ld,

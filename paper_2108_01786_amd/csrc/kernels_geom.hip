@@ -275,7 +275,8 @@ __global__ void k_tmv(Nodes N, Flow F, int first, int count, double *out) {
     out[i] = v;
 }
 
-// dphi/ds = (s dphi_mv/ds + local + sum of the split partials of Q gamma) / s,
+// dphi/ds = (s dphi_mv/ds + local + sum of the split partials of Q gamma) / s
+// (s dphi/ds when s is null),
 // local = gamma_0 / 2 on the surface and -(H gamma_k)/2 on wall k.
 __global__ void k_tangential_finalize(int n, int n0, const double *s, const double *tmv,
                                       const double *gamma, const double *hg, const double *part,
@@ -284,7 +285,7 @@ __global__ void k_tangential_finalize(int n, int n0, const double *s, const doub
     if (p >= n) return;
     const double acc = sum_slices(part, nsplit, n, p);
     const double loc = p < n0 ? 0.5 * gamma[p] : -0.5 * hg[p];
-    out[p] = (tmv[p] + loc + acc) / s[p];
+    out[p] = s ? (tmv[p] + loc + acc) / s[p] : tmv[p] + loc + acc;
 }
 
 // fV = V gamma_0 / s and fU = U gamma_0 / s on the surface (Sec. 4.2 F operators)

@@ -1,0 +1,193 @@
+// Values inside the fluid from boundary values (Sec. 5.1 and the
+// Helsing-Ojala appendix): for z in the fluid,
+//   f(z) = sum_km lam_km f_km / sum_km lam_km,
+//   lam_km = sigma_k / M_k * (1/2) cot((zeta_km - z)/2) zeta'_km,
+// the trapezoid sums of contour integrals over the positively oriented
+// boundary of the fluid: the free surface against its parameter
+// (sigma_0 = -1), the bottom and the clockwise obstacles along theirs.
+// A point that coincides with a node takes that node's value.
+//
+// Also the boundary velocity u - i v = (dphi/ds - i dphi/dn) |zeta'| / zeta'.
+#include "entries.h"
+#include "internal.h"
+
+namespace wwbi {
+
+namespace {
+
+inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+constexpr int kHoStage = 256;
+
+struct HoNode {
+    double ex, ey, x, y, dx, dy, w, fr, fi;
+    int neg;   // free-surface node (sigma = -1)
+};
+
+// Partial sums over chunk blockIdx.y of the nodes, one point per thread:
+// part[c][s][p] for c = Re num, Im num, Re den, Im den; hit[s][p] = the first
+// node of the chunk that coincides with the point, or -1.
+__global__ __launch_bounds__(256) void k_ho_partial(Nodes N, int n, int n0, int P,
+                                                    const double *__restrict__ zx,
+                                                    const double *__restrict__ zy,
+                                                    const double *__restrict__ fr,
+                                                    const double *__restrict__ fi, int chunk,
+                                                    double *__restrict__ part,
+                                                    int *__restrict__ hit) {
+    __shared__ HoNode sn[kHoStage];
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    const bool live = p < P;
+    const double x = live ? zx[p] : 0.0, y = live ? zy[p] : 0.0;
+    double s, c;
+    sincos(x, &s, &c);
+    const double mag = exp(-y);
+    const double er = mag * c, ei = mag * s;           // E_z = e^{i z}
+    const double ee = er * er + ei * ei;
+    double nr = 0.0, ni = 0.0, dr = 0.0, di = 0.0;
+    int h = -1;
+    const int qb = blockIdx.y * chunk, qe = min(n, qb + chunk);
+    for (int qq = qb; qq < qe; qq += kHoStage) {
+        const int q = qq + threadIdx.x;
+        if (q < qe) {
+            HoNode v;
+            v.ex = N.ex[q]; v.ey = N.ey[q]; v.x = N.x[q]; v.y = N.y[q];
+            v.dx = N.dx[q]; v.dy = N.dy[q]; v.w = N.w[q]; v.fr = fr[q]; v.fi = fi[q];
+            v.neg = q < n0 ? 1 : 0;
+            sn[threadIdx.x] = v;
+        }
+        __syncthreads();
+        const int m = min(kHoStage, qe - qq);
+        if (live) {
+            for (int i = 0; i < m; ++i) {
+                const HoNode &v = sn[i];
+                const double ddr = v.ex - er, ddi = v.ey - ei;
+                const double den = ddr * ddr + ddi * ddi;
+                double kr, ki;
+                if (den == 0.0) {       // the point is this node (or a period image)
+                    if (h < 0) h = qq + i;
+                    continue;
+                }
+                if (den * 4096.0 < ee) {
+                    cot_half64(v.x - x, v.y - y, kr, ki);
+                } else {
+                    // cot((zeta - z)/2) = i (E_zeta + E_z) / (E_zeta - E_z)
+                    const double sr = v.ex + er, si = v.ey + ei;
+                    const double inv = 1.0 / den;
+                    const double pr = (sr * ddr + si * ddi) * inv;
+                    const double pi = (si * ddr - sr * ddi) * inv;
+                    kr = -pi;
+                    ki = pr;
+                }
+                // lam = sigma w (1/2) kappa zeta'
+                const double sw = (v.neg ? -0.5 : 0.5) * v.w;
+                const double lr = sw * (kr * v.dx - ki * v.dy);
+                const double li = sw * (kr * v.dy + ki * v.dx);
+                nr += lr * v.fr - li * v.fi;
+                ni += lr * v.fi + li * v.fr;
+                dr += lr;
+                di += li;
+            }
+        }
+        __syncthreads();
+    }
+    if (live) {
+        const long st = (long)gridDim.y * P;
+        const long o = (long)blockIdx.y * P + p;
+        part[o] = nr;
+        part[st + o] = ni;
+        part[2 * st + o] = dr;
+        part[3 * st + o] = di;
+        hit[o] = h;
+    }
+}
+
+// f(z) = num / den, or the coinciding node's value; neg_im stores -Im f
+__global__ void k_ho_finalize(int P, int ns, const double *__restrict__ part,
+                              const int *__restrict__ hit, const double *__restrict__ fr,
+                              const double *__restrict__ fi, int neg_im,
+                              double *__restrict__ outr, double *__restrict__ outi) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    int h = -1;
+    for (int s = 0; s < ns && h < 0; ++s) h = hit[(long)s * P + p];
+    const double sg = neg_im ? -1.0 : 1.0;
+    if (h >= 0) {
+        outr[p] = fr[h];
+        outi[p] = sg * fi[h];
+        return;
+    }
+    const long st = (long)ns * P;
+    const double nr = sum_slices(part, ns, P, p), ni = sum_slices(part + st, ns, P, p);
+    const double dr = sum_slices(part + 2 * st, ns, P, p);
+    const double di = sum_slices(part + 3 * st, ns, P, p);
+    const double inv = 1.0 / (dr * dr + di * di);
+    outr[p] = (nr * dr + ni * di) * inv;
+    outi[p] = sg * (ni * dr - nr * di) * inv;
+}
+
+// u - i v on every node from s dphi/ds and s dphi/dn:
+// (dphi/ds - i dphi/dn) |zeta'| / zeta' = (sds - i sdn) / zeta';
+// stores (u, v), or (Re, Im) of u - i v when phi_prime is set
+__global__ void k_boundary_velocity(int n, const double *dx, const double *dy, const double *sds,
+                                    const double *sdn, int phi_prime, double *u, double *v) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const double a = dx[p], b = dy[p];
+    const double inv = 1.0 / (a * a + b * b);
+    // (sds - i sdn) (a - i b) / |zeta'|^2
+    const double re = (sds[p] * a - sdn[p] * b) * inv;
+    const double im = (-sds[p] * b - sdn[p] * a) * inv;
+    u[p] = re;
+    v[p] = phi_prime ? im : -im;
+}
+
+// s dphi/dn = s dphi_mv/dn + local + sum of the split partials of T gamma,
+// local = H gamma_0 / 2 on the surface and -gamma_k / 2 on wall k
+__global__ void k_normal_finalize(int n, int n0, const double *umv, const double *gamma,
+                                  const double *hg, const double *part, int nsplit,
+                                  double *out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const double acc = sum_slices(part, nsplit, n, p);
+    const double loc = p < n0 ? 0.5 * hg[p] : -0.5 * gamma[p];
+    out[p] = umv[p] + loc + acc;
+}
+
+}  // namespace
+
+static int ho_chunk(int P, int n) {
+    int ns = cdiv(2048, cdiv(P, 256));
+    ns = ns < 1 ? 1 : (ns > 64 ? 64 : ns);
+    int c = cdiv(n, ns);
+    c = cdiv(c, 32) * 32;
+    return c < 32 ? 32 : c;
+}
+
+int ho_slices(int P, int n) { return cdiv(n, ho_chunk(P, n)); }
+
+void launch_helsing_ojala(const Nodes &N, int n, int n0, int P, const double *zx,
+                          const double *zy, const double *fr, const double *fi, double *part,
+                          int *hit, bool neg_im, double *outr, double *outi, hipStream_t st) {
+    const int chunk = ho_chunk(P, n);
+    const int ns = cdiv(n, chunk);
+    hipLaunchKernelGGL(k_ho_partial, dim3(cdiv(P, 256), ns), dim3(256), 0, st, N, n, n0, P, zx, zy,
+                       fr, fi, chunk, part, hit);
+    hipLaunchKernelGGL(k_ho_finalize, dim3(cdiv(P, 64)), dim3(64), 0, st, P, ns, part, hit, fr, fi,
+                       neg_im ? 1 : 0, outr, outi);
+}
+
+void launch_boundary_velocity(int n, const double *dx, const double *dy, const double *sds,
+                              const double *sdn, bool phi_prime, double *u, double *v,
+                              hipStream_t st) {
+    hipLaunchKernelGGL(k_boundary_velocity, dim3(cdiv(n, 256)), dim3(256), 0, st, n, dx, dy, sds,
+                       sdn, phi_prime ? 1 : 0, u, v);
+}
+
+void launch_normal_finalize(int n, int n0, const double *umv, const double *gamma,
+                            const double *hg, const double *part, int nsplit, double *out,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_normal_finalize, dim3(cdiv(n, 64)), dim3(64), 0, st, n, n0, umv, gamma, hg,
+                       part, nsplit, out);
+}
+
+}  // namespace wwbi

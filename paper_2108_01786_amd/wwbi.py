@@ -80,6 +80,13 @@ _SIGS = {
                                C.POINTER(C.c_double), C.POINTER(C.c_double), C.c_double,
                                C.c_void_p, C.c_void_p, C.c_double, C.c_double, C.c_int32,
                                C.POINTER(_Opts), C.POINTER(Report)]),
+    "wwbi_boundary_velocity": (C.c_int, [C.c_void_p, C.POINTER(_Geom), C.c_void_p, C.c_void_p,
+                                         C.c_void_p]),
+    "wwbi_interior_eval": (C.c_int, [C.c_void_p, C.POINTER(_Geom), C.c_void_p, C.c_void_p,
+                                     C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p]),
+    "wwbi_interior_velocity": (C.c_int, [C.c_void_p, C.POINTER(_Geom), C.c_void_p, C.c_int32,
+                                         C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "wwbi_adjoint_phi": (C.c_int, [C.c_void_p, C.POINTER(_Geom), C.c_void_p, C.c_void_p,
                                    C.POINTER(_Opts)] + [C.c_void_p] * 7 + [C.POINTER(Report)]),
     "wwbi_solve_phi_multi": (C.c_int, [C.c_void_p, C.POINTER(_Geom), C.c_void_p, C.c_int32,
@@ -348,6 +355,47 @@ class Context:
         if rc < 0 or (check and rc != OK):
             raise WWBIError(rc, "wwbi_rk_step")
         return rep
+
+    def boundary_velocity(self, geom: DeviceGeometry, omega: torch.Tensor):
+        """(u, v) on every boundary node (device, sum(M) each)."""
+        self._stream()
+        dev = self._dev()
+        omega = _f64(omega, dev)
+        u = torch.empty(geom.n, dtype=torch.float64, device=dev)
+        v = torch.empty_like(u)
+        g = geom.c_struct()
+        rc = self.lib.wwbi_boundary_velocity(self.h, C.byref(g), _ptr(omega), _ptr(u), _ptr(v))
+        if rc != OK:
+            raise WWBIError(rc, "wwbi_boundary_velocity")
+        return u, v
+
+    def interior_eval(self, geom: DeviceGeometry, f: torch.Tensor, z: torch.Tensor):
+        """f (complex, sum(M)) on the boundary nodes -> f at the complex points z."""
+        self._stream()
+        dev = self._dev()
+        fr, fi = _f64(f.real, dev), _f64(f.imag, dev)
+        zx, zy = _f64(z.real, dev), _f64(z.imag, dev)
+        outr, outi = torch.empty_like(zx), torch.empty_like(zx)
+        g = geom.c_struct()
+        rc = self.lib.wwbi_interior_eval(self.h, C.byref(g), _ptr(fr), _ptr(fi), int(zx.numel()),
+                                         _ptr(zx), _ptr(zy), _ptr(outr), _ptr(outi))
+        if rc != OK:
+            raise WWBIError(rc, "wwbi_interior_eval")
+        return torch.complex(outr, outi)
+
+    def interior_velocity(self, geom: DeviceGeometry, omega: torch.Tensor, z: torch.Tensor):
+        """(u, v) at the complex points z inside the fluid."""
+        self._stream()
+        dev = self._dev()
+        omega = _f64(omega, dev)
+        zx, zy = _f64(z.real, dev), _f64(z.imag, dev)
+        u, v = torch.empty_like(zx), torch.empty_like(zx)
+        g = geom.c_struct()
+        rc = self.lib.wwbi_interior_velocity(self.h, C.byref(g), _ptr(omega), int(zx.numel()),
+                                             _ptr(zx), _ptr(zy), _ptr(u), _ptr(v))
+        if rc != OK:
+            raise WWBIError(rc, "wwbi_interior_velocity")
+        return u, v
 
     def adjoint_phi(self, geom: DeviceGeometry, omega: torch.Tensor, dJdU: torch.Tensor,
                     check: bool = True, **kw):

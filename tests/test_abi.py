@@ -23,7 +23,8 @@ def test_header_declares_the_documented_entry_points():
                  "wwbi_adjoint_phi", "wwbi_solve_phi_multi", "wwbi_spectral",
                  "wwbi_debug_matrix", "wwbi_matvec", "wwbi_status_str", "wwbi_default_opts",
                  "wwbi_tangential_energy", "wwbi_solve_gamma_t", "wwbi_stage_rhs",
-                 "wwbi_rk_step"):
+                 "wwbi_rk_step", "wwbi_boundary_velocity", "wwbi_interior_eval",
+                 "wwbi_interior_velocity"):
         assert must in names
 
 
