@@ -17,7 +17,7 @@ with background flow over obstacles and topography" (arXiv 2108.01786):
 * energy E ................................................. Sec. 5.2
 * gamma_t system (time derivative of the sheet strengths) .. Sec. 4.2
 * one Runge-Kutta stage: graph and HLS surfaces, V, filter . Sec. 2, 3.5, 5
-* velocity inside the fluid (Helsing-Ojala rule) ........... Sec. 5.1, appendix
+* velocity and pressure inside the fluid (Helsing-Ojala) .... Sec. 5.1, appendix
 * spectral derivative and Hilbert transform (FFT symbols) .. Sec. 3.4
 
 Conventions the paper leaves open and that are fixed here: the Nyquist
@@ -617,6 +617,65 @@ def helsing_ojala(g: OGeom, fvals: List[torch.Tensor], z: torch.Tensor) -> torch
             hitv = torch.where(rows, fvals[k].to(C128)[idx], hitv)
             hit = torch.where(rows, torch.full_like(hit, k), hit)
     return torch.where(hit >= 0, hitv, num / den)
+
+
+def layer_potential_direct(g: OGeom, omega: List[torch.Tensor], z: torch.Tensor) -> torch.Tensor:
+    """The Cauchy integrals of Sec. 3 summed by the trapezoid rule at points z
+    away from the boundaries: Phi_0 carries 1/(2 pi i), Phi_j (walls) 1/(2 pi)."""
+    z = z.to(C128)
+    out = torch.zeros_like(z)
+    for k in range(g.nb):
+        c = -1j if k == 0 else 1.0
+        ker = half_cot(g.z[k][None, :] - z[:, None]) * g.d[k][None, :]
+        out = out + c * (ker * omega[k].to(C128)[None, :]).sum(1) / g.M[k]
+    return out
+
+
+def boundary_Phi(g: OGeom, omega: List[torch.Tensor]) -> List[torch.Tensor]:
+    """Fluid-side boundary values of the Cauchy integrals sum_k Phi_k (no
+    multi-valued part), from the Plemelj formulas with the Table 1 kernels:
+      surface: Re = -omega_0/2 + K_00 omega_0 + sum_j G_0j omega_j,
+               Im = H(omega_0)/2 - G_00 omega_0 + sum_j K_0j omega_j;
+      wall k:  Re = K_k0 omega_0 + sum_j G_kj omega_j - H(omega_k)/2,
+               Im = -G_k0 omega_0 + omega_k/2 + sum_j K_kj omega_j,
+    every block divided by its source count (the trapezoid weights)."""
+    out = []
+    for k in range(g.nb):
+        if k == 0:
+            re = -0.5 * omega[0] + (K_block(g, 0, 0) @ omega[0]) / g.M[0]
+            im = 0.5 * spectral(omega[0], "H") - (G_block(g, 0, 0) @ omega[0]) / g.M[0]
+            for j in range(1, g.nb):
+                re = re + (G_block(g, 0, j) @ omega[j]) / g.M[j]
+                im = im + (K_block(g, 0, j) @ omega[j]) / g.M[j]
+        else:
+            re = (K_block(g, k, 0) @ omega[0]) / g.M[0] - 0.5 * spectral(omega[k], "H")
+            im = -(G_block(g, k, 0) @ omega[0]) / g.M[0] + 0.5 * omega[k]
+            for j in range(1, g.nb):
+                re = re + (G_block(g, k, j) @ omega[j]) / g.M[j]
+                im = im + (K_block(g, k, j) @ omega[j]) / g.M[j]
+        out.append(re + 1j * im)
+    return out
+
+
+def pressure(g: OGeom, phi: torch.Tensor, tau: float, grav: float, z: torch.Tensor):
+    """p / rho = C - phi_t - |grad phi|^2 / 2 - g y inside the fluid (Sec. 5.1).
+    phi_t - C is the harmonic function with the Dirichlet data
+    tau kappa - |grad phi|^2 / 2 - g eta on the surface (Laplace-Young,
+    p = -tau kappa there) and zero normal derivative on the walls: the same
+    matrix A with b_0 = that data and b_k = 0, its Cauchy integrals carried
+    inside by the Helsing-Ojala rule, as is u - i v."""
+    r = solve_phi(g, phi)
+    om = split(g, r["omega"])
+    U = r["U"]
+    ds = dphi_ds_from_omega(g, om)[0]
+    s0 = torch.abs(g.d[0])
+    kappa = (g.e[0] / g.d[0]).imag / s0
+    data = tau * kappa - 0.5 * (ds * ds + U * U) - grav * g.z[0].imag
+    b = torch.cat([data] + [torch.zeros(m, dtype=F64) for m in g.M[1:]])
+    om_aux = split(g, torch.linalg.solve(r["A"], b))
+    phit = helsing_ojala(g, boundary_Phi(g, om_aux), z).real
+    w = helsing_ojala(g, boundary_dPhi(g, om), z)
+    return -phit - 0.5 * (w.abs() ** 2) - grav * z.imag
 
 
 # ---------------------------------------------------------------------------

@@ -422,3 +422,44 @@ def test_walls_are_streamlines():
     assert float((dn[0] - r["U"]).abs().max()) < 1e-14
     for v in dn[1:]:
         assert float(v.abs().max()) < 1e-10
+
+
+def test_plemelj_boundary_values_consistent():
+    """For an arbitrary density omega, the Helsing-Ojala rule applied to the
+    Plemelj boundary values of sum_k Phi_k (Re and Im on every boundary)
+    reproduces the directly summed Cauchy integrals at points away from the
+    boundaries: a wrong sign or kernel in any of the eight formulas fails."""
+    cfg = make_config(1)
+    g = O.OGeom.from_synth(cfg["geom"])
+    rng = np.random.default_rng(3)
+    om = [torch.as_tensor(0.2 * np.cos(np.arange(m) * 2 * np.pi / m * rng.integers(1, 4))
+                          + 0.1 * rng.standard_normal()) for m in g.M]
+    xs = torch.linspace(0.3, 2 * np.pi - 0.3, 9, dtype=torch.float64)
+    z = torch.cat([xs - 0.25j, xs - 0.8j])
+    z = z[((z.real - np.pi) / 0.3) ** 2 + ((z.imag + 0.5) / 0.15) ** 2 > 2.0]
+    direct = O.layer_potential_direct(g, om, z)
+    ho = O.helsing_ojala(g, O.boundary_Phi(g, om), z)
+    assert float((direct - ho).abs().max() / direct.abs().max()) < 1e-12
+
+
+@pytest.mark.parametrize("V1", [0.0, 0.7])
+def test_pressure_hydrostatic_and_uniform_current(V1):
+    """Flat surface over a flat bottom, phi~ = 0: at rest and in a uniform
+    current V1 the pressure is hydrostatic, p = -g y (steady Bernoulli)."""
+    geom = flat_strip(64, 64, 1.0, V1)
+    g = O.OGeom.from_synth(geom)
+    z = torch.tensor([1.0 - 0.3j, 2.0 - 0.6j, 4.0 - 0.95j], dtype=torch.complex128)
+    p = O.pressure(g, torch.zeros(64, dtype=torch.float64), 0.1, 1.0, z)
+    assert float((p + z.imag).abs().max()) < 1e-14
+
+
+def test_pressure_surface_limit():
+    """Approaching the free surface the pressure tends to -tau kappa
+    (Laplace-Young), the Dirichlet data of the auxiliary problem."""
+    cfg = make_config(1)
+    g = O.OGeom.from_synth(cfg["geom"])
+    d = g.d[0][::16]
+    z = g.z[0][::16] + 1e-9 * (-1j) * d / d.abs()
+    p = O.pressure(g, torch.as_tensor(cfg["phi"]), 0.1, 1.0, z)
+    kappa = ((g.e[0] / g.d[0]).imag / g.d[0].abs())[::16]
+    assert float((p + 0.1 * kappa).abs().max()) < 1e-7
