@@ -298,6 +298,22 @@ int wwbi_interior_velocity(wwbi_ctx *ctx, const wwbi_geom *g, const double *omeg
                            int32_t npts, const double *zx, const double *zy, double *u,
                            double *v);
 
+/* Pressure inside the fluid (Sec. 5.1): p / rho = C - phi_t - |grad phi|^2/2 - grav y.
+ * phi_t - C is harmonic with the Dirichlet data tau kappa - |grad phi|^2/2 -
+ * grav eta on the surface (Laplace-Young: p = -tau kappa there) and zero
+ * normal derivative on the walls: the matrix A of the velocity-potential
+ * solve (assembled once, used for both solves) with b_0 = that data and
+ * b_k = 0.  Its Cauchy integrals take their fluid-side boundary values from
+ * the Plemelj formulas and are carried inside by the Helsing-Ojala rule, as
+ * is u - i v.
+ *   phi (device) M_0; tau, grav; o as for wwbi_solve_phi.
+ *   zx, zy (device) npts points inside the fluid; p (device) npts.
+ * rep: the velocity-potential solve's report with the second solve's
+ * iterations added. */
+int wwbi_pressure(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi, double tau,
+                  double grav, const wwbi_opts *o, int32_t npts, const double *zx,
+                  const double *zy, double *p, wwbi_report *rep);
+
 /* Adjoint of the velocity-potential solve.  With omega from wwbi_solve_phi on
  * the same inputs and dJdU = dJ/dU (device, M_0), returns the gradient of J
  * with respect to the surface samples (walls held fixed):

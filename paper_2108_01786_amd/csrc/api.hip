@@ -1401,6 +1401,106 @@ int wwbi_interior_velocity(wwbi_ctx *ctx, const wwbi_geom *g, const double *omeg
     return hip_ok(hipGetLastError());
 }
 
+int wwbi_pressure(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi, double tau,
+                  double grav, const wwbi_opts *o, int32_t npts, const double *zx,
+                  const double *zy, double *p, wwbi_report *rep) {
+    if (!ctx) return WWBI_EINVAL_NULL;
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    SolveStats st{};
+    int rc = Ctx::check_opts(o);
+    if (!rc && (!phi || !zx || !zy || !p)) rc = WWBI_EINVAL_NULL;
+    if (!rc && !(std::isfinite(tau) && std::isfinite(grav))) rc = WWBI_EINVAL_NONFINITE;
+    if (!rc && (npts < 1 || npts > (1 << 26))) rc = WWBI_EINVAL_SIZE;
+    if (!rc && (!g || !g->M)) rc = WWBI_EINVAL_NULL;
+    if (!rc && (g->nb < 2 || g->nb > kMaxB)) rc = WWBI_EINVAL_SIZE;
+    long nsum = 0;
+    for (int k = 0; !rc && k < g->nb; ++k) {
+        if (g->M[k] < 8 || (g->M[k] & 1)) rc = WWBI_EINVAL_SIZE;
+        nsum += g->M[k];
+    }
+    if (!rc && nsum > (1L << 28)) rc = WWBI_EINVAL_SIZE;
+    if (!rc) {
+        // workspace first: the solve below writes into workspace vectors
+        c->restart_cap = std::max(c->restart_cap, o->restart);
+        rc = c->ensure((int)nsum, c->restart_cap);
+    }
+    if (!rc) {
+        const size_t ns = (size_t)ho_slices(npts, (int)nsum);
+        rc = grow(c->hop, c->caphop, 4 * ns * npts + 3 * (size_t)npts + 64);
+        if (!rc) rc = grow(c->hoi, c->caphoi, ns * npts + 64);
+    }
+    if (rc) {
+        if (rep) { std::memset(rep, 0, sizeof(*rep)); rep->status = rc; }
+        return rc;
+    }
+    // 1. the velocity-potential solve; its stored matrix serves the second solve
+    wwbi_report r1{};
+    const int s1 = solve_phi_impl(c, g, phi, o, c->vec[VU0], c->vec[VOM], nullptr, &r1);
+    if (s1 < 0) {
+        if (rep) *rep = r1;
+        return s1;
+    }
+    hipStream_t sm = c->stream;
+    const Layout &L = c->L;
+    const int n = L.n, n0 = L.off[1], nw = n - n0;
+    const long ld = round_up(n, 64);
+    double *om = c->vec[VOM], *sds = c->vec[VE], *sdn = c->vec[VQG];
+    double *b = c->vec[VB], *x = c->vec[VX];
+    // 2. Dirichlet data tau kappa - |grad phi|^2/2 - g eta on the surface, 0 on the walls
+    boundary_derivs(c, om, sds, sdn);
+    launch_fill(b, 0.0, n, sm);
+    launch_pressure_data(n0, c->N, sds, sdn, tau, grav, b, sm);
+    // 3. A omega_aux = b with the matrix of step 1
+    const bool stored = o->matvec != WWBI_MATVEC_ON_THE_FLY;
+    const bool fp32 = o->precision == WWBI_FP32_REFINED;
+    Op op64{stored ? OP_A_S64 : OP_A_O64, n, ld, o->flags, o->band};
+    int status;
+    if (!fp32) {
+        status = c->gmres(op64, b, x, true, o->tol, o->restart, o->max_iter, o->poll_every, false,
+                          true, st);
+    } else {
+        Op op32{stored ? OP_A_S32 : OP_A_O32, n, ld, o->flags, o->band};
+        Op opres{OP_A_O64, n, ld, o->flags, o->band};
+        status = c->refine(op32, opres, b, x, true, *o, st);
+    }
+    if (status < 0) {
+        if (rep) { *rep = r1; rep->status = status; }
+        return status;
+    }
+    // 4. boundary values of the auxiliary Cauchy integrals
+    double *ps = c->vec[VTMP], *rw = c->vec[VTMP2], *hw = c->vec[VHF], *means = c->vec[VRR];
+    double *fr = c->vec[VFV], *fi = c->vec[VFU];
+    launch_circulant_apply(L, c->rowH, x, hw, 1.0, 0.0, 0, L.nb - 1, sm);
+    launch_block_means(L, x, means, sm);
+    launch_rflavour(L, c->N, c->hrow, 4, 0, 0, n0, 0, n, x, c->part, nullptr, sm);
+    launch_reduce_partials(n0, c->part, rflavour_nsplit(n0, n, 0), nullptr, 1.0, ps, nullptr, sm);
+    if (nw > 0) {
+        launch_rflavour(L, c->N, c->hrow, 6, 0, n0, nw, 0, n0, x, c->part, nullptr, sm);
+        launch_reduce_partials(nw, c->part, rflavour_nsplit(nw, n0, 0), nullptr, 1.0, rw, nullptr,
+                               sm);
+        launch_rflavour(L, c->N, c->hrow, 7, 0, n0, nw, n0, nw, x + n0, c->part, nullptr, sm);
+        launch_reduce_partials(nw, c->part, rflavour_nsplit(nw, nw, 0), rw, -1.0, rw, nullptr, sm);
+    }
+    launch_phi_aux_values(n, n0, b, ps, rw, hw, c->bid, means, fr, fi, sm);
+    // 5. phi_t - C and u - i v inside the fluid, then the pressure
+    const size_t ns = (size_t)ho_slices(npts, n);
+    double *phit = c->hop + 4 * ns * npts, *wr = phit + npts, *wi = wr + npts;
+    launch_helsing_ojala(c->N, n, n0, npts, zx, zy, fr, fi, c->hop, c->hoi, false, phit, wi, sm);
+    double *vr = c->vec[VKF], *vi = c->vec[VGF];
+    launch_boundary_velocity(n, g->dx, g->dy, sds, sdn, true, vr, vi, sm);
+    launch_helsing_ojala(c->N, n, n0, npts, zx, zy, vr, vi, c->hop, c->hoi, false, wr, wi, sm);
+    launch_pressure_final(npts, phit, wr, wi, zy, grav, p, sm);
+    const bool ok = hipStreamSynchronize(sm) == hipSuccess && hipGetLastError() == hipSuccess;
+    if (rep) {
+        *rep = r1;
+        rep->iters += st.iters;
+        rep->refine_steps += st.refine_steps;
+        rep->status = ok ? status : WWBI_EHIP;
+    }
+    if (!ok) return WWBI_EHIP;
+    return status != WWBI_OK ? status : s1;
+}
+
 int wwbi_adjoint_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, const double *dJdU,
                      const wwbi_opts *o, double *g_phi, double *g_x, double *g_y, double *g_dx,
                      double *g_dy, double *g_ddx, double *g_ddy, wwbi_report *rep) {

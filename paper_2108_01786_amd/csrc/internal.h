@@ -181,6 +181,14 @@ void launch_normal_finalize(int n, int n0, const double *umv, const double *gamm
                             const double *hg, const double *part, int nsplit, double *out,
                             hipStream_t st);
 
+void launch_pressure_data(int n0, const Nodes &N, const double *sds, const double *sdn,
+                          double tau, double grav, double *b, hipStream_t st);
+void launch_phi_aux_values(int n, int n0, const double *data, const double *ps,
+                           const double *rw, const double *hw, const int *bid,
+                           const double *means, double *fr, double *fi, hipStream_t st);
+void launch_pressure_final(int P, const double *phit, const double *wr, const double *wi,
+                           const double *zy, double grav, double *out, hipStream_t st);
+
 // ---- kernels_matrix.hip ------------------------------------------------------
 // `active` (device, may be null): when it points to 0 the product is skipped.
 void launch_assemble64(const Layout &L, const Nodes &N, int flags, double *A, long ld,

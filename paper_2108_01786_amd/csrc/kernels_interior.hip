@@ -153,7 +153,64 @@ __global__ void k_normal_finalize(int n, int n0, const double *umv, const double
     out[p] = umv[p] + loc + acc;
 }
 
+// Dirichlet data of phi_t - C on the surface (Sec. 5.1, Laplace-Young):
+// tau kappa - |grad phi|^2 / 2 - g eta, kappa = Im(zeta''/zeta')/s = 2 Im L / s
+__global__ void k_pressure_data(int n0, Nodes N, const double *sds, const double *sdn,
+                                double tau, double grav, double *b) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n0) return;
+    const double s = N.s[m];
+    const double a = sds[m] / s, c = sdn[m] / s;
+    b[m] = tau * 2.0 * N.lim[m] / s - 0.5 * (a * a + c * c) - grav * N.y[m];
+}
+
+// Fluid-side boundary values of the auxiliary Cauchy integrals:
+// surface Re = the data, Im = P omega + H(omega_0)/2; wall k Re = KS omega_0 +
+// GS omega_w - H(omega_k)/2, Im = psi|_k (mean of omega_k for k >= 2, 0 on
+// the bottom).
+__global__ void k_phi_aux_values(int n, int n0, const double *data, const double *ps,
+                                 const double *rw, const double *hw, const int *bid,
+                                 const double *means, double *fr, double *fi) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    if (p < n0) {
+        fr[p] = data[p];
+        fi[p] = ps[p] + 0.5 * hw[p];
+    } else {
+        const int k = bid[p];
+        fr[p] = rw[p - n0] - 0.5 * hw[p];
+        fi[p] = k >= 2 ? means[k - 2] : 0.0;
+    }
+}
+
+// p = -(phi_t - C) - |u - i v|^2 / 2 - g y
+__global__ void k_pressure_final(int P, const double *phit, const double *wr, const double *wi,
+                                 const double *zy, double grav, double *out) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    out[p] = -phit[p] - 0.5 * (wr[p] * wr[p] + wi[p] * wi[p]) - grav * zy[p];
+}
+
 }  // namespace
+
+void launch_pressure_data(int n0, const Nodes &N, const double *sds, const double *sdn,
+                          double tau, double grav, double *b, hipStream_t st) {
+    hipLaunchKernelGGL(k_pressure_data, dim3(cdiv(n0, 256)), dim3(256), 0, st, n0, N, sds, sdn,
+                       tau, grav, b);
+}
+
+void launch_phi_aux_values(int n, int n0, const double *data, const double *ps,
+                           const double *rw, const double *hw, const int *bid,
+                           const double *means, double *fr, double *fi, hipStream_t st) {
+    hipLaunchKernelGGL(k_phi_aux_values, dim3(cdiv(n, 256)), dim3(256), 0, st, n, n0, data, ps, rw,
+                       hw, bid, means, fr, fi);
+}
+
+void launch_pressure_final(int P, const double *phit, const double *wr, const double *wi,
+                           const double *zy, double grav, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_pressure_final, dim3(cdiv(P, 256)), dim3(256), 0, st, P, phit, wr, wi, zy,
+                       grav, out);
+}
 
 static int ho_chunk(int P, int n) {
     int ns = cdiv(2048, cdiv(P, 256));

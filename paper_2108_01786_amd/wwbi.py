@@ -87,6 +87,9 @@ _SIGS = {
                                      C.c_void_p]),
     "wwbi_interior_velocity": (C.c_int, [C.c_void_p, C.POINTER(_Geom), C.c_void_p, C.c_int32,
                                          C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "wwbi_pressure": (C.c_int, [C.c_void_p, C.POINTER(_Geom), C.c_void_p, C.c_double, C.c_double,
+                                C.POINTER(_Opts), C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                C.POINTER(Report)]),
     "wwbi_adjoint_phi": (C.c_int, [C.c_void_p, C.POINTER(_Geom), C.c_void_p, C.c_void_p,
                                    C.POINTER(_Opts)] + [C.c_void_p] * 7 + [C.POINTER(Report)]),
     "wwbi_solve_phi_multi": (C.c_int, [C.c_void_p, C.POINTER(_Geom), C.c_void_p, C.c_int32,
@@ -396,6 +399,23 @@ class Context:
         if rc != OK:
             raise WWBIError(rc, "wwbi_interior_velocity")
         return u, v
+
+    def pressure(self, geom: DeviceGeometry, phi: torch.Tensor, z: torch.Tensor, tau: float = 0.0,
+                 grav: float = 1.0, check: bool = True, **kw):
+        """p / rho at the complex points z inside the fluid, and the report."""
+        self._stream()
+        dev = self._dev()
+        phi = _f64(phi, dev)
+        zx, zy = _f64(z.real, dev), _f64(z.imag, dev)
+        p = torch.empty_like(zx)
+        rep = Report()
+        g = geom.c_struct()
+        o = make_opts(**kw)
+        rc = self.lib.wwbi_pressure(self.h, C.byref(g), _ptr(phi), tau, grav, C.byref(o),
+                                    int(zx.numel()), _ptr(zx), _ptr(zy), _ptr(p), C.byref(rep))
+        if rc < 0 or (check and rc != OK):
+            raise WWBIError(rc, "wwbi_pressure")
+        return p, rep
 
     def adjoint_phi(self, geom: DeviceGeometry, omega: torch.Tensor, dJdU: torch.Tensor,
                     check: bool = True, **kw):

@@ -24,7 +24,7 @@ def test_header_declares_the_documented_entry_points():
                  "wwbi_debug_matrix", "wwbi_matvec", "wwbi_status_str", "wwbi_default_opts",
                  "wwbi_tangential_energy", "wwbi_solve_gamma_t", "wwbi_stage_rhs",
                  "wwbi_rk_step", "wwbi_boundary_velocity", "wwbi_interior_eval",
-                 "wwbi_interior_velocity"):
+                 "wwbi_interior_velocity", "wwbi_pressure"):
         assert must in names
 
 

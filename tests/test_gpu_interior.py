@@ -84,3 +84,32 @@ def test_boundary_and_interior_velocity(ww, ctx, name):
         ee = float((fi - ex).abs().max() / ex.abs().max())
         say(f"  interior vs closed form {ee:.1e}")
         assert ee <= 1e-10
+
+
+@pytest.mark.parametrize("name,prec", [("c1", "fp64"), ("ragged", "fp64"), ("c1", "fp32")])
+def test_pressure_matches_oracle(ww, ctx, name, prec):
+    """Pressure at points inside the fluid, down to 1e-7 from the boundaries."""
+    say(f"case pressure {name} {prec}")
+    cfg = make_config(1) if name == "c1" else ragged_config()
+    geom, phi = cfg["geom"], cfg["phi"]
+    dg = ww.DeviceGeometry.from_synth(geom, DEV)
+    g = O.OGeom.from_synth(geom)
+    z = _inward_points(g, dists=(1e-1, 1e-3, 1e-7), stride=11)
+    p, rep = ctx.pressure(dg, torch.as_tensor(phi, device=DEV), z.to(DEV), tau=0.1,
+                          tol=1e-13 if prec == "fp64" else 1e-14,
+                          precision=ww.FP64 if prec == "fp64" else ww.FP32_REFINED)
+    ref = O.pressure(g, torch.as_tensor(phi), 0.1, 1.0, z)
+    err = float((p.cpu() - ref).abs().max() / ref.abs().max())
+    say(f"  err {err:.1e}  iters {rep.iters}")
+    assert err <= (1e-11 if prec == "fp64" else 1e-10)
+
+
+@pytest.mark.parametrize("V1", [0.0, 0.7])
+def test_pressure_hydrostatic(ww, ctx, V1):
+    say(f"case pressure hydrostatic V1={V1}")
+    from manufactured import flat_strip
+    geom = flat_strip(64, 64, 1.0, V1)
+    dg = ww.DeviceGeometry.from_synth(geom, DEV)
+    z = torch.tensor([1.0 - 0.3j, 2.0 - 0.6j, 4.0 - 0.95j], dtype=torch.complex128)
+    p, _ = ctx.pressure(dg, torch.zeros(64, dtype=torch.float64, device=DEV), z.to(DEV), tau=0.1)
+    assert float((p.cpu() + z.imag).abs().max()) <= 1e-13
