@@ -107,9 +107,11 @@ def timed_solves(ctx, dg, phi, steps, warmup, flags=0, **kw):
 
 
 def time_extras(ctx, dg, geom, phi, a, reps=5):
-    """Per-call times of the diagnostics (tangential velocity on every node and
-    the energy) and of the gamma_t stage (its own velocity-potential solve plus
-    the right-hand side and the n x n FP64 system), on the same cell."""
+    """Per-call times, on the same cell, of the other entry points: the
+    diagnostics (tangential velocity on every node and the energy), the
+    gamma_t stage (its own velocity-potential solve plus the right-hand side
+    and the n x n FP64 system), one evolution stage and one DOP853 step (HLS
+    surface), and velocity and pressure at 4096 points inside the fluid."""
     from paper_2108_01786_amd import wwbi
     M0 = geom.M[0]
     al = torch.arange(M0, dtype=torch.float64, device=phi.device) * (2 * np.pi / M0)
@@ -155,6 +157,24 @@ def time_extras(ctx, dg, geom, phi, a, reps=5):
         out["dop853_step_iters"] = rep.iters
     except ImportError:
         pass
+    # velocity and pressure at 4096 points inside the fluid (Helsing-Ojala rule)
+    g0 = geom.curves[0]
+    Mq = 4096
+    idx = np.arange(Mq) * (M0 // Mq if M0 >= Mq else 1) % M0
+    nrm = -1j * g0.d[idx] / np.abs(g0.d[idx])
+    zpts = torch.as_tensor(g0.z[idx] + np.geomspace(1e-6, 0.2, Mq) * nrm, device=phi.device)
+    vel, prs = [], []
+    for _ in range(reps + 1):
+        t0 = time.perf_counter()
+        ctx.interior_velocity(dg, omega, zpts)
+        torch.cuda.synchronize()
+        vel.append(1e3 * (time.perf_counter() - t0))
+        t0 = time.perf_counter()
+        ctx.pressure(dg, phi, zpts, tau=0.1, tol=1e-13, poll_every=a.poll)
+        torch.cuda.synchronize()
+        prs.append(1e3 * (time.perf_counter() - t0))
+    out["interior_velocity_4096pts_ms"] = float(np.median(vel[1:]))
+    out["pressure_4096pts_ms"] = float(np.median(prs[1:]))
     return out
 
 
