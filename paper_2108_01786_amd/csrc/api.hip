@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -101,6 +102,8 @@ void Ctx::release() {
     gs = nullptr;
     if (hst) hipHostFree(hst);
     hst = nullptr;
+    if (hmir) hipHostFree(hmir);
+    hmir = dmir = nullptr;
     for (auto &e : ev) if (e) hipEventDestroy(e);
     for (auto &e : prof) if (e) hipEventDestroy(e);
     for (auto &e : pollev) if (e) hipEventDestroy(e);
@@ -238,6 +241,21 @@ int Ctx::read_state(GState &out) {
     return WWBI_OK;
 }
 
+int Ctx::final_state(GState &out) {
+    const volatile GState *m = hmir;
+    if (m->cyc != cyc_id) return read_state(out);
+    out.active = m->active;
+    out.jdone = m->jdone;
+    out.breakdown = m->breakdown;
+    out.its = m->its;
+    out.bnorm = m->bnorm;
+    out.tol_abs = m->tol_abs;
+    out.beta = m->beta;
+    out.resid = m->resid;
+    out.cyc = m->cyc;
+    return WWBI_OK;
+}
+
 void Ctx::prof_begin() {
     if (profiling && nprof < kProfPairs) {
         hipEventRecord(prof[2 * nprof], stream);
@@ -260,9 +278,11 @@ void Ctx::prof_end() {
 // reads after its next synchronisation (inner solves of the refinement).
 //
 // The host enqueues `poll` Arnoldi steps at a time.  After each batch it
-// queues an asynchronous copy of the cycle flag, enqueues the next batch and
-// only then waits for the previous copy, so the device never idles on the
-// host; steps enqueued after convergence return at once on the device flag.
+// records an event, enqueues the next batch and only then waits for the
+// previous event, so the device never idles on the host.  The kernel that
+// ends a cycle publishes the cycle's state, with its id, into host-mapped
+// memory: the host sees the end without a queued copy, and steps enqueued
+// after it return at once on the device flag.
 int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol, int restart,
                int max_iter, int poll, bool fp32_basis, bool verify, SolveStats &st) {
     const int n = op.n;
@@ -284,7 +304,6 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
     const int its0 = st.iters;
     int its_seen = 0;          // device step count at the previous cycle start
     GState h{};
-    GState *slot = reinterpret_cast<GState *>((char *)hst + kStateSlotOffset);
     for (;;) {
         cur_cycle = -1;        // the residual product is not an Arnoldi step
         const double *r0 = r;
@@ -294,7 +313,9 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
             apply(op, x, nullptr, b, r, nullptr);
             launch_norm_partial(r, n, P3, G, stream);
         }
-        launch_cycle_start(r0, n, P3, G, V, x32, gv, restart + 1, gs, stream);
+        cyc_id = cyc_id == INT_MAX ? 1 : cyc_id + 1;   // never 0, the mirror's initial id
+        const int cid = cyc_id;
+        launch_cycle_start(r0, n, P3, G, V, x32, gv, restart + 1, gs, cid, dmir, stream);
         int jmax = std::min(restart, max_iter - st.iters);
         if (verify) {
             int rc = read_state(h);
@@ -330,21 +351,18 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
                 launch_cgs_dot(V, ldv, w, n, j, P1, P3, G, gs, stream);
                 if (single_pass) {
                     launch_cgs_final(V, ldv, w, n, j, P1, P3, G, x32, H, restart + 1, false, cs,
-                                     sn, gv, jmax, gs, stream);
+                                     sn, gv, jmax, gs, cid, dmir, stream);
                 } else {
                     launch_cgs_first(V, ldv, w, n, j, P1, P2, P3, G, H, restart + 1, gs, stream);
                     launch_cgs_final(V, ldv, w, n, j, P2, P3, G, x32, H, restart + 1, true, cs,
-                                     sn, gv, jmax, gs, stream);
+                                     sn, gv, jmax, gs, cid, dmir, stream);
                 }
             }
             const int cur = (j0 / poll) & 1;
-            if (hipMemcpyAsync(slot + cur, gs, sizeof(GState), hipMemcpyDeviceToHost, stream) !=
-                hipSuccess)
-                return WWBI_EHIP;
             if (hipEventRecord(pollev[cur], stream) != hipSuccess) return WWBI_EHIP;
             if (pending >= 0) {
                 if (hipEventSynchronize(pollev[pending]) != hipSuccess) return WWBI_EHIP;
-                if (!slot[pending].active) ended = true;
+                if (static_cast<const volatile GState *>(hmir)->cyc == cid) ended = true;
             }
             pending = cur;
         }
@@ -354,10 +372,7 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
         st.cycles += 1;
         first = false;
         if (!verify) {
-            if (hipMemcpyAsync(slot + 2, gs, sizeof(GState), hipMemcpyDeviceToHost, stream) !=
-                hipSuccess)
-                return WWBI_EHIP;
-            status = WWBI_OK;
+            status = WWBI_OK;      // the caller reads the final state (final_state)
             break;
         }
     }
@@ -398,7 +413,6 @@ int Ctx::refine(const Op &op32, const Op &op64, const double *b, double *x, bool
     const int G = gmres_nblocks(n);
     double *r = vec[VRR], *d = vec[VD];
     double *Pn = P + 2 * 64 * (restart_cap + 1) + 64;   // norm partials (64 doubles)
-    const GState *slot2 = reinterpret_cast<const GState *>((char *)hst + kStateSlotOffset) + 2;
     // From a cold start the first inner solve takes b itself and writes x;
     // ||b|| then comes back in that solve's final state, read at the first
     // synchronisation, so no host round trip precedes it.
@@ -427,12 +441,14 @@ int Ctx::refine(const Op &op32, const Op &op64, const double *b, double *x, bool
             for (int i = 0; i < G; ++i) s2 += h[i];
             rn = std::sqrt(s2);
             if (inner_pending) {
-                st.iters += slot2->its;
+                GState fin;                    // the inner solve's final state
+                if (final_state(fin)) return WWBI_EHIP;
+                st.iters += fin.its;
                 if (last_cycle >= 0 && last_cycle < (int)cyc_done.size())
-                    cyc_done[last_cycle] = slot2->its;
+                    cyc_done[last_cycle] = fin.its;
                 inner_pending = false;
                 if (bn < 0.0) {
-                    bn = slot2->bnorm;     // the first inner solve's right-hand side was b
+                    bn = fin.bnorm;     // the first inner solve's right-hand side was b
                     prev = bn;
                 }
             }
@@ -635,7 +651,8 @@ int Ctx::gmres_multi(int kind, int n, long ld, const double *B, double *X, int n
         else
             apply_multi(kind, n, ld, X, nullptr, ldv, nr, B, m.r);
         launch_norm_partial(m.r, n, P3, G, stream, bt);
-        launch_cycle_start(m.r, n, P3, G, m.V, x32, m.g, restart + 1, m.gs, stream, bt);
+        launch_cycle_start(m.r, n, P3, G, m.V, x32, m.g, restart + 1, m.gs, 0, nullptr,
+                           stream, bt);
         int rc = read_states(h.data(), nr);
         if (rc) return rc;
         bool any = false;
@@ -664,7 +681,7 @@ int Ctx::gmres_multi(int kind, int n, long ld, const double *B, double *X, int n
                 launch_cgs_dot(m.V, ldv, m.w, n, j, P1, P3, G, m.gs, stream, bt);
                 launch_cgs_first(m.V, ldv, m.w, n, j, P1, P2, P3, G, m.H, ldp, m.gs, stream, bt);
                 launch_cgs_final(m.V, ldv, m.w, n, j, P2, P3, G, x32, m.H, ldp, true, m.cs, m.sn,
-                                 m.g, jmax, m.gs, stream, bt);
+                                 m.g, jmax, m.gs, 0, nullptr, stream, bt);
             }
             const int cur = (j0 / poll) & 1;
             GState *dst = reinterpret_cast<GState *>((char *)slot + cur * kStateSlotBytes);
@@ -828,6 +845,13 @@ int wwbi_create(wwbi_ctx **out, int32_t device, void *stream) {
     int rc = WWBI_OK;
     if (hipMalloc((void **)&c->gs, sizeof(GState)) != hipSuccess) rc = WWBI_ECAPACITY;
     if (!rc && hipHostMalloc(&c->hst, kHostStaging) != hipSuccess) rc = WWBI_ECAPACITY;
+    if (!rc && hipHostMalloc((void **)&c->hmir, sizeof(GState),
+                             hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+        rc = WWBI_ECAPACITY;
+    if (!rc) {
+        std::memset(c->hmir, 0, sizeof(GState));
+        if (hipHostGetDevicePointer((void **)&c->dmir, c->hmir, 0) != hipSuccess) rc = WWBI_EHIP;
+    }
     for (auto &e : c->ev)
         if (!rc && hipEventCreate(&e) != hipSuccess) rc = WWBI_EHIP;
     for (auto &e : c->prof)

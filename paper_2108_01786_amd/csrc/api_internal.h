@@ -118,6 +118,11 @@ struct Ctx {
     MultiWS mw;
     GState *gs = nullptr;
     void *hst = nullptr;    // pinned host staging (4 KiB)
+    // host-mapped coherent copy of the single-solve cycle state, written by
+    // the device kernels (hmir on the host, dmir its device address)
+    GState *hmir = nullptr;
+    GState *dmir = nullptr;
+    int cyc_id = 0;            // id of the latest GMRES cycle enqueued on gs
 
     hipEvent_t ev[5] = {};
     hipEvent_t pollev[2] = {};
@@ -142,6 +147,9 @@ struct Ctx {
                const int *active);
     double op_bytes(const Op &op) const;
     int read_state(GState &out);
+    // state at the end of the latest cycle: the published copy when it is that
+    // cycle's (after a synchronisation past the cycle's end), else a copy of gs
+    int final_state(GState &out);
     void prof_begin();
     void prof_end();
     int gmres(const Op &op, const double *b, double *x, bool x_zero, double tol, int restart,

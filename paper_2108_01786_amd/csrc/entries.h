@@ -287,8 +287,50 @@ __device__ __forceinline__ double gt_val64(const Nodes &N, const Tgt &t, const S
 // same-boundary pair within `nb` grid steps (diagonal included); the near
 // part evaluates exactly those pairs with the full entry functions above.
 // ---------------------------------------------------------------------------
+// nb < 0 means no pair is in the band (a stage that ranges_apart has cleared).
 __device__ __forceinline__ bool in_band(const Tgt &t, const Src &s, int nb) {
-    return t.k == s.k && cyc_dist(t.loc, s.loc, t.M) <= nb;
+    return nb >= 0 && t.k == s.k && cyc_dist(t.loc, s.loc, t.M) <= nb;
+}
+
+// True when no target node in [pa, pb] and source node in [qa, qb] form a
+// same-boundary pair within nb grid steps, so that a tile of the far part can
+// skip the per-pair band test.  A range that crosses from one boundary to the
+// next returns false (the caller keeps the per-pair test).  The pairs of two
+// ranges on one boundary of M nodes have index distances d between their gap
+// and their span, and a pair is in the band when min(d, M - d) <= nb.
+__device__ __forceinline__ bool ranges_apart(const Nodes &N, int pa, int pb, int qa, int qb,
+                                             int nb) {
+    const int kp = N.bid[pa], kq = N.bid[qa];
+    if (N.bid[pb] != kp || N.bid[qb] != kq) return false;
+    if (kp != kq) return true;
+    const int lpa = N.loc[pa], lpb = N.loc[pb], lqa = N.loc[qa], lqb = N.loc[qb];
+    const int gap = max(0, max(lqa - lpb, lpa - lqb));
+    const int span = max(lpb - lqa, lqb - lpa);
+    return gap > nb && N.Mk[pa] - span > nb;
+}
+
+// Boundary of the nodes [a, b], or -1 when the range crosses a boundary end.
+__device__ __forceinline__ int range_boundary(const Nodes &N, int a, int b) {
+    const int k = N.bid[a];
+    return N.bid[b] == k ? k : -1;
+}
+
+// First thread of the calling wave (wave-uniform; call where every lane is active).
+__device__ __forceinline__ int wave_base() {
+    return __builtin_amdgcn_readfirstlane(threadIdx.x) & ~63;
+}
+
+// Whether a wave's outputs [o0, o0 + 64) (clipped to [0, nout)) are clear of
+// the near band of the summed nodes [q0, q0 + m); output node = obase +
+// output, and COLS says the outputs are sources.  Vacuously true for a wave
+// without live outputs.
+template <bool COLS>
+__device__ __forceinline__ bool wave_apart(const Nodes &N, int obase, int o0, int nout, int q0,
+                                           int m, int nb) {
+    if (o0 >= nout) return true;
+    const int a = obase + o0, b = obase + min(o0 + 63, nout - 1);
+    return COLS ? ranges_apart(N, q0, q0 + m - 1, a, b, nb)
+                : ranges_apart(N, a, b, q0, q0 + m - 1, nb);
 }
 
 __device__ __forceinline__ double a_far64(const Tgt &t, const Src &s, bool corr, int nb) {

@@ -66,6 +66,8 @@ struct GState {
     double tol_abs;    // tol * ||b||
     double beta;       // residual norm at the start of the cycle
     double resid;      // current residual estimate |g_{j+1}|
+    int cyc;           // host-visible copy only: the cycle whose end it records
+    int pad;
 };
 
 // Strides of a batch of Krylov solves run in lockstep (system = blockIdx.y).
@@ -262,8 +264,12 @@ void launch_norm_partial(const double *v, int n, double *P, int G, hipStream_t s
                          const Bat &bt = kSingle);
 void launch_set_tol(const double *P, int G, double tol, GState *gs, hipStream_t st,
                     const Bat &bt = kSingle);
+// mirror (may be null): host-visible copy of the cycle state, written once
+// per cycle, by the kernel that ends cycle `cyc` (the cycle start when there
+// is nothing to do, else the Arnoldi step that converges or fills the basis)
 void launch_cycle_start(const double *r, int n, const double *P, int G, double *V, float *v32,
-                        double *g, int ldg, GState *gs, hipStream_t st, const Bat &bt = kSingle);
+                        double *g, int ldg, GState *gs, int cyc, GState *mirror, hipStream_t st,
+                        const Bat &bt = kSingle);
 // partial dots of w with V_0..V_j into P, partial |w|^2 into P3
 void launch_cgs_dot(const double *V, long ldv, const double *w, int n, int j, double *P,
                     double *P3, int G, const GState *gs, hipStream_t st, const Bat &bt = kSingle);
@@ -276,7 +282,7 @@ void launch_cgs_first(const double *V, long ldv, double *w, int n, int j, const 
 void launch_cgs_final(const double *V, long ldv, const double *w, int n, int j,
                       const double *P2, const double *P3, int G, float *v32, double *H, int ldh,
                       bool add, double *cs, double *sn, double *g, int restart_len, GState *gs,
-                      hipStream_t st, const Bat &bt = kSingle);
+                      int cyc, GState *mirror, hipStream_t st, const Bat &bt = kSingle);
 void launch_hsolve(const double *H, int ldh, const double *g, double *y, const GState *gs,
                    hipStream_t st, const Bat &bt = kSingle);
 // x += V y (x = V y when overwrite)

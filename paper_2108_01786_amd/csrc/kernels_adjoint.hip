@@ -84,13 +84,39 @@ __device__ __forceinline__ void store6(double *part, long st, long off, const do
 // Far part of both passes: every pair except the surface pairs within nb
 // grid steps of r (diagonal included), with kappa from E alone.  Chunk
 // blockIdx.y of the other index, written as slice blockIdx.y of `part`
-// (component stride st).
+// (component stride st).  A staged tile that holds no near-band pair for the
+// wave skips the per-pair test (CHECK = false).
+template <bool CHECK>
+__device__ __forceinline__ void adj_rows_tile(const Tgt &t, const Src *ss, const double *sw,
+                                              const double *sg, int m, int nb, double (&a)[6]) {
+    for (int i = 0; i < m; ++i) {
+        const Src &s = ss[i];
+        if (CHECK && in_band(t, s, nb)) continue;
+        double cr, ci;
+        kappa64_far(t, s, cr, ci);
+        row_terms(t, s, cr, ci, sw[i], sg[i], a);
+    }
+}
+
+template <bool CHECK>
+__device__ __forceinline__ void adj_cols_tile(const Src &s, const Tgt *ts, const double *sl,
+                                              const double *sc, int m, int nb, double (&a)[6]) {
+    for (int i = 0; i < m; ++i) {
+        const Tgt &t = ts[i];
+        if (CHECK && in_band(t, s, nb)) continue;
+        double cr, ci;
+        kappa64_far(t, s, cr, ci);
+        col_terms(t, s, cr, ci, sl[i], sc[i], a);
+    }
+}
+
 __global__ __launch_bounds__(256) void k_adj_rows(Nodes N, int n0, int n, int chunk, int nb,
                                                   const double *__restrict__ omega,
                                                   const double *__restrict__ gamma,
                                                   double *__restrict__ part, long st) {
     __shared__ Src ss[kStage];
     __shared__ double sw[kStage], sg[kStage];
+    const int wb = wave_base();
     const int r = blockIdx.x * 256 + threadIdx.x;
     const bool live = r < n0;
     Tgt t;
@@ -106,14 +132,12 @@ __global__ __launch_bounds__(256) void k_adj_rows(Nodes N, int n0, int n, int ch
         }
         __syncthreads();
         const int m = min(kStage, qe - qq);
+        const bool apart = wave_apart<false>(N, 0, blockIdx.x * 256 + wb, n0, qq, m, nb);
         if (live) {
-            for (int i = 0; i < m; ++i) {
-                const Src &s = ss[i];
-                if (in_band(t, s, nb)) continue;
-                double cr, ci;
-                kappa64_far(t, s, cr, ci);
-                row_terms(t, s, cr, ci, sw[i], sg[i], a);
-            }
+            if (apart)
+                adj_rows_tile<false>(t, ss, sw, sg, m, nb, a);
+            else
+                adj_rows_tile<true>(t, ss, sw, sg, m, nb, a);
         }
         __syncthreads();
     }
@@ -126,6 +150,7 @@ __global__ __launch_bounds__(256) void k_adj_cols(Nodes N, int n0, int n, int ch
                                                   double *__restrict__ part, long st) {
     __shared__ Tgt ts[kStage];
     __shared__ double sl[kStage], sc[kStage];
+    const int wb = wave_base();
     const int r = blockIdx.x * 256 + threadIdx.x;
     const bool live = r < n0;
     Src s;
@@ -141,14 +166,12 @@ __global__ __launch_bounds__(256) void k_adj_cols(Nodes N, int n0, int n, int ch
         }
         __syncthreads();
         const int m = min(kStage, pe - pp);
+        const bool apart = wave_apart<true>(N, 0, blockIdx.x * 256 + wb, n0, pp, m, nb);
         if (live) {
-            for (int i = 0; i < m; ++i) {
-                const Tgt &t = ts[i];
-                if (in_band(t, s, nb)) continue;
-                double cr, ci;
-                kappa64_far(t, s, cr, ci);
-                col_terms(t, s, cr, ci, sl[i], sc[i], a);
-            }
+            if (apart)
+                adj_cols_tile<false>(s, ts, sl, sc, m, nb, a);
+            else
+                adj_cols_tile<true>(s, ts, sl, sc, m, nb, a);
         }
         __syncthreads();
     }

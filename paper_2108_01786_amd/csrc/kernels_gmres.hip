@@ -45,6 +45,25 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
     return t;
 }
 
+// Copy of the state at the end of cycle `cyc` into host-visible memory (m may
+// be null), written through volatile stores that bypass the caches, so that
+// the host reads it without a copy once the kernel has completed.  The write
+// crosses to host memory and delays the kernel's completion by a few
+// microseconds, so it happens once per cycle, not per step.
+__device__ __forceinline__ void publish(GState *m, const GState *gs, int cyc) {
+    if (!m) return;
+    volatile GState *d = m;
+    d->its = gs->its;
+    d->jdone = gs->jdone;
+    d->breakdown = gs->breakdown;
+    d->bnorm = gs->bnorm;
+    d->tol_abs = gs->tol_abs;
+    d->beta = gs->beta;
+    d->resid = gs->resid;
+    d->active = gs->active;
+    d->cyc = cyc;
+}
+
 // P[b] = sum over chunk b of v^2
 __global__ __launch_bounds__(kT) void k_norm_partial(const double *v, int n, double *P, int G,
                                                      Bat bt) {
@@ -74,7 +93,8 @@ __global__ void k_set_tol(const double *P, int G, double tol, GState *gs, Bat bt
 // v_0 = r / beta (FP64 and FP32 copies), g = (beta, 0, ...), new cycle state.
 __global__ __launch_bounds__(kT) void k_cycle_start(const double *r, int n, const double *P,
                                                     int G, double *V, float *v32, double *g,
-                                                    int ldg, GState *gs, Bat bt) {
+                                                    int ldg, GState *gs, int cyc,
+                                                    GState *mirror, Bat bt) {
     __shared__ double sb;
     r += sys() * bt.vec;
     P += sys() * bt.p;
@@ -105,21 +125,53 @@ __global__ __launch_bounds__(kT) void k_cycle_start(const double *r, int n, cons
             gs->jdone = 0;
             gs->breakdown = 0;
             gs->active = (beta > gs->tol_abs) ? 1 : 0;
+            if (!gs->active) publish(mirror, gs, cyc);
         }
     }
 }
 
-// P[i*G + b] = <V_i, w> over chunk b, i = 0..j.  Wave wv handles i = wv, wv+4, ...
+// P[i*G + b] = <V_i, w> over chunk b, i = 0..j.  Wave wv handles i = wv, wv+4, ...,
+// four of them per pass so that their loads are in flight together; each sum
+// keeps its own sequential order.
 __device__ __forceinline__ void chunk_dots(const double *V, long ldv, const double *w, int c0,
                                            int c1, int j, double *P, int G) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int i = wv; i <= j; i += kT / 64) {
-        const double *vi = V + (long)i * ldv;
-        double a = 0.0;
-        for (int m = c0 + lane; m < c1; m += 64) a += vi[m] * w[m];
-        a = wave_sum(a);
-        if (lane == 0) P[(long)i * G + blockIdx.x] = a;
+    constexpr int W = kT / 64;
+    for (int i0 = wv; i0 <= j; i0 += 4 * W) {
+        const double *vi[4];
+        bool on[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            on[u] = i0 + u * W <= j;
+            vi[u] = V + (long)(on[u] ? i0 + u * W : i0) * ldv;
+        }
+        double a[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int m = c0 + lane; m < c1; m += 64) {
+            const double wm = w[m];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) a[u] += vi[u][m] * wm;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double t = wave_sum(a[u]);
+            if (lane == 0 && on[u]) P[(long)(i0 + u * W) * G + blockIdx.x] = t;
+        }
     }
+}
+
+// acc - sum_{i<=j} h_i V_i[m] in ascending i, eight loads in flight at a time
+__device__ __forceinline__ double minus_proj(double acc, const double *h, const double *V,
+                                             long ldv, int m, int j) {
+    int i = 0;
+    for (; i + 8 <= j + 1; i += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = V[(long)(i + u) * ldv + m];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc -= h[i + u] * v[u];
+    }
+    for (; i <= j; ++i) acc -= h[i] * V[(long)i * ldv + m];
+    return acc;
 }
 
 // h_i = sum_b P[i*G + b] for i = 0..j into LDS: one wave per i, lanes over b
@@ -189,8 +241,7 @@ __global__ __launch_bounds__(kT) void k_cgs_first(const double *V, long ldv, dou
     chunk_of(n, G, blockIdx.x, c0, c1);
     double nn = 0.0;
     for (int m = c0 + threadIdx.x; m < c1; m += kT) {
-        double acc = w[m];
-        for (int i = 0; i <= j; ++i) acc -= h[i] * V[(long)i * ldv + m];
+        const double acc = minus_proj(w[m], h, V, ldv, m, j);
         w[m] = acc;
         nn += acc * acc;
     }
@@ -215,7 +266,8 @@ __global__ __launch_bounds__(kT) void k_cgs_final(const double *V_, long ldv, co
                                                   const double *P3, int G, float *v32,
                                                   double *H, int ldh, int add, double *cs,
                                                   double *sn, double *g, int restart_len,
-                                                  GState *gs, Bat bt) {
+                                                  GState *gs, int cyc, GState *mirror,
+                                                  Bat bt) {
     gs += sys();
     if (gs->active == 0) return;
     double *V = const_cast<double *>(V_) + sys() * bt.v;
@@ -256,9 +308,7 @@ __global__ __launch_bounds__(kT) void k_cgs_final(const double *V_, long ldv, co
     chunk_of(n, G, blockIdx.x, c0, c1);
     double *vn = V + (long)(j + 1) * ldv;
     for (int m = c0 + threadIdx.x; m < c1; m += kT) {
-        double acc = w[m];
-        for (int i = 0; i <= j; ++i) acc -= h[i] * V[(long)i * ldv + m];
-        const double v = acc * sc;
+        const double v = minus_proj(w[m], h, V, ldv, m, j) * sc;
         vn[m] = v;
         if (v32) v32[m] = (float)v;
     }
@@ -288,7 +338,10 @@ __global__ __launch_bounds__(kT) void k_cgs_final(const double *V_, long ldv, co
         gs->its += 1;
         const bool brk = !(nrm > 0.0);           // exact invariant subspace, or NaN
         gs->breakdown = brk ? 1 : 0;
-        if (res <= gs->tol_abs || brk || j + 1 >= restart_len) gs->active = 0;
+        if (res <= gs->tol_abs || brk || j + 1 >= restart_len) {
+            gs->active = 0;
+            publish(mirror, gs, cyc);
+        }
     }
     __syncthreads();
     double *hc = H + (long)j * ldh;
@@ -327,7 +380,15 @@ __global__ void k_xupdate(double *x, const double *V, long ldv, int n, const dou
     if (m >= n) return;
     const int k = gs->jdone;
     double acc = overwrite ? 0.0 : x[m];
-    for (int i = 0; i < k; ++i) acc += y[i] * V[(long)i * ldv + m];
+    int i = 0;
+    for (; i + 8 <= k; i += 8) {          // eight loads in flight, ascending i
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = V[(long)(i + u) * ldv + m];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += y[i + u] * v[u];
+    }
+    for (; i < k; ++i) acc += y[i] * V[(long)i * ldv + m];
     x[m] = acc;
 }
 
@@ -364,9 +425,10 @@ void launch_set_tol(const double *P, int G, double tol, GState *gs, hipStream_t 
     hipLaunchKernelGGL(k_set_tol, dim3(1, bt.nsys), dim3(64), 0, st, P, G, tol, gs, bt);
 }
 void launch_cycle_start(const double *r, int n, const double *P, int G, double *V, float *v32,
-                        double *g, int ldg, GState *gs, hipStream_t st, const Bat &bt) {
+                        double *g, int ldg, GState *gs, int cyc, GState *mirror,
+                        hipStream_t st, const Bat &bt) {
     hipLaunchKernelGGL(k_cycle_start, dim3(G, bt.nsys), dim3(kT), 0, st, r, n, P, G, V, v32, g,
-                       ldg, gs, bt);
+                       ldg, gs, cyc, mirror, bt);
 }
 void launch_cgs_dot(const double *V, long ldv, const double *w, int n, int j, double *P,
                     double *P3, int G, const GState *gs, hipStream_t st, const Bat &bt) {
@@ -382,9 +444,9 @@ void launch_cgs_first(const double *V, long ldv, double *w, int n, int j, const 
 void launch_cgs_final(const double *V, long ldv, const double *w, int n, int j,
                       const double *P2, const double *P3, int G, float *v32, double *H, int ldh,
                       bool add, double *cs, double *sn, double *g, int restart_len, GState *gs,
-                      hipStream_t st, const Bat &bt) {
+                      int cyc, GState *mirror, hipStream_t st, const Bat &bt) {
     hipLaunchKernelGGL(k_cgs_final, dim3(G, bt.nsys), dim3(kT), 0, st, V, ldv, w, n, j, P2, P3, G,
-                       v32, H, ldh, add ? 1 : 0, cs, sn, g, restart_len, gs, bt);
+                       v32, H, ldh, add ? 1 : 0, cs, sn, g, restart_len, gs, cyc, mirror, bt);
 }
 void launch_hsolve(const double *H, int ldh, const double *g, double *y, const GState *gs,
                    hipStream_t st, const Bat &bt) {

@@ -159,6 +159,62 @@ __global__ __launch_bounds__(256) void k_near_band(Nodes N, const double *hrow, 
 // kTPT entries.
 constexpr int kTPT = 2;
 
+// One staged tile of the forward product; CHECK = false when the tile is
+// known to hold no near-band pair (the entries are then the same as with
+// the test, which always fails).
+template <int MODE, bool ACC32, bool CHECK>
+__device__ __forceinline__ void rows_tile(const Nodes &N, const Tgt (&t)[kTPT], const Src *ss,
+                                          const double *sx, int m, bool corr, int nb,
+                                          const double *hrow, double (&acc)[kTPT],
+                                          float (&acc32)[kTPT]) {
+    for (int i = 0; i < m; ++i) {
+        const Src s = ss[i];
+        const double xv = sx[i];
+#pragma unroll
+        for (int u = 0; u < kTPT; ++u) {
+            const double e = entry<MODE>(N, t[u], s, corr, CHECK ? nb : -1, hrow);
+            if (ACC32)
+                acc32[u] += (float)e * (float)xv;
+            else
+                acc[u] += e * xv;
+        }
+    }
+}
+
+// Far entries of the FP64 matrix A for a tile whose targets all lie on one
+// boundary and whose sources all lie on one boundary, with no near-band pair.
+// With kappa = i (PR + i PI) / |D|^2 (D = E_q - E_p, PR + i PI = (E_q + E_p)
+// conj(D)) and the source data pre-scaled as a = w x dx / 2, b = w x dy / 2,
+// the entry times x_q is
+//   Re part (surface row, wall column): -(a PI + b PR) / |D|^2,
+//   the same negated (wall row, surface column),
+//   Im part (rows and columns of one kind): (a PR - b PI) / |D|^2,
+// less w x_q for the rank-one correction of a pair on one obstacle.
+struct SrcA {
+    double ex, ey, a, b;
+};
+enum { kFastReNeg = 0, kFastRePos = 1, kFastIm = 2 };
+
+template <int KIND, bool ECORR>
+__device__ __forceinline__ void rows_tile_a64(const Tgt (&t)[kTPT], const SrcA *sa,
+                                              const double *swx, int m, double (&acc)[kTPT]) {
+    for (int i = 0; i < m; ++i) {
+        const SrcA q = sa[i];
+#pragma unroll
+        for (int u = 0; u < kTPT; ++u) {
+            const double dr = q.ex - t[u].ex, di = q.ey - t[u].ey;
+            const double nr = q.ex + t[u].ex, ni = q.ey + t[u].ey;
+            const double inv = recip64(dr * dr + di * di);
+            const double pr = nr * dr + ni * di;
+            const double pi = ni * dr - nr * di;
+            if (KIND == kFastReNeg) acc[u] -= (q.a * pi + q.b * pr) * inv;
+            if (KIND == kFastRePos) acc[u] += (q.a * pi + q.b * pr) * inv;
+            if (KIND == kFastIm) acc[u] += (q.a * pr - q.b * pi) * inv;
+            if (ECORR) acc[u] -= swx[i];
+        }
+    }
+}
+
 template <int MODE, bool ACC32>
 __global__ __launch_bounds__(256) void k_otf_rows(Nodes N, const double *hrow, int r0, int nr,
                                                   int c0, int nc,
@@ -167,8 +223,13 @@ __global__ __launch_bounds__(256) void k_otf_rows(Nodes N, const double *hrow, i
                                                   double *__restrict__ part,
                                                   const int *active) {
     if (active && *active == 0) return;
+    constexpr bool FAST = MODE == 0 && !ACC32;        // specialised far tiles of A
+    constexpr int kFastStage = FAST ? kStage : 1;
     __shared__ Src ss[kStage];
     __shared__ double sx[kStage];
+    __shared__ SrcA sa[kFastStage];
+    __shared__ double swx[kFastStage];
+    const int wb = wave_base();
     Tgt t[kTPT];
     bool live[kTPT];
 #pragma unroll
@@ -186,21 +247,44 @@ __global__ __launch_bounds__(256) void k_otf_rows(Nodes N, const double *hrow, i
     for (int cc = cb; cc < ce; cc += kStage) {
         const int q = cc + threadIdx.x;
         if (q < ce) {
-            ss[threadIdx.x] = load_src(N, c0 + q);
-            sx[threadIdx.x] = x[q];
+            const Src sv = load_src(N, c0 + q);
+            const double xv = x[q];
+            ss[threadIdx.x] = sv;
+            sx[threadIdx.x] = xv;
+            if (FAST) {
+                const double hw = 0.5 * sv.w * xv;
+                sa[threadIdx.x] = SrcA{sv.ex, sv.ey, hw * sv.dx, hw * sv.dy};
+                swx[threadIdx.x] = sv.w * xv;
+            }
         }
         __syncthreads();
         const int m = min(kStage, ce - cc);
-        for (int i = 0; i < m; ++i) {
-            const Src s = ss[i];
-            const double xv = sx[i];
+        bool apart = true;
+        int kp = -2;               // the wave's target boundary (-1: not one boundary)
 #pragma unroll
-            for (int u = 0; u < kTPT; ++u) {
-                if (ACC32)
-                    acc32[u] += (float)entry<MODE>(N, t[u], s, corr != 0, nb, hrow) * (float)xv;
-                else
-                    acc[u] += entry<MODE>(N, t[u], s, corr != 0, nb, hrow) * xv;
+        for (int u = 0; u < kTPT; ++u) {
+            const int o0 = blockIdx.x * 256 * kTPT + u * 256 + wb;
+            apart = apart && wave_apart<false>(N, r0, o0, nr, c0 + cc, m, nb);
+            if (FAST && o0 < nr) {
+                const int k = range_boundary(N, r0 + o0, r0 + min(o0 + 63, nr - 1));
+                kp = (kp == -2 || kp == k) ? k : -1;
             }
+        }
+        const int kq = FAST ? range_boundary(N, c0 + cc, c0 + cc + m - 1) : -1;
+        if (FAST && apart && kp >= 0 && kq >= 0) {
+            const bool ec = corr != 0 && kp == kq && kp >= 2;
+            if ((kp == 0) == (kq == 0)) {
+                if (ec) rows_tile_a64<kFastIm, true>(t, sa, swx, m, acc);
+                else rows_tile_a64<kFastIm, false>(t, sa, swx, m, acc);
+            } else if (kp == 0) {
+                rows_tile_a64<kFastReNeg, false>(t, sa, swx, m, acc);
+            } else {
+                rows_tile_a64<kFastRePos, false>(t, sa, swx, m, acc);
+            }
+        } else if (apart) {
+            rows_tile<MODE, ACC32, false>(N, t, ss, sx, m, corr != 0, nb, hrow, acc, acc32);
+        } else {
+            rows_tile<MODE, ACC32, true>(N, t, ss, sx, m, corr != 0, nb, hrow, acc, acc32);
         }
         __syncthreads();
     }
@@ -208,6 +292,19 @@ __global__ __launch_bounds__(256) void k_otf_rows(Nodes N, const double *hrow, i
     for (int u = 0; u < kTPT; ++u) {
         const int r = blockIdx.x * 256 * kTPT + u * 256 + threadIdx.x;
         if (live[u]) part[(long)blockIdx.y * nr + r] = ACC32 ? (double)acc32[u] : acc[u];
+    }
+}
+
+template <int MODE, bool ACC32, bool CHECK>
+__device__ __forceinline__ void cols_tile(const Nodes &N, const Src &s, const Tgt *ts,
+                                          const double *sx, int m, bool corr, int nb,
+                                          const double *hrow, double &acc, float &acc32) {
+    for (int i = 0; i < m; ++i) {
+        const double e = entry<MODE>(N, ts[i], s, corr, CHECK ? nb : -1, hrow);
+        if (ACC32)
+            acc32 += (float)e * (float)sx[i];
+        else
+            acc += e * sx[i];
     }
 }
 
@@ -221,6 +318,7 @@ __global__ __launch_bounds__(256) void k_otf_cols(Nodes N, const double *hrow, i
     if (active && *active == 0) return;
     __shared__ Tgt ts[kStage];
     __shared__ double sx[kStage];
+    const int wb = wave_base();
     const int q = blockIdx.x * 256 + threadIdx.x;
     const bool live = q < nc;
     Src s;
@@ -237,13 +335,12 @@ __global__ __launch_bounds__(256) void k_otf_cols(Nodes N, const double *hrow, i
         }
         __syncthreads();
         const int m = min(kStage, pe - pp);
+        const bool apart = wave_apart<true>(N, c0, blockIdx.x * 256 + wb, nc, r0 + pp, m, nb);
         if (live) {
-            for (int i = 0; i < m; ++i) {
-                if (ACC32)
-                    acc32 += (float)entry<MODE>(N, ts[i], s, corr != 0, nb, hrow) * (float)sx[i];
-                else
-                    acc += entry<MODE>(N, ts[i], s, corr != 0, nb, hrow) * sx[i];
-            }
+            if (apart)
+                cols_tile<MODE, ACC32, false>(N, s, ts, sx, m, corr != 0, nb, hrow, acc, acc32);
+            else
+                cols_tile<MODE, ACC32, true>(N, s, ts, sx, m, corr != 0, nb, hrow, acc, acc32);
         }
         __syncthreads();
     }
