@@ -351,7 +351,8 @@ int wwbi_surface_fill_adjoint(wwbi_ctx *ctx, int32_t n, const double *g_x, const
 /* Export a matrix for inspection: `which` = WWBI_MAT_A (sum(M)^2) or
  * WWBI_MAT_WALL ((sum(M)-M_0)^2), row-major, FP64 (precision WWBI_FP64) or
  * FP32 (WWBI_FP32_REFINED, with the FP64 band of width `band`).
- * out (device) must hold n*n elements of that type. */
+ * out (device) must hold n*n elements of that type.  The matrix is assembled
+ * in the context's matrix workspace (padded rows) and copied out. */
 int wwbi_debug_matrix(wwbi_ctx *ctx, const wwbi_geom *g, int32_t which, int32_t precision,
                       int32_t band, void *out);
 

@@ -1739,15 +1739,23 @@ int wwbi_debug_matrix(wwbi_ctx *ctx, const wwbi_geom *g, int32_t which, int32_t 
     Ctx *c = reinterpret_cast<Ctx *>(ctx);
     int rc = c->setup(g, nullptr, 0);
     if (rc) return rc;
+    // assemble with the padded leading dimension the kernels write (a multiple
+    // of 64 elements) into the workspace matrix, then copy the dense rows out
     const int n = c->L.n;
-    if (which == WWBI_MAT_WALL) {
-        const int nw = n - c->L.off[1];
-        launch_assemble_wall64(c->L, c->N, c->hrow, (double *)out, nw, c->stream);
-    } else if (precision == WWBI_FP64) {
-        launch_assemble64(c->L, c->N, 0, (double *)out, n, c->stream);
-    } else {
-        launch_assemble32(c->L, c->N, 0, band, (float *)out, n, c->stream);
-    }
+    const int rows = which == WWBI_MAT_WALL ? n - c->L.off[1] : n;
+    const long ld = round_up(rows, 64);
+    const size_t es = precision == WWBI_FP64 ? 8 : 4;
+    rc = c->ensure_matrix((size_t)rows * ld * es);
+    if (rc) return rc;
+    if (which == WWBI_MAT_WALL)
+        launch_assemble_wall64(c->L, c->N, c->hrow, (double *)c->A, ld, c->stream);
+    else if (precision == WWBI_FP64)
+        launch_assemble64(c->L, c->N, 0, (double *)c->A, ld, c->stream);
+    else
+        launch_assemble32(c->L, c->N, 0, band, (float *)c->A, ld, c->stream);
+    if (hipMemcpy2DAsync(out, rows * es, c->A, ld * es, rows * es, rows, hipMemcpyDeviceToDevice,
+                         c->stream) != hipSuccess)
+        return WWBI_EHIP;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return WWBI_EHIP;
     return hip_ok(hipGetLastError());
 }

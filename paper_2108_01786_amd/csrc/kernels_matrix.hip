@@ -12,13 +12,20 @@ namespace {
 
 constexpr int kRowsPerAsmBlock = 32;
 
+// Kinds of a far entry of A when the target and source boundaries are
+// uniform: the real part of the source-flavour term (surface row and wall
+// column), its negative (wall row and surface column), or the imaginary part.
+enum { kFastReNeg = 0, kFastRePos = 1, kFastIm = 2 };
+
 // ---------------------------------------------------------------------------
 // assembly: one thread per column (coalesced row writes), a tile of rows per
 // block with the target data staged in LDS (read as broadcasts).
 // ---------------------------------------------------------------------------
-template <bool FP32, int WALL>
+// FP64 assembly of A (WALL = 0), of the wall operator T - I/2 on the walls
+// (WALL = 1) or of the gamma_t operator (WALL = 2): one column per thread.
+template <int WALL>
 __global__ __launch_bounds__(256) void k_assemble(Nodes N, const double *hrow, int r0, int nr,
-                                                  int c0, int nc, int corr, int band, void *out,
+                                                  int c0, int nc, int corr, double *out,
                                                   long ld) {
     __shared__ Tgt tg[kRowsPerAsmBlock];
     const int col = blockIdx.x * 256 + threadIdx.x;           // column within the output
@@ -34,25 +41,144 @@ __global__ __launch_bounds__(256) void k_assemble(Nodes N, const double *hrow, i
     if (live) s = load_src(N, c0 + col);
     const int rend = min(kRowsPerAsmBlock, nr - rbase);
     for (int i = 0; i < rend; ++i) {
-        const long idx = (long)(rbase + i) * ld + col;
-        if (WALL == 2) {
-            __builtin_nontemporal_store(live ? gt_val64(N, tg[i], s) : 0.0,
-                                        static_cast<double *>(out) + idx);
-        } else if (WALL) {
-            double v = 0.0;
-            if (live) {
+        double v = 0.0;
+        if (live) {
+            if (WALL == 2) {
+                v = gt_val64(N, tg[i], s);
+            } else if (WALL == 1) {
                 v = t_val64(N, tg[i], s, hrow);
                 if (tg[i].k == s.k && tg[i].loc == s.loc) v -= 0.5;
+            } else {
+                v = a_val64(N, tg[i], s, corr != 0);
             }
-            __builtin_nontemporal_store(v, static_cast<double *>(out) + idx);
-        } else if (FP32) {
-            __builtin_nontemporal_store(live ? a_val32(N, tg[i], s, corr != 0, band) : 0.0f,
-                                        static_cast<float *>(out) + idx);
-        } else {
-            __builtin_nontemporal_store(live ? a_val64(N, tg[i], s, corr != 0) : 0.0,
-                                        static_cast<double *>(out) + idx);
         }
+        __builtin_nontemporal_store(v, out + (long)(rbase + i) * ld + col);
     }
+}
+
+// FP32 entry of A for a pair outside the FP64 band, when the wave's columns
+// lie on one boundary (the kind of entry is then wave-uniform): the same
+// quotient as kappa32 with the hardware reciprocal, and the source data
+// pre-scaled as a = w dx / 2, b = w dy / 2 (see rows_tile_a64 for the parts).
+template <int KIND>
+__device__ __forceinline__ float a_far32_fast(const Tgt &t, double sex, double sey, float a,
+                                              float b, float ec) {
+    const float nr = (float)(sex + t.ex), ni = (float)(sey + t.ey);
+    const float dr = (float)(sex - t.ex), di = (float)(sey - t.ey);
+    const float inv = __builtin_amdgcn_rcpf(dr * dr + di * di);
+    const float pr = nr * dr + ni * di;
+    const float pi = ni * dr - nr * di;
+    if (KIND == kFastReNeg) return -(a * pi + b * pr) * inv;
+    if (KIND == kFastRePos) return (a * pi + b * pr) * inv;
+    return (a * pr - b * pi) * inv - ec;
+}
+
+// FP32 assembly of A in two passes.  The far pass writes every entry outside
+// the FP64 band (same-boundary pairs within `band` steps, diagonal included),
+// one column per thread and kRowsPerAsm32 rows per block: a wave whose live
+// columns lie on one boundary and whose row is clear of their band takes the
+// wave-uniform fast entry, any other wave a_far32 (zero inside the band).
+// The band pass then overwrites the band entries with a_val32's FP64 values.
+// Keeping the FP64 near-field code out of the far pass keeps its register
+// count, and so its occupancy, low: the far pass is bound by its stores.
+constexpr int kRowsPerAsm32 = 16;
+
+__global__ __launch_bounds__(256) void k_assemble32_far(Nodes N, int n, int corr, int band,
+                                                        float *out, long ld) {
+    __shared__ Tgt tg[kRowsPerAsm32];
+    const int wb = wave_base();
+    const int col = blockIdx.x * 256 + threadIdx.x;
+    const int rbase = blockIdx.y * kRowsPerAsm32;
+    if (threadIdx.x < kRowsPerAsm32) {
+        const int r = rbase + threadIdx.x;
+        if (r < n) tg[threadIdx.x] = load_tgt(N, r);
+    }
+    __syncthreads();
+    if (col >= ld) return;
+    const bool live = col < n;
+    const Src s = load_src(N, live ? col : 0);
+    const float fa = (float)(0.5 * s.w * s.dx), fb = (float)(0.5 * s.w * s.dy);
+    const float fw = (float)s.w;
+    // the wave's live columns [ca, cb]: on one boundary kq (local indices
+    // [lqa, lqb] of mq nodes), or kq = -1
+    const int ca = blockIdx.x * 256 + wb, cb = min(ca + 63, n - 1);
+    int kq = -1, lqa = 0, lqb = 0, mq = 0;
+    if (ca < n) {
+        kq = range_boundary(N, ca, cb);
+        lqa = N.loc[ca];
+        lqb = N.loc[cb];
+        mq = N.Mk[ca];
+    }
+    const int rend = min(kRowsPerAsm32, n - rbase);
+    float *o = out + (long)rbase * ld + col;
+    // the usual case: all rows of the tile on one boundary kp and clear of the
+    // band of all the wave's columns, one kind of entry for the whole tile
+    const int kr = kq >= 0 ? range_boundary(N, rbase, rbase + rend - 1) : -1;
+    if (kr >= 0 && ranges_apart(N, rbase, rbase + rend - 1, ca, cb, band)) {
+        if ((kr == 0) == (kq == 0)) {
+            const float ec = (corr && kr == kq && kr >= 2) ? fw : 0.0f;
+            for (int i = 0; i < rend; ++i)
+                __builtin_nontemporal_store(
+                    live ? a_far32_fast<kFastIm>(tg[i], s.ex, s.ey, fa, fb, ec) : 0.0f, o + i * ld);
+        } else if (kr == 0) {
+            for (int i = 0; i < rend; ++i)
+                __builtin_nontemporal_store(
+                    live ? a_far32_fast<kFastReNeg>(tg[i], s.ex, s.ey, fa, fb, 0.0f) : 0.0f,
+                    o + i * ld);
+        } else {
+            for (int i = 0; i < rend; ++i)
+                __builtin_nontemporal_store(
+                    live ? a_far32_fast<kFastRePos>(tg[i], s.ex, s.ey, fa, fb, 0.0f) : 0.0f,
+                    o + i * ld);
+        }
+        return;
+    }
+    for (int i = 0; i < rend; ++i) {
+        bool apart = false;
+        int kp = -1;
+        if (kq >= 0) {
+            kp = __builtin_amdgcn_readfirstlane(tg[i].k);
+            apart = kp != kq;
+            if (!apart) {
+                const int lp = __builtin_amdgcn_readfirstlane(tg[i].loc);
+                const int gap = max(0, max(lqa - lp, lp - lqb));
+                const int span = max(lp - lqa, lqb - lp);
+                apart = gap > band && mq - span > band;
+            }
+        }
+        float v;
+        if (apart) {
+            if ((kp == 0) == (kq == 0))
+                v = a_far32_fast<kFastIm>(tg[i], s.ex, s.ey, fa, fb,
+                                          (corr && kp == kq && kp >= 2) ? fw : 0.0f);
+            else if (kp == 0)
+                v = a_far32_fast<kFastReNeg>(tg[i], s.ex, s.ey, fa, fb, 0.0f);
+            else
+                v = a_far32_fast<kFastRePos>(tg[i], s.ex, s.ey, fa, fb, 0.0f);
+        } else {
+            v = a_far32(tg[i], s, corr != 0, band);
+        }
+        __builtin_nontemporal_store(live ? v : 0.0f, o + i * ld);
+    }
+}
+
+// Band pass: thread (row p, offset j) writes A(p, q) for the same-boundary
+// node q at cyclic offset j - band (every node of a boundary with at most
+// 2 band + 1 nodes, each once), evaluated in FP64 and rounded once.
+__global__ __launch_bounds__(256) void k_assemble32_band(Nodes N, int n, int corr, int band,
+                                                         float *out, long ld) {
+    const int w = 2 * band + 1;
+    const long id = (long)blockIdx.x * 256 + threadIdx.x;
+    if (id >= (long)n * w) return;
+    const int p = (int)(id / w), j = (int)(id % w);
+    const int loc = N.loc[p], M = N.Mk[p];
+    const bool whole = w >= M;
+    if (whole && j >= M) return;
+    int l = whole ? j : loc + j - band;
+    if (l < 0) l += M;
+    if (l >= M) l -= M;
+    const int q = p - loc + l;
+    out[(long)p * ld + q] = (float)a_val64(N, load_tgt(N, p), load_src(N, q), corr != 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -193,7 +319,6 @@ __device__ __forceinline__ void rows_tile(const Nodes &N, const Tgt (&t)[kTPT], 
 struct SrcA {
     double ex, ey, a, b;
 };
-enum { kFastReNeg = 0, kFastRePos = 1, kFastIm = 2 };
 
 template <int KIND, bool ECORR>
 __device__ __forceinline__ void rows_tile_a64(const Tgt (&t)[kTPT], const SrcA *sa,
@@ -379,37 +504,34 @@ int rflavour_nsplit(int nr, int nc, int transpose) {
 
 void launch_assemble64(const Layout &L, const Nodes &N, int flags, double *A, long ld,
                        hipStream_t st) {
-    const double *hrow = nullptr;
     const int n = L.n;
     dim3 grid(cdiv(ld, 256), cdiv(n, kRowsPerAsmBlock));
     const int corr = (flags & WWBI_FLAG_NO_CORRECTION) ? 0 : 1;
-    hipLaunchKernelGGL((k_assemble<false, 0>), grid, dim3(256), 0, st, N, hrow, 0, n, 0, n, corr, 0,
-                       (void *)A, ld);
+    hipLaunchKernelGGL(k_assemble<0>, grid, dim3(256), 0, st, N, nullptr, 0, n, 0, n, corr, A, ld);
 }
 
 void launch_assemble32(const Layout &L, const Nodes &N, int flags, int band, float *A, long ld,
                        hipStream_t st) {
-    const double *hrow = nullptr;
     const int n = L.n;
-    dim3 grid(cdiv(ld, 256), cdiv(n, kRowsPerAsmBlock));
     const int corr = (flags & WWBI_FLAG_NO_CORRECTION) ? 0 : 1;
-    hipLaunchKernelGGL((k_assemble<true, 0>), grid, dim3(256), 0, st, N, hrow, 0, n, 0, n, corr,
-                       band, (void *)A, ld);
+    dim3 grid(cdiv(ld, 256), cdiv(n, kRowsPerAsm32));
+    hipLaunchKernelGGL(k_assemble32_far, grid, dim3(256), 0, st, N, n, corr, band, A, ld);
+    const long nbw = (long)n * (2 * band + 1);
+    hipLaunchKernelGGL(k_assemble32_band, dim3(cdiv(nbw, 256)), dim3(256), 0, st, N, n, corr, band,
+                       A, ld);
 }
 
 void launch_assemble_gt64(const Layout &L, const Nodes &N, double *B, long ld, hipStream_t st) {
     const int n = L.n;
     dim3 grid(cdiv(ld, 256), cdiv(n, kRowsPerAsmBlock));
-    hipLaunchKernelGGL((k_assemble<false, 2>), grid, dim3(256), 0, st, N, nullptr, 0, n, 0, n, 1, 0,
-                       (void *)B, ld);
+    hipLaunchKernelGGL(k_assemble<2>, grid, dim3(256), 0, st, N, nullptr, 0, n, 0, n, 1, B, ld);
 }
 
 void launch_assemble_wall64(const Layout &L, const Nodes &N, const double *hrow, double *W, long ld,
                             hipStream_t st) {
     const int c0 = L.off[1], nw = L.n - L.off[1];
     dim3 grid(cdiv(ld, 256), cdiv(nw, kRowsPerAsmBlock));
-    hipLaunchKernelGGL((k_assemble<false, 1>), grid, dim3(256), 0, st, N, hrow, c0, nw, c0, nw, 1, 0,
-                       (void *)W, ld);
+    hipLaunchKernelGGL(k_assemble<1>, grid, dim3(256), 0, st, N, hrow, c0, nw, c0, nw, 1, W, ld);
 }
 
 static int near_width(int band) { return band > kNearBand ? band : kNearBand; }
