@@ -79,7 +79,10 @@ def test_matrix_fp64_entrywise(ww, ctx, name):
     assert np.abs(A - Ar).max() <= 1e-13, np.abs(A - Ar).max()
 
 
-@pytest.mark.parametrize("name", ["ragged", "c1"])
+# tiny: every boundary fits inside the FP64 band (M <= 2 band + 1); ragged:
+# tiles and waves that straddle boundary ends; c2: tiles on one boundary each,
+# where the assembly takes its uniform fast entries
+@pytest.mark.parametrize("name", ["tiny", "ragged", "c1", "c2"])
 def test_matrix_fp32_band_and_offband(ww, ctx, name):
     say(f"case matrix_fp32 {name}")
     cfg = _cfg(name)
@@ -103,7 +106,9 @@ def test_matrix_fp32_band_and_offband(ww, ctx, name):
     assert err.max() <= 1e-6 * np.abs(Ar).max(), err.max()
 
 
-@pytest.mark.parametrize("name", ["ragged", "c1"])
+# c2 has target blocks and source tiles inside single boundaries, so the
+# on-the-fly products take their specialised far tiles there
+@pytest.mark.parametrize("name", ["ragged", "c1", "c2"])
 @pytest.mark.parametrize("mode", ["stored", "otf"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("transpose", [False, True])
