@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--inner-tol", type=float, default=3e-7)
-    ap.add_argument("--poll", type=int, default=4)
+    ap.add_argument("--poll", type=int, default=2)
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (counter calibration)")
     ap.add_argument("--workload", default="solve", choices=["solve", "large-stages"],

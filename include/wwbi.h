@@ -103,7 +103,7 @@ typedef struct {
     int32_t max_iter;    /* budget of Arnoldi steps (all cycles, all refinement steps)     */
     int32_t precision;   /* WWBI_FP64 or WWBI_FP32_REFINED                                 */
     int32_t matvec;      /* WWBI_MATVEC_*                                                  */
-    int32_t poll_every;  /* Arnoldi steps between host reads of the convergence flag       */
+    int32_t poll_every;  /* Arnoldi steps between host checks for the end of a cycle      */
     int32_t max_refine;  /* FP32_REFINED: maximum refinement steps                         */
     int32_t band;        /* FP32: same-boundary pairs with cyclic |l-m| <= band are
                             evaluated in FP64 and rounded (near-singular kernel)          */
@@ -127,7 +127,7 @@ typedef struct {
 } wwbi_report;
 
 /* Fill *o with defaults: tol 1e-13, inner_tol 3e-7, restart 100, max_iter 2000,
- * FP64, stored matvec, poll every 4 steps, max_refine 8, band 16, no flags. */
+ * FP64, stored matvec, poll every 2 steps, max_refine 8, band 16, no flags. */
 void wwbi_default_opts(wwbi_opts *o);
 
 /* Human-readable name of a status code (static string). */

@@ -810,7 +810,7 @@ void wwbi_default_opts(wwbi_opts *o) {
     o->max_iter = 2000;
     o->precision = WWBI_FP64;
     o->matvec = WWBI_MATVEC_AUTO;
-    o->poll_every = 4;
+    o->poll_every = 2;
     o->max_refine = 8;
     o->band = 16;
     o->flags = 0;

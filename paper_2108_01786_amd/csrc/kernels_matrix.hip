@@ -420,6 +420,30 @@ __global__ __launch_bounds__(256) void k_otf_rows(Nodes N, const double *hrow, i
     }
 }
 
+// Transposed counterpart of rows_tile_a64: the thread's source q is fixed
+// (a = w dx / 2, b = w dy / 2, E_q = (sex, sey)) and the staged targets carry
+// (E_p, x_p); acc gains A(p, q) x_p for every target of the tile.
+struct TgtA {
+    double ex, ey, x;
+};
+
+template <int KIND, bool ECORR>
+__device__ __forceinline__ void cols_tile_a64(double sex, double sey, double a, double b,
+                                              double w, const TgtA *ta, int m, double &acc) {
+    for (int i = 0; i < m; ++i) {
+        const TgtA p = ta[i];
+        const double dr = sex - p.ex, di = sey - p.ey;
+        const double nr = sex + p.ex, ni = sey + p.ey;
+        const double ix = recip64(dr * dr + di * di) * p.x;
+        const double pr = nr * dr + ni * di;
+        const double pi = ni * dr - nr * di;
+        if (KIND == kFastReNeg) acc -= (a * pi + b * pr) * ix;
+        if (KIND == kFastRePos) acc += (a * pi + b * pr) * ix;
+        if (KIND == kFastIm) acc += (a * pr - b * pi) * ix;
+        if (ECORR) acc -= w * p.x;
+    }
+}
+
 template <int MODE, bool ACC32, bool CHECK>
 __device__ __forceinline__ void cols_tile(const Nodes &N, const Src &s, const Tgt *ts,
                                           const double *sx, int m, bool corr, int nb,
@@ -441,13 +465,20 @@ __global__ __launch_bounds__(256) void k_otf_cols(Nodes N, const double *hrow, i
                                                   double *__restrict__ part,
                                                   const int *active) {
     if (active && *active == 0) return;
+    constexpr bool FAST = MODE == 0 && !ACC32;        // specialised far tiles of A
+    constexpr int kFastStage = FAST ? kStage : 1;
     __shared__ Tgt ts[kStage];
     __shared__ double sx[kStage];
+    __shared__ TgtA ta[kFastStage];
     const int wb = wave_base();
     const int q = blockIdx.x * 256 + threadIdx.x;
     const bool live = q < nc;
     Src s;
     if (live) s = load_src(N, c0 + q);
+    const double fa = live ? 0.5 * s.w * s.dx : 0.0, fb = live ? 0.5 * s.w * s.dy : 0.0;
+    // the wave's source boundary (-1: the wave's columns cross a boundary end)
+    const int o0 = blockIdx.x * 256 + wb;
+    const int kq = (FAST && o0 < nc) ? range_boundary(N, c0 + o0, c0 + min(o0 + 63, nc - 1)) : -1;
     const int pb = blockIdx.y * chunk;
     const int pe = min(nr, pb + chunk);
     double acc = 0.0;
@@ -455,17 +486,34 @@ __global__ __launch_bounds__(256) void k_otf_cols(Nodes N, const double *hrow, i
     for (int pp = pb; pp < pe; pp += kStage) {
         const int p = pp + threadIdx.x;
         if (p < pe) {
-            ts[threadIdx.x] = load_tgt(N, r0 + p);
-            sx[threadIdx.x] = x[p];
+            const Tgt tv = load_tgt(N, r0 + p);
+            const double xv = x[p];
+            ts[threadIdx.x] = tv;
+            sx[threadIdx.x] = xv;
+            if (FAST) ta[threadIdx.x] = TgtA{tv.ex, tv.ey, xv};
         }
         __syncthreads();
         const int m = min(kStage, pe - pp);
-        const bool apart = wave_apart<true>(N, c0, blockIdx.x * 256 + wb, nc, r0 + pp, m, nb);
+        const bool apart = wave_apart<true>(N, c0, o0, nc, r0 + pp, m, nb);
+        const int kp = (FAST && kq >= 0) ? range_boundary(N, r0 + pp, r0 + pp + m - 1) : -1;
         if (live) {
-            if (apart)
+            if (FAST && apart && kp >= 0 && kq >= 0) {
+                const double w = s.w;
+                if ((kp == 0) == (kq == 0)) {
+                    if (corr != 0 && kp == kq && kp >= 2)
+                        cols_tile_a64<kFastIm, true>(s.ex, s.ey, fa, fb, w, ta, m, acc);
+                    else
+                        cols_tile_a64<kFastIm, false>(s.ex, s.ey, fa, fb, w, ta, m, acc);
+                } else if (kp == 0) {
+                    cols_tile_a64<kFastReNeg, false>(s.ex, s.ey, fa, fb, w, ta, m, acc);
+                } else {
+                    cols_tile_a64<kFastRePos, false>(s.ex, s.ey, fa, fb, w, ta, m, acc);
+                }
+            } else if (apart) {
                 cols_tile<MODE, ACC32, false>(N, s, ts, sx, m, corr != 0, nb, hrow, acc, acc32);
-            else
+            } else {
                 cols_tile<MODE, ACC32, true>(N, s, ts, sx, m, corr != 0, nb, hrow, acc, acc32);
+            }
         }
         __syncthreads();
     }

@@ -197,7 +197,7 @@ class DeviceGeometry:
 
 
 def make_opts(tol=1e-13, inner_tol=3e-7, restart=100, max_iter=2000, precision=FP64,
-              matvec=MATVEC_AUTO, poll_every=4, max_refine=8, band=16, flags=0,
+              matvec=MATVEC_AUTO, poll_every=2, max_refine=8, band=16, flags=0,
               x0: Optional[torch.Tensor] = None) -> _Opts:
     o = _Opts()
     load_library().wwbi_default_opts(C.byref(o))
