@@ -769,7 +769,8 @@ int Ctx::refine_multi(int n, long ld, const double *B, double *X, int nr, const 
             const double rel = bnrm[s] > 0 ? rn[s] / bnrm[s] : 0.0;
             worst = std::max(worst, rel);
             done = done && rel <= o.tol;
-            stalled = stalled || !std::isfinite(rn[s]) || (k > 0 && rel > o.tol && rn[s] > 0.5 * prev[s]);
+            stalled = stalled || !std::isfinite(rn[s]) ||
+                      (k > 0 && rel > o.tol && rn[s] > 0.5 * prev[s]);
         }
         st.rel_resid = worst;
         if (done) { status = WWBI_OK; break; }

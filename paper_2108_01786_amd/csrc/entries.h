@@ -358,14 +358,16 @@ __device__ __forceinline__ float a_far32(const Tgt &t, const Src &s, bool corr, 
     return v * (float)s.w - ecorr;
 }
 
-__device__ __forceinline__ double psi_far64(const Tgt &t, const Src &s, const double *hall, int nb) {
+__device__ __forceinline__ double psi_far64(const Tgt &t, const Src &s, const double *hall,
+                                            int nb) {
     if (in_band(t, s, nb)) return 0.0;
     double cr, ci;
     kappa64_far(t, s, cr, ci);
     return psi_s(t, s, cr, ci, hall);
 }
 
-__device__ __forceinline__ double tan_far64(const Tgt &t, const Src &s, const double *hall, int nb) {
+__device__ __forceinline__ double tan_far64(const Tgt &t, const Src &s, const double *hall,
+                                            int nb) {
     if (in_band(t, s, nb)) return 0.0;
     double cr, ci;
     kappa64_far(t, s, cr, ci);

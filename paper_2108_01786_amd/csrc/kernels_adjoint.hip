@@ -25,7 +25,9 @@ constexpr int kStage = 256;
 struct Cx {
     double re, im;
 };
-__device__ __forceinline__ Cx cmul(Cx a, Cx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ __forceinline__ Cx cmul(Cx a, Cx b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
 __device__ __forceinline__ Cx ctimes_i(Cx a) { return {-a.im, a.re}; }
 __device__ __forceinline__ Cx cscale(Cx a, double s) { return {a.re * s, a.im * s}; }
 

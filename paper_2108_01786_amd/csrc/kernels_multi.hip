@@ -45,7 +45,8 @@ template <typename T>
 __device__ __forceinline__ void load4(const T *p, int k, int end, T (&v)[4], bool stream) {
     if (k + 3 < end) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) v[t] = stream ? __builtin_nontemporal_load(p + k + t) : p[k + t];
+        for (int t = 0; t < 4; ++t)
+            v[t] = stream ? __builtin_nontemporal_load(p + k + t) : p[k + t];
     } else {
 #pragma unroll
         for (int t = 0; t < 4; ++t) v[t] = (k + t < end) ? p[k + t] : (T)0;
