@@ -298,3 +298,25 @@ def test_warm_start(ww, ctx, prec):
     say(f"  cold iters {r3.iters} warm iters {r2.iters}")
     assert r2.iters < r3.iters
     assert float((U2 - U3).abs().max() / U3.abs().max()) <= 1e-11
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_poll_interval_does_not_change_results(ww, ctx, prec):
+    """The host only learns where a GMRES cycle ends (from the state the ending
+    kernel publishes); steps enqueued past the end do nothing.  So any polling
+    interval gives the same steps and bitwise the same solution, also when the
+    restart length cuts cycles short (several cycles per solve)."""
+    say(f"case poll interval {prec}")
+    cfg = make_config(1)
+    dg = ww.DeviceGeometry.from_synth(cfg["geom"], DEV)
+    phi = torch.as_tensor(cfg["phi"], device=DEV)
+    for restart in (100, 7 if prec == "fp64" else 10):
+        kw = dict(tol=1e-13 if prec == "fp64" else 1e-14, restart=restart, max_refine=30,
+                  precision=ww.FP64 if prec == "fp64" else ww.FP32_REFINED)
+        runs = [ctx.solve_phi(dg, phi, poll_every=p, **kw) for p in (1, 2, 3, 8, 50)]
+        U0, om0, _, r0 = runs[0]
+        assert r0.status == 0
+        say(f"  restart {restart}: iters {r0.iters} cycles {r0.restarts}")
+        for U, om, _, r in runs[1:]:
+            assert r.status == 0 and r.iters == r0.iters and r.restarts == r0.restarts
+            assert torch.equal(om, om0) and torch.equal(U, U0)
