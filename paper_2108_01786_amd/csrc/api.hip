@@ -493,8 +493,7 @@ void Ctx::eval_U_from_gamma(const double *gamma, double *U) {
 }
 
 void Ctx::gamma_from_omega(const double *omega, double *gamma) {
-    launch_circulant_apply(L, rowD, omega, gamma, -1.0, 0.0, 0, 0, stream);
-    launch_circulant_apply(L, rowD, omega, gamma, 1.0, 0.0, 1, L.nb - 1, stream);
+    launch_circulant_apply2(L, rowD, omega, gamma, -1.0, 1.0, 0.0, 0, L.nb - 1, stream);
 }
 
 int Ctx::check_opts(const wwbi_opts *o) {
@@ -1563,8 +1562,7 @@ int wwbi_adjoint_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, con
     launch_rflavour(c->L, c->N, c->hrow, 2, 1, 0, n0, 0, n, cv, c->part, nullptr, sm);
     launch_reduce_partials(n, c->part, rflavour_nsplit(n0, n, 1), nullptr, 1.0, gbar, nullptr, sm);
     launch_circulant_apply(c->L, c->rowH, cv, gbar, -0.5, 1.0, 0, 0, sm);
-    launch_circulant_apply(c->L, c->rowD, gbar, mu, 1.0, 0.0, 0, 0, sm);
-    launch_circulant_apply(c->L, c->rowD, gbar, mu, -1.0, 0.0, 1, c->L.nb - 1, sm);
+    launch_circulant_apply2(c->L, c->rowD, gbar, mu, 1.0, -1.0, 0.0, 0, c->L.nb - 1, sm);
     hipEventRecord(c->ev[1], sm);
     // transpose solve A^T lambda = mu
     const bool stored = o->matvec != WWBI_MATVEC_ON_THE_FLY;

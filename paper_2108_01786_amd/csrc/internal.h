@@ -119,9 +119,14 @@ void launch_energy(int n0, const Nodes &N, const Flow &F, double tau, double gra
                    const double *tmv, const double *psi_k, double *e, double *E, hipStream_t st);
 // op: WWBI_OP_D, WWBI_OP_H or kOpHalfCot, one row per boundary laid out like the nodes
 void launch_circulant_rows(const Layout &L, int op, double *rows, hipStream_t st);
+// out = alpha C_k f + beta out on boundaries first..last (one launch);
+// launch_circulant_apply2 scales boundary 0 by alpha0 and the others by alpha
 void launch_circulant_apply(const Layout &L, const double *rows, const double *f, double *out,
                             double alpha, double beta, int first_block, int last_block,
                             hipStream_t st);
+void launch_circulant_apply2(const Layout &L, const double *rows, const double *f, double *out,
+                             double alpha0, double alpha, double beta, int first_block,
+                             int last_block, hipStream_t st);
 void launch_circ_row1(int M, int op, double *row, hipStream_t st);
 void launch_circ_apply1(int M, const double *row, const double *f, double *out, double alpha,
                         double beta, hipStream_t st);

@@ -183,15 +183,14 @@ __global__ void k_circ_row1(int M, int op, double *row) {
 // a fixed order at the end.
 constexpr int kCT = 64;
 constexpr int kCW = 16;
-__global__ __launch_bounds__(kCT * kCW) void k_circ_tile(int M, const double *__restrict__ row,
-                                                         const double *__restrict__ f,
-                                                         double *out, double alpha,
-                                                         double beta) {
+// out[m0 .. m0+63] of one boundary of M nodes (see above).
+__device__ __forceinline__ void circ_tile(int M, int m0, const double *__restrict__ row,
+                                          const double *__restrict__ f, double *out,
+                                          double alpha, double beta) {
     __shared__ double fs[kCW][kCT];
     __shared__ double rs[kCW][2 * kCT];
     __shared__ double red[kCW][kCT];
     const int lane = threadIdx.x % kCT, wv = threadIdx.x / kCT;
-    const int m0 = blockIdx.x * kCT;
     const int ntiles = (M + kCT - 1) / kCT;
     const int rounds = (ntiles + kCW - 1) / kCW;
     double acc = 0.0;
@@ -226,6 +225,31 @@ __global__ __launch_bounds__(kCT * kCW) void k_circ_tile(int M, const double *__
         const int m = m0 + lane;
         if (m < M) out[m] = alpha * s + (beta != 0.0 ? beta * out[m] : 0.0);
     }
+}
+
+__global__ __launch_bounds__(kCT * kCW) void k_circ_tile(int M, const double *__restrict__ row,
+                                                         const double *__restrict__ f,
+                                                         double *out, double alpha,
+                                                         double beta) {
+    circ_tile(M, blockIdx.x * kCT, row, f, out, alpha, beta);
+}
+
+// The same for boundaries first..last of a layout in one launch (their tiles
+// run side by side): block b takes the tile of the boundary its index falls
+// in; alpha0 scales boundary 0, alpha every other one.
+__global__ __launch_bounds__(kCT * kCW) void k_circ_tiles(Layout L, int first, int last,
+                                                          const double *__restrict__ rows,
+                                                          const double *__restrict__ f,
+                                                          double *out, double alpha0,
+                                                          double alpha, double beta) {
+    int b = blockIdx.x, k = first;
+    for (; k < last; ++k) {
+        const int t = (L.off[k + 1] - L.off[k] + kCT - 1) / kCT;
+        if (b < t) break;
+        b -= t;
+    }
+    const int o = L.off[k], M = L.off[k + 1] - o;
+    circ_tile(M, b * kCT, rows + o, f + o, out + o, k == 0 ? alpha0 : alpha, beta);
 }
 
 // psi|_k = (1/M_k) sum_m omega_(k,m) for k >= 2 (Sec. 3.2); one block per boundary.
@@ -425,14 +449,20 @@ void launch_circulant_rows(const Layout &L, int op, double *rows, hipStream_t st
     hipLaunchKernelGGL(k_circ_rows, dim3(cdiv(L.n, 256)), dim3(256), 0, st, L, op, rows);
 }
 
+void launch_circulant_apply2(const Layout &L, const double *rows, const double *f, double *out,
+                             double alpha0, double alpha, double beta, int first_block,
+                             int last_block, hipStream_t st) {
+    int tiles = 0;
+    for (int k = first_block; k <= last_block; ++k) tiles += cdiv(L.off[k + 1] - L.off[k], kCT);
+    if (tiles == 0) return;
+    hipLaunchKernelGGL(k_circ_tiles, dim3(tiles), dim3(kCT * kCW), 0, st, L, first_block,
+                       last_block, rows, f, out, alpha0, alpha, beta);
+}
+
 void launch_circulant_apply(const Layout &L, const double *rows, const double *f, double *out,
                             double alpha, double beta, int first_block, int last_block,
                             hipStream_t st) {
-    for (int k = first_block; k <= last_block; ++k) {
-        const int o = L.off[k], M = L.off[k + 1] - o;
-        hipLaunchKernelGGL(k_circ_tile, dim3(cdiv(M, kCT)), dim3(kCT * kCW), 0, st, M, rows + o,
-                           f + o, out + o, alpha, beta);
-    }
+    launch_circulant_apply2(L, rows, f, out, alpha, alpha, beta, first_block, last_block, st);
 }
 
 void launch_circ_row1(int M, int op, double *row, hipStream_t st) {
