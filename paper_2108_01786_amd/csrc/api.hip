@@ -57,7 +57,7 @@ int Ctx::ensure(int n, int restart) {
     G(gv, capg, rr + 1);
     G(yv, capy, rr + 1);
     G(P, capP, 3 * 64 * (rr + 1) + 64);
-    G(part, cappart, 130 * nn + 64);   // up to 128 far slices + the near-band slice
+    G(part, cappart, 258 * nn + 64);   // up to 256 far slices + the near-band slice
     Gi(bid, capbid, nn);
     Gi(loc, caploc, nn);
     Gi(Mk, capMk, nn);

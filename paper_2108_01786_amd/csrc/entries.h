@@ -71,6 +71,17 @@ __device__ __forceinline__ double recip64(double x) {
     return fma(r, e, r);
 }
 
+// The same from the FP32 reciprocal estimate (1 ulp of FP32, about 2^-23):
+// two Newton steps reach 2^-46 and then the FP64 rounding.  For x within the
+// FP32 normal range (every |E_q - E_p|^2 of a far pair).
+__device__ __forceinline__ double recip64_from32(double x) {
+    double r = (double)__builtin_amdgcn_rcpf((float)x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 __device__ __forceinline__ int cyc_dist(int a, int b, int M) {
     int d = a - b;
     if (d < 0) d = -d;

@@ -191,8 +191,12 @@ __global__ __launch_bounds__(256) void k_assemble32_band(Nodes N, int n, int cor
 // 6 / 7 = source-flavour maps KS / GS of the F operators, 8 = gamma_t operator.
 // ---------------------------------------------------------------------------
 constexpr int kStage = 256;
-constexpr int kOtfBlocks = 2048;     // target grid size of an on-the-fly product
-constexpr int kOtfMaxSlices = 128;   // at most this many partial slices (+ the near band)
+// Sources (targets) staged per pass of the forward (transpose) product: 128
+// keeps a block's LDS near 13 KB, so that LDS does not limit the resident
+// blocks below the wave limit.
+constexpr int kOtfStage = 128;
+constexpr int kOtfBlocks = 8192;     // target grid size of an on-the-fly product
+constexpr int kOtfMaxSlices = 256;   // at most this many partial slices (+ the near band)
 
 // Far part of an entry (zero inside the near band of width nb).
 template <int MODE>
@@ -283,7 +287,7 @@ __global__ __launch_bounds__(256) void k_near_band(Nodes N, const double *hrow, 
 // Forward product: each thread owns kTPT target rows (rows t, t + 256, ... of
 // the block's 256 * kTPT), so every source staged in LDS is read once for
 // kTPT entries.
-constexpr int kTPT = 2;
+constexpr int kTPT = 1;
 
 // One staged tile of the forward product; CHECK = false when the tile is
 // known to hold no near-band pair (the entries are then the same as with
@@ -329,7 +333,7 @@ __device__ __forceinline__ void rows_tile_a64(const Tgt (&t)[kTPT], const SrcA *
         for (int u = 0; u < kTPT; ++u) {
             const double dr = q.ex - t[u].ex, di = q.ey - t[u].ey;
             const double nr = q.ex + t[u].ex, ni = q.ey + t[u].ey;
-            const double inv = recip64(dr * dr + di * di);
+            const double inv = recip64_from32(dr * dr + di * di);
             const double pr = nr * dr + ni * di;
             const double pi = ni * dr - nr * di;
             if (KIND == kFastReNeg) acc[u] -= (q.a * pi + q.b * pr) * inv;
@@ -349,9 +353,9 @@ __global__ __launch_bounds__(256) void k_otf_rows(Nodes N, const double *hrow, i
                                                   const int *active) {
     if (active && *active == 0) return;
     constexpr bool FAST = MODE == 0 && !ACC32;        // specialised far tiles of A
-    constexpr int kFastStage = FAST ? kStage : 1;
-    __shared__ Src ss[kStage];
-    __shared__ double sx[kStage];
+    constexpr int kFastStage = FAST ? kOtfStage : 1;
+    __shared__ Src ss[kOtfStage];
+    __shared__ double sx[kOtfStage];
     __shared__ SrcA sa[kFastStage];
     __shared__ double swx[kFastStage];
     const int wb = wave_base();
@@ -369,9 +373,9 @@ __global__ __launch_bounds__(256) void k_otf_rows(Nodes N, const double *hrow, i
     float acc32[kTPT];
 #pragma unroll
     for (int u = 0; u < kTPT; ++u) { acc[u] = 0.0; acc32[u] = 0.0f; }
-    for (int cc = cb; cc < ce; cc += kStage) {
+    for (int cc = cb; cc < ce; cc += kOtfStage) {
         const int q = cc + threadIdx.x;
-        if (q < ce) {
+        if (threadIdx.x < kOtfStage && q < ce) {
             const Src sv = load_src(N, c0 + q);
             const double xv = x[q];
             ss[threadIdx.x] = sv;
@@ -383,7 +387,7 @@ __global__ __launch_bounds__(256) void k_otf_rows(Nodes N, const double *hrow, i
             }
         }
         __syncthreads();
-        const int m = min(kStage, ce - cc);
+        const int m = min(kOtfStage, ce - cc);
         bool apart = true;
         int kp = -2;               // the wave's target boundary (-1: not one boundary)
 #pragma unroll
@@ -434,7 +438,7 @@ __device__ __forceinline__ void cols_tile_a64(double sex, double sey, double a, 
         const TgtA p = ta[i];
         const double dr = sex - p.ex, di = sey - p.ey;
         const double nr = sex + p.ex, ni = sey + p.ey;
-        const double ix = recip64(dr * dr + di * di) * p.x;
+        const double ix = recip64_from32(dr * dr + di * di) * p.x;
         const double pr = nr * dr + ni * di;
         const double pi = ni * dr - nr * di;
         if (KIND == kFastReNeg) acc -= (a * pi + b * pr) * ix;
@@ -466,9 +470,9 @@ __global__ __launch_bounds__(256) void k_otf_cols(Nodes N, const double *hrow, i
                                                   const int *active) {
     if (active && *active == 0) return;
     constexpr bool FAST = MODE == 0 && !ACC32;        // specialised far tiles of A
-    constexpr int kFastStage = FAST ? kStage : 1;
-    __shared__ Tgt ts[kStage];
-    __shared__ double sx[kStage];
+    constexpr int kFastStage = FAST ? kOtfStage : 1;
+    __shared__ Tgt ts[kOtfStage];
+    __shared__ double sx[kOtfStage];
     __shared__ TgtA ta[kFastStage];
     const int wb = wave_base();
     const int q = blockIdx.x * 256 + threadIdx.x;
@@ -483,9 +487,9 @@ __global__ __launch_bounds__(256) void k_otf_cols(Nodes N, const double *hrow, i
     const int pe = min(nr, pb + chunk);
     double acc = 0.0;
     float acc32 = 0.0f;
-    for (int pp = pb; pp < pe; pp += kStage) {
+    for (int pp = pb; pp < pe; pp += kOtfStage) {
         const int p = pp + threadIdx.x;
-        if (p < pe) {
+        if (threadIdx.x < kOtfStage && p < pe) {
             const Tgt tv = load_tgt(N, r0 + p);
             const double xv = x[p];
             ts[threadIdx.x] = tv;
@@ -493,7 +497,7 @@ __global__ __launch_bounds__(256) void k_otf_cols(Nodes N, const double *hrow, i
             if (FAST) ta[threadIdx.x] = TgtA{tv.ex, tv.ey, xv};
         }
         __syncthreads();
-        const int m = min(kStage, pe - pp);
+        const int m = min(kOtfStage, pe - pp);
         const bool apart = wave_apart<true>(N, c0, o0, nc, r0 + pp, m, nb);
         const int kp = (FAST && kq >= 0) ? range_boundary(N, r0 + pp, r0 + pp + m - 1) : -1;
         if (live) {
