@@ -183,7 +183,22 @@ class DeviceGeometry:
     def nb(self) -> int:
         return len(self.M)
 
+    def _fields(self):
+        return (self.x, self.y, self.dx, self.dy, self.ddx, self.ddy, self.psi_wall, self.zc,
+                self.a)
+
+    def _key(self):
+        # the cache holds the field objects, so equal ids mean the same objects
+        return (tuple(self.M), self.V1) + tuple(map(id, self._fields()))
+
     def c_struct(self) -> _Geom:
+        """The C view of the geometry; rebuilt only when a field was replaced
+        (building it costs tens of microseconds of Python per call)."""
+        key = self._key()
+        if getattr(self, "_cache", None) is not None and self._cache[0] == key:
+            return self._cache[1]
+        if tuple(self.M) != tuple(self._M):
+            self._M = (C.c_int32 * len(self.M))(*self.M)
         g = _Geom()
         g.nb = len(self.M)
         g.M = C.cast(self._M, C.POINTER(C.c_int32))
@@ -193,6 +208,7 @@ class DeviceGeometry:
         g.a = self.a.ctypes.data_as(C.POINTER(C.c_double))
         g.V1 = self.V1
         g.psi_wall = _ptr(self.psi_wall)
+        self._cache = (key, g, self._fields())
         return g
 
 
