@@ -78,7 +78,8 @@ __device__ __forceinline__ float a_far32_fast(const Tgt &t, double sex, double s
 // one column per thread and kRowsPerAsm32 rows per block: a wave whose live
 // columns lie on one boundary and whose row is clear of their band takes the
 // wave-uniform fast entry, any other wave a_far32 (zero inside the band).
-// The band pass then overwrites the band entries with a_val32's FP64 values.
+// The band pass then overwrites the band entries with FP64 values rounded
+// once, as a_val32 gives them.
 // Keeping the FP64 near-field code out of the far pass keeps its register
 // count, and so its occupancy, low: the far pass is bound by its stores.
 constexpr int kRowsPerAsm32 = 16;
@@ -190,7 +191,7 @@ __global__ __launch_bounds__(256) void k_assemble32_band(Nodes N, int n, int cor
 // 4 = stream-function map P on the surface, 5 = tangential map Q,
 // 6 / 7 = source-flavour maps KS / GS of the F operators, 8 = gamma_t operator.
 // ---------------------------------------------------------------------------
-constexpr int kStage = 256;
+constexpr int kStage = 256;          // chunk granularity of otf_chunk (adjoint contractions)
 // Sources (targets) staged per pass of the forward (transpose) product: 128
 // keeps a block's LDS near 13 KB, so that LDS does not limit the resident
 // blocks below the wave limit.
@@ -285,8 +286,9 @@ __global__ __launch_bounds__(256) void k_near_band(Nodes N, const double *hrow, 
 }
 
 // Forward product: each thread owns kTPT target rows (rows t, t + 256, ... of
-// the block's 256 * kTPT), so every source staged in LDS is read once for
-// kTPT entries.
+// the block's 256 * kTPT).  One row per thread and many short blocks measured
+// fastest: the FP64 entry is a long dependent chain, and more resident blocks
+// hide it better than more rows per thread (2 rows: +3%, 4 rows: +18%).
 constexpr int kTPT = 1;
 
 // One staged tile of the forward product; CHECK = false when the tile is
