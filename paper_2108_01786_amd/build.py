@@ -18,7 +18,7 @@ OUT = os.path.join(PKG, "libwwbi.so")
 BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["api.hip", "kernels_geom.hip", "kernels_matrix.hip", "kernels_gemv.hip",
-           "kernels_gemvt.hip", "kernels_gmres.hip", "kernels_adjoint.hip", "kernels_multi.hip",
+           "kernels_reduce.hip", "kernels_gmres.hip", "kernels_adjoint.hip", "kernels_multi.hip",
            "kernels_evolve.hip", "kernels_interior.hip"]
 
 HIPCC_FLAGS = [

@@ -18,10 +18,8 @@ enum OpKind {
     OP_A_S32,       // stored FP32 (FP32 accumulation)
     OP_A_O64,       // on the fly FP64
     OP_A_O32,       // on the fly FP32 (FP64 band and limits)
-    OP_AT_S64,      // transposes of the above
-    OP_AT_S32,
-    OP_AT_O64,
-    OP_AT_O32,
+    OP_AT_O64,      // transposes on the fly (a stored transpose is assembled as
+    OP_AT_O32,      // A^T and applied with OP_A_S64 / OP_A_S32)
     OP_W_S64,       // vortex-sheet wall operator, stored FP64
     OP_W_O64,       // on the fly FP64
     OP_GT_S64,      // gamma_t operator (Sec. 4.2), stored FP64

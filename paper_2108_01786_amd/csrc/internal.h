@@ -202,6 +202,12 @@ void launch_assemble64(const Layout &L, const Nodes &N, int flags, double *A, lo
                        hipStream_t st);
 void launch_assemble32(const Layout &L, const Nodes &N, int flags, int band, float *A, long ld,
                        hipStream_t st);
+// the transpose A^T in the same layout (row q = source q), for products with
+// A^T by the forward stored matvec
+void launch_assemble32_T(const Layout &L, const Nodes &N, int flags, int band, float *AT,
+                         long ld, hipStream_t st);
+void launch_assemble64_T(const Layout &L, const Nodes &N, int flags, double *AT, long ld,
+                         hipStream_t st);
 // operator of the gamma_t system (Sec. 4.2), n x n FP64
 void launch_assemble_gt64(const Layout &L, const Nodes &N, double *B, long ld, hipStream_t st);
 void launch_assemble_wall64(const Layout &L, const Nodes &N, const double *hrow, double *W, long ld,
@@ -213,10 +219,6 @@ void launch_gemv32(const float *A, long ld, int n, const float *x, const double 
                    const int *active, hipStream_t st);
 void launch_gemv32_x64(const float *A, long ld, int n, const double *x, const double *c,
                        double *y, const int *active, hipStream_t st);
-void launch_gemvT64(const double *A, long ld, int n, const double *x, const double *c, double *y,
-                    double *part, const int *active, hipStream_t st);
-void launch_gemvT32(const float *A, long ld, int n, const double *x, const double *c, double *y,
-                    double *part, const int *active, hipStream_t st);
 void launch_otf_matvec(const Layout &L, const Nodes &N, int flags, int fp32, int band,
                        int transpose, const double *x, const double *c, double *y, double *part,
                        const int *active, hipStream_t st);
@@ -228,7 +230,7 @@ void launch_rflavour(const Layout &L, const Nodes &N, const double *hrow, int mo
                      int r0, int nr, int c0, int nc, const double *x, double *part,
                      const int *active, hipStream_t st);
 // partial slices (far chunks + the near band) of a product over nr rows and
-// nc columns, forward or transposed; at most 129, each of length nr
+// nc columns, forward or transposed; at most 257, each of length nr
 // (forward) or nc (transposed)
 int rflavour_nsplit(int nr, int nc, int transpose);
 void launch_reduce_partials(int n, const double *part, int nsplit, const double *c, double scale,

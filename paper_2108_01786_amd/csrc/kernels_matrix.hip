@@ -56,6 +56,27 @@ __global__ __launch_bounds__(256) void k_assemble(Nodes N, const double *hrow, i
     }
 }
 
+// FP64 assembly of the transpose A^T (row q = source q, column p = target p):
+// the staged rows hold sources, each thread one target.
+__global__ __launch_bounds__(256) void k_assemble64T(Nodes N, int n, int corr, double *out,
+                                                     long ld) {
+    __shared__ Src ss[kRowsPerAsmBlock];
+    const int col = blockIdx.x * 256 + threadIdx.x;
+    const int rbase = blockIdx.y * kRowsPerAsmBlock;
+    if (threadIdx.x < kRowsPerAsmBlock) {
+        const int r = rbase + threadIdx.x;
+        if (r < n) ss[threadIdx.x] = load_src(N, r);
+    }
+    __syncthreads();
+    if (col >= ld) return;
+    const bool live = col < n;
+    const Tgt t = load_tgt(N, live ? col : 0);
+    const int rend = min(kRowsPerAsmBlock, n - rbase);
+    for (int i = 0; i < rend; ++i)
+        __builtin_nontemporal_store(live ? a_val64(N, t, ss[i], corr != 0) : 0.0,
+                                    out + (long)(rbase + i) * ld + col);
+}
+
 // FP32 entry of A for a pair outside the FP64 band, when the wave's columns
 // lie on one boundary (the kind of entry is then wave-uniform): the same
 // quotient as kappa32 with the hardware reciprocal, and the source data
@@ -163,9 +184,108 @@ __global__ __launch_bounds__(256) void k_assemble32_far(Nodes N, int n, int corr
     }
 }
 
+// The same far pass for the transpose: row q of the output is source q and
+// column p target p, so out = A^T with the same row-major layout (the adjoint
+// then streams it with the forward product).  The staged rows hold sources,
+// each thread one target.
+struct SrcRow {
+    Src s;
+    float fa, fb, fw;   // w dx / 2, w dy / 2, w in FP32
+};
+
+__global__ __launch_bounds__(256) void k_assemble32T_far(Nodes N, int n, int corr, int band,
+                                                         float *out, long ld) {
+    __shared__ SrcRow sr[kRowsPerAsm32];
+    const int wb = wave_base();
+    const int col = blockIdx.x * 256 + threadIdx.x;
+    const int rbase = blockIdx.y * kRowsPerAsm32;
+    if (threadIdx.x < kRowsPerAsm32) {
+        const int r = rbase + threadIdx.x;
+        if (r < n) {
+            const Src v = load_src(N, r);
+            sr[threadIdx.x] = SrcRow{v, (float)(0.5 * v.w * v.dx), (float)(0.5 * v.w * v.dy),
+                                     (float)v.w};
+        }
+    }
+    __syncthreads();
+    if (col >= ld) return;
+    const bool live = col < n;
+    const Tgt t = load_tgt(N, live ? col : 0);
+    // the wave's live columns (targets) [ca, cb]: on one boundary kp (local
+    // indices [lpa, lpb] of mp nodes), or kp = -1
+    const int ca = blockIdx.x * 256 + wb, cb = min(ca + 63, n - 1);
+    int kp = -1, lpa = 0, lpb = 0, mp = 0;
+    if (ca < n) {
+        kp = range_boundary(N, ca, cb);
+        lpa = N.loc[ca];
+        lpb = N.loc[cb];
+        mp = N.Mk[ca];
+    }
+    const int rend = min(kRowsPerAsm32, n - rbase);
+    float *o = out + (long)rbase * ld + col;
+    const int kr = kp >= 0 ? range_boundary(N, rbase, rbase + rend - 1) : -1;   // sources
+    if (kr >= 0 && ranges_apart(N, ca, cb, rbase, rbase + rend - 1, band)) {
+        if ((kp == 0) == (kr == 0)) {
+            const bool ec = corr && kp == kr && kp >= 2;
+            for (int i = 0; i < rend; ++i) {
+                const SrcRow &q = sr[i];
+                __builtin_nontemporal_store(
+                    live ? a_far32_fast<kFastIm>(t, q.s.ex, q.s.ey, q.fa, q.fb, ec ? q.fw : 0.0f)
+                         : 0.0f,
+                    o + i * ld);
+            }
+        } else if (kp == 0) {
+            for (int i = 0; i < rend; ++i) {
+                const SrcRow &q = sr[i];
+                __builtin_nontemporal_store(
+                    live ? a_far32_fast<kFastReNeg>(t, q.s.ex, q.s.ey, q.fa, q.fb, 0.0f) : 0.0f,
+                    o + i * ld);
+            }
+        } else {
+            for (int i = 0; i < rend; ++i) {
+                const SrcRow &q = sr[i];
+                __builtin_nontemporal_store(
+                    live ? a_far32_fast<kFastRePos>(t, q.s.ex, q.s.ey, q.fa, q.fb, 0.0f) : 0.0f,
+                    o + i * ld);
+            }
+        }
+        return;
+    }
+    for (int i = 0; i < rend; ++i) {
+        const SrcRow &q = sr[i];
+        bool apart = false;
+        int kq = -1;
+        if (kp >= 0) {
+            kq = __builtin_amdgcn_readfirstlane(q.s.k);
+            apart = kp != kq;
+            if (!apart) {
+                const int lq = __builtin_amdgcn_readfirstlane(q.s.loc);
+                const int gap = max(0, max(lpa - lq, lq - lpb));
+                const int span = max(lq - lpa, lpb - lq);
+                apart = gap > band && mp - span > band;
+            }
+        }
+        float v;
+        if (apart) {
+            if ((kp == 0) == (kq == 0))
+                v = a_far32_fast<kFastIm>(t, q.s.ex, q.s.ey, q.fa, q.fb,
+                                          (corr && kp == kq && kp >= 2) ? q.fw : 0.0f);
+            else if (kp == 0)
+                v = a_far32_fast<kFastReNeg>(t, q.s.ex, q.s.ey, q.fa, q.fb, 0.0f);
+            else
+                v = a_far32_fast<kFastRePos>(t, q.s.ex, q.s.ey, q.fa, q.fb, 0.0f);
+        } else {
+            v = a_far32(t, q.s, corr != 0, band);
+        }
+        __builtin_nontemporal_store(live ? v : 0.0f, o + i * ld);
+    }
+}
+
 // Band pass: thread (row p, offset j) writes A(p, q) for the same-boundary
 // node q at cyclic offset j - band (every node of a boundary with at most
-// 2 band + 1 nodes, each once), evaluated in FP64 and rounded once.
+// 2 band + 1 nodes, each once), evaluated in FP64 and rounded once; at
+// (q, p) for the transpose.
+template <bool TRANS>
 __global__ __launch_bounds__(256) void k_assemble32_band(Nodes N, int n, int corr, int band,
                                                          float *out, long ld) {
     const int w = 2 * band + 1;
@@ -179,7 +299,11 @@ __global__ __launch_bounds__(256) void k_assemble32_band(Nodes N, int n, int cor
     if (l < 0) l += M;
     if (l >= M) l -= M;
     const int q = p - loc + l;
-    out[(long)p * ld + q] = (float)a_val64(N, load_tgt(N, p), load_src(N, q), corr != 0);
+    const float v = (float)a_val64(N, load_tgt(N, p), load_src(N, q), corr != 0);
+    if (TRANS)
+        out[(long)q * ld + p] = v;
+    else
+        out[(long)p * ld + q] = v;
 }
 
 // ---------------------------------------------------------------------------
@@ -571,8 +695,27 @@ void launch_assemble32(const Layout &L, const Nodes &N, int flags, int band, flo
     dim3 grid(cdiv(ld, 256), cdiv(n, kRowsPerAsm32));
     hipLaunchKernelGGL(k_assemble32_far, grid, dim3(256), 0, st, N, n, corr, band, A, ld);
     const long nbw = (long)n * (2 * band + 1);
-    hipLaunchKernelGGL(k_assemble32_band, dim3(cdiv(nbw, 256)), dim3(256), 0, st, N, n, corr, band,
-                       A, ld);
+    hipLaunchKernelGGL(k_assemble32_band<false>, dim3(cdiv(nbw, 256)), dim3(256), 0, st, N, n,
+                       corr, band, A, ld);
+}
+
+void launch_assemble32_T(const Layout &L, const Nodes &N, int flags, int band, float *AT,
+                         long ld, hipStream_t st) {
+    const int n = L.n;
+    const int corr = (flags & WWBI_FLAG_NO_CORRECTION) ? 0 : 1;
+    dim3 grid(cdiv(ld, 256), cdiv(n, kRowsPerAsm32));
+    hipLaunchKernelGGL(k_assemble32T_far, grid, dim3(256), 0, st, N, n, corr, band, AT, ld);
+    const long nbw = (long)n * (2 * band + 1);
+    hipLaunchKernelGGL(k_assemble32_band<true>, dim3(cdiv(nbw, 256)), dim3(256), 0, st, N, n,
+                       corr, band, AT, ld);
+}
+
+void launch_assemble64_T(const Layout &L, const Nodes &N, int flags, double *AT, long ld,
+                         hipStream_t st) {
+    const int n = L.n;
+    const int corr = (flags & WWBI_FLAG_NO_CORRECTION) ? 0 : 1;
+    dim3 grid(cdiv(ld, 256), cdiv(n, kRowsPerAsmBlock));
+    hipLaunchKernelGGL(k_assemble64T, grid, dim3(256), 0, st, N, n, corr, AT, ld);
 }
 
 void launch_assemble_gt64(const Layout &L, const Nodes &N, double *B, long ld, hipStream_t st) {
