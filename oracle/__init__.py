@@ -15,7 +15,7 @@ from .bim import (OGeom, assemble_A, A_rows, rhs, solve_phi, solve_gamma, spectr
                   dphi_ds_from_omega, gamma_t_matrix, gamma_t_rhs, solve_gamma_t, F_operators,
                   surface_velocity_state, graph_surface, hls_reconstruct, hls_V, stage_rhs,
                   rk_step, boundary_dPhi, helsing_ojala, dphi_dn_all,
-                  layer_potential_direct, boundary_Phi, pressure)
+                  layer_potential_direct, boundary_Phi, pressure, spectral_tail)
 
 __all__ = ["OGeom", "assemble_A", "A_rows", "rhs", "solve_phi", "solve_gamma", "spectral", "split",
            "K_block", "G_block", "A_block", "wall_matrix", "psi_on_surface",
@@ -24,4 +24,4 @@ __all__ = ["OGeom", "assemble_A", "A_rows", "rhs", "solve_phi", "solve_gamma", "
            "gamma_t_matrix", "gamma_t_rhs", "solve_gamma_t", "F_operators", "surface_velocity_state",
            "graph_surface", "hls_reconstruct", "hls_V", "stage_rhs", "rk_step",
            "boundary_dPhi", "helsing_ojala", "dphi_dn_all",
-           "layer_potential_direct", "boundary_Phi", "pressure"]
+           "layer_potential_direct", "boundary_Phi", "pressure", "spectral_tail"]

@@ -258,6 +258,19 @@ def split(g: OGeom, v: torch.Tensor) -> List[torch.Tensor]:
     return list(torch.split(v, g.M))
 
 
+def spectral_tail(f: torch.Tensor) -> float:
+    """Resolution measure of one periodic sample vector (the Fourier-tail test
+    the paper applies before refining its grids, Sec. 7.1: the mode amplitudes
+    must decay before k reaches M/2): the square root of the fraction of the
+    spectral energy held by the modes |k| >= 3M/8, from the full FFT."""
+    M = f.shape[-1]
+    c = torch.fft.fft(f.to(C128))
+    k = torch.fft.fftfreq(M, d=1.0 / M).abs()
+    e = c.abs() ** 2
+    tail = e[k >= -(-3 * M // 8)].sum()
+    return float(torch.sqrt(tail / e.sum())) if float(e.sum()) > 0 else 0.0
+
+
 # ---------------------------------------------------------------------------
 # velocity-potential method (Sec. 3.2 - 3.4)
 # ---------------------------------------------------------------------------

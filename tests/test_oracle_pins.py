@@ -463,3 +463,31 @@ def test_pressure_surface_limit():
     p = O.pressure(g, torch.as_tensor(cfg["phi"]), 0.1, 1.0, z)
     kappa = ((g.e[0] / g.d[0]).imag / g.d[0].abs())[::16]
     assert float((p + 0.1 * kappa).abs().max()) < 1e-7
+
+
+def test_spectral_tail_closed_forms():
+    """The resolution measure (Sec. 7.1's Fourier-tail test): the root of the
+    energy fraction in the modes |k| >= 3M/8.  Single modes below and in the
+    band give 0 and 1; a Nyquist mode carries one coefficient of size M
+    against two of M/2 for the others; and the Poisson kernel
+    1/(1 - 2 rho cos a + rho^2), whose coefficients are rho^|k| / (1 - rho^2),
+    gives a geometric tail sum (sampled, mode k also collects its aliases:
+    (rho^|k| + rho^(M - |k|)) / (1 - rho^M), up to the common factor)."""
+    M = 64
+    a = torch.arange(M, dtype=torch.float64) * (2 * np.pi / M)
+    assert O.spectral_tail(torch.cos(5 * a)) < 1e-14
+    assert O.spectral_tail(torch.cos(23 * a)) < 1e-14          # 23 < 24 = 3M/8
+    assert abs(O.spectral_tail(torch.sin(24 * a)) - 1.0) < 1e-14
+    x, y = 0.6, 1.7
+    r = O.spectral_tail(x * torch.cos(3 * a) + y * torch.cos(30 * a))
+    assert abs(r - y / np.hypot(x, y)) < 1e-14
+    r = O.spectral_tail(x * torch.cos(3 * a) + y * torch.cos(32 * a))   # Nyquist
+    assert abs(r - y / np.sqrt(x * x / 2 + y * y)) < 1e-14
+    M = 256
+    a = torch.arange(M, dtype=torch.float64) * (2 * np.pi / M)
+    rho = 0.9
+    f = 1.0 / (1.0 - 2 * rho * torch.cos(a) + rho * rho)
+    k = np.abs(np.arange(-M // 2 + 1, M // 2 + 1))
+    e = ((rho ** k + rho ** (M - k)) / (1 - rho ** M)) ** 2
+    expect = np.sqrt(e[k >= 96].sum() / e.sum())
+    assert abs(O.spectral_tail(f) / expect - 1.0) < 1e-9
