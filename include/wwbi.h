@@ -52,6 +52,9 @@ extern "C" {
 #define WWBI_NOT_CONVERGED        1  /* iteration budget spent before the tolerance    */
 #define WWBI_STAGNATED            2  /* a restart cycle made no progress               */
 #define WWBI_REFINE_STALLED       3  /* iterative refinement stopped contracting       */
+#define WWBI_WARN_UNDERRESOLVED   4  /* omega's Fourier tail (report.tail_ratio) is above
+                                        max(1e-12, 10 tol) on some boundary: the grid does
+                                        not resolve the solution (Sec. 7.1's test)     */
 
 #define WWBI_MAX_BOUNDARIES      64
 
@@ -124,6 +127,8 @@ typedef struct {
     int32_t pad0;
     double ms_matvec;      /* their summed HIP-event duration (FLAG_PROFILE)              */
     double bytes_matvec;   /* algorithmic bytes moved by one such launch                  */
+    double tail_ratio;     /* wwbi_solve_phi: max over boundaries of the root of the energy
+                              fraction of omega_k in the modes |k| >= 3 M_k / 8 (else 0)  */
 } wwbi_report;
 
 /* Fill *o with defaults: tol 1e-13, inner_tol 3e-7, restart 100, max_iter 2000,
@@ -162,6 +167,12 @@ int wwbi_reserve(wwbi_ctx *ctx, int64_t max_unknowns, int32_t max_restart, int32
  *   U      (device) M_0;
  *   omega  (device) sum(M), or NULL;
  *   psi_k  (host)   nb-2 stream-function constants psi|_k = mean(omega_k), or NULL.
+ * Resolution check (the paper's Fourier-tail test, Sec. 7.1): the solve also
+ * measures, on every boundary, the root of the energy fraction of omega_k in
+ * its modes |k| >= 3 M_k / 8 (report.tail_ratio holds the largest).  Above
+ * max(1e-12, 10 tol) a solve that otherwise succeeded returns
+ * WWBI_WARN_UNDERRESOLVED, with its outputs as usual: typically a boundary
+ * comes too close to another for its grid.
  */
 int wwbi_solve_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi, const wwbi_opts *o,
                    double *U, double *omega, double *psi_k, wwbi_report *rep);

@@ -824,6 +824,7 @@ const char *wwbi_status_str(int s) {
     case WWBI_NOT_CONVERGED: return "not converged";
     case WWBI_STAGNATED: return "stagnated";
     case WWBI_REFINE_STALLED: return "iterative refinement stalled";
+    case WWBI_WARN_UNDERRESOLVED: return "warning: omega not resolved by the grid (Fourier tail)";
     default: return "unknown status";
     }
 }
@@ -951,10 +952,26 @@ static int solve_phi_impl(Ctx *c, const wwbi_geom *g, const double *phi, const w
         hipMemcpyAsync(c->hst, means, sizeof(double) * (c->L.nb - 2), hipMemcpyDeviceToHost,
                        c->stream);
     }
+    // resolution check: the Fourier tail of omega on every boundary
+    double *tails = (double *)((char *)c->hst + kTailOffset);
+    launch_tail_monitor(c->L, x, c->part, c->val, c->stream);
+    hipMemcpyAsync(tails, c->val, sizeof(double) * 2 * c->L.nb, hipMemcpyDeviceToHost, c->stream);
     hipEventRecord(c->ev[4], c->stream);
     c->finish_report(rep, status, st, bytes);
     if (psi_k && c->L.nb > 2) std::memcpy(psi_k, c->hst, sizeof(double) * (c->L.nb - 2));
     if (hipGetLastError() != hipSuccess) return WWBI_EHIP;
+    double tail = 0.0;
+    for (int k = 0; k < c->L.nb; ++k) {
+        const double t = tails[2 * k], e = tails[2 * k + 1];
+        if (e > 0.0) tail = std::max(tail, std::sqrt(t / e));
+    }
+    if (!std::isfinite(tail)) tail = HUGE_VAL;
+    if (status == WWBI_OK && tail > std::max(1e-12, 10.0 * o->tol))
+        status = WWBI_WARN_UNDERRESOLVED;
+    if (rep) {
+        rep->tail_ratio = tail;
+        rep->status = status;
+    }
     return status;
 }
 

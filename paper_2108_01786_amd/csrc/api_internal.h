@@ -48,6 +48,7 @@ enum VecId { VR = 0, VW, VB, VX, VRR, VD, VG, VHG, VUM, VTMP, VTMP2, VLAM, VMU, 
 constexpr int kProfPairs = 2048;
 constexpr int kStateSlotOffset = 8192;   // byte offset of the two polled GState slots in hst
 constexpr int kStateSlotBytes = 8192;    // bytes per slot (up to kMaxMulti states)
+constexpr int kTailOffset = 24576;       // byte offset of the Fourier-tail energies in hst
 constexpr int kHostStaging = 32768;      // pinned host staging bytes
 constexpr int kMaxMulti = 32;            // right-hand sides per multi solve
 

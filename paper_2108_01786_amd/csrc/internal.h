@@ -119,6 +119,12 @@ void launch_energy(int n0, const Nodes &N, const Flow &F, double tau, double gra
                    const double *tmv, const double *psi_k, double *e, double *E, hipStream_t st);
 // op: WWBI_OP_D, WWBI_OP_H or kOpHalfCot, one row per boundary laid out like the nodes
 void launch_circulant_rows(const Layout &L, int op, double *rows, hipStream_t st);
+// Fourier-tail measure of f on every boundary (Sec. 7.1's resolution test):
+// out[2k] = energy in the modes ceil(3 M_k / 8) .. M_k / 2 (both signs),
+// out[2k+1] = total energy; modes holds tail_modes_total(L) doubles.
+int tail_modes_total(const Layout &L);
+void launch_tail_monitor(const Layout &L, const double *f, double *modes, double *out,
+                         hipStream_t st);
 // out = alpha C_k f + beta out on boundaries first..last (one launch);
 // launch_circulant_apply2 scales boundary 0 by alpha0 and the others by alpha
 void launch_circulant_apply(const Layout &L, const double *rows, const double *f, double *out,

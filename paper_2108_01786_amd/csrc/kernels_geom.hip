@@ -263,6 +263,90 @@ __global__ void k_block_means(Layout L, const double *v, double *out) {
     if (threadIdx.x == 0) out[blockIdx.x] = acc / (double)(p1 - p0);
 }
 
+// Fourier-tail resolution measure (the test the paper applies before it
+// refines its grids, Sec. 7.1).  Boundary k of M nodes has the tail modes
+// n = ceil(3M/8) .. M/2 of its real sample vector f; mode n holds
+// |f^_n|^2, f^_n = sum_m f_m e^{-2 pi i n m / M}, counted twice for n < M/2
+// (with its negative) and once for n = M/2.  Parseval gives the total energy
+// M sum_m f_m^2.
+__host__ __device__ __forceinline__ int tail_lo(int M) { return (3 * M + 7) / 8; }
+__host__ __device__ __forceinline__ int tail_count(int M) { return M / 2 - tail_lo(M) + 1; }
+
+// One wave per tail mode of every boundary, in boundary order (four modes per
+// block).  Lane l takes the samples m = l, l + 64, ...; its phase advances by
+// the rotation e^{-2 pi i 64 n / M} and is set exactly every 16 samples, so
+// the twiddles stay within a few ulp (far below the 1e-12 test level).
+constexpr int kTailWaves = 4;
+
+__device__ __forceinline__ double wave_sum64(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(64 * kTailWaves) void k_tail_modes(Layout L, int total,
+                                                                const double *__restrict__ f,
+                                                                double *__restrict__ modes) {
+    const int gid = blockIdx.x * kTailWaves + (threadIdx.x >> 6);
+    if (gid >= total) return;                  // whole waves only
+    const int lane = threadIdx.x & 63;
+    int b = gid, k = 0;
+    for (; k < L.nb - 1; ++k) {
+        const int t = tail_count(L.off[k + 1] - L.off[k]);
+        if (b < t) break;
+        b -= t;
+    }
+    const int M = L.off[k + 1] - L.off[k];
+    const int n = tail_lo(M) + b;
+    const double *fk = f + L.off[k];
+    double sr, cr;                             // rotation by 64 samples
+    sincospi(2.0 * (double)(((long)n * 64) % M) / (double)M, &sr, &cr);
+    double re = 0.0, im = 0.0, c = 1.0, s = 0.0;
+    // eight samples per lane are loaded before they are used
+    for (int m0 = lane, i = 0; m0 < M; m0 += 64 * 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = m0 + 64 * u < M ? fk[m0 + 64 * u] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u, ++i) {
+            const int m = m0 + 64 * u;
+            if ((i & 15) == 0) {
+                sincospi(2.0 * (double)(((long)n * m) % M) / (double)M, &s, &c);
+            } else {
+                const double c2 = c * cr - s * sr;
+                s = s * cr + c * sr;
+                c = c2;
+            }
+            re += v[u] * c;
+            im -= v[u] * s;
+        }
+    }
+    re = wave_sum64(re);
+    im = wave_sum64(im);
+    if (lane == 0) modes[gid] = (2 * n == M ? 1.0 : 2.0) * (re * re + im * im);
+}
+
+// One block per boundary: out[2k] = tail energy, out[2k+1] = total energy.
+__global__ __launch_bounds__(256) void k_tail_finish(Layout L, const double *__restrict__ f,
+                                                     const double *__restrict__ modes,
+                                                     double *__restrict__ out) {
+    __shared__ double sh[8];
+    const int k = blockIdx.x;
+    int m0 = 0;
+    for (int j = 0; j < k; ++j) m0 += tail_count(L.off[j + 1] - L.off[j]);
+    const int M = L.off[k + 1] - L.off[k];
+    const int cnt = tail_count(M);
+    double t = 0.0;
+    for (int i = threadIdx.x; i < cnt; i += blockDim.x) t += modes[m0 + i];
+    double e = 0.0;
+    for (int m = threadIdx.x; m < M; m += blockDim.x) e += f[L.off[k] + m] * f[L.off[k] + m];
+    t = block_sum(t, sh);
+    e = block_sum(e, sh);
+    if (threadIdx.x == 0) {
+        out[2 * k] = t;
+        out[2 * k + 1] = (double)M * e;
+    }
+}
+
 // U_m = (u_mv + (1/2) H gamma_0 + sum over split partials of T gamma) / s_m
 __global__ void k_U_finalize(int n0, const double *s, const double *umv, const double *hg,
                              const double *part, int nsplit, double *U) {
@@ -473,6 +557,20 @@ void launch_circ_apply1(int M, const double *row, const double *f, double *out, 
                         double beta, hipStream_t st) {
     hipLaunchKernelGGL(k_circ_tile, dim3(cdiv(M, kCT)), dim3(kCT * kCW), 0, st, M, row, f, out,
                        alpha, beta);
+}
+
+int tail_modes_total(const Layout &L) {
+    int t = 0;
+    for (int k = 0; k < L.nb; ++k) t += tail_count(L.off[k + 1] - L.off[k]);
+    return t;
+}
+
+void launch_tail_monitor(const Layout &L, const double *f, double *modes, double *out,
+                         hipStream_t st) {
+    const int total = tail_modes_total(L);
+    hipLaunchKernelGGL(k_tail_modes, dim3((total + kTailWaves - 1) / kTailWaves),
+                       dim3(64 * kTailWaves), 0, st, L, total, f, modes);
+    hipLaunchKernelGGL(k_tail_finish, dim3(L.nb), dim3(256), 0, st, L, f, modes, out);
 }
 
 void launch_block_means(const Layout &L, const double *v, double *out, hipStream_t st) {

@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes as C
 import os
+import warnings
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
@@ -20,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libwwbi.so")
 # status codes and option values (mirror include/wwbi.h)
 OK, EINVAL_NULL, EINVAL_SIZE, EINVAL_NONFINITE, EINVAL_ORIENTATION = 0, -1, -2, -3, -4
 ECAPACITY, EHIP, EINVAL_OPTS = -5, -6, -7
-NOT_CONVERGED, STAGNATED, REFINE_STALLED = 1, 2, 3
+NOT_CONVERGED, STAGNATED, REFINE_STALLED, WARN_UNDERRESOLVED = 1, 2, 3, 4
 FP64, FP32_REFINED = 0, 1
 SURF_GRAPH, SURF_HLS = 0, 1
 MATVEC_AUTO, MATVEC_STORED, MATVEC_ON_THE_FLY = 0, 1, 2
@@ -49,7 +50,8 @@ class Report(C.Structure):
                 ("refine_steps", C.c_int32), ("rel_resid", C.c_double),
                 ("ms_prep", C.c_double), ("ms_assemble", C.c_double), ("ms_solve", C.c_double),
                 ("ms_U", C.c_double), ("ms_total", C.c_double), ("n_matvec", C.c_int32),
-                ("pad0", C.c_int32), ("ms_matvec", C.c_double), ("bytes_matvec", C.c_double)]
+                ("pad0", C.c_int32), ("ms_matvec", C.c_double), ("bytes_matvec", C.c_double),
+                ("tail_ratio", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad0"}
@@ -134,6 +136,19 @@ class WWBIError(RuntimeError):
 
 def status_str(status: int) -> str:
     return load_library().wwbi_status_str(status).decode()
+
+
+def _check(rc: int, check: bool, name: str):
+    """Raise for an error (rc < 0), and with check for a numerical warning;
+    an under-resolved grid (WARN_UNDERRESOLVED) only emits a RuntimeWarning,
+    as the solve itself succeeded."""
+    if rc == WARN_UNDERRESOLVED:
+        if check:
+            warnings.warn(f"{name}: omega is not resolved by the grid (Fourier tail above "
+                          "max(1e-12, 10 tol))", RuntimeWarning, stacklevel=3)
+        return
+    if rc < 0 or (check and rc != OK):
+        raise WWBIError(rc, name)
 
 
 def _ptr(t: Optional[torch.Tensor]):
@@ -275,8 +290,7 @@ class Context:
         o = make_opts(**kw)
         rc = self.lib.wwbi_solve_phi(self.h, C.byref(g), _ptr(phi), C.byref(o), _ptr(U),
                                      _ptr(omega), psi, C.byref(rep))
-        if rc < 0 or (check and rc != OK):
-            raise WWBIError(rc, "wwbi_solve_phi")
+        _check(rc, check, "wwbi_solve_phi")
         psi_k = np.array(psi[: max(0, geom.nb - 2)], dtype=np.float64)
         return U, omega, psi_k, rep
 
@@ -291,8 +305,7 @@ class Context:
         o = make_opts(**kw)
         rc = self.lib.wwbi_solve_gamma(self.h, C.byref(g), _ptr(gamma0), C.byref(o), _ptr(U),
                                        _ptr(gw), C.byref(rep))
-        if rc < 0 or (check and rc != OK):
-            raise WWBIError(rc, "wwbi_solve_gamma")
+        _check(rc, check, "wwbi_solve_gamma")
         return U, gw, rep
 
     def tangential_energy(self, geom: DeviceGeometry, omega: torch.Tensor,
@@ -329,8 +342,7 @@ class Context:
         o = make_opts(**kw)
         rc = self.lib.wwbi_solve_gamma_t(self.h, C.byref(g), _ptr(phi), _ptr(V), tau, grav,
                                          C.byref(o), _ptr(gt), _ptr(U), C.byref(r1), C.byref(r2))
-        if rc < 0 or (check and rc != OK):
-            raise WWBIError(rc, "wwbi_solve_gamma_t")
+        _check(rc, check, "wwbi_solve_gamma_t")
         return gt, U, r1, r2
 
     def stage_rhs(self, geom: DeviceGeometry, mode: int, q: torch.Tensor, phi: torch.Tensor,
@@ -346,8 +358,7 @@ class Context:
         o = make_opts(**kw)
         rc = self.lib.wwbi_stage_rhs(self.h, C.byref(g), mode, _ptr(q), _ptr(phi), tau, grav,
                                      C.byref(o), *[_ptr(t) for t in out], C.byref(rep))
-        if rc < 0 or (check and rc != OK):
-            raise WWBIError(rc, "wwbi_stage_rhs")
+        _check(rc, check, "wwbi_stage_rhs")
         return out[0], out[1], out[2], out[3], rep
 
     def rk_step(self, geom: DeviceGeometry, mode: int, A, b, h: float, q: torch.Tensor,
@@ -371,8 +382,7 @@ class Context:
         bc = b.ctypes.data_as(C.POINTER(C.c_double))
         rc = self.lib.wwbi_rk_step(self.h, C.byref(g), mode, ns, Ac, bc, h, _ptr(q), _ptr(phi),
                                    tau, grav, 1 if filt else 0, C.byref(o), C.byref(rep))
-        if rc < 0 or (check and rc != OK):
-            raise WWBIError(rc, "wwbi_rk_step")
+        _check(rc, check, "wwbi_rk_step")
         return rep
 
     def boundary_velocity(self, geom: DeviceGeometry, omega: torch.Tensor):
@@ -429,8 +439,7 @@ class Context:
         o = make_opts(**kw)
         rc = self.lib.wwbi_pressure(self.h, C.byref(g), _ptr(phi), tau, grav, C.byref(o),
                                     int(zx.numel()), _ptr(zx), _ptr(zy), _ptr(p), C.byref(rep))
-        if rc < 0 or (check and rc != OK):
-            raise WWBIError(rc, "wwbi_pressure")
+        _check(rc, check, "wwbi_pressure")
         return p, rep
 
     def adjoint_phi(self, geom: DeviceGeometry, omega: torch.Tensor, dJdU: torch.Tensor,
@@ -444,8 +453,7 @@ class Context:
         o = make_opts(**kw)
         rc = self.lib.wwbi_adjoint_phi(self.h, C.byref(g), _ptr(omega), _ptr(dJdU), C.byref(o),
                                        *[_ptr(t) for t in outs], C.byref(rep))
-        if rc < 0 or (check and rc != OK):
-            raise WWBIError(rc, "wwbi_adjoint_phi")
+        _check(rc, check, "wwbi_adjoint_phi")
         names = ["phi", "x", "y", "dx", "dy", "ddx", "ddy"]
         return dict(zip(names, outs)), rep
 
@@ -461,8 +469,7 @@ class Context:
         o = make_opts(**kw)
         rc = self.lib.wwbi_solve_phi_multi(self.h, C.byref(g), _ptr(rhs), nr, C.byref(o),
                                            _ptr(out), C.byref(rep))
-        if rc < 0 or (check and rc != OK):
-            raise WWBIError(rc, "wwbi_solve_phi_multi")
+        _check(rc, check, "wwbi_solve_phi_multi")
         return out, rep
 
     def spectral(self, f: torch.Tensor, op: int, alpha: float = 1.0, beta: float = 0.0,

@@ -43,6 +43,7 @@ def test_host_only_helpers():
     assert o.tol == 1e-13 and o.restart == 100 and o.precision == wwbi.FP64
     assert wwbi.status_str(wwbi.EINVAL_ORIENTATION).startswith("invalid argument")
     assert wwbi.status_str(wwbi.NOT_CONVERGED) == "not converged"
+    assert "Fourier tail" in wwbi.status_str(wwbi.WARN_UNDERRESOLVED)
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libwwbi.so not built")
@@ -50,4 +51,4 @@ def test_struct_layouts_match_header():
     """ctypes mirrors of the option and report structs have the C sizes."""
     from paper_2108_01786_amd import wwbi
     assert ctypes.sizeof(wwbi._Opts) == 8 + 8 + 4 * 8 + 8
-    assert ctypes.sizeof(wwbi.Report) == 4 * 4 + 8 * 6 + 4 * 2 + 8 * 2
+    assert ctypes.sizeof(wwbi.Report) == 4 * 4 + 8 * 6 + 4 * 2 + 8 * 3

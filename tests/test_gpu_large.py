@@ -20,6 +20,7 @@ import oracle as O
 from manufactured import Flow, manufactured_inputs
 from synth import make_config
 from synth.geometry import Geometry, ellipse, fourier_surface, graph_bottom
+from tails import check_tail_status, oracle_tail
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -80,7 +81,11 @@ def _solve_both(ww, ctx, geom, phi):
                                             precision=ww.FP32_REFINED)
     say(f"  refined iters={rep32.iters} steps={rep32.refine_steps} resid={rep32.rel_resid:.2e} "
         f"ms={rep32.ms_total:.1f}")
-    assert rep64.status == 0 and rep32.status == 0
+    # the resolution check, against the FFT measure of the same omega
+    for rep, om, tol in ((rep64, om64, 1e-13), (rep32, om32, 1e-14)):
+        t = oracle_tail(geom, om.cpu().numpy())
+        say(f"  tail ratio {rep.tail_ratio:.2e} (FFT {t:.2e}) status {rep.status}")
+        check_tail_status(ww, rep, tol, t)
     return (U64.cpu().numpy(), om64.cpu().numpy(), psi64), (U32.cpu().numpy(), om32.cpu().numpy(), psi32)
 
 
