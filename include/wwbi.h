@@ -82,6 +82,8 @@ extern "C" {
 
 #define WWBI_MAT_A                0  /* velocity-potential system (Sec. 3.3)             */
 #define WWBI_MAT_WALL             1  /* vortex-sheet wall system (Sec. 4.1)              */
+#define WWBI_MAT_T                2  /* normal-velocity map T on the surface rows
+                                        (Sec. 3.4): s U = u_mv + H gamma_0 / 2 + T gamma */
 
 typedef struct wwbi_ctx wwbi_ctx;
 
@@ -359,8 +361,9 @@ int wwbi_surface_fill_adjoint(wwbi_ctx *ctx, int32_t n, const double *g_x, const
                               const double *g_dx, const double *g_dy, const double *g_ddx,
                               const double *g_ddy, double *g_xt, double *g_yt);
 
-/* Export a matrix for inspection: `which` = WWBI_MAT_A (sum(M)^2) or
- * WWBI_MAT_WALL ((sum(M)-M_0)^2), row-major, FP64 (precision WWBI_FP64) or
+/* Export a matrix for inspection: `which` = WWBI_MAT_A (sum(M)^2),
+ * WWBI_MAT_WALL ((sum(M)-M_0)^2) or WWBI_MAT_T (M_0 x sum(M); FP64 only),
+ * row-major, FP64 (precision WWBI_FP64) or
  * FP32 (WWBI_FP32_REFINED, with the FP64 band of width `band`).
  * out (device) must hold n*n elements of that type.  The matrix is assembled
  * in the context's matrix workspace (padded rows) and copied out. */

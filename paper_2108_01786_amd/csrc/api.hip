@@ -1745,9 +1745,10 @@ int wwbi_debug_matrix(wwbi_ctx *ctx, const wwbi_geom *g, int32_t which, int32_t 
                       int32_t band, void *out) {
     if (!ctx) return WWBI_EINVAL_NULL;
     if (!out) return WWBI_EINVAL_NULL;
-    if (which != WWBI_MAT_A && which != WWBI_MAT_WALL) return WWBI_EINVAL_OPTS;
+    if (which != WWBI_MAT_A && which != WWBI_MAT_WALL && which != WWBI_MAT_T)
+        return WWBI_EINVAL_OPTS;
     if (precision != WWBI_FP64 && precision != WWBI_FP32_REFINED) return WWBI_EINVAL_OPTS;
-    if (which == WWBI_MAT_WALL && precision != WWBI_FP64) return WWBI_EINVAL_OPTS;
+    if (which != WWBI_MAT_A && precision != WWBI_FP64) return WWBI_EINVAL_OPTS;
     if (band < 0) return WWBI_EINVAL_OPTS;
     Ctx *c = reinterpret_cast<Ctx *>(ctx);
     int rc = c->setup(g, nullptr, 0);
@@ -1755,18 +1756,23 @@ int wwbi_debug_matrix(wwbi_ctx *ctx, const wwbi_geom *g, int32_t which, int32_t 
     // assemble with the padded leading dimension the kernels write (a multiple
     // of 64 elements) into the workspace matrix, then copy the dense rows out
     const int n = c->L.n;
-    const int rows = which == WWBI_MAT_WALL ? n - c->L.off[1] : n;
-    const long ld = round_up(rows, 64);
+    int rows = n;
+    if (which == WWBI_MAT_WALL) rows = n - c->L.off[1];
+    if (which == WWBI_MAT_T) rows = c->L.off[1];
+    const int cols = which == WWBI_MAT_WALL ? rows : n;
+    const long ld = round_up(cols, 64);
     const size_t es = precision == WWBI_FP64 ? 8 : 4;
     rc = c->ensure_matrix((size_t)rows * ld * es);
     if (rc) return rc;
     if (which == WWBI_MAT_WALL)
         launch_assemble_wall64(c->L, c->N, c->hrow, (double *)c->A, ld, c->stream);
+    else if (which == WWBI_MAT_T)
+        launch_assemble_T64(c->L, c->N, c->hrow, (double *)c->A, ld, c->stream);
     else if (precision == WWBI_FP64)
         launch_assemble64(c->L, c->N, 0, (double *)c->A, ld, c->stream);
     else
         launch_assemble32(c->L, c->N, 0, band, (float *)c->A, ld, c->stream);
-    if (hipMemcpy2DAsync(out, rows * es, c->A, ld * es, rows * es, rows, hipMemcpyDeviceToDevice,
+    if (hipMemcpy2DAsync(out, cols * es, c->A, ld * es, cols * es, rows, hipMemcpyDeviceToDevice,
                          c->stream) != hipSuccess)
         return WWBI_EHIP;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return WWBI_EHIP;

@@ -218,6 +218,9 @@ void launch_assemble64_T(const Layout &L, const Nodes &N, int flags, double *AT,
 void launch_assemble_gt64(const Layout &L, const Nodes &N, double *B, long ld, hipStream_t st);
 void launch_assemble_wall64(const Layout &L, const Nodes &N, const double *hrow, double *W, long ld,
                             hipStream_t st);
+// the normal-velocity map T (surface rows, all columns), FP64
+void launch_assemble_T64(const Layout &L, const Nodes &N, const double *hrow, double *T, long ld,
+                         hipStream_t st);
 // y = c - A x, or y = A x when c is null
 void launch_gemv64(const double *A, long ld, int n, const double *x, const double *c, double *y,
                    const int *active, hipStream_t st);

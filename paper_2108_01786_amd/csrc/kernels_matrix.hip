@@ -22,7 +22,8 @@ enum { kFastReNeg = 0, kFastRePos = 1, kFastIm = 2 };
 // block with the target data staged in LDS (read as broadcasts).
 // ---------------------------------------------------------------------------
 // FP64 assembly of A (WALL = 0), of the wall operator T - I/2 on the walls
-// (WALL = 1) or of the gamma_t operator (WALL = 2): one column per thread.
+// (WALL = 1), of the gamma_t operator (WALL = 2) or of the normal-velocity
+// map T on the surface rows (WALL = 3): one column per thread.
 template <int WALL>
 __global__ __launch_bounds__(256) void k_assemble(Nodes N, const double *hrow, int r0, int nr,
                                                   int c0, int nc, int corr, double *out,
@@ -45,6 +46,8 @@ __global__ __launch_bounds__(256) void k_assemble(Nodes N, const double *hrow, i
         if (live) {
             if (WALL == 2) {
                 v = gt_val64(N, tg[i], s);
+            } else if (WALL == 3) {
+                v = t_val64(N, tg[i], s, hrow);
             } else if (WALL == 1) {
                 v = t_val64(N, tg[i], s, hrow);
                 if (tg[i].k == s.k && tg[i].loc == s.loc) v -= 0.5;
@@ -722,6 +725,13 @@ void launch_assemble_gt64(const Layout &L, const Nodes &N, double *B, long ld, h
     const int n = L.n;
     dim3 grid(cdiv(ld, 256), cdiv(n, kRowsPerAsmBlock));
     hipLaunchKernelGGL(k_assemble<2>, grid, dim3(256), 0, st, N, nullptr, 0, n, 0, n, 1, B, ld);
+}
+
+void launch_assemble_T64(const Layout &L, const Nodes &N, const double *hrow, double *T, long ld,
+                         hipStream_t st) {
+    const int n = L.n, n0 = L.off[1];
+    dim3 grid(cdiv(ld, 256), cdiv(n0, kRowsPerAsmBlock));
+    hipLaunchKernelGGL(k_assemble<3>, grid, dim3(256), 0, st, N, hrow, 0, n0, 0, n, 1, T, ld);
 }
 
 void launch_assemble_wall64(const Layout &L, const Nodes &N, const double *hrow, double *W, long ld,

@@ -27,7 +27,7 @@ SURF_GRAPH, SURF_HLS = 0, 1
 MATVEC_AUTO, MATVEC_STORED, MATVEC_ON_THE_FLY = 0, 1, 2
 FLAG_PROFILE, FLAG_NO_CORRECTION = 1, 2
 OP_D, OP_D2, OP_H, OP_ABSD = 0, 1, 2, 3
-MAT_A, MAT_WALL = 0, 1
+MAT_A, MAT_WALL, MAT_T = 0, 1, 2
 
 
 class _Geom(C.Structure):
@@ -511,9 +511,13 @@ class Context:
     def debug_matrix(self, geom: DeviceGeometry, which: int = MAT_A, precision: int = FP64,
                      band: int = 16) -> torch.Tensor:
         self._stream()
-        n = geom.n if which == MAT_A else geom.n - geom.M[0]
+        if which == MAT_T:
+            shape = (geom.M[0], geom.n)
+        else:
+            n = geom.n if which == MAT_A else geom.n - geom.M[0]
+            shape = (n, n)
         dt = torch.float64 if precision == FP64 else torch.float32
-        out = torch.empty((n, n), dtype=dt, device=self._dev())
+        out = torch.empty(shape, dtype=dt, device=self._dev())
         g = geom.c_struct()
         rc = self.lib.wwbi_debug_matrix(self.h, C.byref(g), which, precision, band, _ptr(out))
         if rc != OK:

@@ -350,3 +350,25 @@ def test_underresolved_warning(ww, ctx, gap):
     check_tail_status(ww, rep, 1e-13, t_ref)
     assert (rep.status == ww.WARN_UNDERRESOLVED) == (gap < 0.1)
     assert rel(U.cpu().numpy(), ref["U"].numpy()) <= 1e-11
+
+
+@pytest.mark.parametrize("name", ["tiny", "ragged", "c1"])
+def test_T_matrix_entrywise(ww, ctx, name):
+    """The normal-velocity map T of Sec. 3.4 (s U = u_mv + H gamma_0 / 2 +
+    T gamma, gamma_0 = -D omega_0, gamma_j = D omega_j): the transposed G_00
+    block over M_0 on the surface columns and the transposed K_j0 blocks over
+    M_j on wall j, entrywise."""
+    say(f"case T matrix {name}")
+    cfg = _cfg(name)
+    geom = cfg["geom"]
+    g = O.OGeom.from_synth(geom)
+    cols = [O.G_block(g, 0, 0).T / geom.M[0]]
+    cols += [O.K_block(g, j, 0).T / geom.M[j] for j in range(1, geom.nb)]
+    Tr = torch.cat(cols, dim=1).numpy()
+    dg = ww.DeviceGeometry.from_synth(geom, DEV)
+    T = ctx.debug_matrix(dg, ww.MAT_T, ww.FP64).cpu().numpy()
+    assert T.shape == Tr.shape
+    assert np.abs(T - Tr).max() <= 1e-13, np.abs(T - Tr).max()
+    # T v for a seeded v against the oracle's product
+    v = np.random.default_rng(3).standard_normal(geom.Mtot)
+    assert rel(T @ v, Tr @ v) <= 1e-13
