@@ -54,6 +54,53 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+INFINITY_CACHE_BYTES = 256 << 20
+
+
+def copy_bandwidth(dev, mib=1024, reps=5):
+    """Achievable HBM bandwidth of a plain device copy (read + write bytes per
+    second, GB/s), timed with events on torch's stream after the timed region."""
+    src = torch.empty(mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ts = []
+    for _ in range(reps):
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    nbytes = 2 * src.numel() * 4
+    del src, dst
+    return nbytes / (float(np.median(ts)) * 1e-3) / 1e9
+
+
+def add_copy_reference(roof, dev, matrix_bytes):
+    """Put the copy kernel's bandwidth beside the published peak, and label a
+    matrix that fits the 256 MB Infinity Cache as cache-resident (its figure is
+    an effective bandwidth, not an HBM one)."""
+    cb = copy_bandwidth(dev)
+    roof["copy_GBs"] = cb
+    roof["copy_kind"] = "torch device copy of 1 GiB, read + write bytes, median of 5"
+    roof["frac_of_copy"] = roof["achieved"] / cb if cb > 0 else None
+    roof["cache_resident"] = matrix_bytes <= INFINITY_CACHE_BYTES
+    if roof["cache_resident"]:
+        roof["note"] = "effective (cache-resident) bandwidth: the matrix fits the Infinity Cache"
+    return roof
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,9 +114,10 @@ def parse():
     ap.add_argument("--poll", type=int, default=2)
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (counter calibration)")
-    ap.add_argument("--workload", default="solve", choices=["solve", "large-stages"],
-                    help="solve: the M = 10240 solve (default); large-stages: forward + adjoint "
-                         "stages on the M = 40960 cell")
+    ap.add_argument("--workload", default="solve", choices=["solve", "adjoint", "large-stages"],
+                    help="solve: one solve on the cell --config names (default: M = 10240); "
+                         "adjoint: forward + adjoint gradient on the M = 4608 cell; "
+                         "large-stages: forward + adjoint stages on the M = 40960 cell")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip timing the diagnostics and the gamma_t stage")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -152,7 +200,11 @@ def time_extras(ctx, dg, geom, phi, a, reps=5):
         A = np.array(d.A[:d.N_STAGES, :d.N_STAGES], dtype=np.float64)
         b = np.array(d.B[:d.N_STAGES], dtype=np.float64)
         q, p = Pt.clone(), phi.clone().contiguous()
-        rep = ctx.rk_step(dg2, wwbi.SURF_HLS, A, b, 1e-3, q, p, tau=0.1, **kw)
+        # the capillary mode at k = M0/2 turns at about sqrt(tau k^3) = 2.9e4
+        # rad per unit time and DOP853 is stable to |h omega| ~ 5.9 on the
+        # imaginary axis; h = 1e-5 also keeps the stages' high modes at the
+        # FP64 floor
+        rep = ctx.rk_step(dg2, wwbi.SURF_HLS, A, b, 1e-5, q, p, tau=0.1, **kw)
         out["dop853_step_ms"] = rep.ms_total
         out["dop853_step_iters"] = rep.iters
     except ImportError:
@@ -257,6 +309,121 @@ def run_large(a):
         "cpu_baseline": None,
         "cpu_baseline_note": "a dense oracle solve at 40960 unknowns does not fit a bounded CPU sample",
     }
+    line["roofline"] = add_copy_reference(line["roofline"], dev, 4 * geom.Mtot * geom.Mtot)
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+def run_adjoint(a):
+    """Gradient of J = sum w U^2 with respect to the surface displacements and
+    phi on the M = 4608 cell (surface 2048, bottom 1024, three ellipses of 512;
+    weights ~ U[0, 1]).  One step is the forward solve plus the adjoint: the
+    transpose solve, the kernel-derivative contractions and the chain rule
+    through the spectral derivatives.  Timed in refined FP32 (the value) and
+    in FP64."""
+    from paper_2108_01786_amd import wwbi
+    from paper_2108_01786_amd.autograd import SurfaceProblem
+    from synth import make_config
+
+    cfg = make_config(4)
+    geom = cfg["geom"]
+    dev = "cuda:0"
+    ctx = wwbi.Context(0)
+    prob = SurfaceProblem(ctx, geom, dev)
+    M0 = geom.M[0]
+    z0 = geom.curves[0].z
+    al = 2 * np.pi * np.arange(M0) / M0
+    xt_h, yt_h, ph_h = z0.real - al, z0.imag, np.asarray(cfg["phi"])
+    xt, yt, ph = (torch.as_tensor(v, device=dev) for v in (xt_h, yt_h, ph_h))
+    wt = torch.as_tensor(cfg["weights"], device=dev)
+    ctx.reserve(geom.Mtot, 100, wwbi.FP64)
+
+    def step(opts, flags=0):
+        g = prob.fill(xt, yt)
+        U, om, _, rf = ctx.solve_phi(g, ph, flags=flags, **opts)
+        grads, ra = ctx.adjoint_phi(g, om, 2.0 * wt * U, flags=flags, **opts)
+        gx, gy = ctx.surface_fill_adjoint([grads[k] for k in ("x", "y", "dx", "dy", "ddx", "ddy")])
+        return (U, gx, gy, grads["phi"]), rf.as_dict(), ra.as_dict()
+
+    def timed(opts, steps, warmup):
+        for _ in range(warmup):
+            step(opts)
+        torch.cuda.synchronize()
+        fw, ad, wall = [], [], []
+        t0 = time.perf_counter()
+        for k in range(steps):
+            ts = time.perf_counter()
+            out, rf, ra = step(opts, wwbi.FLAG_PROFILE if k == 0 else 0)
+            torch.cuda.synchronize()
+            wall.append({"ms_total": 1e3 * (time.perf_counter() - ts)})
+            fw.append(rf)
+            ad.append(ra)
+        t = (time.perf_counter() - t0) / steps
+        return t, out, fw, ad, wall
+
+    o32 = dict(precision=wwbi.FP32_REFINED, tol=1e-14, inner_tol=a.inner_tol, restart=100,
+               poll_every=a.poll)
+    o64 = dict(precision=wwbi.FP64, tol=1e-13, restart=100, poll_every=a.poll)
+    log(f"bench: adjoint M={geom.Mtot}")
+    t32, out32, fw32, ad32, wall32 = timed(o32, a.steps, a.warmup)
+    log(f"bench: refined fp32 forward+adjoint {1e3 * t32:.3f} ms")
+    t64, out64, fw64, ad64, wall64 = timed(o64, a.steps, a.warmup)
+    log(f"bench: fp64 forward+adjoint {1e3 * t64:.3f} ms")
+
+    nmv = fw32[0]["n_matvec"] + ad32[0]["n_matvec"]
+    msmv = fw32[0]["ms_matvec"] + ad32[0]["ms_matvec"]
+    avg = msmv / max(1, nmv)
+    bytes_mv = fw32[0]["bytes_matvec"]
+    achieved = bytes_mv / (avg * 1e-3) / 1e9 if avg > 0 else 0.0
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "kernel": "k_gemv<float,float,float,2,4> (stored FP32 matvec, A and A^T)",
+            "avg_launch_ms": avg, "launches": nmv, "bytes_per_launch": bytes_mv}
+
+    res = {}
+    cpu = None
+    if not a.no_cpu_baseline:
+        import oracle as O
+        og = O.OGeom.from_synth(geom)
+        n = 0
+        t0 = time.perf_counter()
+        while True:
+            Jr, rx, ry, rp, Ur = O.J_and_grad(og, xt_h, yt_h, ph_h, cfg["weights"])
+            n += 1
+            tc = time.perf_counter() - t0
+            if tc >= a.cpu_seconds:
+                break
+        cpu = {"value": n / tc, "unit": "gradients/s", "cores": torch.get_num_threads(),
+               "kind": "oracle", "cpu_model": cpu_model(),
+               "sample": f"{n} FP64 forward solves with autograd gradients of J on the same "
+                         f"M={geom.Mtot} cell (dense LU), {tc:.1f} s"}
+        ref = [Ur.numpy(), rx.numpy(), ry.numpy(), rp.numpy()]
+        for name, out in (("refined", out32), ("fp64", out64)):
+            res[f"err_vs_oracle_{name}"] = {
+                k: float(np.abs(o.cpu().numpy() - r).max() / np.abs(r).max())
+                for k, o, r in zip(("U", "dJ_dxt", "dJ_dyt", "dJ_dphi"), out, ref)}
+
+    roof = add_copy_reference(roof, dev, 4 * geom.Mtot * geom.Mtot)
+    s32, s64 = stats_ms(wall32), stats_ms(wall64)
+    line = {
+        "metric": "refined-FP32 forward+adjoint gradients/s at 4608 unknowns",
+        "value": 1.0 / t32, "unit": "gradients/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": 1e3 * t32, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32 matvec + f64 refinement",
+        "data": "synthetic",
+        "config": {"workload": f"gradient of sum w U^2, M={geom.Mtot} (surface {M0}, bottom "
+                               f"{geom.M[1]}, {geom.nb - 2} ellipses of {geom.M[2]})",
+                   "unknowns": geom.Mtot, "matvec": "stored", "tol_refined": 1e-14,
+                   "tol_fp64": 1e-13},
+        "ms_per_step_stats": s32, "gradients_per_s_median": 1e3 / s32["median"],
+        "forward_ms": stats_ms(fw32), "adjoint_ms": stats_ms(ad32),
+        "forward_iters": fw32[-1]["iters"], "adjoint_iters": ad32[-1]["iters"],
+        "refine_steps": [fw32[-1]["refine_steps"], ad32[-1]["refine_steps"]],
+        "fp64_gradients_per_s": 1.0 / t64, "fp64_ms_per_step_stats": s64,
+        "fp64_forward_iters": fw64[-1]["iters"], "fp64_adjoint_iters": ad64[-1]["iters"],
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    line.update(res)
     print(json.dumps(line), flush=True)
     ctx.close()
 
@@ -268,6 +435,8 @@ def main():
         sys.exit(2)
     if a.workload == "large-stages":
         return run_large(a)
+    if a.workload == "adjoint":
+        return run_adjoint(a)
     from paper_2108_01786_amd import wwbi
     from synth import make_config, CONFIG_NAMES
 
@@ -294,6 +463,7 @@ def main():
         res["fp64_ms_per_solve"] = 1e3 * t64
         res["fp64_iters"] = reps64[-1]["iters"]
         res["fp64_ms_per_solve_stats"] = stats_ms(reps64)
+        res["fp64_solves_per_s_median"] = 1e3 / res["fp64_ms_per_solve_stats"]["median"]
         mv64 = sum(r["ms_matvec"] for r in reps64) / max(1, sum(r["n_matvec"] for r in reps64))
         res["fp64_matvec_ms"] = mv64
         res["fp64_matvec_GBs"] = reps64[-1]["bytes_matvec"] / (mv64 * 1e-3) / 1e9 if mv64 else None
@@ -322,9 +492,22 @@ def main():
             if tcpu >= a.cpu_seconds:
                 break
         cpu = {"value": nsol / tcpu, "unit": "solves/s", "cores": torch.get_num_threads(),
-               "kind": "oracle",
+               "kind": "oracle", "cpu_model": cpu_model(),
                "sample": f"{nsol} full FP64 solves of the same M={geom.Mtot} cell (assembly, "
                          f"dense LU, U), {tcpu:.1f} s"}
+        if geom.Mtot <= 4608:
+            # the small cells are also timed on one host thread
+            nt = torch.get_num_threads()
+            torch.set_num_threads(1)
+            try:
+                n1 = 0
+                t0 = time.perf_counter()
+                while time.perf_counter() - t0 < min(a.cpu_seconds, 10.0) or n1 == 0:
+                    O.solve_phi(og, torch.as_tensor(cfg["phi"]))
+                    n1 += 1
+                cpu["value_1_thread"] = n1 / (time.perf_counter() - t0)
+            finally:
+                torch.set_num_threads(nt)
         U, omega, psi, _ = out32
         Ur, wr = ref["U"].numpy(), ref["omega"].numpy()
         res["err_vs_oracle_refined"] = {
@@ -354,6 +537,7 @@ def main():
         del evict
         log(f"bench: calibration copy of {a.copy_calib_mb} MiB done")
 
+    roof = add_copy_reference(roof, dev, 4 * geom.Mtot * geom.Mtot)
     last = reps32[-1]
     line = {
         "metric": "assembly+GMRES solves/s at ~10k unknowns; refined FP32 vs FP64 at 1e-10 rel",
@@ -367,6 +551,7 @@ def main():
                    "unknowns": geom.Mtot, "matvec": a.mode, "tol_refined": 1e-14,
                    "tol_fp64": 1e-13},
         "ms_per_solve_stats": stats_ms(reps32),
+        "solves_per_s_median": 1e3 / stats_ms(reps32)["median"],
         "iters": last["iters"], "refine_steps": last["refine_steps"],
         "phase_ms": {k: last[k] for k in ("ms_prep", "ms_assemble", "ms_solve", "ms_U")},
         "roofline": roof, "cpu_baseline": cpu,

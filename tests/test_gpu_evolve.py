@@ -95,7 +95,9 @@ def test_rk_step_matches_oracle(ww, ctx, mode, tab):
     pd = torch.as_tensor(phi, device=DEV).contiguous()
     g = O.OGeom.from_synth(geom)
     qr, pr = torch.as_tensor(q), torch.as_tensor(phi)
-    h = 0.01
+    # the capillary mode at k = 128 turns at about 460 rad per unit time:
+    # h = 2e-3 keeps it inside RK4's stability interval on the imaginary axis
+    h = 2e-3
     for _ in range(2):
         rep = ctx.rk_step(dg, m, A, b, h, qd, pd, tau=0.1, filt=True, tol=1e-13)
         qr, pr = O.rk_step(g, mode, A.tolist(), b.tolist(), h, qr, pr, 0.1, filt=True)
