@@ -159,7 +159,8 @@ def time_extras(ctx, dg, geom, phi, a, reps=5):
     diagnostics (tangential velocity on every node and the energy), the
     gamma_t stage (its own velocity-potential solve plus the right-hand side
     and the n x n FP64 system), one evolution stage and one DOP853 step (HLS
-    surface), and velocity and pressure at 4096 points inside the fluid."""
+    surface), velocity and pressure at 4096 points inside the fluid, and
+    solves with 1, 8 and 32 right-hand sides against one matrix."""
     from paper_2108_01786_amd import wwbi
     M0 = geom.M[0]
     al = torch.arange(M0, dtype=torch.float64, device=phi.device) * (2 * np.pi / M0)
@@ -227,6 +228,24 @@ def time_extras(ctx, dg, geom, phi, a, reps=5):
         prs.append(1e3 * (time.perf_counter() - t0))
     out["interior_velocity_4096pts_ms"] = float(np.median(vel[1:]))
     out["pressure_4096pts_ms"] = float(np.median(prs[1:]))
+    # several right-hand sides against one matrix (matrix-core product and
+    # lockstep GMRES), refined FP32, seeded normal right-hand sides
+    n = geom.Mtot
+    mr = {}
+    for nr in (1, 8, 32):
+        rhs = torch.as_tensor(np.random.default_rng(178610 + nr).standard_normal((nr, n)),
+                              device=phi.device)
+        ts = []
+        for _ in range(reps + 1):
+            t0 = time.perf_counter()
+            _, r = ctx.solve_phi_multi(dg, rhs, precision=wwbi.FP32_REFINED, tol=1e-14,
+                                       inner_tol=a.inner_tol, restart=100, poll_every=a.poll)
+            torch.cuda.synchronize()
+            ts.append(1e3 * (time.perf_counter() - t0))
+        med = float(np.median(ts[1:]))
+        mr[str(nr)] = {"ms": med, "ms_per_rhs": med / nr, "iters": r.iters,
+                       "refine_steps": r.refine_steps}
+    out["multi_rhs_refined"] = mr
     return out
 
 

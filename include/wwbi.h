@@ -339,7 +339,11 @@ int wwbi_adjoint_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, con
 
 /* Several right-hand sides against one matrix: solves A omega_i = rhs_i,
  * i < n, with the matrix read once per Arnoldi step for all i (matrix-core
- * product).  rhs, omega: (device) sum(M) x n, column i at offset i*sum(M). */
+ * product).  rhs, omega: (device) sum(M) x n, column i at offset i*sum(M).
+ * With WWBI_FP32_REFINED the context also holds an FP64 copy of the matrix
+ * (8 bytes per entry beside the FP32 one), from which the residuals of all
+ * systems are formed in one pass; when that copy cannot be allocated they are
+ * formed on the fly, one system at a time. */
 int wwbi_solve_phi_multi(wwbi_ctx *ctx, const wwbi_geom *g, const double *rhs, int32_t n,
                          const wwbi_opts *o, double *omega, wwbi_report *rep);
 

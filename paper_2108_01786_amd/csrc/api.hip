@@ -74,23 +74,36 @@ int Ctx::ensure(int n, int restart) {
     return rc;
 }
 
-int Ctx::ensure_matrix(size_t bytes) {
-    if (bytes <= capA && A) return WWBI_OK;
-    if (A) hipFree(A);
-    A = nullptr;
-    capA = 0;
-    if (hipMalloc(&A, bytes) != hipSuccess) {
-        A = nullptr;
+namespace {
+int grow_bytes(void *&p, size_t &cap, size_t bytes) {
+    if (bytes <= cap && p) return WWBI_OK;
+    if (p) hipFree(p);
+    p = nullptr;
+    cap = 0;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        p = nullptr;
         (void)hipGetLastError();
         return WWBI_ECAPACITY;
     }
-    capA = bytes;
+    cap = bytes;
     return WWBI_OK;
+}
+}  // namespace
+
+int Ctx::ensure_matrix(size_t bytes) { return grow_bytes(A, capA, bytes); }
+
+int Ctx::ensure_matrix64(size_t bytes) {
+    void *p = A64;
+    const int rc = grow_bytes(p, capA64, bytes);
+    A64 = static_cast<double *>(p);
+    return rc;
 }
 
 void Ctx::release() {
     auto F = [](auto *&p) { if (p) hipFree((void *)p); p = nullptr; };
     F(A);
+    F(A64);
+    capA64 = 0;
     F(V);
     F(v32);
     for (int i = 0; i < kNumVec; ++i) F(vec[i]);
@@ -717,10 +730,11 @@ int Ctx::gmres_multi(int kind, int n, long ld, const double *B, double *X, int n
     return status;
 }
 
-// FP64 refinement of nr systems around batched FP32 inner solves; the FP64
-// residual of each system is formed on the fly.
+// FP64 refinement of nr systems around batched FP32 inner solves.  With
+// stored64 the FP64 residuals of all systems come from one matrix-core pass
+// over the FP64 copy A64; otherwise each is formed on the fly.
 int Ctx::refine_multi(int n, long ld, const double *B, double *X, int nr, const wwbi_opts &o,
-                      SolveStats &st) {
+                      bool stored64, SolveStats &st) {
     const long ldv = round_up(n, 64);
     const int G = gmres_nblocks(n);
     MultiWS &m = mw;
@@ -750,9 +764,12 @@ int Ctx::refine_multi(int n, long ld, const double *B, double *X, int nr, const 
             launch_copy(m.rr, B, (int)(nr * ldv), stream);
             rn = bnrm;
         } else {
-            for (int s = 0; s < nr; ++s)
-                launch_otf_matvec(L, N, o.flags, 0, o.band, 0, X + s * ldv, B + s * ldv,
-                                  m.rr + s * ldv, part, nullptr, stream);
+            if (stored64)
+                launch_mfma_multi64(A64, ld, n, X, ldv, nr, B, ldv, m.rr, ldv, m.part, stream);
+            else
+                for (int s = 0; s < nr; ++s)
+                    launch_otf_matvec(L, N, o.flags, 0, o.band, 0, X + s * ldv, B + s * ldv,
+                                      m.rr + s * ldv, part, nullptr, stream);
             rc = norms(m.rr, rn);
             if (rc) return rc;
         }
@@ -1647,17 +1664,22 @@ int wwbi_solve_phi_multi(wwbi_ctx *ctx, const wwbi_geom *g, const double *rhs, i
     hipEventRecord(c->ev[1], sm);
     rc = c->ensure_matrix((size_t)n * ld * (fp32 ? 4 : 8));
     if (rc) { c->finish_report(rep, rc, st, 0); return rc; }
-    if (fp32)
+    // the refined path also keeps an FP64 copy for the residuals of all
+    // systems in one pass; without room for it they are formed on the fly
+    const bool stored64 = fp32 && c->ensure_matrix64((size_t)n * ld * 8) == WWBI_OK;
+    if (fp32) {
         launch_assemble32(c->L, c->N, o->flags, o->band, (float *)c->A, ld, sm);
-    else
+        if (stored64) launch_assemble64(c->L, c->N, o->flags, c->A64, ld, sm);
+    } else {
         launch_assemble64(c->L, c->N, o->flags, (double *)c->A, ld, sm);
+    }
     hipEventRecord(c->ev[2], sm);
     int status;
     if (!fp32)
         status = c->gmres_multi(OP_A_S64, n, ld, c->mw.b, c->mw.x, nr, o->tol, o->restart,
                                 o->max_iter, o->poll_every, true, st);
     else
-        status = c->refine_multi(n, ld, c->mw.b, c->mw.x, nr, *o, st);
+        status = c->refine_multi(n, ld, c->mw.b, c->mw.x, nr, *o, stored64, st);
     hipEventRecord(c->ev[3], sm);
     if (status >= 0) launch_copy_strided(c->mw.x, ldv, omega, n, n, nr, sm);
     hipEventRecord(c->ev[4], sm);

@@ -81,6 +81,7 @@ struct Ctx {
     const double *psi_wall = nullptr;
 
     void *A = nullptr;      size_t capA = 0;
+    double *A64 = nullptr;  size_t capA64 = 0;   // FP64 copy beside an FP32 A (multi refine)
     double *V = nullptr;    size_t capV = 0;
     float *v32 = nullptr;   size_t capv32 = 0;
     double *vec[kNumVec] = {};  size_t capvec[kNumVec] = {};
@@ -140,6 +141,7 @@ struct Ctx {
 
     int ensure(int n, int restart);
     int ensure_matrix(size_t bytes);
+    int ensure_matrix64(size_t bytes);
     void release();
     int setup(const wwbi_geom *g, const double *phi, int nphi);
     void apply(const Op &op, const double *x, const float *x32, const double *c, double *y,
@@ -163,7 +165,7 @@ struct Ctx {
     int gmres_multi(int kind, int n, long ld, const double *B, double *X, int nr, double tol,
                     int restart, int max_iter, int poll, bool verify, SolveStats &st);
     int refine_multi(int n, long ld, const double *B, double *X, int nr, const wwbi_opts &o,
-                     SolveStats &st);
+                     bool stored64, SolveStats &st);
     void eval_U_from_gamma(const double *gamma, double *U);
     void gamma_from_omega(const double *omega, double *gamma);
     static int check_opts(const wwbi_opts *o);

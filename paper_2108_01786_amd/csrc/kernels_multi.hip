@@ -1,17 +1,32 @@
 // One pass over the stored matrix for several right-hand sides:
 //   Y_s = A X_s,  s < nr,
 // on the matrix cores (v_mfma_f64_16x16x4_f64 for an FP64 matrix,
-// v_mfma_f32_16x16x4_f32 for FP32).  A wave owns 16 rows and up to 32
-// systems (two 16x16 accumulators); K is split over grid.y and the partial
-// products are reduced in a fixed order.
+// v_mfma_f32_16x16x4_f32 for FP32).  A wave owns RT tiles of 16 rows and ST
+// tiles of 16 systems (ST = 2 for nr > 16) and shares each B fragment across
+// its row tiles; K is split over grid.y and the partial products are reduced
+// in a fixed order.
 //
 // Operand mapping of one 16x16x4 step: lane l supplies A(i, k) with
 // i = l % 16, k = l / 16 and B(k, j) with j = l % 16, k = l / 16.  The result
 // D(i, j) sits in lane l with j = l % 16 and element r, where the row is
 // i = 4 (l / 16) + r for the FP32 instruction and i = l / 16 + 4 r for the
-// FP64 one (checked on the device).  The four k indices of a step are
-// relabelled so that every lane reads four consecutive columns: step t of a
-// 16-column tile uses columns k0 + 4 (l / 16) + t.
+// FP64 one (checked on the device).  The contraction does not care which
+// column a k slot stands for: with E elements per 16 bytes, group u of a step
+// gives lane (i, q) the E consecutive columns 4E u + E q .. of row i, and
+// element e of them feeds the MFMA in slot q.
+//
+// The matrix is read in 256-byte row pieces, 4 rows per load instruction, so
+// that every instruction reads whole contiguous runs; each wave writes its
+// tile into its own LDS region and reads it back in the MFMA layout (16-byte
+// reads, rows padded by 16 bytes so that 16 lanes hit 16 different bank
+// groups).  The next step's matrix and B loads are issued right after the
+// LDS write, behind the current step's B loads, so the only wait per step is
+// for data requested one step earlier.
+//
+// Reads run to the end of the step that holds column n - 1, at most
+// round_up(n, 64) columns: the matrix rows (ld) and the system rows (xs, and
+// the allocation behind the last one) must extend that far.  Columns at or
+// past n are zeroed in registers, so padding of any value is harmless.
 #include "internal.h"
 
 namespace wwbi {
@@ -20,12 +35,15 @@ namespace {
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
 
 inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
 template <typename T> struct Mfma;
 template <> struct Mfma<double> {
     using acc = v4d;
+    using vec = v2d;                 // 16 bytes
+    static constexpr int E = 2;
     static __device__ __forceinline__ int row(int q, int r) { return q + 4 * r; }
     static __device__ __forceinline__ acc step(double a, double b, acc c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -33,66 +51,150 @@ template <> struct Mfma<double> {
 };
 template <> struct Mfma<float> {
     using acc = v4f;
+    using vec = v4f;
+    static constexpr int E = 4;
     static __device__ __forceinline__ int row(int q, int r) { return 4 * q + r; }
     static __device__ __forceinline__ acc step(float a, float b, acc c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
 };
 
-// four consecutive elements p[0..3] of a row, zero past `end`; the matrix is
-// streamed with a non-temporal hint
-template <typename T>
-__device__ __forceinline__ void load4(const T *p, int k, int end, T (&v)[4], bool stream) {
-    if (k + 3 < end) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t)
-            v[t] = stream ? __builtin_nontemporal_load(p + k + t) : p[k + t];
-    } else {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) v[t] = (k + t < end) ? p[k + t] : (T)0;
-    }
-}
+// rows per wave (in tiles of 16) and the wave count the K split aims at:
+// measured at n = 10240, 32 rows suit the FP32 single-tile case and 64 rows
+// the others (the 64-row waves run one round on the chip)
+template <typename T, int ST> struct MultiShape {
+    static constexpr int RT = (sizeof(T) == 4 && ST == 1) ? 2 : 4;
+    static constexpr int waves = RT == 2 ? 4096 : 1920;
+};
 
-template <typename T>
+template <typename T, int ST>
 __global__ __launch_bounds__(256) void k_mfma_multi(const T *__restrict__ A, long ld, int n,
                                                     const T *__restrict__ X, long xs, int nr,
                                                     int kchunk, double *__restrict__ part) {
     using M = Mfma<T>;
+    using V = typename M::vec;
+    constexpr int RT = MultiShape<T, ST>::RT;
+    constexpr int E = M::E;
+    constexpr int KS = 16 * E;           // columns per step: 256 bytes of a row
+    constexpr int R = 16 * RT;           // rows per wave
+    constexpr int P = R / 4;             // load instructions per step, 4 rows each
+    constexpr int U = 4;                 // MFMA groups per step (KS / (4 E))
+    constexpr int SW = 64 + 4;           // LDS row stride in 4-byte words
+    __shared__ float lds[4][R * SW];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int row0 = (blockIdx.x * 4 + wv) * 16;
+    const int row0 = (blockIdx.x * 4 + wv) * R;
     if (row0 >= n) return;
     const int kb = blockIdx.y * kchunk;
     const int ke = min(n, kb + kchunk);
     const int i = lane & 15, q = lane >> 4;
-    const int row = row0 + i;
-    const bool rok = row < n;
-    const T *arow = A + (long)(rok ? row : 0) * ld;
-    const bool two = nr > 16;
-    const int s0 = i, s1 = 16 + i;
-    const T *x0 = X + (long)(s0 < nr ? s0 : 0) * xs;
-    const T *x1 = X + (long)(s1 < nr ? s1 : 0) * xs;
-    typename M::acc c0 = {0, 0, 0, 0}, c1 = {0, 0, 0, 0};
-    for (int k0 = kb; k0 < ke; k0 += 16) {
-        const int kk = k0 + 4 * q;
-        T a[4], b[4];
-        load4(arow, kk, rok ? ke : kk, a, true);
-        load4(x0, kk, s0 < nr ? ke : kk, b, false);
+    // load p: lane l reads 16 bytes at column (l % 16) E of row 4 p + l / 16
+    const int lr = lane >> 4, lc = (lane & 15) * E;
+    const V *ap[P];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) c0 = M::step(a[t], b[t], c0);
-        if (two) {
-            load4(x1, kk, s1 < nr ? ke : kk, b, false);
-#pragma unroll
-            for (int t = 0; t < 4; ++t) c1 = M::step(a[t], b[t], c1);
-        }
+    for (int p = 0; p < P; ++p) {
+        const int r = min(row0 + 4 * p + lr, n - 1);
+        ap[p] = reinterpret_cast<const V *>(A + (long)r * ld + kb + lc);
     }
+    const V *xp[ST];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        const int rr = row0 + M::row(q, r);
-        if (rr < n) {
-            if (s0 < nr) part[((long)blockIdx.y * nr + s0) * n + rr] = (double)c0[r];
-            if (two && s1 < nr) part[((long)blockIdx.y * nr + s1) * n + rr] = (double)c1[r];
-        }
+    for (int st = 0; st < ST; ++st) {
+        const int s = 16 * st + i;
+        xp[st] = reinterpret_cast<const V *>(X + (long)(s < nr ? s : 0) * xs + kb + E * q);
     }
+    float *L = lds[wv];
+    typename M::acc c[RT][ST];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int st = 0; st < ST; ++st) c[rt][st] = typename M::acc{0, 0, 0, 0};
+    V ga[P];
+    V bb[U][ST];
+#pragma unroll
+    for (int p = 0; p < P; ++p) ga[p] = __builtin_nontemporal_load(ap[p]);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+        for (int st = 0; st < ST; ++st) bb[u][st] = xp[st][4 * u];
+    // one step at column k0; pf: fetch the next step, tail: zero columns >= ke
+    auto body = [&](const int k0, const bool pf, const bool tail) __attribute__((always_inline)) {
+        const int off = (k0 - kb) / E;
+        if (tail) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                const bool in = k0 + lc + e < ke;
+#pragma unroll
+                for (int p = 0; p < P; ++p) ga[p][e] = in ? ga[p][e] : (T)0;
+            }
+        }
+        // the compiler keeps LDS and global accesses in this order; one
+        // wave's LDS operations complete in issue order, so the writes land
+        // after the previous step's fragment reads
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+            *reinterpret_cast<V *>(L + (4 * p + lr) * SW + lc * (int)sizeof(T) / 4) = ga[p];
+        asm volatile("" ::: "memory");
+        V bn[U][ST];
+        if (pf) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int st = 0; st < ST; ++st) bn[u][st] = xp[st][off + KS / E + 4 * u];
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                ga[p] = __builtin_nontemporal_load(ap[p] + off + KS / E);
+        }
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            V b[ST];
+#pragma unroll
+            for (int st = 0; st < ST; ++st) b[st] = bb[u][st];
+            if (tail) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const bool in = k0 + 4 * E * u + E * q + e < ke;
+#pragma unroll
+                    for (int st = 0; st < ST; ++st) b[st][e] = in ? b[st][e] : (T)0;
+                }
+            }
+            V a[RT];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+                a[rt] = *reinterpret_cast<const V *>(L + (16 * rt + i) * SW +
+                                                     (4 * E * u + E * q) * (int)sizeof(T) / 4);
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int st = 0; st < ST; ++st)
+                        c[rt][st] = M::step(a[rt][e], b[st][e], c[rt][st]);
+        }
+        if (pf) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int st = 0; st < ST; ++st) bb[u][st] = bn[u][st];
+        }
+    };
+    // every step but the last fetches its successor unconditionally, so the
+    // waits of the loop count only the loads they need
+    int k0 = kb;
+    for (; k0 + KS < ke; k0 += KS) body(k0, true, false);
+    body(k0, false, k0 + KS > ke);
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int st = 0; st < ST; ++st) {
+            const int s = 16 * st + i;
+            if (s >= nr) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int rr = row0 + 16 * rt + M::row(q, r);
+                if (rr < n) part[((long)blockIdx.y * nr + s) * n + rr] = (double)c[rt][st][r];
+            }
+        }
 }
 
 // y_s = c_s - sum_k part[k][s] (or the plain sum when c is null)
@@ -119,36 +221,55 @@ __global__ void k_to_f32_batched(const double *src, long ss, float *dst, long ds
     if (m < n) dst[s * ds + m] = (float)src[s * ss + m];
 }
 
-}  // namespace
+// K split: chunks a multiple of 64 columns (every step then starts on a
+// 64-column boundary), as many as bring the grid near the shape's wave count
+struct MultiGrid {
+    int kchunk, ksn;
+};
 
-int multi_ksplit(int n) {
-    // about 16 waves of K per row tile; K chunks a multiple of 16 columns
-    int ks = cdiv(n, 16) >= 16 * 64 ? 16 : 8;
-    return ks;
+MultiGrid multi_grid(int n, int rt, int waves) {
+    const int tiles = cdiv(n, 16 * rt);
+    const int ks = std::max(1, std::min(16, cdiv(waves, tiles)));
+    const int kchunk = cdiv(cdiv(n, ks), 64) * 64;
+    return {kchunk, cdiv(n, kchunk)};
 }
+
+template <typename T, int ST> MultiGrid multi_grid_for(int n) {
+    return multi_grid(n, MultiShape<T, ST>::RT, MultiShape<T, ST>::waves);
+}
+
+template <typename T, int ST>
+void launch_mfma_st(const T *A, long ld, int n, const T *X, long xs, int nr, const double *c,
+                    long cs, double *y, long ys, double *part, hipStream_t st) {
+    const MultiGrid g = multi_grid_for<T, ST>(n);
+    const dim3 grid(cdiv(n, 4 * 16 * MultiShape<T, ST>::RT), g.ksn);
+    hipLaunchKernelGGL((k_mfma_multi<T, ST>), grid, dim3(256), 0, st, A, ld, n, X, xs, nr,
+                       g.kchunk, part);
+    hipLaunchKernelGGL(k_reduce_multi, dim3(cdiv(n, 256), nr), dim3(256), 0, st, n, nr, part,
+                       g.ksn, c, cs, y, ys);
+}
+
+template <typename T>
+void launch_mfma_multi(const T *A, long ld, int n, const T *X, long xs, int nr, const double *c,
+                       long cs, double *y, long ys, double *part, hipStream_t st) {
+    if (nr > 16)
+        launch_mfma_st<T, 2>(A, ld, n, X, xs, nr, c, cs, y, ys, part, st);
+    else
+        launch_mfma_st<T, 1>(A, ld, n, X, xs, nr, c, cs, y, ys, part, st);
+}
+
+}  // namespace
 
 void launch_mfma_multi64(const double *A, long ld, int n, const double *X, long xs, int nr,
                          const double *c, long cs, double *y, long ys, double *part,
                          hipStream_t st) {
-    const int ks = multi_ksplit(n);
-    const int kchunk = cdiv(cdiv(n, ks), 16) * 16;
-    const int ksn = cdiv(n, kchunk);
-    hipLaunchKernelGGL((k_mfma_multi<double>), dim3(cdiv(n, 64), ksn), dim3(256), 0, st, A, ld, n,
-                       X, xs, nr, kchunk, part);
-    hipLaunchKernelGGL(k_reduce_multi, dim3(cdiv(n, 256), nr), dim3(256), 0, st, n, nr, part, ksn,
-                       c, cs, y, ys);
+    launch_mfma_multi<double>(A, ld, n, X, xs, nr, c, cs, y, ys, part, st);
 }
 
 void launch_mfma_multi32(const float *A, long ld, int n, const float *X, long xs, int nr,
                          const double *c, long cs, double *y, long ys, double *part,
                          hipStream_t st) {
-    const int ks = multi_ksplit(n);
-    const int kchunk = cdiv(cdiv(n, ks), 16) * 16;
-    const int ksn = cdiv(n, kchunk);
-    hipLaunchKernelGGL((k_mfma_multi<float>), dim3(cdiv(n, 64), ksn), dim3(256), 0, st, A, ld, n,
-                       X, xs, nr, kchunk, part);
-    hipLaunchKernelGGL(k_reduce_multi, dim3(cdiv(n, 256), nr), dim3(256), 0, st, n, nr, part, ksn,
-                       c, cs, y, ys);
+    launch_mfma_multi<float>(A, ld, n, X, xs, nr, c, cs, y, ys, part, st);
 }
 
 void launch_to_f32_batched(const double *src, long ss, float *dst, long ds, int n, int nr,
@@ -163,10 +284,13 @@ void launch_copy_strided(const double *src, long ss, double *dst, long ds, int n
                        n);
 }
 
+// the largest partial-sum buffer any shape and precision needs for nr systems
 int multi_part_size(int n, int nr) {
-    const int ks = multi_ksplit(n);
-    const int kchunk = cdiv(cdiv(n, ks), 16) * 16;
-    return cdiv(n, kchunk) * nr * n;
+    int ks = 0;
+    for (const MultiGrid g : {multi_grid_for<float, 1>(n), multi_grid_for<float, 2>(n),
+                              multi_grid_for<double, 1>(n), multi_grid_for<double, 2>(n)})
+        ks = std::max(ks, g.ksn);
+    return ks * nr * n;
 }
 
 }  // namespace wwbi

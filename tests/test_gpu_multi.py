@@ -37,9 +37,10 @@ def oracle_A(name, geom):
     return _A[name]
 
 
-@pytest.mark.parametrize("name,nr,prec", [("ragged", 5, "fp64"), ("c1", 20, "fp64"),
-                                          ("c1", 32, "fp64"), ("c1", 7, "fp32"),
-                                          ("c2", 16, "fp32"), ("c2", 4, "fp64")])
+@pytest.mark.parametrize("name,nr,prec", [("ragged", 5, "fp64"), ("ragged", 17, "fp32"),
+                                          ("c1", 20, "fp64"), ("c1", 32, "fp64"),
+                                          ("c1", 7, "fp32"), ("c2", 16, "fp32"),
+                                          ("c2", 32, "fp32"), ("c2", 4, "fp64")])
 def test_multi_rhs_matches_dense_lu(ww, ctx, name, nr, prec):
     say(f"case multi {name} nr={nr} {prec}")
     cfg = ragged_config() if name == "ragged" else make_config(int(name[1]))
