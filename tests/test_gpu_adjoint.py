@@ -74,7 +74,7 @@ def _gpu_J_grad(ctx, geom, phi, w, **opts):
     U = normal_velocity(xt, yt, ph, prob)
     J = (wt * U * U).sum()
     J.backward()
-    return float(J), xt.grad.cpu().numpy(), yt.grad.cpu().numpy(), ph.grad.cpu().numpy(), prob
+    return float(J.detach()), xt.grad.cpu().numpy(), yt.grad.cpu().numpy(), ph.grad.cpu().numpy(), prob
 
 
 @pytest.mark.parametrize("which", ["c1", "tiny"])
