@@ -156,7 +156,7 @@ def timed_solves(ctx, dg, phi, steps, warmup, flags=0, **kw):
 
 def time_extras(ctx, dg, geom, phi, a, reps=5):
     """Per-call times, on the same cell, of the other entry points: the
-    diagnostics (tangential velocity on every node and the energy), the
+    vortex-sheet solve, the diagnostics (tangential velocity on every node and the energy), the
     gamma_t stage (its own velocity-potential solve plus the right-hand side
     and the n x n FP64 system), one evolution stage and one DOP853 step (HLS
     surface), velocity and pressure at 4096 points inside the fluid, and
@@ -165,8 +165,19 @@ def time_extras(ctx, dg, geom, phi, a, reps=5):
     M0 = geom.M[0]
     al = torch.arange(M0, dtype=torch.float64, device=phi.device) * (2 * np.pi / M0)
     V = 0.1 * torch.sin(al) + 0.03 * torch.cos(2 * al)
-    _, omega, _, _ = ctx.solve_phi(dg, phi, tol=1e-13)
+    U64, omega, _, _ = ctx.solve_phi(dg, phi, tol=1e-13)
     out = {}
+    # the vortex-sheet entry on the same cell, gamma_0 = -D omega_0 from the
+    # FP64 velocity-potential solve; both formulations give the same U
+    gam0 = ctx.spectral(omega[:M0].contiguous(), wwbi.OP_D, alpha=-1.0)
+    gs = []
+    for _ in range(reps + 1):
+        Ug, _, r = ctx.solve_gamma(dg, gam0, tol=1e-13, restart=100, poll_every=a.poll)
+        gs.append(r.as_dict())
+    out["solve_gamma_ms"] = stats_ms(gs[1:])
+    out["solve_gamma_iters"] = gs[-1]["iters"]
+    out["solve_gamma_phases_ms"] = {k: gs[-1][k] for k in ("ms_prep", "ms_assemble", "ms_solve", "ms_U")}
+    out["solve_gamma_U_vs_solve_phi_U"] = float((Ug - U64).abs().max() / U64.abs().max())
     te = []
     for _ in range(reps + 1):
         _, _, r = ctx.tangential_energy(dg, omega, phi, tau=0.1, grav=1.0)
