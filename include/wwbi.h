@@ -343,7 +343,10 @@ int wwbi_adjoint_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, con
  * With WWBI_FP32_REFINED the context also holds an FP64 copy of the matrix
  * (8 bytes per entry beside the FP32 one), from which the residuals of all
  * systems are formed in one pass; when that copy cannot be allocated they are
- * formed on the fly, one system at a time. */
+ * formed on the fly, one system at a time.
+ * Errors: WWBI_EINVAL_OPTS for n outside 1..32, an on-the-fly matvec or a
+ * warm start; WWBI_EINVAL_NONFINITE for a non-finite right-hand side entry
+ * (omega untouched); the geometry is checked as for wwbi_solve_phi. */
 int wwbi_solve_phi_multi(wwbi_ctx *ctx, const wwbi_geom *g, const double *rhs, int32_t n,
                          const wwbi_opts *o, double *omega, wwbi_report *rep);
 

@@ -1647,9 +1647,17 @@ int wwbi_solve_phi_multi(wwbi_ctx *ctx, const wwbi_geom *g, const double *rhs, i
     if (!rc && (nr < 1 || nr > kMaxMulti)) rc = WWBI_EINVAL_OPTS;
     if (!rc && (o->matvec == WWBI_MATVEC_ON_THE_FLY || o->x0)) rc = WWBI_EINVAL_OPTS;
     if (!rc) {
-        c->restart_cap = std::max(c->restart_cap, o->restart);
-        c->begin_report((o->flags & WWBI_FLAG_PROFILE) != 0);
-        rc = c->setup(g, nullptr, 0);
+        // the right-hand sides are checked with the geometry: nr x sum(M)
+        // values (setup rejects a malformed geometry before reading them)
+        long ntot = 0;
+        if (g && g->M && g->nb >= 2 && g->nb <= kMaxB)
+            for (int k = 0; k < g->nb; ++k) ntot += std::max(0, g->M[k]);
+        if (ntot * nr > INT32_MAX) rc = WWBI_EINVAL_SIZE;
+        if (!rc) {
+            c->restart_cap = std::max(c->restart_cap, o->restart);
+            c->begin_report((o->flags & WWBI_FLAG_PROFILE) != 0);
+            rc = c->setup(g, rhs, (int)(ntot * nr));
+        }
     }
     if (!rc) rc = c->ensure_multi(c->L.n, nr, o->restart);
     if (rc) {

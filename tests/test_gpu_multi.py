@@ -73,3 +73,28 @@ def test_multi_equals_single_solves(ww, ctx):
     o = out.cpu().numpy()
     for s, f in enumerate((1.0, 2.0, -1.0)):
         assert np.abs(o[s] - f * om).max() <= 1e-11 * np.abs(om).max()
+
+
+def test_multi_errors(ww, ctx):
+    """Invalid calls are rejected before any output is written."""
+    say("case multi errors")
+    cfg = make_config(1)
+    geom = cfg["geom"]
+    dg = ww.DeviceGeometry.from_synth(geom, DEV)
+    n = geom.Mtot
+    rhs = torch.as_tensor(np.random.default_rng(3).standard_normal((3, n)), device=DEV)
+    for kw in (dict(matvec=ww.MATVEC_ON_THE_FLY), dict(x0=torch.zeros(n, dtype=torch.float64, device=DEV))):
+        with pytest.raises(ww.WWBIError) as e:
+            ctx.solve_phi_multi(dg, rhs, **kw)
+        assert e.value.status == ww.EINVAL_OPTS
+    with pytest.raises(ww.WWBIError) as e:
+        ctx.solve_phi_multi(dg, torch.zeros((33, n), dtype=torch.float64, device=DEV))
+    assert e.value.status == ww.EINVAL_OPTS
+    bad = rhs.clone()
+    bad[2, n - 1] = float("nan")
+    with pytest.raises(ww.WWBIError) as e:
+        ctx.solve_phi_multi(dg, bad)
+    assert e.value.status == ww.EINVAL_NONFINITE
+    # a valid call after the rejected ones still solves
+    out, rep = ctx.solve_phi_multi(dg, rhs, tol=1e-13)
+    assert rep.status == 0 and torch.isfinite(out).all()
