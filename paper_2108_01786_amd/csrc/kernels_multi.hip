@@ -2,9 +2,10 @@
 //   Y_s = A X_s,  s < nr,
 // on the matrix cores (v_mfma_f64_16x16x4_f64 for an FP64 matrix,
 // v_mfma_f32_16x16x4_f32 for FP32).  A wave owns RT tiles of 16 rows and ST
-// tiles of 16 systems (ST = 2 for nr > 16) and shares each B fragment across
-// its row tiles; K is split over grid.y and the partial products are reduced
-// in a fixed order.
+// tiles of 16 systems and shares each B fragment across its row tiles; K is
+// split over grid.y and the partial products are reduced in a fixed order.
+// The launcher runs k_mfma_multi for up to 16 systems and
+// k_mfma_multi_shared, which shares the B tile across the block, for more.
 //
 // Operand mapping of one 16x16x4 step: lane l supplies A(i, k) with
 // i = l % 16, k = l / 16 and B(k, j) with j = l % 16, k = l / 16.  The result
@@ -59,12 +60,13 @@ template <> struct Mfma<float> {
     }
 };
 
-// rows per wave (in tiles of 16) and the wave count the K split aims at:
-// measured at n = 10240, 32 rows suit the FP32 single-tile case and 64 rows
-// the others (the 64-row waves run one round on the chip)
+// rows per wave (in tiles of 16) and the wave count the K split aims at,
+// measured at n = 10240: for up to 16 systems, 32 rows (FP32) or 64 rows
+// (FP64) per wave; for more, 32 rows per wave with the B tile shared by the
+// block (k_mfma_multi_shared), on a grid that runs in one round
 template <typename T, int ST> struct MultiShape {
-    static constexpr int RT = (sizeof(T) == 4 && ST == 1) ? 2 : 4;
-    static constexpr int waves = RT == 2 ? 4096 : 1920;
+    static constexpr int RT = (ST == 2 || sizeof(T) == 4) ? 2 : 4;
+    static constexpr int waves = ST == 2 ? 2304 : (RT == 2 ? 4096 : 1920);
 };
 
 template <typename T, int ST>
@@ -197,6 +199,132 @@ __global__ __launch_bounds__(256) void k_mfma_multi(const T *__restrict__ A, lon
         }
 }
 
+// The same product for 17..32 systems with the B tile shared by the block:
+// the 4 waves of a block cover consecutive row tiles over one K chunk, so the
+// block loads the 32 x 256-byte B tile of a step once, into one of two LDS
+// buffers, and synchronises once per step.  The buffer written at step t was
+// last read at step t - 2, and every wave has passed the barrier of step t - 1
+// (which follows its reads of step t - 2) before any wave writes it again.
+// Each wave keeps its own matrix tile in LDS as in k_mfma_multi.  Waves past
+// the last row load row n - 1, join every barrier and store nothing.
+template <typename T>
+__global__ __launch_bounds__(256) void k_mfma_multi_shared(const T *__restrict__ A, long ld, int n,
+                                                           const T *__restrict__ X, long xs,
+                                                           int nr, int kchunk,
+                                                           double *__restrict__ part) {
+    using M = Mfma<T>;
+    using V = typename M::vec;
+    constexpr int RT = MultiShape<T, 2>::RT;
+    constexpr int E = M::E;
+    constexpr int KS = 16 * E;           // columns per step: 256 bytes of a row
+    constexpr int R = 16 * RT;           // rows per wave
+    constexpr int P = R / 4;             // matrix load instructions per step
+    constexpr int U = 4;                 // MFMA groups per step
+    constexpr int SW = 64 + 4;           // LDS row stride in 4-byte words
+    constexpr int NS = 32;               // systems in the B tile
+    constexpr int XB = NS * 16 / 256;    // B pieces of 16 bytes per thread per step
+    __shared__ float lds[4][R * SW];
+    __shared__ float ldx[2][NS * SW];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, tid = threadIdx.x;
+    const int row0 = (blockIdx.x * 4 + wv) * R;
+    const int kb = blockIdx.y * kchunk;
+    const int ke = min(n, kb + kchunk);
+    const int i = lane & 15, q = lane >> 4;
+    const int lr = lane >> 4, lc = (lane & 15) * E;
+    const V *ap[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int r = min(row0 + 4 * p + lr, n - 1);
+        ap[p] = reinterpret_cast<const V *>(A + (long)r * ld + kb + lc);
+    }
+    // B piece f = tid + 256 j: system f / 16, columns (f % 16) E ..
+    const V *xq[XB];
+    int xrow[XB], xcol[XB];
+#pragma unroll
+    for (int j = 0; j < XB; ++j) {
+        const int f = tid + 256 * j;
+        xrow[j] = f / 16;
+        xcol[j] = (f % 16) * E;
+        xq[j] = reinterpret_cast<const V *>(X + (long)(xrow[j] < nr ? xrow[j] : 0) * xs + kb +
+                                            xcol[j]);
+    }
+    float *L = lds[wv];
+    typename M::acc c[RT][2];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) c[rt][0] = c[rt][1] = typename M::acc{0, 0, 0, 0};
+    V ga[P], gx[XB];
+#pragma unroll
+    for (int p = 0; p < P; ++p) ga[p] = __builtin_nontemporal_load(ap[p]);
+#pragma unroll
+    for (int j = 0; j < XB; ++j) gx[j] = xq[j][0];
+    int buf = 0;
+    auto body = [&](const int k0, const bool pf, const bool tail) __attribute__((always_inline)) {
+        const int off = (k0 - kb) / E;
+        if (tail) {
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+#pragma unroll
+                for (int p = 0; p < P; ++p) ga[p][e] = (k0 + lc + e < ke) ? ga[p][e] : (T)0;
+#pragma unroll
+                for (int j = 0; j < XB; ++j) gx[j][e] = (k0 + xcol[j] + e < ke) ? gx[j][e] : (T)0;
+            }
+        }
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int p = 0; p < P; ++p)
+            *reinterpret_cast<V *>(L + (4 * p + lr) * SW + lc * (int)sizeof(T) / 4) = ga[p];
+        float *LX = ldx[buf];
+#pragma unroll
+        for (int j = 0; j < XB; ++j)
+            *reinterpret_cast<V *>(LX + xrow[j] * SW + xcol[j] * (int)sizeof(T) / 4) = gx[j];
+        asm volatile("" ::: "memory");
+        if (pf) {
+#pragma unroll
+            for (int j = 0; j < XB; ++j) gx[j] = xq[j][off + KS / E];
+#pragma unroll
+            for (int p = 0; p < P; ++p)
+                ga[p] = __builtin_nontemporal_load(ap[p] + off + KS / E);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            V a[RT], b[2];
+#pragma unroll
+            for (int st = 0; st < 2; ++st)
+                b[st] = *reinterpret_cast<const V *>(LX + (16 * st + i) * SW +
+                                                     (4 * E * u + E * q) * (int)sizeof(T) / 4);
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+                a[rt] = *reinterpret_cast<const V *>(L + (16 * rt + i) * SW +
+                                                     (4 * E * u + E * q) * (int)sizeof(T) / 4);
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int st = 0; st < 2; ++st)
+                        c[rt][st] = M::step(a[rt][e], b[st][e], c[rt][st]);
+        }
+        buf ^= 1;
+    };
+    int k0 = kb;
+    for (; k0 + KS < ke; k0 += KS) body(k0, true, false);
+    body(k0, false, k0 + KS > ke);
+    if (row0 >= n) return;
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int st = 0; st < 2; ++st) {
+            const int s = 16 * st + i;
+            if (s >= nr) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int rr = row0 + 16 * rt + M::row(q, r);
+                if (rr < n) part[((long)blockIdx.y * nr + s) * n + rr] = (double)c[rt][st][r];
+            }
+        }
+}
+
 // y_s = c_s - sum_k part[k][s] (or the plain sum when c is null)
 __global__ void k_reduce_multi(int n, int nr, const double *__restrict__ part, int ks,
                                const double *__restrict__ c, long cs, double *__restrict__ y,
@@ -243,8 +371,12 @@ void launch_mfma_st(const T *A, long ld, int n, const T *X, long xs, int nr, con
                     long cs, double *y, long ys, double *part, hipStream_t st) {
     const MultiGrid g = multi_grid_for<T, ST>(n);
     const dim3 grid(cdiv(n, 4 * 16 * MultiShape<T, ST>::RT), g.ksn);
-    hipLaunchKernelGGL((k_mfma_multi<T, ST>), grid, dim3(256), 0, st, A, ld, n, X, xs, nr,
-                       g.kchunk, part);
+    if (ST == 2)
+        hipLaunchKernelGGL((k_mfma_multi_shared<T>), grid, dim3(256), 0, st, A, ld, n, X, xs, nr,
+                           g.kchunk, part);
+    else
+        hipLaunchKernelGGL((k_mfma_multi<T, 1>), grid, dim3(256), 0, st, A, ld, n, X, xs, nr,
+                           g.kchunk, part);
     hipLaunchKernelGGL(k_reduce_multi, dim3(cdiv(n, 256), nr), dim3(256), 0, st, n, nr, part,
                        g.ksn, c, cs, y, ys);
 }
