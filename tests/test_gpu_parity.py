@@ -271,6 +271,28 @@ def test_deterministic(ww, ctx):
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("h", [1.0, 3.0])
+def test_flat_strip_closed_form(ww, ctx, prec, h):
+    """No obstacles, flat bottom at depth h, phi~ = cos(k alpha): the device U
+    is the finite-depth Dirichlet-Neumann operator k tanh(k h) cos(k alpha)
+    (Sec. 3 with N = 1), on both precision paths and both matvec modes; the
+    ragged surface/bottom sizes give tiles with tails."""
+    say(f"case flat strip h={h} {prec}")
+    from manufactured import flat_strip
+    geom = flat_strip(200, 136, h, 1.0)
+    dg = ww.DeviceGeometry.from_synth(geom, DEV)
+    al = 2 * np.pi * np.arange(200) / 200
+    kw = dict(tol=1e-13 if prec == "fp64" else 1e-14,
+              precision=ww.FP64 if prec == "fp64" else ww.FP32_REFINED)
+    for k in (1, 3, 7):
+        phi = torch.as_tensor(np.cos(k * al), device=DEV)
+        for mode in (ww.MATVEC_STORED, ww.MATVEC_ON_THE_FLY):
+            U, _, _, rep = ctx.solve_phi(dg, phi, matvec=mode, **kw)
+            err = np.abs(U.cpu().numpy() - k * np.tanh(k * h) * np.cos(k * al)).max()
+            assert rep.status == 0 and err <= (1e-12 if prec == "fp64" else 1e-11) * k, (k, err)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_zero_right_hand_side(ww, ctx, prec):
     """b = 0 (flat strip, phi~ = 0, V1 = 0, no obstacles): omega = 0 and U = 0
     exactly, on both precision paths (the cold start writes x without a fill)."""
