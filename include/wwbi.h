@@ -49,6 +49,8 @@ extern "C" {
 #define WWBI_ECAPACITY           -5  /* workspace allocation failed                    */
 #define WWBI_EHIP                -6  /* a HIP runtime call failed                      */
 #define WWBI_EINVAL_OPTS         -7  /* option out of range                            */
+#define WWBI_EINVAL_RANGE        -8  /* a node has |y| > 30: far pairs use e^{-y} in
+                                        FP32 intermediate steps, whose range this keeps */
 #define WWBI_NOT_CONVERGED        1  /* iteration budget spent before the tolerance    */
 #define WWBI_STAGNATED            2  /* a restart cycle made no progress               */
 #define WWBI_REFINE_STALLED       3  /* iterative refinement stopped contracting       */

@@ -70,7 +70,7 @@ int Ctx::ensure(int n, int restart) {
     G(hrow, caphrow, nn);
     G(eR, capeR, nn);
     G(eI, capeI, nn);
-    G(val, capval, 3 * kMaxB + 8);
+    G(val, capval, 4 * kMaxB + 8);
     return rc;
 }
 
@@ -166,17 +166,19 @@ int Ctx::setup(const wwbi_geom *g, const double *phi, int nphi) {
                       eR, eI, stream);
     launch_circulant_rows(L, kOpHalfCot, hrow, stream);
     launch_validate(L, N, phi, phi ? nphi : 0, val, stream);
-    if (hipMemcpyAsync(hst, val, sizeof(double) * (3 * L.nb + 1), hipMemcpyDeviceToHost,
+    if (hipMemcpyAsync(hst, val, sizeof(double) * (4 * L.nb + 1), hipMemcpyDeviceToHost,
                        stream) != hipSuccess)
         return WWBI_EHIP;
     if (hipStreamSynchronize(stream) != hipSuccess) return WWBI_EHIP;
     const double *h = (const double *)hst;
     for (int k = 0; k < L.nb; ++k)
-        if (h[3 * k] != 0.0) return WWBI_EINVAL_NONFINITE;
-    if (h[3 * L.nb] != 0.0) return WWBI_EINVAL_NONFINITE;
+        if (h[4 * k] != 0.0) return WWBI_EINVAL_NONFINITE;
+    if (h[4 * L.nb] != 0.0) return WWBI_EINVAL_NONFINITE;
+    for (int k = 0; k < L.nb; ++k)
+        if (h[4 * k + 3] != 0.0) return WWBI_EINVAL_RANGE;
     for (int k = 0; k < L.nb; ++k) {
-        if (k <= 1 && !(h[3 * k + 2] > 0.0)) return WWBI_EINVAL_ORIENTATION;
-        if (k >= 2 && !(h[3 * k + 1] < 0.0)) return WWBI_EINVAL_ORIENTATION;
+        if (k <= 1 && !(h[4 * k + 2] > 0.0)) return WWBI_EINVAL_ORIENTATION;
+        if (k >= 2 && !(h[4 * k + 1] < 0.0)) return WWBI_EINVAL_ORIENTATION;
     }
     return WWBI_OK;
 }
@@ -838,6 +840,7 @@ const char *wwbi_status_str(int s) {
     case WWBI_ECAPACITY: return "out of device memory";
     case WWBI_EHIP: return "HIP runtime error";
     case WWBI_EINVAL_OPTS: return "invalid options";
+    case WWBI_EINVAL_RANGE: return "invalid argument: a node lies more than 30 above or below y = 0";
     case WWBI_NOT_CONVERGED: return "not converged";
     case WWBI_STAGNATED: return "stagnated";
     case WWBI_REFINE_STALLED: return "iterative refinement stalled";

@@ -10,6 +10,13 @@ namespace wwbi {
 
 constexpr int kMaxB = WWBI_MAX_BOUNDARIES;
 
+// Largest |y| of a node.  Far pairs work with E = e^{i zeta}, |E| = e^{-y}:
+// the FP32 assembly forms |E_q - E_p|^2 and the FP64 far tiles seed their
+// reciprocal of it in FP32, so e^{+-2|y|} and the products of two such
+// quantities must stay inside the FP32 normal range.  |y| <= 30 keeps them
+// within [1e-30, 1e30] after the near-pair cut (|E_q - E_p| >= |E_p| / 64).
+constexpr double kMaxAbsY = 30.0;
+
 // Boundary layout: node p of boundary k has global index off[k] + m.
 struct Layout {
     int nb;

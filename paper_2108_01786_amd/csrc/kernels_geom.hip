@@ -65,27 +65,30 @@ __global__ void k_validate(Layout L, Nodes N, const double *phi, int nphi, doubl
         for (int i = threadIdx.x; i < nphi; i += blockDim.x)
             bad += isfinite(phi[i]) ? 0.0 : 1.0;
         bad = block_sum(bad, sh);
-        if (threadIdx.x == 0) out[3 * L.nb] = bad;
+        if (threadIdx.x == 0) out[4 * L.nb] = bad;
         return;
     }
     const int p0 = L.off[k], p1 = L.off[k + 1];
     const double M = (double)(p1 - p0);
-    double bad = 0.0, area = 0.0, mdx = 0.0;
+    double bad = 0.0, area = 0.0, mdx = 0.0, far = 0.0;
     for (int p = p0 + threadIdx.x; p < p1; p += blockDim.x) {
         const double v[6] = {N.x[p], N.y[p], N.dx[p], N.dy[p], N.ddx[p], N.ddy[p]};
         bool fin = true;
         for (int i = 0; i < 6; ++i) fin = fin && isfinite(v[i]);
         bad += fin ? 0.0 : 1.0;
+        far += fabs(v[1]) > kMaxAbsY ? 1.0 : 0.0;
         area += 0.5 * (v[0] * v[3] - v[1] * v[2]) * (2.0 * M_PI / M);
         mdx += v[2] / M;
     }
     bad = block_sum(bad, sh);
     area = block_sum(area, sh);
     mdx = block_sum(mdx, sh);
+    far = block_sum(far, sh);
     if (threadIdx.x == 0) {
-        out[3 * k + 0] = bad;
-        out[3 * k + 1] = area;
-        out[3 * k + 2] = mdx;
+        out[4 * k + 0] = bad;
+        out[4 * k + 1] = area;
+        out[4 * k + 2] = mdx;
+        out[4 * k + 3] = far;
     }
 }
 

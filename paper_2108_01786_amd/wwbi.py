@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libwwbi.so")
 
 # status codes and option values (mirror include/wwbi.h)
 OK, EINVAL_NULL, EINVAL_SIZE, EINVAL_NONFINITE, EINVAL_ORIENTATION = 0, -1, -2, -3, -4
-ECAPACITY, EHIP, EINVAL_OPTS = -5, -6, -7
+ECAPACITY, EHIP, EINVAL_OPTS, EINVAL_RANGE = -5, -6, -7, -8
 NOT_CONVERGED, STAGNATED, REFINE_STALLED, WARN_UNDERRESOLVED = 1, 2, 3, 4
 FP64, FP32_REFINED = 0, 1
 SURF_GRAPH, SURF_HLS = 0, 1

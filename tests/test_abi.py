@@ -44,6 +44,7 @@ def test_host_only_helpers():
     assert wwbi.status_str(wwbi.EINVAL_ORIENTATION).startswith("invalid argument")
     assert wwbi.status_str(wwbi.NOT_CONVERGED) == "not converged"
     assert "Fourier tail" in wwbi.status_str(wwbi.WARN_UNDERRESOLVED)
+    assert "30" in wwbi.status_str(wwbi.EINVAL_RANGE)
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libwwbi.so not built")

@@ -292,6 +292,27 @@ def test_flat_strip_closed_form(ww, ctx, prec, h):
             assert rep.status == 0 and err <= (1e-12 if prec == "fp64" else 1e-11) * k, (k, err)
 
 
+def test_node_height_range(ww, ctx):
+    """Far pairs use E = e^{i zeta} with FP32 intermediate steps, so nodes must
+    keep |y| <= 30: a bottom at depth 29 solves (U = k tanh(29 k) cos(k alpha),
+    both precisions), one at depth 31 is rejected with the outputs untouched."""
+    say("case node height range")
+    from manufactured import flat_strip
+    al = 2 * np.pi * np.arange(64) / 64
+    phi = torch.as_tensor(np.cos(3 * al), device=DEV)
+    dg = ww.DeviceGeometry.from_synth(flat_strip(64, 48, 29.0, 0.0), DEV)
+    for prec, tol in ((ww.FP64, 1e-13), (ww.FP32_REFINED, 1e-14)):
+        U, _, _, rep = ctx.solve_phi(dg, phi, precision=prec, tol=tol)
+        assert rep.status == 0
+        assert np.abs(U.cpu().numpy() - 3 * np.tanh(87.0) * np.cos(3 * al)).max() <= 1e-11
+    deep = ww.DeviceGeometry.from_synth(flat_strip(64, 48, 31.0, 0.0), DEV)
+    U = torch.full((64,), 7.0, dtype=torch.float64, device=DEV)
+    with pytest.raises(ww.WWBIError) as e:
+        ctx.solve_phi(deep, phi, U=U)
+    assert e.value.status == ww.EINVAL_RANGE
+    assert bool((U == 7.0).all())
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_zero_right_hand_side(ww, ctx, prec):
     """b = 0 (flat strip, phi~ = 0, V1 = 0, no obstacles): omega = 0 and U = 0
