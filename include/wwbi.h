@@ -55,8 +55,9 @@ extern "C" {
 #define WWBI_STAGNATED            2  /* a restart cycle made no progress               */
 #define WWBI_REFINE_STALLED       3  /* iterative refinement stopped contracting       */
 #define WWBI_WARN_UNDERRESOLVED   4  /* omega's Fourier tail (report.tail_ratio) is above
-                                        max(1e-12, 10 tol) on some boundary: the grid does
-                                        not resolve the solution (Sec. 7.1's test)     */
+                                        max(1e-12, 10 tol) on some boundary, at the scale
+                                        of the solution: the grid does not resolve it
+                                        (Sec. 7.1's test)                               */
 
 #define WWBI_MAX_BOUNDARIES      64
 
@@ -131,8 +132,11 @@ typedef struct {
     int32_t pad0;
     double ms_matvec;      /* their summed HIP-event duration (FLAG_PROFILE)              */
     double bytes_matvec;   /* algorithmic bytes moved by one such launch                  */
-    double tail_ratio;     /* wwbi_solve_phi: max over boundaries of the root of the energy
-                              fraction of omega_k in the modes |k| >= 3 M_k / 8 (else 0)  */
+    double tail_ratio;     /* wwbi_solve_phi: max over boundaries k of the root of the
+                              energy of omega_k in its modes |k| >= 3 M_k / 8 over M_k^2
+                              times the largest mean square of omega on any boundary
+                              (Parseval: the tail's share at the solution's scale; 0
+                              for other entry points)                                   */
 } wwbi_report;
 
 /* Fill *o with defaults: tol 1e-13, inner_tol 3e-7, restart 100, max_iter 2000,

@@ -980,12 +980,24 @@ static int solve_phi_impl(Ctx *c, const wwbi_geom *g, const double *phi, const w
     c->finish_report(rep, status, st, bytes);
     if (psi_k && c->L.nb > 2) std::memcpy(psi_k, c->hst, sizeof(double) * (c->L.nb - 2));
     if (hipGetLastError() != hipSuccess) return WWBI_EHIP;
-    double tail = 0.0;
+    // per boundary: the root of its tail energy over M_k^2 times the largest
+    // mean square of omega on any boundary, i.e. its tail in units of the
+    // solution's scale.  On the boundary carrying that largest mean square this
+    // is the energy fraction of its own tail; a boundary whose omega is at the
+    // solver's noise level (a bottom far below the surface) is not judged by
+    // the spectrum of that noise
+    double tail = 0.0, smax = 0.0;
+    bool finite = true;
     for (int k = 0; k < c->L.nb; ++k) {
-        const double t = tails[2 * k], e = tails[2 * k + 1];
-        if (e > 0.0) tail = std::max(tail, std::sqrt(t / e));
+        const double M = (double)(c->L.off[k + 1] - c->L.off[k]);
+        smax = std::max(smax, tails[2 * k + 1] / (M * M));
+        finite = finite && std::isfinite(tails[2 * k]) && std::isfinite(tails[2 * k + 1]);
     }
-    if (!std::isfinite(tail)) tail = HUGE_VAL;
+    for (int k = 0; k < c->L.nb && smax > 0.0; ++k) {
+        const double M = (double)(c->L.off[k + 1] - c->L.off[k]);
+        tail = std::max(tail, std::sqrt(tails[2 * k] / (smax * M * M)));
+    }
+    if (!finite || !std::isfinite(tail)) tail = HUGE_VAL;
     if (status == WWBI_OK && tail > std::max(1e-12, 10.0 * o->tol))
         status = WWBI_WARN_UNDERRESOLVED;
     if (rep) {

@@ -8,9 +8,18 @@ import oracle as O
 
 
 def oracle_tail(geom, omega) -> float:
-    """Largest tail ratio over the boundaries of an omega (oracle or GPU)."""
+    """Largest tail ratio over the boundaries of an omega (oracle or GPU): the
+    root of boundary k's tail energy over M_k^2 times the largest mean square of
+    omega on any boundary (on the boundary carrying that mean square, the
+    energy fraction of its own tail)."""
     w = torch.as_tensor(np.asarray(omega, dtype=np.float64))
-    return max(O.spectral_tail(v) for v in torch.split(w, list(geom.M)))
+    parts = torch.split(w, list(geom.M))
+    total = [len(v) * float((v * v).sum()) for v in parts]       # FFT energy (Parseval)
+    smax = max(t / len(v) ** 2 for t, v in zip(total, parts))
+    if smax == 0.0:
+        return 0.0
+    return max(float(np.sqrt(O.spectral_tail(v) ** 2 * t / (smax * len(v) ** 2))) if t > 0 else 0.0
+               for t, v in zip(total, parts))
 
 
 def check_tail_status(ww, rep, tol, ref_tail):
