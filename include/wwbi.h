@@ -304,7 +304,10 @@ int wwbi_boundary_velocity(wwbi_ctx *ctx, const wwbi_geom *g, const double *omeg
  * Spectrally accurate up to and on the boundary; a point equal to a node
  * (or a period image of one) takes that node's value.
  *   f_re, f_im (device) sum(M); zx, zy (device) npts points inside the fluid;
- *   out_re, out_im (device) npts. */
+ *   out_re, out_im (device) npts.
+ * The points are checked first (here, in wwbi_interior_velocity and in
+ * wwbi_pressure): WWBI_EINVAL_NONFINITE for a non-finite coordinate,
+ * WWBI_EINVAL_RANGE for |y| > 30, outputs untouched. */
 int wwbi_interior_eval(wwbi_ctx *ctx, const wwbi_geom *g, const double *f_re,
                        const double *f_im, int32_t npts, const double *zx, const double *zy,
                        double *out_re, double *out_im);

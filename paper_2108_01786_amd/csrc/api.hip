@@ -1417,6 +1417,16 @@ static int interior_common(Ctx *c, const wwbi_geom *g, int32_t npts, const doubl
     if (npts < 1 || npts > (1 << 26)) return WWBI_EINVAL_SIZE;
     int rc = c->setup(g, nullptr, 0);
     if (rc) return rc;
+    // the points: finite, and within the node height limit (a point inside
+    // the fluid lies between the bottom and the surface anyway)
+    launch_check_points(npts, zx, zy, c->val, c->stream);
+    if (hipMemcpyAsync(c->hst, c->val, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return WWBI_EHIP;
+    const double *h = (const double *)c->hst;
+    if (h[0] != 0.0) return WWBI_EINVAL_NONFINITE;
+    if (h[1] != 0.0) return WWBI_EINVAL_RANGE;
     const size_t ns = (size_t)ho_slices(npts, c->L.n);
     rc = grow(c->hop, c->caphop, 4 * ns * npts + 64);
     if (!rc) rc = grow(c->hoi, c->caphoi, ns * npts + 64);
@@ -1495,6 +1505,17 @@ int wwbi_pressure(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi, double t
         const size_t ns = (size_t)ho_slices(npts, (int)nsum);
         rc = grow(c->hop, c->caphop, 4 * ns * npts + 3 * (size_t)npts + 64);
         if (!rc) rc = grow(c->hoi, c->caphoi, ns * npts + 64);
+    }
+    if (!rc) {
+        // the points, before any work: finite and within the node height limit
+        launch_check_points(npts, zx, zy, c->val, c->stream);
+        if (hipMemcpyAsync(c->hst, c->val, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                           c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
+            rc = WWBI_EHIP;
+        const double *h = (const double *)c->hst;
+        if (!rc && h[0] != 0.0) rc = WWBI_EINVAL_NONFINITE;
+        if (!rc && h[1] != 0.0) rc = WWBI_EINVAL_RANGE;
     }
     if (rc) {
         if (rep) { std::memset(rep, 0, sizeof(*rep)); rep->status = rc; }

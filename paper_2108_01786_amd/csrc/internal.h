@@ -189,6 +189,10 @@ void launch_rk_combine(int M, const double *base, const double *K, long ld, cons
 // Helsing-Ojala rule at P points from boundary values f (partial slices in
 // part: 4 * ho_slices * P doubles; hit: ho_slices * P ints)
 int ho_slices(int P, int n);
+// out[0] = points with a non-finite coordinate, out[1] = finite points with
+// |y| > kMaxAbsY (2 doubles, device)
+void launch_check_points(int P, const double *zx, const double *zy, double *out,
+                         hipStream_t st);
 void launch_helsing_ojala(const Nodes &N, int n, int n0, int P, const double *zx,
                           const double *zy, const double *fr, const double *fi, double *part,
                           int *hit, bool neg_im, double *outr, double *outi, hipStream_t st);

@@ -222,6 +222,47 @@ static int ho_chunk(int P, int n) {
 
 int ho_slices(int P, int n) { return cdiv(n, ho_chunk(P, n)); }
 
+namespace {
+// out[0] = points with a non-finite coordinate, out[1] = points with |y| above
+// the node height limit (one block; the counts are exact small integers)
+__global__ __launch_bounds__(256) void k_check_points(int P, const double *__restrict__ zx,
+                                                      const double *__restrict__ zy,
+                                                      double *__restrict__ out) {
+    __shared__ double sh[8];
+    double bad = 0.0, far = 0.0;
+    for (int p = threadIdx.x; p < P; p += blockDim.x) {
+        const double x = zx[p], y = zy[p];
+        const bool fin = isfinite(x) && isfinite(y);
+        bad += fin ? 0.0 : 1.0;
+        far += fin && fabs(y) > kMaxAbsY ? 1.0 : 0.0;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        bad += __shfl_xor(bad, o, 64);
+        far += __shfl_xor(far, o, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        sh[2 * w] = bad;
+        sh[2 * w + 1] = far;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = 0.0, f = 0.0;
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+            b += sh[2 * i];
+            f += sh[2 * i + 1];
+        }
+        out[0] = b;
+        out[1] = f;
+    }
+}
+}  // namespace
+
+void launch_check_points(int P, const double *zx, const double *zy, double *out,
+                         hipStream_t st) {
+    hipLaunchKernelGGL(k_check_points, dim3(1), dim3(256), 0, st, P, zx, zy, out);
+}
+
 void launch_helsing_ojala(const Nodes &N, int n, int n0, int P, const double *zx,
                           const double *zy, const double *fr, const double *fi, double *part,
                           int *hit, bool neg_im, double *outr, double *outi, hipStream_t st) {

@@ -113,3 +113,30 @@ def test_pressure_hydrostatic(ww, ctx, V1):
     z = torch.tensor([1.0 - 0.3j, 2.0 - 0.6j, 4.0 - 0.95j], dtype=torch.complex128)
     p, _ = ctx.pressure(dg, torch.zeros(64, dtype=torch.float64, device=DEV), z.to(DEV), tau=0.1)
     assert float((p.cpu() + z.imag).abs().max()) <= 1e-13
+
+
+def test_interior_point_checks(ww, ctx):
+    """Interior points are checked before any work: a non-finite coordinate
+    gives EINVAL_NONFINITE, |y| > 30 gives EINVAL_RANGE, on all three entries;
+    valid points afterwards still evaluate."""
+    say("case interior point checks")
+    cfg = make_config(1)
+    dg = ww.DeviceGeometry.from_synth(cfg["geom"], DEV)
+    phi = torch.as_tensor(cfg["phi"], device=DEV)
+    _, omega, _, _ = ctx.solve_phi(dg, phi, tol=1e-13)
+    good = torch.tensor([1.0 - 0.3j, 2.0 - 0.7j], dtype=torch.complex128, device=DEV)
+    f = torch.zeros(dg.n, dtype=torch.complex128, device=DEV)
+    for bad, status in ((torch.tensor([1.0 - 0.3j, complex(float("nan"), -0.5)]), ww.EINVAL_NONFINITE),
+                        (torch.tensor([1.0 - 0.3j, 2.0 - 31.0j]), ww.EINVAL_RANGE)):
+        z = bad.to(torch.complex128).to(DEV)
+        with pytest.raises(ww.WWBIError) as e:
+            ctx.interior_eval(dg, f, z)
+        assert e.value.status == status
+        with pytest.raises(ww.WWBIError) as e:
+            ctx.interior_velocity(dg, omega, z)
+        assert e.value.status == status
+        with pytest.raises(ww.WWBIError) as e:
+            ctx.pressure(dg, phi, z, tol=1e-13)
+        assert e.value.status == status
+    u, v = ctx.interior_velocity(dg, omega, good)
+    assert torch.isfinite(u).all() and torch.isfinite(v).all()
