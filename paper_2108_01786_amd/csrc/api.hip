@@ -984,7 +984,7 @@ static int solve_phi_impl(Ctx *c, const wwbi_geom *g, const double *phi, const w
     // mean square of omega on any boundary, i.e. its tail in units of the
     // solution's scale.  On the boundary carrying that largest mean square this
     // is the energy fraction of its own tail; a boundary whose omega is at the
-    // solver's noise level (a bottom far below the surface) is not judged by
+    // solver's noise level (a bottom far below the surface) is not flagged by
     // the spectrum of that noise
     double tail = 0.0, smax = 0.0;
     bool finite = true;
