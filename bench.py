@@ -29,15 +29,16 @@ import torch  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_k_gemv_fp32_config3_M10240.md")
+TRAFFIC_FILE_LARGE = os.path.join(ROOT, "profiles", "hbm_traffic_k_gemv_fp32_large_M40960.md")
 
 
-def measured_traffic():
-    """HBM bytes per launch of the stored FP32 matvec from the committed
+def measured_traffic(path=TRAFFIC_FILE):
+    """HBM bytes per launch of the stored FP32 matvec from a committed
     rocprofv3 counter summary (FETCH_SIZE and WRITE_SIZE, each scaled by a
     1 GiB copy), or None when the kernel source changed since it was taken."""
     import hashlib
     try:
-        text = open(TRAFFIC_FILE).read()
+        text = open(path).read()
         src = open(os.path.join(ROOT, "paper_2108_01786_amd", "csrc", "kernels_gemv.hip"), "rb").read()
     except OSError:
         return None
@@ -332,7 +333,7 @@ def run_large(a):
         "forward_iters_cold": cold["iters"] if cold else None,
         "adjoint_iters": [r["iters"] for r in ad],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(TRAFFIC_FILE_LARGE),
                      "kernel": "k_gemv<float,float,float,2,4> (stored FP32 matvec)",
                      "avg_launch_ms": avg, "launches": p["n_matvec"],
                      "bytes_per_launch": p["bytes_matvec"]},
