@@ -194,6 +194,18 @@ def time_extras(ctx, dg, geom, phi, a, reps=5):
     out["gamma_t_phi_solve_ms"] = stats_ms(gp[1:])
     out["gamma_t_iters"] = gt[-1]["iters"]
     out["gamma_t_phases_ms"] = {k: gt[-1][k] for k in ("ms_prep", "ms_assemble", "ms_solve")}
+    # the same stage with both solves in refined FP32
+    gr, gpr = [], []
+    for _ in range(reps + 1):
+        _, _, r1, r2 = ctx.solve_gamma_t(dg, phi, V, tau=0.1, tol=1e-14, restart=100,
+                                         precision=wwbi.FP32_REFINED, inner_tol=a.inner_tol,
+                                         poll_every=a.poll)
+        gr.append(r2.as_dict())
+        gpr.append(r1.as_dict())
+    out["gamma_t_stage_refined_ms"] = stats_ms(gr[1:])
+    out["gamma_t_phi_solve_refined_ms"] = stats_ms(gpr[1:])
+    out["gamma_t_refined_iters"] = gr[-1]["iters"]
+    out["gamma_t_refined_refine_steps"] = gr[-1]["refine_steps"]
     # one evolution stage (HLS surface, refined FP32 solve) and one DOP853 step
     # (tableau read from scipy) on the same walls; the stage's surface is
     # written into a copy of the geometry

@@ -235,9 +235,11 @@ int wwbi_tangential_energy(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi,
  *   phi    (device) M_0: phi~ of the state.
  *   V      (device) M_0: tangential velocity of the surface parameterisation.
  *   tau, grav: surface tension and gravity.
- *   o: tol, restart, max_iter and matvec apply to both solves; precision and
- *      x0 (an omega warm start) to the velocity-potential solve only; the
- *      gamma_t system is solved in FP64 (stored or on the fly).
+ *   o: tol, restart, max_iter, matvec and precision apply to both solves, x0
+ *      (an omega warm start) to the velocity-potential solve only.  The gamma_t
+ *      system is solved in FP64 (stored or on the fly) or, with a stored matvec
+ *      and WWBI_FP32_REFINED, by FP32 products (entries evaluated in FP64,
+ *      stored rounded) inside FP64 refinement with on-the-fly FP64 residuals.
  * Outputs: gamma_t (device) sum(M), concatenated boundary by boundary;
  *   U (device) M_0 or NULL: the normal velocity of the state;
  *   rep_phi / rep (either may be NULL): reports of the velocity-potential

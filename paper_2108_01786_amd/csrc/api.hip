@@ -195,6 +195,7 @@ void Ctx::apply(const Op &op, const double *x, const float *x32, const double *c
         launch_gemv64((const double *)A, ld, op.n, x, c, y, active, stream);
         break;
     case OP_A_S32:
+    case OP_GT_S32:
         if (x32)
             launch_gemv32((const float *)A, ld, op.n, x32, c, y, active, stream);
         else
@@ -237,7 +238,7 @@ double Ctx::op_bytes(const Op &op) const {
     switch (op.kind) {
     case OP_A_S64: case OP_W_S64: case OP_GT_S64:
         return n * n * 8.0 + 2.0 * n * 8.0;
-    case OP_A_S32: return n * n * 4.0 + n * 4.0 + n * 8.0;
+    case OP_A_S32: case OP_GT_S32: return n * n * 4.0 + n * 4.0 + n * 8.0;
     default: return 0.0;
     }
 }
@@ -479,7 +480,7 @@ int Ctx::refine(const Op &op32, const Op &op64, const double *b, double *x, bool
         // for the cold step rn = ||b||, where the inner tolerance does not depend on ||b||
         const double itol = cold ? inner_tolerance(o, 1.0, 1.0) : inner_tolerance(o, bn, rn);
         const int rc = gmres(op32, cold ? b : r, cold ? x : d, true, itol, o.restart,
-                             o.max_iter - st.iters, o.poll_every, op32.kind == OP_A_S32, false,
+                             o.max_iter - st.iters, o.poll_every, stored_fp32(op32.kind), false,
                              in);
         if (rc < 0) return rc;
         inner_pending = true;
@@ -1184,17 +1185,29 @@ int wwbi_solve_gamma_t(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi, con
     }
     launch_circulant_apply(L, c->rowD, e, b, 1.0, 0.0, 0, L.nb - 1, sm);
     hipEventRecord(c->ev[1], sm);
-    // 3. the gamma_t operator, stored or on the fly, and GMRES in FP64
+    // 3. the gamma_t operator, stored or on the fly: GMRES in FP64, or (stored,
+    // FP32_REFINED) FP32 products inside FP64 refinement with on-the-fly
+    // FP64 residuals
     const bool stored = o->matvec != WWBI_MATVEC_ON_THE_FLY;
+    const bool refined = stored && o->precision == WWBI_FP32_REFINED;
     if (stored) {
-        rc = c->ensure_matrix((size_t)n * ld * 8);
+        rc = c->ensure_matrix((size_t)n * ld * (refined ? 4 : 8));
         if (rc) { c->finish_report(rep, rc, st, 0); return rc; }
-        launch_assemble_gt64(L, c->N, (double *)c->A, ld, sm);
+        if (refined)
+            launch_assemble_gt32(L, c->N, (float *)c->A, ld, sm);
+        else
+            launch_assemble_gt64(L, c->N, (double *)c->A, ld, sm);
     }
     hipEventRecord(c->ev[2], sm);
-    Op op{stored ? OP_GT_S64 : OP_GT_O64, n, ld, o->flags, o->band};
-    const int status = c->gmres(op, b, x, true, o->tol, o->restart, o->max_iter, o->poll_every,
-                                false, true, st);
+    Op op{refined ? OP_GT_S32 : (stored ? OP_GT_S64 : OP_GT_O64), n, ld, o->flags, o->band};
+    int status;
+    if (refined) {
+        const Op op64{OP_GT_O64, n, ld, o->flags, o->band};
+        status = c->refine(op, op64, b, x, true, *o, st);
+    } else {
+        status = c->gmres(op, b, x, true, o->tol, o->restart, o->max_iter, o->poll_every, false,
+                          true, st);
+    }
     hipEventRecord(c->ev[3], sm);
     if (status < 0) { c->finish_report(rep, status, st, c->op_bytes(op)); return status; }
     launch_copy(gamma_t, x, n, sm);

@@ -24,9 +24,9 @@ enum { kFastReNeg = 0, kFastRePos = 1, kFastIm = 2 };
 // FP64 assembly of A (WALL = 0), of the wall operator T - I/2 on the walls
 // (WALL = 1), of the gamma_t operator (WALL = 2) or of the normal-velocity
 // map T on the surface rows (WALL = 3): one column per thread.
-template <int WALL>
+template <int WALL, typename OutT = double>
 __global__ __launch_bounds__(256) void k_assemble(Nodes N, const double *hrow, int r0, int nr,
-                                                  int c0, int nc, int corr, double *out,
+                                                  int c0, int nc, int corr, OutT *out,
                                                   long ld) {
     __shared__ Tgt tg[kRowsPerAsmBlock];
     const int col = blockIdx.x * 256 + threadIdx.x;           // column within the output
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void k_assemble(Nodes N, const double *hrow, i
                 v = a_val64(N, tg[i], s, corr != 0);
             }
         }
-        __builtin_nontemporal_store(v, out + (long)(rbase + i) * ld + col);
+        __builtin_nontemporal_store((OutT)v, out + (long)(rbase + i) * ld + col);
     }
 }
 
@@ -725,6 +725,13 @@ void launch_assemble_gt64(const Layout &L, const Nodes &N, double *B, long ld, h
     const int n = L.n;
     dim3 grid(cdiv(ld, 256), cdiv(n, kRowsPerAsmBlock));
     hipLaunchKernelGGL(k_assemble<2>, grid, dim3(256), 0, st, N, nullptr, 0, n, 0, n, 1, B, ld);
+}
+
+void launch_assemble_gt32(const Layout &L, const Nodes &N, float *B, long ld, hipStream_t st) {
+    const int n = L.n;
+    dim3 grid(cdiv(ld, 256), cdiv(n, kRowsPerAsmBlock));
+    hipLaunchKernelGGL((k_assemble<2, float>), grid, dim3(256), 0, st, N, nullptr, 0, n, 0, n, 1,
+                       B, ld);
 }
 
 void launch_assemble_T64(const Layout &L, const Nodes &N, const double *hrow, double *T, long ld,

@@ -62,7 +62,8 @@ def _oracle(name, cfg, V, tau):
 
 @pytest.mark.parametrize("name,mode,prec", [("tiny", "stored", "fp64"), ("ragged", "stored", "fp64"),
                                             ("c1", "stored", "fp64"), ("c1", "otf", "fp64"),
-                                            ("c1", "stored", "fp32"), ("c2", "stored", "fp32")])
+                                            ("ragged", "stored", "fp32"), ("c1", "stored", "fp32"),
+                                            ("c1", "otf", "fp32"), ("c2", "stored", "fp32")])
 def test_gamma_t_matches_oracle(ww, ctx, name, mode, prec):
     say(f"case gamma_t {name} {mode} {prec}")
     cfg = _cfg(name)
