@@ -179,6 +179,14 @@ def time_extras(ctx, dg, geom, phi, a, reps=5):
     out["solve_gamma_iters"] = gs[-1]["iters"]
     out["solve_gamma_phases_ms"] = {k: gs[-1][k] for k in ("ms_prep", "ms_assemble", "ms_solve", "ms_U")}
     out["solve_gamma_U_vs_solve_phi_U"] = float((Ug - U64).abs().max() / U64.abs().max())
+    gr = []
+    for _ in range(reps + 1):
+        Ugr, _, r = ctx.solve_gamma(dg, gam0, tol=1e-14, restart=100, poll_every=a.poll,
+                                    precision=wwbi.FP32_REFINED, inner_tol=a.inner_tol)
+        gr.append(r.as_dict())
+    out["solve_gamma_refined_ms"] = stats_ms(gr[1:])
+    out["solve_gamma_refined_iters"] = gr[-1]["iters"]
+    out["solve_gamma_refined_U_vs_solve_phi_U"] = float((Ugr - U64).abs().max() / U64.abs().max())
     te = []
     for _ in range(reps + 1):
         _, _, r = ctx.tangential_energy(dg, omega, phi, tau=0.1, grav=1.0)

@@ -176,8 +176,10 @@ int wwbi_reserve(wwbi_ctx *ctx, int64_t max_unknowns, int32_t max_restart, int32
  *   omega  (device) sum(M), or NULL;
  *   psi_k  (host)   nb-2 stream-function constants psi|_k = mean(omega_k), or NULL.
  * Resolution check (the paper's Fourier-tail test, Sec. 7.1): the solve also
- * measures, on every boundary, the root of the energy fraction of omega_k in
- * its modes |k| >= 3 M_k / 8 (report.tail_ratio holds the largest).  Above
+ * measures, on every boundary, the root of the energy of omega_k in its
+ * modes |k| >= 3 M_k / 8 over M_k^2 times the largest mean square of omega on
+ * any boundary, i.e. the tail at the solution's scale (report.tail_ratio holds
+ * the largest).  Above
  * max(1e-12, 10 tol) a solve that otherwise succeeded returns
  * WWBI_WARN_UNDERRESOLVED, with its outputs as usual: typically a boundary
  * comes too close to another for its grid.
@@ -191,7 +193,11 @@ int wwbi_solve_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi, const w
  * - s dphi_mv/dn (zero normal velocity on every wall) by GMRES and returns
  *   U = [H gamma_0 / 2 + G_00^dagger gamma_0 + sum_j K_j0^dagger gamma_j
  *        + s dphi_mv/dn] / |zeta'|.
- * Outputs: U (device) M_0; gamma_wall (device) sum(M)-M_0 or NULL. */
+ * Outputs: U (device) M_0; gamma_wall (device) sum(M)-M_0 or NULL.
+ * Precision: FP64, or with a stored matvec and WWBI_FP32_REFINED, FP32
+ * products of the wall operator (entries evaluated in FP64, stored rounded)
+ * inside FP64 refinement with on-the-fly FP64 residuals; an on-the-fly
+ * matvec always runs in FP64.  o->x0 warm-starts gamma_wall. */
 int wwbi_solve_gamma(wwbi_ctx *ctx, const wwbi_geom *g, const double *gamma0, const wwbi_opts *o,
                      double *U, double *gamma_wall, wwbi_report *rep);
 

@@ -196,6 +196,7 @@ void Ctx::apply(const Op &op, const double *x, const float *x32, const double *c
         break;
     case OP_A_S32:
     case OP_GT_S32:
+    case OP_W_S32:
         if (x32)
             launch_gemv32((const float *)A, ld, op.n, x32, c, y, active, stream);
         else
@@ -238,7 +239,7 @@ double Ctx::op_bytes(const Op &op) const {
     switch (op.kind) {
     case OP_A_S64: case OP_W_S64: case OP_GT_S64:
         return n * n * 8.0 + 2.0 * n * 8.0;
-    case OP_A_S32: case OP_GT_S32: return n * n * 4.0 + n * 4.0 + n * 8.0;
+    case OP_A_S32: case OP_GT_S32: case OP_W_S32: return n * n * 4.0 + n * 4.0 + n * 8.0;
     default: return 0.0;
     }
 }
@@ -1021,7 +1022,6 @@ int wwbi_solve_gamma(wwbi_ctx *ctx, const wwbi_geom *g, const double *gamma0, co
     SolveStats st{};
     int rc = Ctx::check_opts(o);
     if (!rc && (!gamma0 || !U)) rc = WWBI_EINVAL_NULL;
-    if (!rc && o->precision != WWBI_FP64) rc = WWBI_EINVAL_OPTS;
     if (!rc) {
         c->restart_cap = std::max(c->restart_cap, o->restart);
         c->begin_report((o->flags & WWBI_FLAG_PROFILE) != 0);
@@ -1040,19 +1040,32 @@ int wwbi_solve_gamma(wwbi_ctx *ctx, const wwbi_geom *g, const double *gamma0, co
     launch_rflavour(c->L, c->N, c->hrow, 2, 0, n0, nw, 0, n0, gamma0, c->part, nullptr, c->stream);
     launch_wall_rhs_finalize(nw, um, c->part, rflavour_nsplit(nw, n0, 0), rhs, c->stream);
     hipEventRecord(c->ev[1], c->stream);
+    // the wall operator: GMRES in FP64 (stored or on the fly), or (stored,
+    // FP32_REFINED) FP32 products inside FP64 refinement with on-the-fly FP64
+    // residuals
     const bool stored = o->matvec != WWBI_MATVEC_ON_THE_FLY;
+    const bool refined = stored && o->precision == WWBI_FP32_REFINED;
     if (stored) {
-        rc = c->ensure_matrix((size_t)nw * ldw * 8);
+        rc = c->ensure_matrix((size_t)nw * ldw * (refined ? 4 : 8));
         if (rc) { c->finish_report(rep, rc, st, 0); return rc; }
-        launch_assemble_wall64(c->L, c->N, c->hrow, (double *)c->A, ldw, c->stream);
+        if (refined)
+            launch_assemble_wall32(c->L, c->N, c->hrow, (float *)c->A, ldw, c->stream);
+        else
+            launch_assemble_wall64(c->L, c->N, c->hrow, (double *)c->A, ldw, c->stream);
     }
     hipEventRecord(c->ev[2], c->stream);
     double *gw = gam + n0;
     const bool xz = o->x0 == nullptr;
     if (!xz) launch_copy(gw, o->x0, nw, c->stream);
-    Op op{stored ? OP_W_S64 : OP_W_O64, nw, ldw, o->flags, o->band};
-    const int status =
-        c->gmres(op, rhs, gw, xz, o->tol, o->restart, o->max_iter, o->poll_every, false, true, st);
+    Op op{refined ? OP_W_S32 : (stored ? OP_W_S64 : OP_W_O64), nw, ldw, o->flags, o->band};
+    int status;
+    if (refined) {
+        const Op op64{OP_W_O64, nw, ldw, o->flags, o->band};
+        status = c->refine(op, op64, rhs, gw, xz, *o, st);
+    } else {
+        status = c->gmres(op, rhs, gw, xz, o->tol, o->restart, o->max_iter, o->poll_every, false,
+                          true, st);
+    }
     hipEventRecord(c->ev[3], c->stream);
     if (status < 0) { c->finish_report(rep, status, st, c->op_bytes(op)); return status; }
     launch_copy(gam, gamma0, n0, c->stream);

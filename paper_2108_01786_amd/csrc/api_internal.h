@@ -25,10 +25,13 @@ enum OpKind {
     OP_GT_S64,      // gamma_t operator (Sec. 4.2), stored FP64
     OP_GT_O64,      // on the fly FP64
     OP_GT_S32,      // stored FP32 (FP32 accumulation), inside FP64 refinement
+    OP_W_S32,       // wall operator, stored FP32, inside FP64 refinement
 };
 
 // stored FP32 operators, whose products can read the FP32 copy of a basis vector
-inline bool stored_fp32(int kind) { return kind == OP_A_S32 || kind == OP_GT_S32; }
+inline bool stored_fp32(int kind) {
+    return kind == OP_A_S32 || kind == OP_GT_S32 || kind == OP_W_S32;
+}
 
 struct Op {
     int kind;

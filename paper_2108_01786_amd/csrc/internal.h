@@ -231,6 +231,9 @@ void launch_assemble_gt64(const Layout &L, const Nodes &N, double *B, long ld, h
 void launch_assemble_gt32(const Layout &L, const Nodes &N, float *B, long ld, hipStream_t st);
 void launch_assemble_wall64(const Layout &L, const Nodes &N, const double *hrow, double *W, long ld,
                             hipStream_t st);
+// the same entries, evaluated in FP64 and stored rounded to FP32 (refined solves)
+void launch_assemble_wall32(const Layout &L, const Nodes &N, const double *hrow, float *W, long ld,
+                            hipStream_t st);
 // the normal-velocity map T (surface rows, all columns), FP64
 void launch_assemble_T64(const Layout &L, const Nodes &N, const double *hrow, double *T, long ld,
                          hipStream_t st);

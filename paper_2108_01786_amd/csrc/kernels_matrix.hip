@@ -748,6 +748,14 @@ void launch_assemble_wall64(const Layout &L, const Nodes &N, const double *hrow,
     hipLaunchKernelGGL(k_assemble<1>, grid, dim3(256), 0, st, N, hrow, c0, nw, c0, nw, 1, W, ld);
 }
 
+void launch_assemble_wall32(const Layout &L, const Nodes &N, const double *hrow, float *W, long ld,
+                            hipStream_t st) {
+    const int c0 = L.off[1], nw = L.n - L.off[1];
+    dim3 grid(cdiv(ld, 256), cdiv(nw, kRowsPerAsmBlock));
+    hipLaunchKernelGGL((k_assemble<1, float>), grid, dim3(256), 0, st, N, hrow, c0, nw, c0, nw, 1,
+                       W, ld);
+}
+
 static int near_width(int band) { return band > kNearBand ? band : kNearBand; }
 
 void launch_otf_matvec(const Layout &L, const Nodes &N, int flags, int fp32, int band,
