@@ -188,6 +188,30 @@ def test_solve_gamma(ww, ctx, name):
         assert rel(U.cpu().numpy(), ref_vp["U"].numpy()) <= bar
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_solve_gamma_warm_start(ww, ctx, prec):
+    """x0 = the converged wall strengths: the vortex-sheet solve stops at once
+    with the same U; x0 from a nearby gamma_0 takes fewer steps to the same
+    answer, in FP64 and in refined FP32."""
+    say(f"case solve_gamma warm start {prec}")
+    cfg = _cfg("c1")
+    g = O.OGeom.from_synth(cfg["geom"])
+    gamma0 = -O.spectral(O.split(g, oracle_solution("c1")["omega"])[0], "D").numpy()
+    dg = ww.DeviceGeometry.from_synth(cfg["geom"], DEV)
+    kw = dict(tol=1e-13 if prec == "fp64" else 1e-14,
+              precision=ww.FP64 if prec == "fp64" else ww.FP32_REFINED)
+    g0 = torch.as_tensor(gamma0, device=DEV)
+    U0, gw0, r0 = ctx.solve_gamma(dg, g0, **kw)
+    U1, gw1, r1 = ctx.solve_gamma(dg, g0, x0=gw0.clone(), **kw)
+    assert r1.status == 0 and r1.iters == 0
+    assert rel(U1.cpu().numpy(), U0.cpu().numpy()) <= 1e-13
+    U2, _, r2 = ctx.solve_gamma(dg, g0 * 1.001, x0=gw0.clone(), **kw)
+    U3, _, r3 = ctx.solve_gamma(dg, g0 * 1.001, **kw)
+    say(f"  cold iters {r3.iters} warm iters {r2.iters}")
+    assert r2.status == 0 and r2.iters < r3.iters
+    assert rel(U2.cpu().numpy(), U3.cpu().numpy()) <= 1e-11
+
+
 def test_wall_matrix_entrywise(ww, ctx):
     say("case wall_matrix ragged")
     cfg = _cfg("ragged")
