@@ -18,6 +18,8 @@
  *  - The surface and bottom run left to right with
  *    zeta(alpha + 2 pi) = zeta(alpha) + 2 pi; obstacles are closed curves
  *    traversed clockwise (fluid on the left, Sec. 2).
+ *  - Every node, and every point given for evaluation inside the fluid, has
+ *    |y| <= 30 (WWBI_EINVAL_RANGE otherwise).
  *  - Pointers marked (device) are HIP device pointers; (host) are host
  *    pointers.  The caller owns every input and output buffer.  The context
  *    owns its workspace, which grows to the largest problem seen and is then
