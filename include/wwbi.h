@@ -365,7 +365,10 @@ int wwbi_adjoint_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, con
  * formed on the fly, one system at a time.
  * Errors: WWBI_EINVAL_OPTS for n outside 1..32, an on-the-fly matvec or a
  * warm start; WWBI_EINVAL_NONFINITE for a non-finite right-hand side entry
- * (omega untouched); the geometry is checked as for wwbi_solve_phi. */
+ * (omega untouched); the geometry is checked as for wwbi_solve_phi.
+ * The lockstep path pays off from a few systems on; a single system solves
+ * faster through wwbi_solve_phi (at 10240 unknowns, refined: 3.9 ms against
+ * 5.9 ms here; 32 systems take 8.5 ms here). */
 int wwbi_solve_phi_multi(wwbi_ctx *ctx, const wwbi_geom *g, const double *rhs, int32_t n,
                          const wwbi_opts *o, double *omega, wwbi_report *rep);
 
