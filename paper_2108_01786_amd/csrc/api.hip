@@ -58,6 +58,7 @@ int Ctx::ensure(int n, int restart) {
     G(yv, capy, rr + 1);
     G(P, capP, 3 * 64 * (rr + 1) + 64);
     G(part, cappart, 258 * nn + 64);   // up to 256 far slices + the near-band slice
+    G(pw, cappw, 65 * (size_t)gemv_partials(nn) + 64);   // 64 dot rows + the norms
     Gi(bid, capbid, nn);
     Gi(loc, caploc, nn);
     Gi(Mk, capMk, nn);
@@ -104,6 +105,8 @@ void Ctx::release() {
     F(A);
     F(A64);
     capA64 = 0;
+    F(pw);
+    cappw = 0;
     F(V);
     F(v32);
     for (int i = 0; i < kNumVec; ++i) F(vec[i]);
@@ -302,6 +305,7 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
     const long ldv = round_up(n, 64);
     double *r = vec[VR], *w = vec[VW];
     double *P1 = P, *P2 = P + 64 * ldp, *P3 = P + 2 * 64 * ldp;   // P[i*G + b] layout
+    const int NB = gemv_partials(n);
     float *x32 = fp32_basis ? v32 : nullptr;
     // the inner solves of the refinement (the only callers without the
     // true-residual check) orthogonalise once; every other solve twice
@@ -356,9 +360,21 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
             for (int j = j0; j < j1; ++j) {
                 const double *vj = V + (long)j * ldv;
                 cur_step = j;
+                // single-pass steps on a stored FP32 matrix take the Gram-Schmidt
+                // dots in the product's epilogue (one partial per product block)
+                const bool fuse = single_pass && x32 && stored_fp32(op.kind) && j < 64;
                 prof_begin();
-                apply(op, vj, x32, nullptr, w, &gs->active);
+                if (fuse)
+                    launch_gemv32_dots((const float *)A, op.ld, n, x32, w, &gs->active, V, ldv, j,
+                                       pw, pw + 64L * NB, stream);
+                else
+                    apply(op, vj, x32, nullptr, w, &gs->active);
                 prof_end();
+                if (fuse) {
+                    launch_cgs_final(V, ldv, w, n, j, pw, pw + 64L * NB, G, x32, H, restart + 1,
+                                     false, cs, sn, gv, jmax, gs, cid, dmir, stream, kSingle, NB);
+                    continue;
+                }
                 launch_cgs_dot(V, ldv, w, n, j, P1, P3, G, gs, stream);
                 if (single_pass) {
                     launch_cgs_final(V, ldv, w, n, j, P1, P3, G, x32, H, restart + 1, false, cs,

@@ -99,6 +99,7 @@ struct Ctx {
     double *yv = nullptr;   size_t capy = 0;
     double *P = nullptr;    size_t capP = 0;
     double *part = nullptr; size_t cappart = 0;
+    double *pw = nullptr;   size_t cappw = 0;     // partials of the fused Arnoldi product
     int *bid = nullptr;     size_t capbid = 0;
     int *loc = nullptr;     size_t caploc = 0;
     int *Mk = nullptr;      size_t capMk = 0;

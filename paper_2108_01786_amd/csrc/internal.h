@@ -242,6 +242,14 @@ void launch_gemv64(const double *A, long ld, int n, const double *x, const doubl
                    const int *active, hipStream_t st);
 void launch_gemv32(const float *A, long ld, int n, const float *x, const double *c, double *y,
                    const int *active, hipStream_t st);
+// Number of per-block partials of the fused Arnoldi product below.
+int gemv_partials(int n);
+// y = A x (FP32 matrix and x, FP32 accumulation) fused with the first
+// Gram-Schmidt dots: P[i * gemv_partials(n) + b] (i <= j < 64) and the squared
+// norm partials P3[b] of y, per block b, summed later in a fixed order.
+void launch_gemv32_dots(const float *A, long ld, int n, const float *x, double *y,
+                        const int *active, const double *V, long ldv, int j, double *P,
+                        double *P3, hipStream_t st);
 void launch_gemv32_x64(const float *A, long ld, int n, const double *x, const double *c,
                        double *y, const int *active, hipStream_t st);
 void launch_otf_matvec(const Layout &L, const Nodes &N, int flags, int fp32, int band,
@@ -311,10 +319,12 @@ void launch_cgs_first(const double *V, long ldv, double *w, int n, int j, const 
                       hipStream_t st, const Bat &bt = kSingle);
 // last pass fused with normalisation into V_{j+1} and the Givens step
 // (add: column j of H already holds a first pass)
+// GP: the number of partials in P2 and P3 (0: G, the chunk count)
 void launch_cgs_final(const double *V, long ldv, const double *w, int n, int j,
                       const double *P2, const double *P3, int G, float *v32, double *H, int ldh,
                       bool add, double *cs, double *sn, double *g, int restart_len, GState *gs,
-                      int cyc, GState *mirror, hipStream_t st, const Bat &bt = kSingle);
+                      int cyc, GState *mirror, hipStream_t st, const Bat &bt = kSingle,
+                      int GP = 0);
 void launch_hsolve(const double *H, int ldh, const double *g, double *y, const GState *gs,
                    hipStream_t st, const Bat &bt = kSingle);
 // x += V y (x = V y when overwrite)

@@ -175,15 +175,27 @@ __device__ __forceinline__ double minus_proj(double acc, const double *h, const 
 }
 
 // h_i = sum_b P[i*G + b] for i = 0..j into LDS: one wave per i, lanes over b
-// (G <= 64), four coefficients in flight per wave.
+// (lane l sums b = l, l + 64, ... in order), four coefficients per wave with
+// eight partials each in flight.
 __device__ __forceinline__ void reduce_coeffs(const double *P, int G, int j, double *h) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int i0 = wv; i0 <= j; i0 += 4 * (kT / 64)) {
-        double v[4];
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int b0 = lane; b0 < G; b0 += 64 * 8) {
+            double t[4][8];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int i = i0 + u * (kT / 64);
-            v[u] = (i <= j && lane < G) ? P[(long)i * G + lane] : 0.0;
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + u * (kT / 64);
+#pragma unroll
+                for (int k = 0; k < 8; ++k) {
+                    const int b = b0 + 64 * k;
+                    t[u][k] = (i <= j && b < G) ? P[(long)i * G + b] : 0.0;
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int k = 0; k < 8; ++k) v[u] += t[u][k];
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -263,7 +275,7 @@ __global__ __launch_bounds__(kT) void k_cgs_first(const double *V, long ldv, dou
 // estimate, with the column and the rotations staged in LDS.
 __global__ __launch_bounds__(kT) void k_cgs_final(const double *V_, long ldv, const double *w,
                                                   int n, int j, const double *P2,
-                                                  const double *P3, int G, float *v32,
+                                                  const double *P3, int G, int GP, float *v32,
                                                   double *H, int ldh, int add, double *cs,
                                                   double *sn, double *g, int restart_len,
                                                   GState *gs, int cyc, GState *mirror,
@@ -282,10 +294,17 @@ __global__ __launch_bounds__(kT) void k_cgs_final(const double *V_, long ldv, co
     __shared__ double h[WWBI_MAX_RESTART + 1];
     __shared__ double snrm;
     __shared__ double col[WWBI_MAX_RESTART + 2], lc[WWBI_MAX_RESTART], ls[WWBI_MAX_RESTART];
-    reduce_coeffs(P2, G, j, h);
+    reduce_coeffs(P2, GP, j, h);
     const bool b0 = blockIdx.x == 0;
     if (threadIdx.x < 64) {
-        double v = (int)threadIdx.x < G ? P3[threadIdx.x] : 0.0;
+        double v = 0.0;
+        for (int b0 = threadIdx.x; b0 < GP; b0 += 64 * 8) {
+            double t[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) t[k] = b0 + 64 * k < GP ? P3[b0 + 64 * k] : 0.0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v += t[k];
+        }
         v = wave_sum(v);
         if (threadIdx.x == 0) snrm = v;
     }
@@ -444,9 +463,10 @@ void launch_cgs_first(const double *V, long ldv, double *w, int n, int j, const 
 void launch_cgs_final(const double *V, long ldv, const double *w, int n, int j,
                       const double *P2, const double *P3, int G, float *v32, double *H, int ldh,
                       bool add, double *cs, double *sn, double *g, int restart_len, GState *gs,
-                      int cyc, GState *mirror, hipStream_t st, const Bat &bt) {
+                      int cyc, GState *mirror, hipStream_t st, const Bat &bt, int GP) {
     hipLaunchKernelGGL(k_cgs_final, dim3(G, bt.nsys), dim3(kT), 0, st, V, ldv, w, n, j, P2, P3, G,
-                       v32, H, ldh, add ? 1 : 0, cs, sn, g, restart_len, gs, cyc, mirror, bt);
+                       GP > 0 ? GP : G, v32, H, ldh, add ? 1 : 0, cs, sn, g, restart_len, gs,
+                       cyc, mirror, bt);
 }
 void launch_hsolve(const double *H, int ldh, const double *g, double *y, const GState *gs,
                    hipStream_t st, const Bat &bt) {
