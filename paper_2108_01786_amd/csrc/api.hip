@@ -360,19 +360,30 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
             for (int j = j0; j < j1; ++j) {
                 const double *vj = V + (long)j * ldv;
                 cur_step = j;
-                // single-pass steps on a stored FP32 matrix take the Gram-Schmidt
-                // dots in the product's epilogue (one partial per product block)
-                const bool fuse = single_pass && x32 && stored_fp32(op.kind) && j < 64;
+                // steps on a stored matrix take the first Gram-Schmidt dots in the
+                // product's epilogue (one partial per product block)
+                const bool fuse32 = single_pass && x32 && stored_fp32(op.kind) && j < 64;
+                const bool fuse64 = !single_pass && stored_fp64(op.kind) && j < 64;
                 prof_begin();
-                if (fuse)
+                if (fuse32)
                     launch_gemv32_dots((const float *)A, op.ld, n, x32, w, &gs->active, V, ldv, j,
+                                       pw, pw + 64L * NB, stream);
+                else if (fuse64)
+                    launch_gemv64_dots((const double *)A, op.ld, n, vj, w, &gs->active, V, ldv, j,
                                        pw, pw + 64L * NB, stream);
                 else
                     apply(op, vj, x32, nullptr, w, &gs->active);
                 prof_end();
-                if (fuse) {
+                if (fuse32) {
                     launch_cgs_final(V, ldv, w, n, j, pw, pw + 64L * NB, G, x32, H, restart + 1,
                                      false, cs, sn, gv, jmax, gs, cid, dmir, stream, kSingle, NB);
+                    continue;
+                }
+                if (fuse64) {
+                    launch_cgs_first(V, ldv, w, n, j, pw, P2, P3, G, H, restart + 1, gs, stream,
+                                     kSingle, NB);
+                    launch_cgs_final(V, ldv, w, n, j, P2, P3, G, x32, H, restart + 1, true, cs,
+                                     sn, gv, jmax, gs, cid, dmir, stream);
                     continue;
                 }
                 launch_cgs_dot(V, ldv, w, n, j, P1, P3, G, gs, stream);

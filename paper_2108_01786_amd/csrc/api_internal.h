@@ -28,6 +28,11 @@ enum OpKind {
     OP_W_S32,       // wall operator, stored FP32, inside FP64 refinement
 };
 
+// stored FP64 operators
+inline bool stored_fp64(int kind) {
+    return kind == OP_A_S64 || kind == OP_GT_S64 || kind == OP_W_S64;
+}
+
 // stored FP32 operators, whose products can read the FP32 copy of a basis vector
 inline bool stored_fp32(int kind) {
     return kind == OP_A_S32 || kind == OP_GT_S32 || kind == OP_W_S32;

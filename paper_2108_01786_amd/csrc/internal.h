@@ -250,6 +250,10 @@ int gemv_partials(int n);
 void launch_gemv32_dots(const float *A, long ld, int n, const float *x, double *y,
                         const int *active, const double *V, long ldv, int j, double *P,
                         double *P3, hipStream_t st);
+// the same for an FP64 matrix (FP64 accumulation)
+void launch_gemv64_dots(const double *A, long ld, int n, const double *x, double *y,
+                        const int *active, const double *V, long ldv, int j, double *P,
+                        double *P3, hipStream_t st);
 void launch_gemv32_x64(const float *A, long ld, int n, const double *x, const double *c,
                        double *y, const int *active, hipStream_t st);
 void launch_otf_matvec(const Layout &L, const Nodes &N, int flags, int fp32, int band,
@@ -314,9 +318,10 @@ void launch_cycle_start(const double *r, int n, const double *P, int G, double *
 void launch_cgs_dot(const double *V, long ldv, const double *w, int n, int j, double *P,
                     double *P3, int G, const GState *gs, hipStream_t st, const Bat &bt = kSingle);
 // first Gram-Schmidt pass (w -= V h; dots of V with w into P2, |w|^2 into P3)
+// GP: the number of partials in P1 (0: G, the chunk count)
 void launch_cgs_first(const double *V, long ldv, double *w, int n, int j, const double *P1,
                       double *P2, double *P3, int G, double *H, int ldh, const GState *gs,
-                      hipStream_t st, const Bat &bt = kSingle);
+                      hipStream_t st, const Bat &bt = kSingle, int GP = 0);
 // last pass fused with normalisation into V_{j+1} and the Givens step
 // (add: column j of H already holds a first pass)
 // GP: the number of partials in P2 and P3 (0: G, the chunk count)

@@ -191,6 +191,14 @@ void launch_gemv32_dots(const float *A, long ld, int n, const float *x, double *
                        y, active, GemvDots{V, ldv, j, P, P3});
 }
 
+void launch_gemv64_dots(const double *A, long ld, int n, const double *x, double *y,
+                        const int *active, const double *V, long ldv, int j, double *P,
+                        double *P3, hipStream_t st) {
+    hipLaunchKernelGGL((k_gemv<double, double, double, kGemvR, kGemvU, true, kDotsWaves>),
+                       dim3(gemv_partials(n)), dim3(64 * kDotsWaves), 0, st, A, ld, n, x,
+                       nullptr, y, active, GemvDots{V, ldv, j, P, P3});
+}
+
 void launch_gemv32_x64(const float *A, long ld, int n, const double *x, const double *c,
                        double *y, const int *active, hipStream_t st) {
     hipLaunchKernelGGL((k_gemv<float, double, float, kGemvR, kGemvU>),

@@ -233,7 +233,7 @@ __global__ __launch_bounds__(kT) void k_cgs_dot(const double *V, long ldv, const
 // column j of H.
 __global__ __launch_bounds__(kT) void k_cgs_first(const double *V, long ldv, double *w, int n,
                                                   int j, const double *P1, double *P2,
-                                                  double *P3, int G, double *H, int ldh,
+                                                  double *P3, int G, int GP, double *H, int ldh,
                                                   const GState *gs, Bat bt) {
     gs += sys();
     if (gs->active == 0) return;
@@ -245,7 +245,7 @@ __global__ __launch_bounds__(kT) void k_cgs_first(const double *V, long ldv, dou
     H += sys() * bt.h;
     __shared__ double h[WWBI_MAX_RESTART + 1];
     __shared__ double sh[kT / 64];
-    reduce_coeffs(P1, G, j, h);
+    reduce_coeffs(P1, GP, j, h);
     __syncthreads();
     if (blockIdx.x == 0)
         for (int i = threadIdx.x; i <= j; i += kT) H[(long)j * ldh + i] = h[i];
@@ -456,9 +456,9 @@ void launch_cgs_dot(const double *V, long ldv, const double *w, int n, int j, do
 }
 void launch_cgs_first(const double *V, long ldv, double *w, int n, int j, const double *P1,
                       double *P2, double *P3, int G, double *H, int ldh, const GState *gs,
-                      hipStream_t st, const Bat &bt) {
+                      hipStream_t st, const Bat &bt, int GP) {
     hipLaunchKernelGGL(k_cgs_first, dim3(G, bt.nsys), dim3(kT), 0, st, V, ldv, w, n, j, P1, P2,
-                       P3, G, H, ldh, gs, bt);
+                       P3, G, GP > 0 ? GP : G, H, ldh, gs, bt);
 }
 void launch_cgs_final(const double *V, long ldv, const double *w, int n, int j,
                       const double *P2, const double *P3, int G, float *v32, double *H, int ldh,
