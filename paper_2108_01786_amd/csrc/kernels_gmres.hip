@@ -176,20 +176,24 @@ __device__ __forceinline__ double minus_proj(double acc, const double *h, const 
 
 // h_i = sum_b P[i*G + b] for i = 0..j into LDS: one wave per i, lanes over b
 // (lane l sums b = l, l + 64, ... in order), four coefficients per wave with
-// eight partials each in flight.
-__device__ __forceinline__ void reduce_coeffs(const double *P, int G, int j, double *h) {
+// eight partials each in flight. A non-null Px is summed the same way as one
+// more row, into h[j + 1], alongside the others.
+__device__ __forceinline__ void reduce_coeffs(const double *P, int G, int j, double *h,
+                                              const double *Px = nullptr) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int i0 = wv; i0 <= j; i0 += 4 * (kT / 64)) {
+    const int last = Px ? j + 1 : j;
+    for (int i0 = wv; i0 <= last; i0 += 4 * (kT / 64)) {
         double v[4] = {0.0, 0.0, 0.0, 0.0};
         for (int b0 = lane; b0 < G; b0 += 64 * 8) {
             double t[4][8];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int i = i0 + u * (kT / 64);
+                const double *row = i > j ? (Px ? Px : P) : P + (long)i * G;
 #pragma unroll
                 for (int k = 0; k < 8; ++k) {
                     const int b = b0 + 64 * k;
-                    t[u][k] = (i <= j && b < G) ? P[(long)i * G + b] : 0.0;
+                    t[u][k] = (i <= last && b < G) ? row[b] : 0.0;
                 }
             }
 #pragma unroll
@@ -201,7 +205,7 @@ __device__ __forceinline__ void reduce_coeffs(const double *P, int G, int j, dou
         for (int u = 0; u < 4; ++u) {
             const int i = i0 + u * (kT / 64);
             const double t = wave_sum(v[u]);
-            if (lane == 0 && i <= j) h[i] = t;
+            if (lane == 0 && i <= last) h[i] = t;
         }
     }
 }
@@ -294,20 +298,9 @@ __global__ __launch_bounds__(kT) void k_cgs_final(const double *V_, long ldv, co
     __shared__ double h[WWBI_MAX_RESTART + 1];
     __shared__ double snrm;
     __shared__ double col[WWBI_MAX_RESTART + 2], lc[WWBI_MAX_RESTART], ls[WWBI_MAX_RESTART];
-    reduce_coeffs(P2, GP, j, h);
+    // h[0..j] from P2 and ||w'||^2 from P3 into h[j + 1], in one pass
+    reduce_coeffs(P2, GP, j, h, P3);
     const bool b0 = blockIdx.x == 0;
-    if (threadIdx.x < 64) {
-        double v = 0.0;
-        for (int b0 = threadIdx.x; b0 < GP; b0 += 64 * 8) {
-            double t[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) t[k] = b0 + 64 * k < GP ? P3[b0 + 64 * k] : 0.0;
-#pragma unroll
-            for (int k = 0; k < 8; ++k) v += t[k];
-        }
-        v = wave_sum(v);
-        if (threadIdx.x == 0) snrm = v;
-    }
     if (b0) {
         const double *hc = H + (long)j * ldh;
         for (int i = threadIdx.x; i <= j; i += kT) col[i] = add ? hc[i] : 0.0;
@@ -317,7 +310,7 @@ __global__ __launch_bounds__(kT) void k_cgs_final(const double *V_, long ldv, co
     if (threadIdx.x == 0) {
         double s2 = 0.0;
         for (int i = 0; i <= j; ++i) s2 += h[i] * h[i];
-        const double q = snrm - s2;
+        const double q = h[j + 1] - s2;
         snrm = q > 0.0 ? sqrt(q) : 0.0;
     }
     __syncthreads();
