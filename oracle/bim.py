@@ -19,6 +19,8 @@ with background flow over obstacles and topography" (arXiv 2108.01786):
 * one Runge-Kutta stage: graph and HLS surfaces, V, filter . Sec. 2, 3.5, 5
 * velocity and pressure inside the fluid (Helsing-Ojala) .... Sec. 5.1, appendix
 * spectral derivative and Hilbert transform (FFT symbols) .. Sec. 3.4
+* restarted GMRES on the stored matrix ...................... Sec. 7.4 (solver)
+* tangent-linear model of J = sum w U^2 ..................... Sec. 3.2-3.4 differentiated
 
 Conventions the paper leaves open and that are fixed here: the Nyquist
 coefficient of D, H and |d| is set to zero; the point z_j inside obstacle j
@@ -748,3 +750,158 @@ def J_and_grad(g_walls: OGeom, xt, yt, phi, weights):
     J = (w * U * U).sum()
     gx, gy, gp = torch.autograd.grad(J, (xt, yt, ph))
     return float(J.detach()), gx.detach(), gy.detach(), gp.detach(), U.detach()
+
+
+# ---------------------------------------------------------------------------
+# large systems: row-blocked assembly, restarted GMRES, the U map summed over
+# source chunks, and the tangent-linear model of the solve
+# ---------------------------------------------------------------------------
+
+def assemble_A_blocked(g: OGeom, chunk: int = 1024) -> torch.Tensor:
+    """The matrix of assemble_A built chunk by chunk of rows (A_rows): every
+    entry is the same elementwise expression (equal to assemble_A's up to the
+    last bit of the vectorised tan), and the peak memory of the intermediates
+    is bounded by the chunk."""
+    n = sum(g.M)
+    A = torch.empty(n, n, dtype=F64)
+    for r0 in range(0, n, chunk):
+        A[r0:r0 + chunk] = A_rows(g, range(r0, min(n, r0 + chunk)))
+    return A
+
+
+def gmres(matvec, b: torch.Tensor, tol: float = 1e-13, restart: int = 100,
+          max_iter: int = 2000, x0: Optional[torch.Tensor] = None):
+    """Restarted GMRES for A x = b, unpreconditioned, in the Euclidean norm
+    (the paper's solver for the collocated system, Sec. 7.4; its unstated
+    details follow the readings: start from x0, zero by default; the Arnoldi
+    vectors are orthogonalised by classical Gram-Schmidt applied twice; the
+    small least-squares problem is reduced by Givens rotations).
+
+    Convergence is declared only on the true residual ||b - A x||_2 <=
+    tol ||b||_2, formed at the start of every cycle; inside a cycle the
+    rotated right-hand side only decides when the cycle ends.  Returns
+    (x, relative true residual at every cycle start, Arnoldi steps)."""
+    b = b.to(F64)
+    n = b.shape[0]
+    x = torch.zeros_like(b) if x0 is None else x0.to(F64).clone()
+    bn = float(torch.linalg.vector_norm(b))
+    hist: List[float] = []
+    steps = 0
+    if bn == 0.0:
+        return torch.zeros_like(b), [0.0], 0
+    while True:
+        r = b - matvec(x) if (x0 is not None or steps > 0) else b.clone()
+        beta = float(torch.linalg.vector_norm(r))
+        hist.append(beta / bn)
+        if beta <= tol * bn or steps >= max_iter:
+            break
+        if len(hist) > 1 and beta > 0.99 * hist[-2] * bn:
+            break                       # the last cycle made no progress
+        V = torch.zeros(restart + 1, n, dtype=F64)
+        H = torch.zeros(restart + 1, restart, dtype=F64)
+        cs = torch.zeros(restart, dtype=F64)
+        sn = torch.zeros(restart, dtype=F64)
+        gr = torch.zeros(restart + 1, dtype=F64)
+        V[0] = r / beta
+        gr[0] = beta
+        k = 0
+        for j in range(restart):
+            w = matvec(V[j])
+            for _ in range(2):          # classical Gram-Schmidt, twice
+                h = V[:j + 1] @ w
+                w = w - V[:j + 1].T @ h
+                H[:j + 1, j] += h
+            hn = float(torch.linalg.vector_norm(w))
+            H[j + 1, j] = hn
+            if hn > 0.0:
+                V[j + 1] = w / hn
+            for i in range(j):          # earlier rotations on the new column
+                a_, b_ = float(H[i, j]), float(H[i + 1, j])
+                H[i, j] = cs[i] * a_ + sn[i] * b_
+                H[i + 1, j] = -sn[i] * a_ + cs[i] * b_
+            a_, b_ = float(H[j, j]), float(H[j + 1, j])
+            rho = math.hypot(a_, b_)
+            cs[j], sn[j] = a_ / rho, b_ / rho
+            H[j, j], H[j + 1, j] = rho, 0.0
+            gr[j + 1] = -sn[j] * gr[j]
+            gr[j] = cs[j] * gr[j]
+            k = j + 1
+            steps += 1
+            if abs(float(gr[k])) <= tol * bn or hn == 0.0 or steps >= max_iter:
+                break
+        y = torch.linalg.solve_triangular(H[:k, :k], gr[:k, None], upper=True)[:, 0]
+        x = x + V[:k].T @ y
+    return x, hist, steps
+
+
+def dphi_dn_from_omega_chunked(g: OGeom, omega: List[torch.Tensor],
+                               chunk: int = 2048) -> torch.Tensor:
+    """dphi_dn_from_omega with the transposed blocks G_00^T and K_j0^T applied
+    chunk by chunk of their rows (the sources): the same sums, grouped, so that
+    the M_0 x M map never has to be held at once."""
+    dw = [spectral(w, "D") for w in omega]
+    s0 = torch.abs(g.d[0])
+    acc = u_mv(g, g.z[0], g.d[0]) - 0.5 * spectral(dw[0], "H")
+    for j in range(g.nb):
+        sign = -1.0 if j == 0 else 1.0
+        blk = G_block if j == 0 else K_block
+        for r0 in range(0, g.M[j], chunk):
+            rows = torch.arange(r0, min(g.M[j], r0 + chunk))
+            acc = acc + sign * (blk(g, j, 0, rows).T @ dw[j][rows]) / g.M[j]
+    return acc / s0
+
+
+def A_times_blocked(g: OGeom, x: torch.Tensor, chunk: int = 1024) -> torch.Tensor:
+    """A x with the rows of A formed chunk by chunk and never stored."""
+    n = sum(g.M)
+    return torch.cat([A_rows(g, range(r0, min(n, r0 + chunk))) @ x for r0 in range(0, n, chunk)])
+
+
+def tangent_J(g_walls: OGeom, xt, yt, phi, weights, dirs, solve, omega=None,
+              chunk: int = 1024):
+    """Directional derivatives of J = sum_m w_m U_m^2 along directions
+    (dxt, dyt, dphi) of the surface displacements and the surface potential,
+    walls fixed: the tangent-linear model of the velocity-potential solve
+    (Sec. 3.2-3.4 differentiated).  With A omega = b,
+        d omega = A^{-1} (db - dA omega),   db = (dphi, 0, ..., 0),
+        dU = (dU/dgeometry)[d] + (dU/domega)[d omega],
+        dJ = sum_m 2 w_m U_m dU_m,
+    where dA omega and both parts of dU are forward-mode derivatives of the
+    assembly (row chunks of A times the fixed omega) and of the U map.
+    solve(r) must return A^{-1} r for the matrix at (xt, yt); omega, when
+    given, is the solution at the base state.  Returns (J, U, omega, [dJ_i],
+    [dU_i])."""
+    xt = torch.as_tensor(xt, dtype=F64)
+    yt = torch.as_tensor(yt, dtype=F64)
+    phi = torch.as_tensor(phi, dtype=F64)
+    w = torch.as_tensor(weights, dtype=F64)
+
+    def geom(a, b):
+        z0, d0, e0 = surface_from_periodic(a, b)
+        return g_walls.with_surface(z0, d0, e0)
+
+    g0 = geom(xt, yt)
+    if omega is None:
+        omega = solve(rhs(g0, phi))
+    n = omega.shape[0]
+
+    def u_of(a, b, om):
+        return dphi_dn_from_omega_chunked(geom(a, b), split(g_walls, om))
+
+    U = u_of(xt, yt, omega)
+    J = float((w * U * U).sum())
+    dJ, dUs = [], []
+    for d in dirs:
+        dx, dy, dp = (torch.as_tensor(v, dtype=F64) for v in d)
+        dAw = []
+        for r0 in range(0, n, chunk):
+            rows = range(r0, min(n, r0 + chunk))
+            f = lambda a, b: A_rows(geom(a, b), rows) @ omega
+            dAw.append(torch.func.jvp(f, (xt, yt), (dx, dy))[1])
+        dAw = torch.cat(dAw)
+        db = torch.cat([dp, torch.zeros(n - dp.shape[0], dtype=F64)])
+        dom = solve(db - dAw)
+        dU = torch.func.jvp(u_of, (xt, yt, omega), (dx, dy, dom))[1]
+        dUs.append(dU)
+        dJ.append(float((2.0 * w * U * dU).sum()))
+    return J, U, omega, dJ, dUs

@@ -147,6 +147,23 @@ def _adjoint_draws(M0: int) -> Dict:
     return {"weights": w, "directions": np.stack(dirs), "fd_h": 1e-6}
 
 
+def large_adjoint_draws(M0: int = 16384) -> Dict:
+    """Weights and directions of J = sum w U^2 on the large cell: w_m ~ U[0, 1]
+    from seed 178605, and 4 directions (x~, y, phi), each component
+    sum_{k=1..32} e^{-k/8}(N cos k alpha + N sin k alpha) scaled to max-norm 1,
+    from seed 178615."""
+    w = np.random.default_rng(178605).uniform(0.0, 1.0, M0)
+    rng = np.random.default_rng(178615)
+    dirs = []
+    for _ in range(4):
+        comps = []
+        for _c in range(3):
+            f = _smooth_field(rng, M0, 32, 8.0)
+            comps.append(f / np.abs(f).max())
+        dirs.append(np.stack(comps))
+    return {"weights": w, "directions": np.stack(dirs)}
+
+
 def _config5(rng) -> Dict:
     g = rng.standard_normal(31)
     h = rng.standard_normal(31)
