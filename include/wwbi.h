@@ -53,6 +53,8 @@ extern "C" {
 #define WWBI_EINVAL_OPTS         -7  /* option out of range                            */
 #define WWBI_EINVAL_RANGE        -8  /* a node has |y| > 30: far pairs use e^{-y} in
                                         FP32 intermediate steps, whose range this keeps */
+#define WWBI_ESCRATCH            -9  /* wwbi_solve_phi_noalloc: the problem's workspace
+                                        exceeds the static scratch array               */
 #define WWBI_NOT_CONVERGED        1  /* iteration budget spent before the tolerance    */
 #define WWBI_STAGNATED            2  /* a restart cycle made no progress               */
 #define WWBI_REFINE_STALLED       3  /* iterative refinement stopped contracting       */
@@ -188,6 +190,33 @@ int wwbi_reserve(wwbi_ctx *ctx, int64_t max_unknowns, int32_t max_restart, int32
  */
 int wwbi_solve_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi, const wwbi_opts *o,
                    double *U, double *omega, double *psi_k, wwbi_report *rep);
+
+/* Allocation-free variant of wwbi_solve_phi, for callers that cannot
+ * allocate device memory (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  The same solve, with the same inputs,
+ * outputs, report and status codes, under these limits:
+ *   - the matvec must be WWBI_MATVEC_ON_THE_FLY (precision WWBI_FP64 or
+ *     WWBI_FP32_REFINED); no matrix is stored;
+ *   - the whole per-solve workspace (Krylov basis, partial sums, node data,
+ *     cycle state) lives in one static device array of
+ *     WWBI_NOALLOC_SCRATCH_BYTES per GPU, which the library holds until the
+ *     process ends.  It needs about (restart + 302) * 8 * round_up(n, 64)
+ *     bytes for n = sum(M) unknowns (restart counted as at least 8): n up to
+ *     15552 fits at restart 100 and up to 14528 at restart 128.  A larger
+ *     problem returns WWBI_ESCRATCH before any work, outputs untouched;
+ *   - o->max_iter + o->max_refine <= 4088 (host bookkeeping reserved by
+ *     wwbi_create), else WWBI_EINVAL_OPTS.
+ * The call allocates nothing: no hipMalloc, hipFree or host allocation.  The
+ * context must have been created by wwbi_create beforehand.  Every call on
+ * one GPU shares that GPU's array, which keeps the last call's contents (each
+ * call clears the part it uses first): calls that overlap on one GPU (other
+ * streams, other threads, other contexts) race and must not be issued.  The
+ * context's own workspace is neither used nor changed.  The call returns
+ * after its work on the context's stream has completed. */
+#define WWBI_NOALLOC_SCRATCH_BYTES (48LL * 1024 * 1024)
+int wwbi_solve_phi_noalloc(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi,
+                           const wwbi_opts *o, double *U, double *omega, double *psi_k,
+                           wwbi_report *rep);
 
 /* Vortex-sheet solve (Sec. 4.1).
  *   gamma0 (device) M_0: vortex sheet strength gamma_0 = -omega_0'.

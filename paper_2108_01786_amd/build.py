@@ -19,7 +19,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 
 SOURCES = ["api.hip", "kernels_geom.hip", "kernels_matrix.hip", "kernels_gemv.hip",
            "kernels_reduce.hip", "kernels_gmres.hip", "kernels_adjoint.hip", "kernels_multi.hip",
-           "kernels_evolve.hip", "kernels_interior.hip"]
+           "kernels_evolve.hip", "kernels_interior.hip", "noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -40,39 +40,62 @@ static int grow(T *&p, size_t &cap, size_t want) {
     return WWBI_OK;
 }
 
-int Ctx::ensure(int n, int restart) {
-    trace = std::getenv("WWBI_TRACE") != nullptr;
+// The per-solve workspace of n unknowns and restart length `restart`: every
+// buffer with its element count.  ensure() grows each to that count; the
+// allocation-free entry point carves the same list out of its static array.
+int Ctx::ws_plan(int n, int restart, WsItem *it) {
     const size_t nn = (size_t)round_up(n, 64);
     const size_t rr = (size_t)std::max(restart, 8);
-    int rc = WWBI_OK;
-    auto G = [&](double *&p, size_t &c, size_t w) { if (rc == WWBI_OK) rc = grow(p, c, w); };
-    auto Gi = [&](int *&p, size_t &c, size_t w) { if (rc == WWBI_OK) rc = grow(p, c, w); };
-    auto Gf = [&](float *&p, size_t &c, size_t w) { if (rc == WWBI_OK) rc = grow(p, c, w); };
-    G(V, capV, (rr + 1) * nn);
-    Gf(v32, capv32, nn);
-    for (int i = 0; i < kNumVec; ++i) G(vec[i], capvec[i], nn);
-    G(H, capH, (rr + 1) * (rr + 1));
-    G(cs, capcs, rr + 1);
-    G(sn, capsn, rr + 1);
-    G(gv, capg, rr + 1);
-    G(yv, capy, rr + 1);
-    G(P, capP, 3 * 64 * (rr + 1) + 64);
-    G(part, cappart, 258 * nn + 64);   // up to 256 far slices + the near-band slice
-    G(pw, cappw, 65 * (size_t)gemv_partials(nn) + 64);   // 64 dot rows + the norms
-    Gi(bid, capbid, nn);
-    Gi(loc, caploc, nn);
-    Gi(Mk, capMk, nn);
-    G(wq, capwq, nn);
-    G(s, caps, nn);
-    G(lre, caplre, nn);
-    G(lim, caplim, nn);
-    G(rowD, caprowD, nn);
-    G(rowH, caprowH, nn);
-    G(hrow, caphrow, nn);
-    G(eR, capeR, nn);
-    G(eI, capeI, nn);
-    G(val, capval, 4 * kMaxB + 8);
-    return rc;
+    int k = 0;
+    auto D = [&](double *&p, size_t &c, size_t w) { it[k++] = WsItem{(void **)&p, &c, w, 8}; };
+    auto I = [&](int *&p, size_t &c, size_t w) { it[k++] = WsItem{(void **)&p, &c, w, 4}; };
+    auto Fl = [&](float *&p, size_t &c, size_t w) { it[k++] = WsItem{(void **)&p, &c, w, 4}; };
+    D(V, capV, (rr + 1) * nn);
+    Fl(v32, capv32, nn);
+    for (int i = 0; i < kNumVec; ++i) D(vec[i], capvec[i], nn);
+    D(H, capH, (rr + 1) * (rr + 1));
+    D(cs, capcs, rr + 1);
+    D(sn, capsn, rr + 1);
+    D(gv, capg, rr + 1);
+    D(yv, capy, rr + 1);
+    D(P, capP, 3 * 64 * (rr + 1) + 64);
+    D(part, cappart, 258 * nn + 64);   // up to 256 far slices + the near-band slice
+    D(pw, cappw, 65 * (size_t)gemv_partials(nn) + 64);   // 64 dot rows + the norms
+    I(bid, capbid, nn);
+    I(loc, caploc, nn);
+    I(Mk, capMk, nn);
+    D(wq, capwq, nn);
+    D(s, caps, nn);
+    D(lre, caplre, nn);
+    D(lim, caplim, nn);
+    D(rowD, caprowD, nn);
+    D(rowH, caprowH, nn);
+    D(hrow, caphrow, nn);
+    D(eR, capeR, nn);
+    D(eI, capeI, nn);
+    D(val, capval, 4 * kMaxB + 8);
+    return k;
+}
+
+int Ctx::ensure(int n, int restart) {
+    trace = std::getenv("WWBI_TRACE") != nullptr;
+    WsItem it[kMaxWsItems];
+    const int k = ws_plan(n, restart, it);
+    if (fixed_ws) {
+        // workspace carved for this call: it cannot grow
+        for (int i = 0; i < k; ++i)
+            if (it[i].count > *it[i].cap) return WWBI_ESCRATCH;
+        return WWBI_OK;
+    }
+    for (int i = 0; i < k; ++i) {
+        unsigned char *p = static_cast<unsigned char *>(*it[i].p);
+        size_t cap = *it[i].cap * it[i].esize;
+        const int rc = grow(p, cap, it[i].count * it[i].esize);
+        *it[i].p = p;
+        *it[i].cap = cap / it[i].esize;
+        if (rc) return rc;
+    }
+    return WWBI_OK;
 }
 
 namespace {
@@ -870,6 +893,7 @@ const char *wwbi_status_str(int s) {
     case WWBI_EHIP: return "HIP runtime error";
     case WWBI_EINVAL_OPTS: return "invalid options";
     case WWBI_EINVAL_RANGE: return "invalid argument: a node lies more than 30 above or below y = 0";
+    case WWBI_ESCRATCH: return "workspace exceeds the allocation-free entry point's static scratch";
     case WWBI_NOT_CONVERGED: return "not converged";
     case WWBI_STAGNATED: return "stagnated";
     case WWBI_REFINE_STALLED: return "iterative refinement stalled";
@@ -886,6 +910,10 @@ int wwbi_create(wwbi_ctx **out, int32_t device, void *stream) {
     if (!c) return WWBI_ECAPACITY;
     c->device = device;
     c->stream = (hipStream_t)stream;
+    // the per-cycle bookkeeping never grows inside a solve of up to 4096 cycles
+    c->cyc_done.reserve(4096);
+    // device address of the allocation-free entry point's static scratch array
+    scratch_init(device);
     int rc = WWBI_OK;
     if (hipMalloc((void **)&c->gs, sizeof(GState)) != hipSuccess) rc = WWBI_ECAPACITY;
     if (!rc && hipHostMalloc(&c->hst, kHostStaging) != hipSuccess) rc = WWBI_ECAPACITY;
@@ -942,8 +970,12 @@ int wwbi_reserve(wwbi_ctx *ctx, int64_t max_unknowns, int32_t max_restart, int32
     return rc;
 }
 
-static int solve_phi_impl(Ctx *c, const wwbi_geom *g, const double *phi, const wwbi_opts *o,
-                          double *U, double *omega, double *psi_k, wwbi_report *rep) {
+}  // extern "C"
+
+namespace wwbi {
+
+int solve_phi_impl(Ctx *c, const wwbi_geom *g, const double *phi, const wwbi_opts *o,
+                   double *U, double *omega, double *psi_k, wwbi_report *rep) {
     SolveStats st{};
     int rc = Ctx::check_opts(o);
     if (!rc && (!phi || !U)) rc = WWBI_EINVAL_NULL;
@@ -1035,6 +1067,10 @@ static int solve_phi_impl(Ctx *c, const wwbi_geom *g, const double *phi, const w
     }
     return status;
 }
+
+}  // namespace wwbi
+
+extern "C" {
 
 int wwbi_solve_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi, const wwbi_opts *o,
                    double *U, double *omega, double *psi_k, wwbi_report *rep) {

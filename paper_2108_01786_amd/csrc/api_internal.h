@@ -66,6 +66,16 @@ constexpr int kMaxMulti = 32;            // right-hand sides per multi solve
 
 double inner_tolerance(const wwbi_opts &o, double bnorm, double rnorm);
 
+// One buffer of the per-solve workspace: the context's pointer and capacity
+// (elements) and the element count and size a solve needs.
+struct WsItem {
+    void **p;
+    size_t *cap;
+    size_t count;
+    size_t esize;
+};
+constexpr int kMaxWsItems = 64;
+
 // Batched Krylov workspace of a multi right-hand-side solve.
 struct MultiWS {
     double *V = nullptr; size_t cV = 0;
@@ -152,6 +162,11 @@ struct Ctx {
     bool trace = false;     // WWBI_TRACE set: one stderr line per GMRES cycle
     int nprof = 0;
 
+    // workspace carved from a fixed region for one call (the allocation-free
+    // entry point): ensure() then checks capacities and never allocates
+    bool fixed_ws = false;
+
+    int ws_plan(int n, int restart, WsItem *it);
     int ensure(int n, int restart);
     int ensure_matrix(size_t bytes);
     int ensure_matrix64(size_t bytes);
@@ -185,5 +200,14 @@ struct Ctx {
     void begin_report(bool prof);
     void finish_report(wwbi_report *rep, int status, const SolveStats &st, double bytes);
 };
+
+// The velocity-potential solve behind wwbi_solve_phi (its workspace is the
+// context's, grown on demand unless Ctx::fixed_ws).
+int solve_phi_impl(Ctx *c, const wwbi_geom *g, const double *phi, const wwbi_opts *o,
+                   double *U, double *omega, double *psi_k, wwbi_report *rep);
+
+// Looks up, once per device and with that device current, the device address
+// of the allocation-free entry point's static scratch array.
+void scratch_init(int device);
 
 }  // namespace wwbi

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libwwbi.so")
 
 # status codes and option values (mirror include/wwbi.h)
 OK, EINVAL_NULL, EINVAL_SIZE, EINVAL_NONFINITE, EINVAL_ORIENTATION = 0, -1, -2, -3, -4
-ECAPACITY, EHIP, EINVAL_OPTS, EINVAL_RANGE = -5, -6, -7, -8
+ECAPACITY, EHIP, EINVAL_OPTS, EINVAL_RANGE, ESCRATCH = -5, -6, -7, -8, -9
 NOT_CONVERGED, STAGNATED, REFINE_STALLED, WARN_UNDERRESOLVED = 1, 2, 3, 4
 FP64, FP32_REFINED = 0, 1
 SURF_GRAPH, SURF_HLS = 0, 1
@@ -67,6 +67,9 @@ _SIGS = {
     "wwbi_solve_phi": (C.c_int, [C.c_void_p, C.POINTER(_Geom), C.c_void_p, C.POINTER(_Opts),
                                  C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
                                  C.POINTER(Report)]),
+    "wwbi_solve_phi_noalloc": (C.c_int, [C.c_void_p, C.POINTER(_Geom), C.c_void_p,
+                                         C.POINTER(_Opts), C.c_void_p, C.c_void_p,
+                                         C.POINTER(C.c_double), C.POINTER(Report)]),
     "wwbi_solve_gamma": (C.c_int, [C.c_void_p, C.POINTER(_Geom), C.c_void_p, C.POINTER(_Opts),
                                    C.c_void_p, C.c_void_p, C.POINTER(Report)]),
     "wwbi_tangential_energy": (C.c_int, [C.c_void_p, C.POINTER(_Geom), C.c_void_p, C.c_void_p,
@@ -291,6 +294,30 @@ class Context:
         rc = self.lib.wwbi_solve_phi(self.h, C.byref(g), _ptr(phi), C.byref(o), _ptr(U),
                                      _ptr(omega), psi, C.byref(rep))
         _check(rc, check, "wwbi_solve_phi")
+        psi_k = np.array(psi[: max(0, geom.nb - 2)], dtype=np.float64)
+        return U, omega, psi_k, rep
+
+    def solve_phi_noalloc(self, geom: DeviceGeometry, phi: torch.Tensor, check: bool = True,
+                          U: Optional[torch.Tensor] = None, omega: Optional[torch.Tensor] = None,
+                          **kw):
+        """wwbi_solve_phi_noalloc: the on-the-fly solve with its workspace in the
+        library's static scratch array (no device allocation inside the call).
+        U and omega may be passed in; they are allocated here otherwise."""
+        self._stream()
+        dev = self._dev()
+        phi = _f64(phi, dev)
+        if U is None:
+            U = torch.empty(geom.M[0], dtype=torch.float64, device=dev)
+        if omega is None:
+            omega = torch.empty(geom.n, dtype=torch.float64, device=dev)
+        psi = (C.c_double * max(1, geom.nb - 2))()
+        rep = Report()
+        g = geom.c_struct()
+        kw.setdefault("matvec", MATVEC_ON_THE_FLY)
+        o = make_opts(**kw)
+        rc = self.lib.wwbi_solve_phi_noalloc(self.h, C.byref(g), _ptr(phi), C.byref(o), _ptr(U),
+                                             _ptr(omega), psi, C.byref(rep))
+        _check(rc, check, "wwbi_solve_phi_noalloc")
         psi_k = np.array(psi[: max(0, geom.nb - 2)], dtype=np.float64)
         return U, omega, psi_k, rep
 
