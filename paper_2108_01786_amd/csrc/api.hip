@@ -59,7 +59,7 @@ int Ctx::ws_plan(int n, int restart, WsItem *it) {
     D(gv, capg, rr + 1);
     D(yv, capy, rr + 1);
     D(P, capP, 3 * 64 * (rr + 1) + 64);
-    D(part, cappart, 258 * nn + 64);   // up to 256 far slices + the near-band slice
+    D(part, cappart, 258 * nn + 64);   // up to 256 far slices + the near-band and near-fix slices
     D(pw, cappw, 65 * (size_t)gemv_partials(nn) + 64);   // 64 dot rows + the norms
     I(bid, capbid, nn);
     I(loc, caploc, nn);
@@ -73,6 +73,10 @@ int Ctx::ws_plan(int n, int restart, WsItem *it) {
     D(hrow, caphrow, nn);
     D(eR, capeR, nn);
     D(eI, capeI, nn);
+    D(eRl, capeRl, nn);
+    D(eIl, capeIl, nn);
+    D(cell, capcell, 4 * (nn / kCellNodes) + 4);
+    I(nlist, capnlist, (size_t)kNearStride * (nn / kCellNodes));
     D(val, capval, 4 * kMaxB + 8);
     return k;
 }
@@ -136,7 +140,7 @@ void Ctx::release() {
     F(H); F(cs); F(sn); F(gv); F(yv); F(P); F(part);
     F(bid); F(loc); F(Mk); F(wq); F(s); F(lre); F(lim); F(rowD); F(rowH); F(val); F(apart);
     F(evrow); F(ew); F(ek); F(hop); F(hoi);
-    F(hrow); F(eR); F(eI);
+    F(hrow); F(eR); F(eI); F(eRl); F(eIl); F(cell); F(nlist);
     if (gs) hipFree(gs);
     gs = nullptr;
     if (hst) hipHostFree(hst);
@@ -185,14 +189,17 @@ int Ctx::setup(const wwbi_geom *g, const double *phi, int nphi) {
     if (rc) return rc;
     N.x = g->x; N.y = g->y; N.dx = g->dx; N.dy = g->dy; N.ddx = g->ddx; N.ddy = g->ddy;
     N.bid = bid; N.loc = loc; N.Mk = Mk; N.w = wq; N.s = s; N.lre = lre; N.lim = lim;
-    N.ex = eR; N.ey = eI;
+    N.ex = eR; N.ey = eI; N.exl = eRl; N.eyl = eIl; N.cell = cell; N.nlist = nlist;
     N.n = L.n;
     psi_wall = g->psi_wall;
     launch_prep_nodes(L, g->x, g->y, g->dx, g->dy, g->ddx, g->ddy, bid, loc, Mk, wq, s, lre, lim,
-                      eR, eI, stream);
+                      eR, eI, eRl, eIl, stream);
+    launch_cells(N, cell, stream);
     launch_circulant_rows(L, kOpHalfCot, hrow, stream);
-    launch_validate(L, N, phi, phi ? nphi : 0, val, stream);
-    if (hipMemcpyAsync(hst, val, sizeof(double) * (4 * L.nb + 1), hipMemcpyDeviceToHost,
+    N.near = 0;
+    launch_validate(L, N, phi, phi ? nphi : 0, val, stream);   // also zeroes val[4 nb + 1]
+    launch_near_cells(N, nlist, val + 4 * L.nb + 1, stream);
+    if (hipMemcpyAsync(hst, val, sizeof(double) * (4 * L.nb + 2), hipMemcpyDeviceToHost,
                        stream) != hipSuccess)
         return WWBI_EHIP;
     if (hipStreamSynchronize(stream) != hipSuccess) return WWBI_EHIP;
@@ -202,6 +209,8 @@ int Ctx::setup(const wwbi_geom *g, const double *phi, int nphi) {
     if (h[4 * L.nb] != 0.0) return WWBI_EINVAL_NONFINITE;
     for (int k = 0; k < L.nb; ++k)
         if (h[4 * k + 3] != 0.0) return WWBI_EINVAL_RANGE;
+    N.near = h[4 * L.nb + 1] > 0.0 ? 1 : 0;
+    near_pairs = (long)h[4 * L.nb + 1];
     for (int k = 0; k < L.nb; ++k) {
         if (k <= 1 && !(h[4 * k + 2] > 0.0)) return WWBI_EINVAL_ORIENTATION;
         if (k >= 2 && !(h[4 * k + 1] < 0.0)) return WWBI_EINVAL_ORIENTATION;
@@ -246,7 +255,8 @@ void Ctx::apply(const Op &op, const double *x, const float *x32, const double *c
     case OP_W_O64: {
         const int o1 = L.off[1], nw = L.n - o1;
         launch_rflavour(L, N, hrow, 3, 0, o1, nw, o1, nw, x, part, active, stream);
-        launch_reduce_partials(nw, part, rflavour_nsplit(nw, nw, 0), c, 1.0, y, active, stream);
+        launch_reduce_partials(nw, part, rflavour_nsplit(N, nw, nw, 0), c, 1.0, y, active,
+                               stream);
         break;
     }
     case OP_GT_S64:
@@ -254,7 +264,7 @@ void Ctx::apply(const Op &op, const double *x, const float *x32, const double *c
         break;
     case OP_GT_O64:
         launch_rflavour(L, N, hrow, 8, 0, 0, L.n, 0, L.n, x, part, active, stream);
-        launch_reduce_partials(L.n, part, rflavour_nsplit(L.n, L.n, 0), c, 1.0, y, active,
+        launch_reduce_partials(L.n, part, rflavour_nsplit(N, L.n, L.n, 0), c, 1.0, y, active,
                                stream);
         break;
     }
@@ -550,7 +560,7 @@ void Ctx::eval_U_from_gamma(const double *gamma, double *U) {
     launch_circulant_apply(L, rowH, gamma, hg, 1.0, 0.0, 0, 0, stream);
     launch_umv(N, F, 0, n0, um, stream);
     launch_rflavour(L, N, hrow, 2, 0, 0, n0, 0, L.n, gamma, part, nullptr, stream);
-    launch_U_finalize(n0, s, um, hg, part, rflavour_nsplit(n0, L.n, 0), U, stream);
+    launch_U_finalize(n0, s, um, hg, part, rflavour_nsplit(N, n0, L.n, 0), U, stream);
 }
 
 void Ctx::gamma_from_omega(const double *omega, double *gamma) {
@@ -1101,7 +1111,7 @@ int wwbi_solve_gamma(wwbi_ctx *ctx, const wwbi_geom *g, const double *gamma0, co
     // wall right-hand side: -G_0k^dagger gamma_0 - s dphi_mv/dn on every wall
     launch_umv(c->N, c->F, n0, nw, um, c->stream);
     launch_rflavour(c->L, c->N, c->hrow, 2, 0, n0, nw, 0, n0, gamma0, c->part, nullptr, c->stream);
-    launch_wall_rhs_finalize(nw, um, c->part, rflavour_nsplit(nw, n0, 0), rhs, c->stream);
+    launch_wall_rhs_finalize(nw, um, c->part, rflavour_nsplit(c->N, nw, n0, 0), rhs, c->stream);
     hipEventRecord(c->ev[1], c->stream);
     // the wall operator: GMRES in FP64 (stored or on the fly), or (stored,
     // FP32_REFINED) FP32 products inside FP64 refinement with on-the-fly FP64
@@ -1171,8 +1181,8 @@ int wwbi_tangential_energy(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi,
         if (c->L.nb > 1)
             launch_circulant_apply(c->L, c->rowH, gam, hg, 1.0, 0.0, 1, c->L.nb - 1, sm);
         launch_rflavour(c->L, c->N, c->hrow, 5, 0, 0, n, 0, n, gam, c->part, nullptr, sm);
-        launch_tangential_finalize(n, n0, c->s, tm, gam, hg, c->part, rflavour_nsplit(n, n, 0),
-                                   dphids, sm);
+        launch_tangential_finalize(n, n0, c->s, tm, gam, hg, c->part,
+                                   rflavour_nsplit(c->N, n, n, 0), dphids, sm);
     }
     hipEventRecord(c->ev[3], sm);
     if (energy) {
@@ -1182,8 +1192,8 @@ int wwbi_tangential_energy(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi,
         launch_circulant_apply(c->L, c->rowD, phi, dphi, 1.0, 0.0, 0, 0, sm);
         launch_block_means(c->L, omega, means, sm);
         launch_rflavour(c->L, c->N, c->hrow, 4, 0, 0, n0, 0, n, omega, c->part, nullptr, sm);
-        launch_energy(n0, c->N, c->F, tau, grav, hw, c->part, rflavour_nsplit(n0, n, 0), dphi, tm,
-                      means, e, E, sm);
+        launch_energy(n0, c->N, c->F, tau, grav, hw, c->part, rflavour_nsplit(c->N, n0, n, 0),
+                      dphi, tm, means, e, E, sm);
         if (hipMemcpyAsync(c->hst, E, sizeof(double), hipMemcpyDeviceToHost, sm) != hipSuccess)
             return WWBI_EHIP;
     }
@@ -1243,10 +1253,11 @@ int wwbi_solve_gamma_t(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi, con
     c->gamma_from_omega(om, gam);
     launch_tmv(c->N, c->F, 0, n0, tm, sm);
     launch_rflavour(L, c->N, c->hrow, 5, 0, 0, n0, 0, n, gam, c->part, nullptr, sm);
-    launch_reduce_partials(n0, c->part, rflavour_nsplit(n0, n, 0), nullptr, 1.0, qg, nullptr, sm);
+    launch_reduce_partials(n0, c->part, rflavour_nsplit(c->N, n0, n, 0), nullptr, 1.0, qg,
+                           nullptr, sm);
     launch_gt_vectors(n0, V, u0, gam, c->s, fV, fU, sm);
     launch_circulant_apply(L, c->rowH, fU, hfu, 1.0, 0.0, 0, 0, sm);
-    const int nss = rflavour_nsplit(n0, n0, 0), nsw = rflavour_nsplit(nw, n0, 0);
+    const int nss = rflavour_nsplit(c->N, n0, n0, 0), nsw = rflavour_nsplit(c->N, nw, n0, 0);
     launch_rflavour(L, c->N, c->hrow, 6, 0, 0, n0, 0, n0, fV, c->part, nullptr, sm);
     launch_reduce_partials(n0, c->part, nss, nullptr, 1.0, kfv, nullptr, sm);
     launch_rflavour(L, c->N, c->hrow, 7, 0, 0, n0, 0, n0, fU, c->part, nullptr, sm);
@@ -1493,7 +1504,7 @@ static void boundary_derivs(Ctx *c, const double *omega, double *sds, double *sd
     launch_circulant_apply(L, c->rowH, gam, hg, 1.0, 0.0, 0, L.nb - 1, sm);
     launch_tmv(c->N, c->F, 0, n, tm, sm);
     launch_umv(c->N, c->F, 0, n, um, sm);
-    const int ns = rflavour_nsplit(n, n, 0);
+    const int ns = rflavour_nsplit(c->N, n, n, 0);
     launch_rflavour(L, c->N, c->hrow, 5, 0, 0, n, 0, n, gam, c->part, nullptr, sm);
     launch_tangential_finalize(n, n0, nullptr, tm, gam, hg, c->part, ns, sds, sm);
     launch_rflavour(L, c->N, c->hrow, 2, 0, 0, n, 0, n, gam, c->part, nullptr, sm);
@@ -1650,13 +1661,16 @@ int wwbi_pressure(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi, double t
     launch_circulant_apply(L, c->rowH, x, hw, 1.0, 0.0, 0, L.nb - 1, sm);
     launch_block_means(L, x, means, sm);
     launch_rflavour(L, c->N, c->hrow, 4, 0, 0, n0, 0, n, x, c->part, nullptr, sm);
-    launch_reduce_partials(n0, c->part, rflavour_nsplit(n0, n, 0), nullptr, 1.0, ps, nullptr, sm);
+    launch_reduce_partials(n0, c->part, rflavour_nsplit(c->N, n0, n, 0), nullptr, 1.0, ps,
+                           nullptr, sm);
     if (nw > 0) {
         launch_rflavour(L, c->N, c->hrow, 6, 0, n0, nw, 0, n0, x, c->part, nullptr, sm);
-        launch_reduce_partials(nw, c->part, rflavour_nsplit(nw, n0, 0), nullptr, 1.0, rw, nullptr,
+        launch_reduce_partials(nw, c->part, rflavour_nsplit(c->N, nw, n0, 0), nullptr, 1.0, rw,
+                               nullptr,
                                sm);
         launch_rflavour(L, c->N, c->hrow, 7, 0, n0, nw, n0, nw, x + n0, c->part, nullptr, sm);
-        launch_reduce_partials(nw, c->part, rflavour_nsplit(nw, nw, 0), rw, -1.0, rw, nullptr, sm);
+        launch_reduce_partials(nw, c->part, rflavour_nsplit(c->N, nw, nw, 0), rw, -1.0, rw,
+                               nullptr, sm);
     }
     launch_phi_aux_values(n, n0, b, ps, rw, hw, c->bid, means, fr, fi, sm);
     // 5. phi_t - C and u - i v inside the fluid, then the pressure
@@ -1713,7 +1727,8 @@ int wwbi_adjoint_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, con
     // c = Ubar / s;  gammabar = T^T c - H c / 2 (surface block);  mu = Gamma^T gammabar
     launch_adj_c(n0, dJdU, c->s, cv, sm);
     launch_rflavour(c->L, c->N, c->hrow, 2, 1, 0, n0, 0, n, cv, c->part, nullptr, sm);
-    launch_reduce_partials(n, c->part, rflavour_nsplit(n0, n, 1), nullptr, 1.0, gbar, nullptr, sm);
+    launch_reduce_partials(n, c->part, rflavour_nsplit(c->N, n0, n, 1), nullptr, 1.0, gbar,
+                           nullptr, sm);
     launch_circulant_apply(c->L, c->rowH, cv, gbar, -0.5, 1.0, 0, 0, sm);
     launch_circulant_apply2(c->L, c->rowD, gbar, mu, 1.0, -1.0, 0.0, 0, c->L.nb - 1, sm);
     hipEventRecord(c->ev[1], sm);

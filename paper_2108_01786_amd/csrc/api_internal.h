@@ -127,6 +127,10 @@ struct Ctx {
     double *hrow = nullptr; size_t caphrow = 0;     // (1/2) cot(pi n / M_0)
     double *eR = nullptr;   size_t capeR = 0;       // E = e^{i zeta}
     double *eI = nullptr;   size_t capeI = 0;
+    double *eRl = nullptr;  size_t capeRl = 0;      // trailing parts of E
+    double *eIl = nullptr;  size_t capeIl = 0;
+    double *cell = nullptr; size_t capcell = 0;     // E discs of the 64-node cells
+    int *nlist = nullptr;   size_t capnlist = 0;    // near-pair cell lists
     double *val = nullptr;  size_t capval = 0;
     double *apart = nullptr; size_t capapart = 0;   // adjoint partial sums
     // surface evolution: rows of D, the antiderivative and the filter on the
@@ -162,6 +166,7 @@ struct Ctx {
     bool trace = false;     // WWBI_TRACE set: one stderr line per GMRES cycle
     int nprof = 0;
 
+    long near_pairs = 0;       // near pairs outside the band of the last geometry
     // workspace carved from a fixed region for one call (the allocation-free
     // entry point): ensure() then checks capacities and never allocates
     bool fixed_ws = false;

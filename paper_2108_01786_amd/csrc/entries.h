@@ -19,27 +19,32 @@
 namespace wwbi {
 
 struct Src {               // source node q
-    double ex, ey, dx, dy, w;   // E = e^{i zeta}, zeta', weight 1/M_k
+    double ex, ey, exl, eyl, dx, dy, w;   // E = e^{i zeta} (leading + trailing), zeta', 1/M_k
+    double x, y;                          // zeta (the near pairs' exact differences)
     int k, loc, M, idx;
 };
 struct Tgt {               // target node p
-    double ex, ey, dx, dy, lre, lim;
+    double ex, ey, exl, eyl, dx, dy, lre, lim;
+    double x, y;
     int k, loc, M, idx;
 };
 
-// Same-boundary pairs closer than this many grid steps take kappa from the
-// difference of the positions (see kappa64).
+// Same-boundary pairs within this many grid steps take kappa from the exact
+// difference of the positions (see kappa64); the on-the-fly products leave
+// them (and the diagonal) to their near-band kernels.
 constexpr int kNearBand = 16;
 
 __device__ __forceinline__ Src load_src(const Nodes &N, int q) {
     Src s;
-    s.ex = N.ex[q]; s.ey = N.ey[q]; s.dx = N.dx[q]; s.dy = N.dy[q]; s.w = N.w[q];
+    s.ex = N.ex[q]; s.ey = N.ey[q]; s.exl = N.exl[q]; s.eyl = N.eyl[q];
+    s.dx = N.dx[q]; s.dy = N.dy[q]; s.w = N.w[q]; s.x = N.x[q]; s.y = N.y[q];
     s.k = N.bid[q]; s.loc = N.loc[q]; s.M = N.Mk[q]; s.idx = q;
     return s;
 }
 __device__ __forceinline__ Tgt load_tgt(const Nodes &N, int p) {
     Tgt t;
-    t.ex = N.ex[p]; t.ey = N.ey[p]; t.dx = N.dx[p]; t.dy = N.dy[p];
+    t.ex = N.ex[p]; t.ey = N.ey[p]; t.exl = N.exl[p]; t.eyl = N.eyl[p];
+    t.dx = N.dx[p]; t.dy = N.dy[p]; t.x = N.x[p]; t.y = N.y[p];
     t.lre = N.lre[p]; t.lim = N.lim[p];
     t.k = N.bid[p]; t.loc = N.loc[p]; t.M = N.Mk[p]; t.idx = p;
     return t;
@@ -88,20 +93,31 @@ __device__ __forceinline__ int cyc_dist(int a, int b, int M) {
     return d < M - d ? d : M - d;
 }
 
-// kappa = cot((zeta_q - zeta_p)/2).  Far pairs use E = e^{i zeta} stored per
-// node: cot(w/2) = i (e^{iw} + 1) / (e^{iw} - 1) with e^{i(zeta_q - zeta_p)} =
+// kappa = cot((zeta_q - zeta_p)/2) from E = e^{i zeta} stored per node:
+// cot(w/2) = i (e^{iw} + 1) / (e^{iw} - 1) with e^{i(zeta_q - zeta_p)} =
 // E_q / E_p, i.e. kappa = i (E_q + E_p) / (E_q - E_p) -- one complex quotient
-// and no transcendental function.  The rounding of E is amplified by
-// 1/|zeta_q - zeta_p| in E_q - E_p, so near pairs (same boundary within
-// kNearBand steps, or |E_q - E_p| < |E_p| / 64) use the half-angle formula on
-// the exact difference of the positions instead.
+// and no transcendental function.  E is stored as a double-double, and the
+// difference D = E_q - E_p is formed from both parts: the leading parts
+// subtract exactly for nearby nodes, so D carries a relative error of a few
+// units of rounding however close the pair (a single rounded E would leave
+// an error of about 1e-16 / |zeta_q - zeta_p| relative).  The sum in the
+// numerator needs no such care.
+//
+// Near pairs -- on one boundary within kNearBand grid steps, or closer than
+// |E_q - E_p| < max(|E_p|, |E_q|) / 64 (|zeta_q - zeta_p| below about 1/64,
+// any boundaries) -- take the half-angle formula on the exact difference of the
+// positions instead: its real and imaginary parts are each accurate to their
+// own size, while the quotient's error is a few units of |kappa| in both.
+// Near a nearly flat stretch of boundary the entries Im(zeta' kappa)/2
+// cancel a term 1/|slope| times their size, where that difference shows.
 __device__ __forceinline__ void kappa64(const Nodes &N, const Tgt &t, const Src &s, double &cr,
                                         double &ci) {
-    const double dr = s.ex - t.ex, di = s.ey - t.ey;
+    const double dr = (s.ex - t.ex) + (s.exl - t.exl);
+    const double di = (s.ey - t.ey) + (s.eyl - t.eyl);
     const double den = dr * dr + di * di;
-    const double ee = t.ex * t.ex + t.ey * t.ey;
+    const double ee = max(t.ex * t.ex + t.ey * t.ey, s.ex * s.ex + s.ey * s.ey);
     if ((t.k == s.k && cyc_dist(t.loc, s.loc, t.M) <= kNearBand) || den * 4096.0 < ee) {
-        cot_half64(N.x[s.idx] - N.x[t.idx], N.y[s.idx] - N.y[t.idx], cr, ci);
+        cot_half64(s.x - t.x, s.y - t.y, cr, ci);
         return;
     }
     const double nr = s.ex + t.ex, ni = s.ey + t.ey;
@@ -113,10 +129,11 @@ __device__ __forceinline__ void kappa64(const Nodes &N, const Tgt &t, const Src 
     ci = pr;
 }
 
-// kappa for a pair known to be outside the near band (no near-field branch,
-// so the loops of the on-the-fly products carry no transcendental code).
+// The quotient alone, for pairs outside the band (the loops of the on-the-fly
+// products).
 __device__ __forceinline__ void kappa64_far(const Tgt &t, const Src &s, double &cr, double &ci) {
-    const double dr = s.ex - t.ex, di = s.ey - t.ey;
+    const double dr = (s.ex - t.ex) + (s.exl - t.exl);
+    const double di = (s.ey - t.ey) + (s.eyl - t.eyl);
     const double nr = s.ex + t.ex, ni = s.ey + t.ey;
     const double inv = recip64(dr * dr + di * di);
     const double pr = (nr * dr + ni * di) * inv;

@@ -14,7 +14,7 @@ constexpr int kMaxB = WWBI_MAX_BOUNDARIES;
 // the FP32 assembly forms |E_q - E_p|^2 and the FP64 far tiles seed their
 // reciprocal of it in FP32, so e^{+-2|y|} and the products of two such
 // quantities must stay inside the FP32 normal range.  |y| <= 30 keeps them
-// within [1e-30, 1e30] after the near-pair cut (|E_q - E_p| >= |E_p| / 64).
+// within it for every pair at least 1e-6 apart.
 constexpr double kMaxAbsY = 30.0;
 
 // Boundary layout: node p of boundary k has global index off[k] + m.
@@ -36,7 +36,8 @@ struct Flow {
 // is derived once per call by k_prep_nodes.
 struct Nodes {
     const double *x, *y, *dx, *dy, *ddx, *ddy;
-    const double *ex, *ey;   // E = e^{i zeta} = e^{-y} (cos x, sin x)
+    const double *ex, *ey;   // E = e^{i zeta} = e^{-y} (cos x, sin x), leading part
+    const double *exl, *eyl; // trailing part: E = (ex + exl) + i (ey + eyl) to ~1e-30
     const int *bid;        // boundary index of each node
     const int *loc;        // index m within its boundary
     const int *Mk;         // node count M_k of its boundary
@@ -44,8 +45,19 @@ struct Nodes {
     const double *s;       // |zeta'|
     const double *lre;     // Re{zeta''/(2 zeta')}
     const double *lim;     // Im{zeta''/(2 zeta')}
+    // per cell of kCellNodes consecutive nodes: centre (2), radius of a disc
+    // holding their E values, and the largest |E| (k_cells)
+    const double *cell;
+    const int *nlist;      // per cell: its near-pair list (kNearStride ints)
     int n;
+    int near;              // the geometry has near pairs outside the band (set-up)
 };
+
+constexpr int kCellNodes = 64;
+// Near-pair list of a cell (k_near_cells): its count (-1 when more than
+// kNearList cells hold near pairs with it), then the cells in increasing order.
+constexpr int kNearList = 31;
+constexpr int kNearStride = kNearList + 1;
 
 // sum_{k < ns} part[k * stride + i], added in increasing k; eight loads are
 // issued before their additions (the slices are streamed from HBM/L2).
@@ -99,7 +111,9 @@ struct Ctx;   // host context (api.hip)
 void launch_prep_nodes(const Layout &L, const double *x, const double *y, const double *dx,
                        const double *dy, const double *ddx, const double *ddy, int *bid,
                        int *loc, int *Mk, double *w, double *s, double *lre, double *lim,
-                       double *ex, double *ey, hipStream_t st);
+                       double *ex, double *ey, double *exl, double *eyl, hipStream_t st);
+void launch_cells(const Nodes &N, double *cell, hipStream_t st);
+void launch_near_cells(const Nodes &N, int *lists, double *count, hipStream_t st);
 void launch_validate(const Layout &L, const Nodes &N, const double *phi, int nphi,
                      double *out /* 3*nb+1 */, hipStream_t st);
 void launch_rhs_phi(const Layout &L, const Nodes &N, const Flow &F, const double *phi,
@@ -269,7 +283,7 @@ void launch_rflavour(const Layout &L, const Nodes &N, const double *hrow, int mo
 // partial slices (far chunks + the near band) of a product over nr rows and
 // nc columns, forward or transposed; at most 257, each of length nr
 // (forward) or nc (transposed)
-int rflavour_nsplit(int nr, int nc, int transpose);
+int rflavour_nsplit(const Nodes &N, int nr, int nc, int transpose);
 void launch_reduce_partials(int n, const double *part, int nsplit, const double *c, double scale,
                             double *y, const int *active, hipStream_t st);
 int otf_chunk(int n);

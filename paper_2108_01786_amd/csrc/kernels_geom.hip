@@ -1,5 +1,6 @@
 // Node preparation, validation, right-hand side, multi-valued terms, spectral
 // circulants and the final assembly of the normal velocity.
+#include "ddmath.h"
 #include "entries.h"
 #include "internal.h"
 
@@ -20,7 +21,7 @@ __device__ __forceinline__ int find_block(const Layout &L, int p) {
 __global__ void k_prep_nodes(Layout L, const double *x, const double *y, const double *dx,
                              const double *dy, const double *ddx, const double *ddy, int *bid,
                              int *loc, int *Mk, double *w, double *s, double *lre, double *lim,
-                             double *eR, double *eI) {
+                             double *eR, double *eI, double *eRl, double *eIl) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= L.n) return;
     const int k = find_block(L, p);
@@ -35,12 +36,14 @@ __global__ void k_prep_nodes(Layout L, const double *x, const double *y, const d
     // zeta''/(2 zeta') = (ex + i ey)(a - i b) / (2 |zeta'|^2)
     lre[p] = (ex * a + ey * b) / (2.0 * d2);
     lim[p] = (ey * a - ex * b) / (2.0 * d2);
-    // E = e^{i zeta} = e^{-y} (cos x + i sin x)
-    double sx, cx;
-    sincos(x[p], &sx, &cx);
-    const double mag = exp(-y[p]);
-    eR[p] = mag * cx;
-    eI[p] = mag * sx;
+    // E = e^{i zeta} = e^{-y} (cos x + i sin x) as a double-double, so that
+    // differences of E between nodes keep their relative accuracy
+    DD er, ei;
+    dd_expi(x[p], y[p], er, ei);
+    eR[p] = er.hi;
+    eI[p] = ei.hi;
+    eRl[p] = er.lo;
+    eIl[p] = ei.lo;
 }
 
 __device__ __forceinline__ double block_sum(double v, double *sh) {
@@ -65,7 +68,10 @@ __global__ void k_validate(Layout L, Nodes N, const double *phi, int nphi, doubl
         for (int i = threadIdx.x; i < nphi; i += blockDim.x)
             bad += isfinite(phi[i]) ? 0.0 : 1.0;
         bad = block_sum(bad, sh);
-        if (threadIdx.x == 0) out[4 * L.nb] = bad;
+        if (threadIdx.x == 0) {
+            out[4 * L.nb] = bad;
+            out[4 * L.nb + 1] = 0.0;      // the near-pair count, added next
+        }
         return;
     }
     const int p0 = L.off[k], p1 = L.off[k + 1];
@@ -475,9 +481,9 @@ __global__ void k_add_scalar(int n, double *v, double c) {
 void launch_prep_nodes(const Layout &L, const double *x, const double *y, const double *dx,
                        const double *dy, const double *ddx, const double *ddy, int *bid,
                        int *loc, int *Mk, double *w, double *s, double *lre, double *lim,
-                       double *ex, double *ey, hipStream_t st) {
+                       double *ex, double *ey, double *exl, double *eyl, hipStream_t st) {
     hipLaunchKernelGGL(k_prep_nodes, dim3(cdiv(L.n, 256)), dim3(256), 0, st, L, x, y, dx, dy, ddx,
-                       ddy, bid, loc, Mk, w, s, lre, lim, ex, ey);
+                       ddy, bid, loc, Mk, w, s, lre, lim, ex, ey, exl, eyl);
 }
 
 void launch_validate(const Layout &L, const Nodes &N, const double *phi, int nphi, double *out,

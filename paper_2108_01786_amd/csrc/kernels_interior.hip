@@ -8,6 +8,7 @@
 // A point that coincides with a node takes that node's value.
 //
 // Also the boundary velocity u - i v = (dphi/ds - i dphi/dn) |zeta'| / zeta'.
+#include "ddmath.h"
 #include "entries.h"
 #include "internal.h"
 
@@ -20,7 +21,7 @@ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 constexpr int kHoStage = 256;
 
 struct HoNode {
-    double ex, ey, x, y, dx, dy, w, fr, fi;
+    double ex, ey, exl, eyl, x, y, dx, dy, w, fr, fi;
     int neg;   // free-surface node (sigma = -1)
 };
 
@@ -38,10 +39,11 @@ __global__ __launch_bounds__(256) void k_ho_partial(Nodes N, int n, int n0, int 
     const int p = blockIdx.x * 256 + threadIdx.x;
     const bool live = p < P;
     const double x = live ? zx[p] : 0.0, y = live ? zy[p] : 0.0;
-    double s, c;
-    sincos(x, &s, &c);
-    const double mag = exp(-y);
-    const double er = mag * c, ei = mag * s;           // E_z = e^{i z}
+    // E_z = e^{i z} as a double-double, like the nodes' E: the difference
+    // E_zeta - E_z then keeps its relative accuracy for nearby points
+    DD ezr, ezi;
+    dd_expi(x, y, ezr, ezi);
+    const double er = ezr.hi, ei = ezi.hi, erl = ezr.lo, eil = ezi.lo;
     const double ee = er * er + ei * ei;
     double nr = 0.0, ni = 0.0, dr = 0.0, di = 0.0;
     int h = -1;
@@ -50,7 +52,8 @@ __global__ __launch_bounds__(256) void k_ho_partial(Nodes N, int n, int n0, int 
         const int q = qq + threadIdx.x;
         if (q < qe) {
             HoNode v;
-            v.ex = N.ex[q]; v.ey = N.ey[q]; v.x = N.x[q]; v.y = N.y[q];
+            v.ex = N.ex[q]; v.ey = N.ey[q]; v.exl = N.exl[q]; v.eyl = N.eyl[q];
+            v.x = N.x[q]; v.y = N.y[q];
             v.dx = N.dx[q]; v.dy = N.dy[q]; v.w = N.w[q]; v.fr = fr[q]; v.fi = fi[q];
             v.neg = q < n0 ? 1 : 0;
             sn[threadIdx.x] = v;
@@ -60,7 +63,8 @@ __global__ __launch_bounds__(256) void k_ho_partial(Nodes N, int n, int n0, int 
         if (live) {
             for (int i = 0; i < m; ++i) {
                 const HoNode &v = sn[i];
-                const double ddr = v.ex - er, ddi = v.ey - ei;
+                const double ddr = (v.ex - er) + (v.exl - erl);
+                const double ddi = (v.ey - ei) + (v.eyl - eil);
                 const double den = ddr * ddr + ddi * ddi;
                 double kr, ki;
                 if (den == 0.0) {       // the point is this node (or a period image)
@@ -68,7 +72,12 @@ __global__ __launch_bounds__(256) void k_ho_partial(Nodes N, int n, int n0, int 
                     continue;
                 }
                 if (den * 4096.0 < ee) {
-                    cot_half64(v.x - x, v.y - y, kr, ki);
+                    const double u = v.x - x, w = v.y - y;
+                    if (u == 0.0 && w == 0.0) {   // the node itself
+                        if (h < 0) h = qq + i;
+                        continue;
+                    }
+                    cot_half64(u, w, kr, ki);
                 } else {
                     // cot((zeta - z)/2) = i (E_zeta + E_z) / (E_zeta - E_z)
                     const double sr = v.ex + er, si = v.ey + ei;

@@ -324,7 +324,7 @@ constexpr int kStage = 256;          // chunk granularity of otf_chunk (adjoint 
 // blocks below the wave limit.
 constexpr int kOtfStage = 128;
 constexpr int kOtfBlocks = 8192;     // target grid size of an on-the-fly product
-constexpr int kOtfMaxSlices = 256;   // at most this many partial slices (+ the near band)
+constexpr int kOtfMaxSlices = 256;   // at most this many far slices (+ near band and near fix)
 
 // Far part of an entry (zero inside the near band of width nb).
 template <int MODE>
@@ -412,6 +412,249 @@ __global__ __launch_bounds__(256) void k_near_band(Nodes N, const double *hrow, 
     if (i < nout && g == 0) out[i] = acc;
 }
 
+// Smallest distance between two discs of E values (centre, radius) against
+// the cut |E| / f of the larger |E| (a relative margin covers the rounding of
+// the discs): false when no pair of the two cells is closer than the cut.
+__device__ __forceinline__ bool discs_within(const double *a, const double *b, double f) {
+    const double gx = a[0] - b[0], gy = a[1] - b[1];
+    return (sqrt(gx * gx + gy * gy) - a[2] - b[2]) * f < 1.001 * max(a[3], b[3]);
+}
+__device__ __forceinline__ bool discs_may_be_near(const double *a, const double *b) {
+    return discs_within(a, b, 64.0);
+}
+
+// True when every pair of target nodes [pa, pb] and source nodes [qa, qb] is
+// at least |E_p| / 4 apart in E (tested on the 64-node cells' discs).  The far
+// tiles of A then form E_q - E_p from the leading parts of E alone: its
+// relative error stays below about 8 units of rounding, against 2 with the
+// trailing parts, which nearer pairs need.
+__device__ __forceinline__ bool cells_far(const Nodes &N, int pa, int pb, int qa, int qb) {
+    for (int a = pa / kCellNodes; a <= pb / kCellNodes; ++a)
+        for (int b = qa / kCellNodes; b <= qb / kCellNodes; ++b)
+            if (discs_within(N.cell + 4 * a, N.cell + 4 * b, 4.0)) return false;
+    return true;
+}
+
+// Near pairs outside the band.  The far loops of the on-the-fly products
+// take kappa from the E quotient for every pair outside the same-boundary
+// band; a pair closer than |E_q - E_p| < max(|E_p|, |E_q|) / 64 (kappa64's
+// near test: two boundaries that come close, or one boundary folding back
+// towards itself) needs the half-angle formula instead.  E is periodic, so
+// distances between E values cover every period image.
+//
+// Once per geometry, k_near_cells lists for every 64-node cell a the cells b
+// holding a node q that forms a near pair outside the band with a node of a
+// (at most kNearList of them, in increasing order; more, and the list is
+// marked full).  The relation is symmetric.  Each product then adds, as one
+// more partial slice, (full entry - far entry) x for exactly those pairs
+// (k_near_fix), visiting only the listed cells.
+constexpr int kMaxScanCells = 1024;        // cells tested per pass of the full scan
+
+// The pair test shared by the list build and the fix: outside the band of
+// `nb` steps (by index: me's boundary starts at mbase, has mM nodes, me is
+// node mloc of it) and inside the near cut.
+__device__ __forceinline__ bool near_pair(int q, int mbase, int mloc, int mM, int nb, double ex,
+                                          double ey, double exl, double eyl, double qx, double qy,
+                                          double qxl, double qyl) {
+    const int l = q - mbase;
+    if (l >= 0 && l < mM && cyc_dist(l, mloc, mM) <= nb) return false;
+    const double dr = (qx - ex) + (qxl - exl);
+    const double di = (qy - ey) + (qyl - eyl);
+    return (dr * dr + di * di) * 4096.0 < max(ex * ex + ey * ey, qx * qx + qy * qy);
+}
+
+// Ordered list, in LDS, of the cells of [c0, c0 + cn) whose discs come within
+// the near cut of disc `d` (cn <= kMaxScanCells); returns its length.  Every
+// thread of the block calls it.
+__device__ int list_disc_cells(const Nodes &N, const double *d, int c0, int cn, int *list,
+                               int *wcnt) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    int nl = 0;
+    for (int j0 = 0; j0 < cn; j0 += 256) {
+        const int j = j0 + (int)threadIdx.x;
+        const bool f = j < cn && discs_may_be_near(N.cell + 4 * (long)(c0 + j), d);
+        const unsigned long long bal = __ballot(f);
+        if (lane == 0) wcnt[wv] = __popcll(bal);
+        __syncthreads();
+        int before = nl;
+        for (int w = 0; w < wv; ++w) before += wcnt[w];
+        if (f) list[before + __popcll(bal & ((1ull << lane) - 1ull))] = c0 + j;
+        nl += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+        __syncthreads();
+    }
+    return nl;
+}
+
+// Stage the E values of cell b's nodes in LDS (threads 0..63; clamped to the
+// last node).  Every thread of the block calls it.
+__device__ __forceinline__ void stage_cell(const Nodes &N, int b, double (*se)[kCellNodes]) {
+    __syncthreads();
+    if (threadIdx.x < kCellNodes) {
+        const int q = min(b * kCellNodes + (int)threadIdx.x, N.n - 1);
+        se[0][threadIdx.x] = N.ex[q];
+        se[1][threadIdx.x] = N.ey[q];
+        se[2][threadIdx.x] = N.exl[q];
+        se[3][threadIdx.x] = N.eyl[q];
+    }
+    __syncthreads();
+}
+
+// One block per cell a: its list, and the number of near pairs (p in a, any
+// q) added into *count.
+__global__ __launch_bounds__(256) void k_near_cells(Nodes N, int nb, int *lists, double *count) {
+    __shared__ int list[kMaxScanCells];
+    __shared__ int wcnt[4];
+    __shared__ int hit;
+    __shared__ double se[4][kCellNodes];
+    __shared__ double red[4];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int a = blockIdx.x;
+    const int p = a * kCellNodes + lane;
+    const bool live = p < N.n;
+    const int me = live ? p : a * kCellNodes;
+    const double ex = N.ex[me], ey = N.ey[me], exl = N.exl[me], eyl = N.eyl[me];
+    const int mloc = N.loc[me], mM = N.Mk[me], mbase = me - mloc;
+    const double *da = N.cell + 4 * a;
+    const int ncell = (N.n + kCellNodes - 1) / kCellNodes;
+    int nfound = 0;
+    bool full = false;
+    double pairs = 0.0;
+    for (int c0 = 0; c0 < ncell; c0 += kMaxScanCells) {
+        __syncthreads();
+        const int nl = list_disc_cells(N, da, c0, min(kMaxScanCells, ncell - c0), list, wcnt);
+        for (int li = 0; li < nl; ++li) {
+            const int b = list[li];
+            if (threadIdx.x == 0) hit = 0;
+            stage_cell(N, b, se);
+            int mine = 0;
+            if (live) {
+                for (int jj = 16 * wv; jj < 16 * wv + 16; ++jj) {
+                    const int q = b * kCellNodes + jj;
+                    if (q >= N.n) break;
+                    mine += near_pair(q, mbase, mloc, mM, nb, ex, ey, exl, eyl, se[0][jj],
+                                      se[1][jj], se[2][jj], se[3][jj]) ? 1 : 0;
+                }
+            }
+            if (mine) atomicOr(&hit, 1);
+            pairs += (double)mine;
+            __syncthreads();
+            const bool h = hit != 0;
+            __syncthreads();                // every thread has read hit before it is reset
+            if (h) {
+                if (nfound < kNearList) {
+                    if (threadIdx.x == 0) lists[(long)a * kNearStride + 1 + nfound] = b;
+                    ++nfound;
+                } else {
+                    full = true;
+                }
+            }
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) pairs += __shfl_xor(pairs, o, 64);
+    if (lane == 0) red[wv] = pairs;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        lists[(long)a * kNearStride] = full ? -1 : nfound;
+        const double tot = ((red[0] + red[1]) + red[2]) + red[3];
+        if (tot > 0.0) atomicAdd(count, tot);       // integer counts: exact in any order
+    }
+}
+
+// Everything the entries need of one node, staged in LDS by the fix kernel.
+struct NodeRec {
+    double ex, ey, exl, eyl, dx, dy, w, lre, lim, x, y;
+    int k, loc, M;
+};
+__device__ __forceinline__ NodeRec load_rec(const Nodes &N, int q) {
+    return NodeRec{N.ex[q], N.ey[q], N.exl[q], N.eyl[q], N.dx[q], N.dy[q], N.w[q], N.lre[q],
+                   N.lim[q], N.x[q], N.y[q], N.bid[q], N.loc[q], N.Mk[q]};
+}
+__device__ __forceinline__ Src rec_src(const NodeRec &r, int q) {
+    Src s;
+    s.ex = r.ex; s.ey = r.ey; s.exl = r.exl; s.eyl = r.eyl; s.dx = r.dx; s.dy = r.dy;
+    s.w = r.w; s.x = r.x; s.y = r.y; s.k = r.k; s.loc = r.loc; s.M = r.M; s.idx = q;
+    return s;
+}
+__device__ __forceinline__ Tgt rec_tgt(const NodeRec &r, int p) {
+    Tgt t;
+    t.ex = r.ex; t.ey = r.ey; t.exl = r.exl; t.eyl = r.eyl; t.dx = r.dx; t.dy = r.dy;
+    t.lre = r.lre; t.lim = r.lim; t.x = r.x; t.y = r.y; t.k = r.k; t.loc = r.loc; t.M = r.M;
+    t.idx = p;
+    return t;
+}
+
+// The fix slice: one block per 64-node cell a overlapping the outputs, one
+// output (node 64 a + lane) per lane; wave w takes nodes 16 w .. 16 w + 15 of
+// every visited cell for every output, and the waves' sums are added in a
+// fixed order.  A full list falls back to scanning every cell whose disc
+// comes within the cut.
+template <int MODE, bool COLS>
+__global__ __launch_bounds__(256) void k_near_fix(Nodes N, const int *lists, const double *hrow,
+                                                  int r0, int nr, int c0, int nc, int corr,
+                                                  int band, int nb,
+                                                  const double *__restrict__ x,
+                                                  double *__restrict__ out, const int *active) {
+    if (active && *active == 0) return;
+    __shared__ int list[kMaxScanCells];
+    __shared__ int wcnt[4];
+    __shared__ NodeRec rec[kCellNodes];
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int obase = COLS ? c0 : r0, nout = COLS ? nc : nr;
+    const int sbase = COLS ? r0 : c0, nsum = COLS ? nr : nc;
+    const int a = obase / kCellNodes + blockIdx.x;
+    const int p = a * kCellNodes + lane;
+    const bool live = p >= obase && p < obase + nout;
+    const int me = live ? p : max(obase, a * kCellNodes);
+    const NodeRec mr = load_rec(N, me);
+    const Tgt mt = rec_tgt(mr, me);
+    const Src ms = rec_src(mr, me);
+    const int mbase = me - mr.loc;
+    const int *la = lists + (long)a * kNearStride;
+    const int cnt = la[0];
+    double acc = 0.0;
+    const int cfirst = sbase / kCellNodes, clast = (sbase + nsum - 1) / kCellNodes;
+    for (int cs = cnt < 0 ? cfirst : 0; cs <= (cnt < 0 ? clast : 0); cs += kMaxScanCells) {
+        int nl;
+        const int *cells;
+        if (cnt < 0) {
+            __syncthreads();
+            nl = list_disc_cells(N, N.cell + 4 * a, cs, min(kMaxScanCells, clast - cs + 1), list,
+                                 wcnt);
+            cells = list;
+        } else {
+            nl = cnt;
+            cells = la + 1;
+        }
+        for (int li = 0; li < nl; ++li) {
+            const int b = cells[li];
+            if (b < cfirst || b > clast) continue;        // block-uniform
+            __syncthreads();
+            if (threadIdx.x < kCellNodes)
+                rec[threadIdx.x] = load_rec(N, min(b * kCellNodes + (int)threadIdx.x, N.n - 1));
+            __syncthreads();
+            if (!live) continue;
+            for (int jj = 16 * wv; jj < 16 * wv + 16; ++jj) {
+                const int q = b * kCellNodes + jj;
+                if (q < sbase || q >= sbase + nsum) continue;
+                const NodeRec &r = rec[jj];
+                if (!near_pair(q, mbase, mr.loc, mr.M, nb, mr.ex, mr.ey, mr.exl, mr.eyl, r.ex,
+                               r.ey, r.exl, r.eyl))
+                    continue;
+                const Tgt t = COLS ? rec_tgt(r, q) : mt;
+                const Src s = COLS ? ms : rec_src(r, q);
+                const double e = entry_full<MODE>(N, t, s, corr != 0, band, hrow) -
+                                 entry<MODE>(N, t, s, corr != 0, -1, hrow);
+                acc += e * x[q - sbase];
+            }
+        }
+    }
+    red[wv][lane] = acc;
+    __syncthreads();
+    if (wv == 0 && live)
+        out[p - obase] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+}
+
 // Forward product: each thread owns kTPT target rows (rows t, t + 256, ... of
 // the block's 256 * kTPT).  One row per thread and many short blocks measured
 // fastest: the FP64 entry is a long dependent chain, and more resident blocks
@@ -450,17 +693,18 @@ __device__ __forceinline__ void rows_tile(const Nodes &N, const Tgt (&t)[kTPT], 
 //   Im part (rows and columns of one kind): (a PR - b PI) / |D|^2,
 // less w x_q for the rank-one correction of a pair on one obstacle.
 struct SrcA {
-    double ex, ey, a, b;
+    double ex, ey, exl, eyl, a, b;
 };
 
-template <int KIND, bool ECORR>
+template <int KIND, bool ECORR, bool LO>
 __device__ __forceinline__ void rows_tile_a64(const Tgt (&t)[kTPT], const SrcA *sa,
                                               const double *swx, int m, double (&acc)[kTPT]) {
     for (int i = 0; i < m; ++i) {
         const SrcA q = sa[i];
 #pragma unroll
         for (int u = 0; u < kTPT; ++u) {
-            const double dr = q.ex - t[u].ex, di = q.ey - t[u].ey;
+            const double dr = LO ? (q.ex - t[u].ex) + (q.exl - t[u].exl) : q.ex - t[u].ex;
+            const double di = LO ? (q.ey - t[u].ey) + (q.eyl - t[u].eyl) : q.ey - t[u].ey;
             const double nr = q.ex + t[u].ex, ni = q.ey + t[u].ey;
             const double inv = recip64_from32(dr * dr + di * di);
             const double pr = nr * dr + ni * di;
@@ -511,7 +755,7 @@ __global__ __launch_bounds__(256) void k_otf_rows(Nodes N, const double *hrow, i
             sx[threadIdx.x] = xv;
             if (FAST) {
                 const double hw = 0.5 * sv.w * xv;
-                sa[threadIdx.x] = SrcA{sv.ex, sv.ey, hw * sv.dx, hw * sv.dy};
+                sa[threadIdx.x] = SrcA{sv.ex, sv.ey, sv.exl, sv.eyl, hw * sv.dx, hw * sv.dy};
                 swx[threadIdx.x] = sv.w * xv;
             }
         }
@@ -531,13 +775,28 @@ __global__ __launch_bounds__(256) void k_otf_rows(Nodes N, const double *hrow, i
         const int kq = FAST ? range_boundary(N, c0 + cc, c0 + cc + m - 1) : -1;
         if (FAST && apart && kp >= 0 && kq >= 0) {
             const bool ec = corr != 0 && kp == kq && kp >= 2;
-            if ((kp == 0) == (kq == 0)) {
-                if (ec) rows_tile_a64<kFastIm, true>(t, sa, swx, m, acc);
-                else rows_tile_a64<kFastIm, false>(t, sa, swx, m, acc);
-            } else if (kp == 0) {
-                rows_tile_a64<kFastReNeg, false>(t, sa, swx, m, acc);
+            const int o0 = blockIdx.x * 256 * kTPT + wb;
+            const bool lo = o0 >= nr || !cells_far(N, r0 + o0, r0 + min(o0 + 256 * (kTPT - 1) + 63,
+                                                                         nr - 1),
+                                                   c0 + cc, c0 + cc + m - 1);
+            if (lo) {
+                if ((kp == 0) == (kq == 0)) {
+                    if (ec) rows_tile_a64<kFastIm, true, true>(t, sa, swx, m, acc);
+                    else rows_tile_a64<kFastIm, false, true>(t, sa, swx, m, acc);
+                } else if (kp == 0) {
+                    rows_tile_a64<kFastReNeg, false, true>(t, sa, swx, m, acc);
+                } else {
+                    rows_tile_a64<kFastRePos, false, true>(t, sa, swx, m, acc);
+                }
             } else {
-                rows_tile_a64<kFastRePos, false>(t, sa, swx, m, acc);
+                if ((kp == 0) == (kq == 0)) {
+                    if (ec) rows_tile_a64<kFastIm, true, false>(t, sa, swx, m, acc);
+                    else rows_tile_a64<kFastIm, false, false>(t, sa, swx, m, acc);
+                } else if (kp == 0) {
+                    rows_tile_a64<kFastReNeg, false, false>(t, sa, swx, m, acc);
+                } else {
+                    rows_tile_a64<kFastRePos, false, false>(t, sa, swx, m, acc);
+                }
             }
         } else if (apart) {
             rows_tile<MODE, ACC32, false>(N, t, ss, sx, m, corr != 0, nb, hrow, acc, acc32);
@@ -557,15 +816,17 @@ __global__ __launch_bounds__(256) void k_otf_rows(Nodes N, const double *hrow, i
 // (a = w dx / 2, b = w dy / 2, E_q = (sex, sey)) and the staged targets carry
 // (E_p, x_p); acc gains A(p, q) x_p for every target of the tile.
 struct TgtA {
-    double ex, ey, x;
+    double ex, ey, exl, eyl, x;
 };
 
-template <int KIND, bool ECORR>
-__device__ __forceinline__ void cols_tile_a64(double sex, double sey, double a, double b,
-                                              double w, const TgtA *ta, int m, double &acc) {
+template <int KIND, bool ECORR, bool LO>
+__device__ __forceinline__ void cols_tile_a64(double sex, double sey, double sexl, double seyl,
+                                              double a, double b, double w, const TgtA *ta, int m,
+                                              double &acc) {
     for (int i = 0; i < m; ++i) {
         const TgtA p = ta[i];
-        const double dr = sex - p.ex, di = sey - p.ey;
+        const double dr = LO ? (sex - p.ex) + (sexl - p.exl) : sex - p.ex;
+        const double di = LO ? (sey - p.ey) + (seyl - p.eyl) : sey - p.ey;
         const double nr = sex + p.ex, ni = sey + p.ey;
         const double ix = recip64_from32(dr * dr + di * di) * p.x;
         const double pr = nr * dr + ni * di;
@@ -623,24 +884,49 @@ __global__ __launch_bounds__(256) void k_otf_cols(Nodes N, const double *hrow, i
             const double xv = x[p];
             ts[threadIdx.x] = tv;
             sx[threadIdx.x] = xv;
-            if (FAST) ta[threadIdx.x] = TgtA{tv.ex, tv.ey, xv};
+            if (FAST) ta[threadIdx.x] = TgtA{tv.ex, tv.ey, tv.exl, tv.eyl, xv};
         }
         __syncthreads();
         const int m = min(kOtfStage, pe - pp);
         const bool apart = wave_apart<true>(N, c0, o0, nc, r0 + pp, m, nb);
         const int kp = (FAST && kq >= 0) ? range_boundary(N, r0 + pp, r0 + pp + m - 1) : -1;
+        const bool lo = FAST && kp >= 0 && kq >= 0 &&
+                        (o0 >= nc || !cells_far(N, r0 + pp, r0 + pp + m - 1, c0 + o0,
+                                                 c0 + min(o0 + 63, nc - 1)));
         if (live) {
             if (FAST && apart && kp >= 0 && kq >= 0) {
                 const double w = s.w;
-                if ((kp == 0) == (kq == 0)) {
-                    if (corr != 0 && kp == kq && kp >= 2)
-                        cols_tile_a64<kFastIm, true>(s.ex, s.ey, fa, fb, w, ta, m, acc);
-                    else
-                        cols_tile_a64<kFastIm, false>(s.ex, s.ey, fa, fb, w, ta, m, acc);
-                } else if (kp == 0) {
-                    cols_tile_a64<kFastReNeg, false>(s.ex, s.ey, fa, fb, w, ta, m, acc);
+                const bool ec = corr != 0 && kp == kq && kp >= 2;
+                if (lo) {
+                    if ((kp == 0) == (kq == 0)) {
+                        if (ec)
+                            cols_tile_a64<kFastIm, true, true>(s.ex, s.ey, s.exl, s.eyl, fa, fb,
+                                                               w, ta, m, acc);
+                        else
+                            cols_tile_a64<kFastIm, false, true>(s.ex, s.ey, s.exl, s.eyl, fa, fb,
+                                                                w, ta, m, acc);
+                    } else if (kp == 0) {
+                        cols_tile_a64<kFastReNeg, false, true>(s.ex, s.ey, s.exl, s.eyl, fa, fb,
+                                                               w, ta, m, acc);
+                    } else {
+                        cols_tile_a64<kFastRePos, false, true>(s.ex, s.ey, s.exl, s.eyl, fa, fb,
+                                                               w, ta, m, acc);
+                    }
                 } else {
-                    cols_tile_a64<kFastRePos, false>(s.ex, s.ey, fa, fb, w, ta, m, acc);
+                    if ((kp == 0) == (kq == 0)) {
+                        if (ec)
+                            cols_tile_a64<kFastIm, true, false>(s.ex, s.ey, s.exl, s.eyl, fa, fb,
+                                                                w, ta, m, acc);
+                        else
+                            cols_tile_a64<kFastIm, false, false>(s.ex, s.ey, s.exl, s.eyl, fa,
+                                                                 fb, w, ta, m, acc);
+                    } else if (kp == 0) {
+                        cols_tile_a64<kFastReNeg, false, false>(s.ex, s.ey, s.exl, s.eyl, fa, fb,
+                                                                w, ta, m, acc);
+                    } else {
+                        cols_tile_a64<kFastRePos, false, false>(s.ex, s.ey, s.exl, s.eyl, fa, fb,
+                                                                w, ta, m, acc);
+                    }
                 }
             } else if (apart) {
                 cols_tile<MODE, ACC32, false>(N, s, ts, sx, m, corr != 0, nb, hrow, acc, acc32);
@@ -651,6 +937,31 @@ __global__ __launch_bounds__(256) void k_otf_cols(Nodes N, const double *hrow, i
         __syncthreads();
     }
     if (live) part[(long)blockIdx.y * nc + q] = ACC32 ? (double)acc32 : acc;
+}
+
+// Disc of the E values of every cell of kCellNodes consecutive nodes: the
+// centre and half-diagonal of their bounding box, and the largest |E|; one
+// wave per cell.
+__global__ __launch_bounds__(256) void k_cells(Nodes N, double *cell) {
+    const int c = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int a = c * kCellNodes;
+    if (a >= N.n) return;
+    const int q = min(a + (int)(threadIdx.x & 63), N.n - 1);
+    const double ex = N.ex[q], ey = N.ey[q];
+    double xlo = ex, xhi = ex, ylo = ey, yhi = ey, amax = ex * ex + ey * ey;
+    for (int o = 32; o > 0; o >>= 1) {
+        xlo = min(xlo, __shfl_xor(xlo, o, 64));
+        xhi = max(xhi, __shfl_xor(xhi, o, 64));
+        ylo = min(ylo, __shfl_xor(ylo, o, 64));
+        yhi = max(yhi, __shfl_xor(yhi, o, 64));
+        amax = max(amax, __shfl_xor(amax, o, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        cell[4 * c] = 0.5 * (xlo + xhi);
+        cell[4 * c + 1] = 0.5 * (ylo + yhi);
+        cell[4 * c + 2] = 0.5 * sqrt((xhi - xlo) * (xhi - xlo) + (yhi - ylo) * (yhi - ylo));
+        cell[4 * c + 3] = sqrt(amax);
+    }
 }
 
 inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
@@ -679,9 +990,27 @@ static int split_chunk(int nout, int nsum, int per_block) {
 static int rows_chunk(int nr, int nc) { return split_chunk(nr, nc, 256 * kTPT); }
 static int cols_chunk(int nr, int nc) { return split_chunk(nc, nr, 256); }
 
-int rflavour_nsplit(int nr, int nc, int transpose) {
-    return transpose ? cdiv(nr, cols_chunk(nr, nc)) + 1 : cdiv(nc, rows_chunk(nr, nc)) + 1;
+// Partial slices of an on-the-fly product of modes 2..8: the far chunks, the
+// near band and, when the geometry has near pairs, the near-pair fix.
+int rflavour_nsplit(const Nodes &N, int nr, int nc, int transpose) {
+    const int fix = N.near ? 2 : 1;
+    return transpose ? cdiv(nr, cols_chunk(nr, nc)) + fix : cdiv(nc, rows_chunk(nr, nc)) + fix;
 }
+
+void launch_cells(const Nodes &N, double *cell, hipStream_t st) {
+    hipLaunchKernelGGL(k_cells, dim3(cdiv(cdiv(N.n, kCellNodes), 4)), dim3(256), 0, st, N, cell);
+}
+
+// Lists of the cells holding near pairs outside the kNearBand band, and their
+// pair count added into *count (the products launch their fix kernels only
+// when there are any).
+void launch_near_cells(const Nodes &N, int *lists, double *count, hipStream_t st) {
+    hipLaunchKernelGGL(k_near_cells, dim3(cdiv(N.n, kCellNodes)), dim3(256), 0, st, N, kNearBand,
+                       lists, count);
+}
+
+// Blocks of the fix kernel: the 64-node cells overlapping [o, o + n).
+static int fix_blocks(int o, int n) { return (o + n - 1) / kCellNodes - o / kCellNodes + 1; }
 
 void launch_assemble64(const Layout &L, const Nodes &N, int flags, double *A, long ld,
                        hipStream_t st) {
@@ -770,7 +1099,9 @@ void launch_otf_matvec(const Layout &L, const Nodes &N, int flags, int fp32, int
     dim3 grid(cdiv(n, 256), ns);
     dim3 gridr(cdiv(n, 256 * kTPT), ns);
     const dim3 gnear(cdiv(n, kNearPerBlock));
+    const dim3 gfix(fix_blocks(0, n));
     double *near = part + (long)ns * n;
+    double *fix = near + n;
     if (!transpose) {
         if (fp32) {
             hipLaunchKernelGGL((k_otf_rows<1, true>), gridr, dim3(256), 0, st, N, hrow, 0, n, 0, n,
@@ -782,6 +1113,9 @@ void launch_otf_matvec(const Layout &L, const Nodes &N, int flags, int fp32, int
                                chunk, corr, nb, x, part, active);
             hipLaunchKernelGGL((k_near_band<0, false>), gnear, dim3(256), 0, st, N,
                                hrow, 0, n, 0, n, corr, band, nb, x, near, active);
+            if (N.near)
+                hipLaunchKernelGGL((k_near_fix<0, false>), gfix, dim3(256), 0, st, N, N.nlist,
+                                   hrow, 0, n, 0, n, corr, band, nb, x, fix, active);
         }
     } else {
         if (fp32) {
@@ -794,9 +1128,14 @@ void launch_otf_matvec(const Layout &L, const Nodes &N, int flags, int fp32, int
                                chunk, corr, nb, x, part, active);
             hipLaunchKernelGGL((k_near_band<0, true>), gnear, dim3(256), 0, st, N,
                                hrow, 0, n, 0, n, corr, band, nb, x, near, active);
+            if (N.near)
+                hipLaunchKernelGGL((k_near_fix<0, true>), gfix, dim3(256), 0, st, N, N.nlist,
+                                   hrow, 0, n, 0, n, corr, band, nb, x, fix, active);
         }
     }
-    launch_reduce_partials(n, part, ns + 1, c, 1.0, y, active, st);
+    // FP64: far chunks, near band and the near-pair fix when there are near
+    // pairs; FP32 takes no fix (the quotient's error is far below FP32 rounding)
+    launch_reduce_partials(n, part, (fp32 || !N.near) ? ns + 1 : ns + 2, c, 1.0, y, active, st);
 }
 
 
@@ -814,6 +1153,10 @@ static void rflavour_mode(const Nodes &N, const double *hrow, int transpose, int
         hipLaunchKernelGGL((k_near_band<MODE, false>), dim3(cdiv(nr, kNearPerBlock)), dim3(256), 0,
                            st, N, hrow, r0, nr, c0, nc, 1, 0, nb, x, part + (long)ns * nr,
                            active);
+        if (N.near)
+            hipLaunchKernelGGL((k_near_fix<MODE, false>), dim3(fix_blocks(r0, nr)), dim3(256), 0,
+                               st, N, N.nlist, hrow, r0, nr, c0, nc, 1, 0, nb, x,
+                               part + (long)(ns + 1) * nr, active);
     } else {
         const int chunk = cols_chunk(nr, nc);
         const int ns = cdiv(nr, chunk);
@@ -823,6 +1166,10 @@ static void rflavour_mode(const Nodes &N, const double *hrow, int transpose, int
         hipLaunchKernelGGL((k_near_band<MODE, true>), dim3(cdiv(nc, kNearPerBlock)), dim3(256), 0,
                            st, N, hrow, r0, nr, c0, nc, 1, 0, nb, x, part + (long)ns * nc,
                            active);
+        if (N.near)
+            hipLaunchKernelGGL((k_near_fix<MODE, true>), dim3(fix_blocks(c0, nc)), dim3(256), 0,
+                               st, N, N.nlist, hrow, r0, nr, c0, nc, 1, 0, nb, x,
+                               part + (long)(ns + 1) * nc, active);
     }
 }
 

@@ -87,6 +87,38 @@ def ellipse(M: int, cx: float, cy: float, q: float, b: float, theta: float,
     return Curve(z, d, e)
 
 
+def clustered_flat_surface(M: int, x0: float, beta: float, h: float = 0.0) -> Curve:
+    """zeta(alpha) = alpha + beta sin(alpha - x0) ... reparameterised flat line
+    y = h whose nodes cluster around x = x0: xi(alpha) = alpha - beta sin(alpha - x0)
+    with 0 <= beta < 1, so xi' = 1 - beta cos(alpha - x0) is smallest (1 - beta)
+    at alpha = x0 and the curve still runs left to right (Sec. 2 allows any
+    parameterisation of the surface)."""
+    al = grid(M)
+    s, c = np.sin(al - x0), np.cos(al - x0)
+    z = al - beta * s + 1j * h
+    d = (1.0 - beta * c) + 0j
+    e = beta * s + 0j
+    return Curve(z.astype(np.complex128), d.astype(np.complex128), e.astype(np.complex128))
+
+
+def clustered_ellipse(M: int, cx: float, cy: float, q: float, b: float, theta_c: float,
+                      gamma: float) -> Curve:
+    """The clockwise ellipse c + q cos(t) - i b sin(t) with its parameter t(alpha)
+    = alpha - gamma sin(alpha - theta_c), 0 <= gamma < 1: nodes cluster around
+    t = theta_c (t' = 1 - gamma cos(alpha - theta_c))."""
+    al = grid(M)
+    t = al - gamma * np.sin(al - theta_c)
+    t1 = 1.0 - gamma * np.cos(al - theta_c)
+    t2 = gamma * np.sin(al - theta_c)
+    w = q * np.cos(t) - 1j * b * np.sin(t)
+    w1 = -q * np.sin(t) - 1j * b * np.cos(t)      # d/dt
+    w2 = -q * np.cos(t) + 1j * b * np.sin(t)      # d2/dt2
+    z = (cx + 1j * cy) + w
+    d = w1 * t1
+    e = w2 * t1 * t1 + w1 * t2
+    return Curve(z.astype(np.complex128), d.astype(np.complex128), e.astype(np.complex128))
+
+
 def trig_potential(M: int, A: Sequence[float], B: Sequence[float]) -> np.ndarray:
     """phi(alpha) = sum_{k>=1} A_k cos(k alpha) + B_k sin(k alpha)."""
     al = grid(M)
