@@ -6,8 +6,9 @@ CPU-baseline leg of the benchmark use it.  It shares no code with the GPU
 path: it is written directly from the paper's formulas in plain PyTorch CPU
 operations in float64/complex128, builds every matrix block literally from
 the kernel table of Sec. 3.2 (and the transposed "dagger" blocks of Sec.
-4.1), applies spectral operators with the FFT, and solves by dense LU or,
-for systems too large for that, by a plain restarted GMRES on the stored
+4.1), applies spectral operators with the FFT, and solves by dense LU with
+one step of iterative refinement (residual in extended precision) or, for
+systems too large for that, by a plain restarted GMRES on the stored
 matrix.  Gradients come from PyTorch autograd through these same plain
 operations; directional derivatives from the tangent-linear model
 (forward-mode derivatives of the assembly and of the U map around one
@@ -21,7 +22,7 @@ from .bim import (OGeom, assemble_A, A_rows, rhs, solve_phi, solve_gamma, spectr
                   rk_step, boundary_dPhi, helsing_ojala, dphi_dn_all,
                   layer_potential_direct, boundary_Phi, pressure, spectral_tail,
                   assemble_A_blocked, gmres, dphi_dn_from_omega_chunked, A_times_blocked,
-                  tangent_J)
+                  tangent_J, tangent_J_nodes, J_and_grad_nodes, dense_solve, residual_ext)
 
 __all__ = ["OGeom", "assemble_A", "A_rows", "rhs", "solve_phi", "solve_gamma", "spectral", "split",
            "K_block", "G_block", "A_block", "wall_matrix", "psi_on_surface",
@@ -32,4 +33,4 @@ __all__ = ["OGeom", "assemble_A", "A_rows", "rhs", "solve_phi", "solve_gamma", "
            "boundary_dPhi", "helsing_ojala", "dphi_dn_all",
            "layer_potential_direct", "boundary_Phi", "pressure", "spectral_tail",
            "assemble_A_blocked", "gmres", "dphi_dn_from_omega_chunked", "A_times_blocked",
-           "tangent_J"]
+           "tangent_J", "tangent_J_nodes", "J_and_grad_nodes", "dense_solve", "residual_ext"]

@@ -20,7 +20,9 @@ with background flow over obstacles and topography" (arXiv 2108.01786):
 * velocity and pressure inside the fluid (Helsing-Ojala) .... Sec. 5.1, appendix
 * spectral derivative and Hilbert transform (FFT symbols) .. Sec. 3.4
 * restarted GMRES on the stored matrix ...................... Sec. 7.4 (solver)
+* dense LU with one extended-precision refinement step ...... Sec. 7.4 (tolerance)
 * tangent-linear model of J = sum w U^2 ..................... Sec. 3.2-3.4 differentiated
+  (along surface displacements, or along the surface's node data)
 
 Conventions the paper leaves open and that are fixed here: the Nyquist
 coefficient of D, H and |d| is set to zero; the point z_j inside obstacle j
@@ -34,6 +36,7 @@ from __future__ import annotations
 import math
 from typing import Dict, List, Optional, Sequence
 
+import numpy as np
 import torch
 
 F64 = torch.float64
@@ -322,11 +325,50 @@ def dphi_ds_from_omega(g: OGeom, omega: List[torch.Tensor]) -> List[torch.Tensor
     return out
 
 
+def residual_ext(A: torch.Tensor, b: torch.Tensor, x: torch.Tensor, chunk: int = 1024):
+    """b - A x formed in extended precision (numpy longdouble: a 64-bit
+    significand on x86) and rounded once to FP64, a chunk of rows at a time."""
+    xl = x.numpy().astype(np.longdouble)
+    r = np.empty(tuple(b.shape), dtype=np.float64)
+    for r0 in range(0, A.shape[0], chunk):
+        Al = A[r0:r0 + chunk].numpy().astype(np.longdouble)
+        r[r0:r0 + chunk] = (b[r0:r0 + chunk].numpy().astype(np.longdouble) - Al @ xl)
+    return torch.as_tensor(r)
+
+
+def dense_solve(A: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+    """A x = b by dense LU followed by one step of iterative refinement whose
+    residual is formed in extended precision (residual_ext).
+
+    The paper runs its solver to a relative residual of 1e-15 (Sec. 7.4).  An
+    FP64 LU alone stops near 1e-13 on these systems, with a forward error of
+    about that size that depends on how the LAPACK in use orders its sums:
+    harmless for omega itself, but two spectral derivatives (the gamma_t
+    system, Sec. 4.2) amplify it by up to (M_0/2)^2.  One refinement step takes
+    x to the exact solution of the FP64 system up to its last bits (the LU
+    factors contract the error by their own backward error, about 1e-14 here),
+    independently of the LAPACK.  Autograd differentiates the LU solve; the
+    correction is a constant for it (the derivative of the solution map is the
+    same in exact arithmetic)."""
+    Ad = A.detach()
+    vec = b.dim() == 1
+    if A.requires_grad or b.requires_grad:
+        x = torch.linalg.solve(A, b)
+        LU, piv = torch.linalg.lu_factor(Ad)
+    else:
+        LU, piv = torch.linalg.lu_factor(Ad)
+        x = torch.linalg.lu_solve(LU, piv, b[:, None] if vec else b)
+        x = x[:, 0] if vec else x
+    r = residual_ext(Ad, b.detach(), x.detach())
+    d = torch.linalg.lu_solve(LU, piv, r[:, None] if vec else r)
+    return x + (d[:, 0] if vec else d)
+
+
 def solve_phi(g: OGeom, phi: torch.Tensor) -> Dict[str, torch.Tensor]:
-    """Solve A omega = b by dense LU; return omega, psi|_k (k >= 2) and U."""
+    """Solve A omega = b (dense_solve); return omega, psi|_k (k >= 2) and U."""
     A = assemble_A(g)
     b = rhs(g, phi)
-    omega = torch.linalg.solve(A, b)
+    omega = dense_solve(A, b)
     parts = split(g, omega)
     psi_k = torch.stack([p.mean() for p in parts[2:]]) if g.nb > 2 else torch.zeros(0, dtype=F64)
     U = dphi_dn_from_omega(g, parts)
@@ -361,7 +403,7 @@ def solve_gamma(g: OGeom, gamma0: torch.Tensor) -> Dict[str, torch.Tensor]:
         rk = -(G_block(g, 0, k).T @ gamma0) / g.M[0] - u_mv(g, g.z[k], g.d[k])
         rhs_w.append(rk)
     W = wall_matrix(g)
-    gw = torch.linalg.solve(W, torch.cat(rhs_w))
+    gw = dense_solve(W, torch.cat(rhs_w))
     gparts = split(OGeom(g.z[1:], g.d[1:], g.e[1:], g.zc, g.a, g.V1), gw)
     s0 = torch.abs(g.d[0])
     acc = 0.5 * spectral(gamma0, "H") + (G_block(g, 0, 0).T @ gamma0) / g.M[0]
@@ -445,10 +487,10 @@ def gamma_t_rhs(g: OGeom, phi: torch.Tensor, V: torch.Tensor, tau: float,
 
 def solve_gamma_t(g: OGeom, phi: torch.Tensor, V: torch.Tensor, tau: float,
                   grav: float = 1.0) -> Dict[str, torch.Tensor]:
-    """gamma_t = (gamma_0,t, gamma_1,t, ...) by dense LU of the Sec. 4.2 system."""
+    """gamma_t = (gamma_0,t, gamma_1,t, ...) from the Sec. 4.2 system (dense_solve)."""
     r = gamma_t_rhs(g, phi, V, tau, grav)
     B = gamma_t_matrix(g)
-    r["gamma_t"] = torch.linalg.solve(B, r["b"])
+    r["gamma_t"] = dense_solve(B, r["b"])
     r["B"] = B
     return r
 
@@ -687,7 +729,7 @@ def pressure(g: OGeom, phi: torch.Tensor, tau: float, grav: float, z: torch.Tens
     kappa = (g.e[0] / g.d[0]).imag / s0
     data = tau * kappa - 0.5 * (ds * ds + U * U) - grav * g.z[0].imag
     b = torch.cat([data] + [torch.zeros(m, dtype=F64) for m in g.M[1:]])
-    om_aux = split(g, torch.linalg.solve(r["A"], b))
+    om_aux = split(g, dense_solve(r["A"], b))
     phit = helsing_ojala(g, boundary_Phi(g, om_aux), z).real
     w = helsing_ojala(g, boundary_dPhi(g, om), z)
     return -phit - 0.5 * (w.abs() ** 2) - grav * z.imag
@@ -905,3 +947,66 @@ def tangent_J(g_walls: OGeom, xt, yt, phi, weights, dirs, solve, omega=None,
         dUs.append(dU)
         dJ.append(float((2.0 * w * U * dU).sum()))
     return J, U, omega, dJ, dUs
+
+
+def tangent_J_nodes(g: OGeom, phi, weights, dirs, solve, omega=None, chunk: int = 1024):
+    """Directional derivatives of J = sum_m w_m U_m^2 along directions of the
+    surface's node data and potential, walls fixed: each direction gives the
+    changes of (x, y, x', y', x'', y'') at the surface nodes and of phi~, so
+    no derivative of the direction is taken numerically.  The same
+    tangent-linear model as tangent_J (Sec. 3.2-3.4 differentiated):
+        d omega = A^{-1} (db - dA omega),   db = (dphi, 0, ..., 0),
+        dU = (dU/dnodes)[d] + (dU/domega)[d omega],  dJ = sum_m 2 w_m U_m dU_m,
+    with dA omega and dU forward-mode derivatives of the assembly (row chunks
+    of A times the fixed omega) and of the U map with respect to the six node
+    arrays.  solve(r) returns A^{-1} r for the matrix of g; omega, when given,
+    is the solution at g.  Returns (J, U, omega, [dJ_i], [dU_i])."""
+    phi = torch.as_tensor(phi, dtype=F64)
+    w = torch.as_tensor(weights, dtype=F64)
+    base = (g.z[0].real, g.z[0].imag, g.d[0].real, g.d[0].imag, g.e[0].real, g.e[0].imag)
+
+    def geom(x, y, dx, dy, ex, ey):
+        return g.with_surface(x + 1j * y, dx + 1j * dy, ex + 1j * ey)
+
+    if omega is None:
+        omega = solve(rhs(g, phi))
+    n = omega.shape[0]
+
+    def u_of(x, y, dx, dy, ex, ey, om):
+        return dphi_dn_from_omega_chunked(geom(x, y, dx, dy, ex, ey), split(g, om))
+
+    U = u_of(*base, omega)
+    J = float((w * U * U).sum())
+    dJ, dUs = [], []
+    for d in dirs:
+        tang = tuple(torch.as_tensor(v, dtype=F64) for v in d[:6])
+        dp = torch.as_tensor(d[6], dtype=F64)
+        dAw = []
+        for r0 in range(0, n, chunk):
+            rows = range(r0, min(n, r0 + chunk))
+            f = lambda *a: A_rows(geom(*a), rows) @ omega
+            dAw.append(torch.func.jvp(f, base, tang)[1])
+        dAw = torch.cat(dAw)
+        db = torch.cat([dp, torch.zeros(n - dp.shape[0], dtype=F64)])
+        dom = solve(db - dAw)
+        dU = torch.func.jvp(u_of, base + (omega,), tang + (dom,))[1]
+        dUs.append(dU)
+        dJ.append(float((2.0 * w * U * dU).sum()))
+    return J, U, omega, dJ, dUs
+
+
+def J_and_grad_nodes(g: OGeom, phi, weights):
+    """J = sum_m w_m U_m^2 and its gradient with respect to the surface's node
+    data (x, y, x', y', x'', y'') and phi~ by autograd through the dense
+    solve, walls fixed.  Returns (J, [g_x, g_y, g_x', g_y', g_x'', g_y'',
+    g_phi], U)."""
+    arrs = [v.clone().requires_grad_(True) for v in
+            (g.z[0].real, g.z[0].imag, g.d[0].real, g.d[0].imag, g.e[0].real, g.e[0].imag)]
+    ph = torch.as_tensor(phi, dtype=F64).clone().requires_grad_(True)
+    w = torch.as_tensor(weights, dtype=F64)
+    x, y, dx, dy, ex, ey = arrs
+    gs = g.with_surface(x + 1j * y, dx + 1j * dy, ex + 1j * ey)
+    U = solve_phi(gs, ph)["U"]
+    J = (w * U * U).sum()
+    grads = torch.autograd.grad(J, arrs + [ph])
+    return float(J.detach()), [v.detach() for v in grads], U.detach()
