@@ -75,6 +75,10 @@ extern "C" {
 #define WWBI_FLAG_PROFILE         1  /* time every launch of the dominant matvec kernel  */
 #define WWBI_FLAG_NO_CORRECTION   2  /* drop the E_m rank-one blocks (singular system;
                                         for failure-detection tests only)              */
+#define WWBI_FLAG_NO_RECYCLE      4  /* FP32_REFINED: every inner solve builds its own
+                                        Krylov space (by default the later inner solves
+                                        of a refinement deflate the space of the first:
+                                        fewer Arnoldi steps, same FP64 stopping test)  */
 
 /* spectral operators on one uniform periodic grid (Sec. 3.4), Nyquist mode zeroed */
 #define WWBI_OP_D                 0  /* d/dalpha, symbol i k                             */

@@ -43,14 +43,15 @@ static int grow(T *&p, size_t &cap, size_t want) {
 // The per-solve workspace of n unknowns and restart length `restart`: every
 // buffer with its element count.  ensure() grows each to that count; the
 // allocation-free entry point carves the same list out of its static array.
-int Ctx::ws_plan(int n, int restart, WsItem *it) {
+int Ctx::ws_plan(int n, int restart, WsItem *it, bool recycle) {
     const size_t nn = (size_t)round_up(n, 64);
     const size_t rr = (size_t)std::max(restart, 8);
+    const size_t pre = recycle ? kRecycleMax : 0;
     int k = 0;
     auto D = [&](double *&p, size_t &c, size_t w) { it[k++] = WsItem{(void **)&p, &c, w, 8}; };
     auto I = [&](int *&p, size_t &c, size_t w) { it[k++] = WsItem{(void **)&p, &c, w, 4}; };
     auto Fl = [&](float *&p, size_t &c, size_t w) { it[k++] = WsItem{(void **)&p, &c, w, 4}; };
-    D(V, capV, (rr + 1) * nn);
+    D(V, capV, (pre + rr + 1) * nn);
     Fl(v32, capv32, nn);
     for (int i = 0; i < kNumVec; ++i) D(vec[i], capvec[i], nn);
     D(H, capH, (rr + 1) * (rr + 1));
@@ -58,7 +59,11 @@ int Ctx::ws_plan(int n, int restart, WsItem *it) {
     D(sn, capsn, rr + 1);
     D(gv, capg, rr + 1);
     D(yv, capy, rr + 1);
-    D(P, capP, 3 * 64 * (rr + 1) + 64);
+    D(P, capP, 3 * 64 * (pre + rr + 1) + 128);
+    if (recycle) {
+        D(Urec, capUrec, pre * nn);
+        D(Brec, capBrec, pre * (rr + 2));
+    }
     D(part, cappart, 258 * nn + 64);   // up to 256 far slices + the near-band and near-fix slices
     D(pw, cappw, 65 * (size_t)gemv_partials(nn) + 64);   // 64 dot rows + the norms
     I(bid, capbid, nn);
@@ -84,7 +89,9 @@ int Ctx::ws_plan(int n, int restart, WsItem *it) {
 int Ctx::ensure(int n, int restart) {
     trace = std::getenv("WWBI_TRACE") != nullptr;
     WsItem it[kMaxWsItems];
-    const int k = ws_plan(n, restart, it);
+    // a carved workspace (the allocation-free entry point) has no room for a
+    // recycled space
+    const int k = ws_plan(n, restart, it, !fixed_ws);
     if (fixed_ws) {
         // workspace carved for this call: it cannot grow
         for (int i = 0; i < k; ++i)
@@ -99,6 +106,7 @@ int Ctx::ensure(int n, int restart) {
         *it[i].cap = cap / it[i].esize;
         if (rc) return rc;
     }
+    vpre = kRecycleMax;
     return WWBI_OK;
 }
 
@@ -135,6 +143,9 @@ void Ctx::release() {
     F(pw);
     cappw = 0;
     F(V);
+    F(Urec);
+    F(Brec);
+    vpre = 0;
     F(v32);
     for (int i = 0; i < kNumVec; ++i) F(vec[i]);
     F(H); F(cs); F(sn); F(gv); F(yv); F(P); F(part);
@@ -331,20 +342,34 @@ void Ctx::prof_end() {
 // memory: the host sees the end without a queued copy, and steps enqueued
 // after it return at once on the device flag.
 int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol, int restart,
-               int max_iter, int poll, bool fp32_basis, bool verify, SolveStats &st) {
+               int max_iter, int poll, bool fp32_basis, bool verify, SolveStats &st, int kc) {
     const int n = op.n;
     const int G = gmres_nblocks(n);
-    const int ldp = restart + 1;
+    const int ldp = restart + 1 + vpre;    // rows of Gram-Schmidt partials (recycled ones too)
     const long ldv = round_up(n, 64);
     double *r = vec[VR], *w = vec[VW];
     double *P1 = P, *P2 = P + 64 * ldp, *P3 = P + 2 * 64 * ldp;   // P[i*G + b] layout
     const int NB = gemv_partials(n);
     float *x32 = fp32_basis ? v32 : nullptr;
+    // the Arnoldi basis, and in front of it the kc recycled vectors C
+    double *Vb = V + (long)vpre * ldv;
+    double *Cb = Vb - (long)kc * ldv;
+    double *Bm = Brec, *zc = Brec + (long)kRecycleMax * (restart + 1);
     // the inner solves of the refinement (the only callers without the
     // true-residual check) orthogonalise once; every other solve twice
     const bool single_pass = !verify;
-    launch_norm_partial(b, n, P3, G, stream);
-    launch_set_tol(P3, G, tol, gs, stream);
+    if (kc > 0) {
+        // deflated solve: r0 = b - C C^T b starts the (only) cycle; the
+        // tolerance is relative to ||b||
+        if (verify || !x_zero || kc > vpre) return WWBI_EINVAL_OPTS;
+        restart = std::min(restart, WWBI_MAX_RESTART - kc);
+        launch_recycle_dots(Cb, ldv, b, n, kc, P1, P3, G, stream);
+        launch_set_tol(P3, G, tol, gs, stream);
+        launch_recycle_project(Cb, ldv, b, n, kc, P1, P3, G, r, zc, stream);
+    } else {
+        launch_norm_partial(b, n, P3, G, stream);
+        launch_set_tol(P3, G, tol, gs, stream);
+    }
     bool first = true;
     bool x_set = !x_zero;      // a cold start writes x with its first update
     double prev_beta = HUGE_VAL;
@@ -355,7 +380,9 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
     for (;;) {
         cur_cycle = -1;        // the residual product is not an Arnoldi step
         const double *r0 = r;
-        if (!x_set) {
+        if (kc > 0) {
+            // r holds b - C C^T b and P3 its norm partials
+        } else if (!x_set) {
             r0 = b;            // r = b - A 0, whose norm partials are already in P3
         } else {
             apply(op, x, nullptr, b, r, nullptr);
@@ -363,7 +390,7 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
         }
         cyc_id = cyc_id == INT_MAX ? 1 : cyc_id + 1;   // never 0, the mirror's initial id
         const int cid = cyc_id;
-        launch_cycle_start(r0, n, P3, G, V, x32, gv, restart + 1, gs, cid, dmir, stream);
+        launch_cycle_start(r0, n, P3, G, Vb, x32, gv, restart + 1, gs, cid, dmir, stream);
         int jmax = std::min(restart, max_iter - st.iters);
         if (verify) {
             int rc = read_state(h);
@@ -391,41 +418,44 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
         for (int j0 = 0; j0 < jmax && !ended; j0 += poll) {
             const int j1 = std::min(jmax, j0 + poll);
             for (int j = j0; j < j1; ++j) {
-                const double *vj = V + (long)j * ldv;
+                const double *vj = Vb + (long)j * ldv;
                 cur_step = j;
                 // steps on a stored matrix take the first Gram-Schmidt dots in the
-                // product's epilogue (one partial per product block)
-                const bool fuse32 = single_pass && x32 && stored_fp32(op.kind) && j < 64;
+                // product's epilogue (one partial per product block), for up to
+                // 64 rows (the recycled ones included)
+                const bool fuse32 = single_pass && x32 && stored_fp32(op.kind) && kc + j < 64;
                 const bool fuse64 = !single_pass && stored_fp64(op.kind) && j < 64;
                 prof_begin();
                 if (fuse32)
-                    launch_gemv32_dots((const float *)A, op.ld, n, x32, w, &gs->active, V, ldv, j,
-                                       pw, pw + 64L * NB, stream);
+                    launch_gemv32_dots((const float *)A, op.ld, n, x32, w, &gs->active, Cb, ldv,
+                                       kc + j, pw, pw + 64L * NB, stream);
                 else if (fuse64)
-                    launch_gemv64_dots((const double *)A, op.ld, n, vj, w, &gs->active, V, ldv, j,
-                                       pw, pw + 64L * NB, stream);
+                    launch_gemv64_dots((const double *)A, op.ld, n, vj, w, &gs->active, Vb, ldv,
+                                       j, pw, pw + 64L * NB, stream);
                 else
                     apply(op, vj, x32, nullptr, w, &gs->active);
                 prof_end();
                 if (fuse32) {
-                    launch_cgs_final(V, ldv, w, n, j, pw, pw + 64L * NB, G, x32, H, restart + 1,
-                                     false, cs, sn, gv, jmax, gs, cid, dmir, stream, kSingle, NB);
+                    launch_cgs_final(Cb, ldv, w, n, j, pw, pw + 64L * NB, G, x32, H, restart + 1,
+                                     false, cs, sn, gv, jmax, gs, cid, dmir, stream, kSingle, NB,
+                                     kc, Bm, kRecycleMax);
                     continue;
                 }
                 if (fuse64) {
-                    launch_cgs_first(V, ldv, w, n, j, pw, P2, P3, G, H, restart + 1, gs, stream,
+                    launch_cgs_first(Vb, ldv, w, n, j, pw, P2, P3, G, H, restart + 1, gs, stream,
                                      kSingle, NB);
-                    launch_cgs_final(V, ldv, w, n, j, P2, P3, G, x32, H, restart + 1, true, cs,
+                    launch_cgs_final(Vb, ldv, w, n, j, P2, P3, G, x32, H, restart + 1, true, cs,
                                      sn, gv, jmax, gs, cid, dmir, stream);
                     continue;
                 }
-                launch_cgs_dot(V, ldv, w, n, j, P1, P3, G, gs, stream);
+                launch_cgs_dot(Cb, ldv, w, n, kc + j, P1, P3, G, gs, stream);
                 if (single_pass) {
-                    launch_cgs_final(V, ldv, w, n, j, P1, P3, G, x32, H, restart + 1, false, cs,
-                                     sn, gv, jmax, gs, cid, dmir, stream);
+                    launch_cgs_final(Cb, ldv, w, n, j, P1, P3, G, x32, H, restart + 1, false, cs,
+                                     sn, gv, jmax, gs, cid, dmir, stream, kSingle, 0, kc, Bm,
+                                     kRecycleMax);
                 } else {
-                    launch_cgs_first(V, ldv, w, n, j, P1, P2, P3, G, H, restart + 1, gs, stream);
-                    launch_cgs_final(V, ldv, w, n, j, P2, P3, G, x32, H, restart + 1, true, cs,
+                    launch_cgs_first(Vb, ldv, w, n, j, P1, P2, P3, G, H, restart + 1, gs, stream);
+                    launch_cgs_final(Vb, ldv, w, n, j, P2, P3, G, x32, H, restart + 1, true, cs,
                                      sn, gv, jmax, gs, cid, dmir, stream);
                 }
             }
@@ -438,7 +468,12 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
             pending = cur;
         }
         launch_hsolve(H, restart + 1, gv, yv, gs, stream);
-        launch_xupdate(x, V, ldv, n, yv, !x_set, gs, stream);
+        if (kc > 0) {
+            launch_recycle_coef(zc, Bm, kRecycleMax, yv, kc, gs, stream);
+            launch_xupdate_recycled(x, Vb, ldv, n, yv, Urec, zc, kc, gs, stream);
+        } else {
+            launch_xupdate(x, Vb, ldv, n, yv, !x_set, gs, stream);
+        }
         x_set = true;
         st.cycles += 1;
         first = false;
@@ -462,7 +497,7 @@ double inner_tolerance(const wwbi_opts &o, double bnorm, double rnorm) {
 
 double Ctx::device_norm(const double *v, int n) {
     const int G = gmres_nblocks(n);
-    double *P3 = P + 2 * 64 * (restart_cap + 1);
+    double *P3 = norm_partials();
     launch_norm_partial(v, n, P3, G, stream);
     if (hipMemcpyAsync(hst, P3, sizeof(double) * G, hipMemcpyDeviceToHost, stream) != hipSuccess)
         return NAN;
@@ -478,12 +513,22 @@ double Ctx::device_norm(const double *v, int n) {
 //   solve A32 d = r by GMRES to the inner tolerance; x += d.
 // One host synchronisation per step: the norm of the new residual and the
 // final state of the inner solve are read together.
+//
+// Unless WWBI_FLAG_NO_RECYCLE, the first inner solve's Krylov space is kept
+// (C orthonormal, A32 U = C; up to kRecycleMax vectors) and every later inner
+// solve deflates it: the residuals of the later steps are dominated by the
+// same slowly converging directions, which the first solve has already found.
 int Ctx::refine(const Op &op32, const Op &op64, const double *b, double *x, bool x_zero,
                 const wwbi_opts &o, SolveStats &st) {
     const int n = op64.n;
     const int G = gmres_nblocks(n);
+    const long ldv = round_up(n, 64);
     double *r = vec[VRR], *d = vec[VD];
-    double *Pn = P + 2 * 64 * (restart_cap + 1) + 64;   // norm partials (64 doubles)
+    const bool recycle = !(o.flags & WWBI_FLAG_NO_RECYCLE) && vpre > 0 && op32.n == n &&
+                         stored_fp32(op32.kind);
+    int kc = 0;                // recycled vectors the later inner solves deflate
+    bool first_inner = true;   // the pending inner solve is the first one
+    double *Pn = norm_partials() + 64;   // norm partials (64 doubles)
     // From a cold start the first inner solve takes b itself and writes x;
     // ||b|| then comes back in that solve's final state, read at the first
     // synchronisation, so no host round trip precedes it.
@@ -522,6 +567,16 @@ int Ctx::refine(const Op &op32, const Op &op64, const double *b, double *x, bool
                     bn = fin.bnorm;     // the first inner solve's right-hand side was b
                     prev = bn;
                 }
+                // the first solve's basis, rotated Hessenberg and rotations are
+                // still in place (nothing since has written them)
+                if (first_inner && recycle && fin.jdone >= 1 && fin.jdone <= vpre &&
+                    !fin.breakdown && std::isfinite(fin.resid)) {
+                    kc = fin.jdone;
+                    double *Vb = V + (long)vpre * ldv;
+                    launch_recycle_build(Vb, ldv, n, kc, H, o.restart + 1, cs, sn,
+                                         Vb - (long)kc * ldv, Urec, stream);
+                }
+                first_inner = false;
             }
         }
         if (!cold) {
@@ -542,7 +597,7 @@ int Ctx::refine(const Op &op32, const Op &op64, const double *b, double *x, bool
         const double itol = cold ? inner_tolerance(o, 1.0, 1.0) : inner_tolerance(o, bn, rn);
         const int rc = gmres(op32, cold ? b : r, cold ? x : d, true, itol, o.restart,
                              o.max_iter - st.iters, o.poll_every, stored_fp32(op32.kind), false,
-                             in);
+                             in, kc);
         if (rc < 0) return rc;
         inner_pending = true;
         st.cycles += in.cycles;

@@ -63,6 +63,10 @@ constexpr int kStateSlotBytes = 8192;    // bytes per slot (up to kMaxMulti stat
 constexpr int kTailOffset = 24576;       // byte offset of the Fourier-tail energies in hst
 constexpr int kHostStaging = 32768;      // pinned host staging bytes
 constexpr int kMaxMulti = 32;            // right-hand sides per multi solve
+// Krylov vectors an FP32 inner solve may hand on to the later inner solves of
+// its refinement (recycled space); the basis array keeps room for them in
+// front of the Arnoldi basis.
+constexpr int kRecycleMax = 64;
 
 double inner_tolerance(const wwbi_opts &o, double bnorm, double rnorm);
 
@@ -104,7 +108,10 @@ struct Ctx {
 
     void *A = nullptr;      size_t capA = 0;
     double *A64 = nullptr;  size_t capA64 = 0;   // FP64 copy beside an FP32 A (multi refine)
-    double *V = nullptr;    size_t capV = 0;
+    double *V = nullptr;    size_t capV = 0;      // vpre recycled rows, then the basis
+    int vpre = 0;
+    double *Urec = nullptr; size_t capUrec = 0;   // U of the recycled space (A U = C)
+    double *Brec = nullptr; size_t capBrec = 0;   // B (kRecycleMax x restart) | z
     float *v32 = nullptr;   size_t capv32 = 0;
     double *vec[kNumVec] = {};  size_t capvec[kNumVec] = {};
     double *H = nullptr;    size_t capH = 0;
@@ -171,7 +178,10 @@ struct Ctx {
     // entry point): ensure() then checks capacities and never allocates
     bool fixed_ws = false;
 
-    int ws_plan(int n, int restart, WsItem *it);
+    // recycle: room for the recycled space of the refinement's inner solves
+    int ws_plan(int n, int restart, WsItem *it, bool recycle = true);
+    // 128 doubles of norm partials behind the Gram-Schmidt partials
+    double *norm_partials() const { return P + 3L * 64 * (restart_cap + 1 + vpre); }
     int ensure(int n, int restart);
     int ensure_matrix(size_t bytes);
     int ensure_matrix64(size_t bytes);
@@ -186,8 +196,10 @@ struct Ctx {
     int final_state(GState &out);
     void prof_begin();
     void prof_end();
+    // kc > 0: deflate the kc recycled vectors in front of the basis (one
+    // cycle, no verification, x = the solution from zero)
     int gmres(const Op &op, const double *b, double *x, bool x_zero, double tol, int restart,
-              int max_iter, int poll, bool fp32_basis, bool verify, SolveStats &st);
+              int max_iter, int poll, bool fp32_basis, bool verify, SolveStats &st, int kc = 0);
     double device_norm(const double *v, int n);
     int refine(const Op &op32, const Op &op64, const double *b, double *x, bool x_zero,
                const wwbi_opts &o, SolveStats &st);

@@ -116,7 +116,8 @@ __device__ __forceinline__ void kappa64(const Nodes &N, const Tgt &t, const Src 
     const double di = (s.ey - t.ey) + (s.eyl - t.eyl);
     const double den = dr * dr + di * di;
     const double ee = max(t.ex * t.ex + t.ey * t.ey, s.ex * s.ex + s.ey * s.ey);
-    if ((t.k == s.k && cyc_dist(t.loc, s.loc, t.M) <= kNearBand) || den * 4096.0 < ee) {
+    if ((t.k == s.k && cyc_dist(t.loc, s.loc, t.M) <= kNearBand) ||
+        den * (kNearCut * kNearCut) < ee) {
         cot_half64(s.x - t.x, s.y - t.y, cr, ci);
         return;
     }

@@ -54,6 +54,9 @@ struct Nodes {
 };
 
 constexpr int kCellNodes = 64;
+// Near-pair cut: a pair with |E_q - E_p| < max(|E_p|, |E_q|) / kNearCut takes
+// the exact-difference cotangent (kappa64 and the on-the-fly near-pair fix).
+constexpr double kNearCut = 64.0;
 // Near-pair list of a cell (k_near_cells): its count (-1 when more than
 // kNearList cells hold near pairs with it), then the cells in increasing order.
 constexpr int kNearList = 31;
@@ -339,11 +342,32 @@ void launch_cgs_first(const double *V, long ldv, double *w, int n, int j, const 
 // last pass fused with normalisation into V_{j+1} and the Givens step
 // (add: column j of H already holds a first pass)
 // GP: the number of partials in P2 and P3 (0: G, the chunk count)
+// kc > 0: V points at kc recycled vectors in front of the Arnoldi basis, whose
+// coefficients go to column j of B (ld ldb)
 void launch_cgs_final(const double *V, long ldv, const double *w, int n, int j,
                       const double *P2, const double *P3, int G, float *v32, double *H, int ldh,
                       bool add, double *cs, double *sn, double *g, int restart_len, GState *gs,
                       int cyc, GState *mirror, hipStream_t st, const Bat &bt = kSingle,
-                      int GP = 0);
+                      int GP = 0, int kc = 0, double *B = nullptr, int ldb = 0);
+// Recycling of an inner solve's Krylov space (k steps, basis V, rotated
+// Hessenberg H, rotations cs/sn): C (k rows, orthonormal) and U with A U = C
+void launch_recycle_build(const double *V, long ldv, int n, int k, const double *H, int ldh,
+                          const double *cs, const double *sn, double *C, double *U,
+                          hipStream_t st);
+// partial dots of r with C_0..C_{kc-1} into P, partial |r|^2 into P3
+void launch_recycle_dots(const double *C, long ldv, const double *r, int n, int kc, double *P,
+                         double *P3, int G, hipStream_t st);
+// z = C^T r, r0 = r - C z, partial |r0|^2 into P3
+void launch_recycle_project(const double *C, long ldv, const double *r, int n, int kc,
+                            const double *P, double *P3, int G, double *r0, double *z,
+                            hipStream_t st);
+// z -= B y over the solved columns
+void launch_recycle_coef(double *z, const double *B, int ldb, const double *y, int kc,
+                         const GState *gs, hipStream_t st);
+// x = V y + U z
+void launch_xupdate_recycled(double *x, const double *V, long ldv, int n, const double *y,
+                             const double *U, const double *z, int kc, const GState *gs,
+                             hipStream_t st);
 void launch_hsolve(const double *H, int ldh, const double *g, double *y, const GState *gs,
                    hipStream_t st, const Bat &bt = kSingle);
 // x += V y (x = V y when overwrite)

@@ -277,13 +277,18 @@ __global__ __launch_bounds__(kT) void k_cgs_first(const double *V, long ldv, dou
 // Block 0 adds h to (add = 1) or stores it into (add = 0) column j of H,
 // applies the previous rotations, forms the new one and updates the residual
 // estimate, with the column and the rotations staged in LDS.
+//
+// With kc > 0 recycled vectors C_0..C_{kc-1} sit in front of the Arnoldi
+// basis (V_ points at C_0, the basis vector v_i at row kc + i): w is
+// orthogonalised against all kc + j + 1 rows, the first kc coefficients go to
+// column j of B (ld ldb) and only the rest into the Hessenberg column.
 __global__ __launch_bounds__(kT) void k_cgs_final(const double *V_, long ldv, const double *w,
                                                   int n, int j, const double *P2,
                                                   const double *P3, int G, int GP, float *v32,
                                                   double *H, int ldh, int add, double *cs,
                                                   double *sn, double *g, int restart_len,
                                                   GState *gs, int cyc, GState *mirror,
-                                                  Bat bt) {
+                                                  Bat bt, int kc, double *B, int ldb) {
     gs += sys();
     if (gs->active == 0) return;
     double *V = const_cast<double *>(V_) + sys() * bt.v;
@@ -298,8 +303,9 @@ __global__ __launch_bounds__(kT) void k_cgs_final(const double *V_, long ldv, co
     __shared__ double h[WWBI_MAX_RESTART + 1];
     __shared__ double snrm;
     __shared__ double col[WWBI_MAX_RESTART + 2], lc[WWBI_MAX_RESTART], ls[WWBI_MAX_RESTART];
-    // h[0..j] from P2 and ||w'||^2 from P3 into h[j + 1], in one pass
-    reduce_coeffs(P2, GP, j, h, P3);
+    const int jj = kc + j;     // last row orthogonalised against
+    // h[0..jj] from P2 and ||w'||^2 from P3 into h[jj + 1], in one pass
+    reduce_coeffs(P2, GP, jj, h, P3);
     const bool b0 = blockIdx.x == 0;
     if (b0) {
         const double *hc = H + (long)j * ldh;
@@ -309,8 +315,8 @@ __global__ __launch_bounds__(kT) void k_cgs_final(const double *V_, long ldv, co
     __syncthreads();
     if (threadIdx.x == 0) {
         double s2 = 0.0;
-        for (int i = 0; i <= j; ++i) s2 += h[i] * h[i];
-        const double q = h[j + 1] - s2;
+        for (int i = 0; i <= jj; ++i) s2 += h[i] * h[i];
+        const double q = h[jj + 1] - s2;
         snrm = q > 0.0 ? sqrt(q) : 0.0;
     }
     __syncthreads();
@@ -318,15 +324,19 @@ __global__ __launch_bounds__(kT) void k_cgs_final(const double *V_, long ldv, co
     const double sc = nrm > 0.0 ? 1.0 / nrm : 0.0;
     int c0, c1;
     chunk_of(n, G, blockIdx.x, c0, c1);
-    double *vn = V + (long)(j + 1) * ldv;
+    double *vn = V + (long)(jj + 1) * ldv;
     for (int m = c0 + threadIdx.x; m < c1; m += kT) {
-        const double v = minus_proj(w[m], h, V, ldv, m, j) * sc;
+        const double v = minus_proj(w[m], h, V, ldv, m, jj) * sc;
         vn[m] = v;
         if (v32) v32[m] = (float)v;
     }
     if (!b0) return;
+    if (kc > 0) {
+        double *bc = B + (long)j * ldb;
+        for (int i = threadIdx.x; i < kc; i += kT) bc[i] = (add ? bc[i] : 0.0) + h[i];
+    }
     if (threadIdx.x == 0) {
-        for (int i = 0; i <= j; ++i) col[i] += h[i];
+        for (int i = 0; i <= j; ++i) col[i] += h[kc + i];
         col[j + 1] = nrm;
         for (int i = 0; i < j; ++i) {
             const double a = col[i], b = col[i + 1];
@@ -421,6 +431,106 @@ __global__ void k_to_f32(const double *src, float *dst, int n) {
     if (m < n) dst[m] = (float)src[m];
 }
 
+// ---------------------------------------------------------------------------
+// Recycling of the first inner solve's Krylov space (GCRO-style deflation of
+// the later inner solves of one refinement).  The first solve leaves the
+// Arnoldi relation A V_k = V_{k+1} Hbar with Hbar = Q [R; 0], Q the product
+// of its Givens rotations.  Then C = V_{k+1} Q[:, :k] has orthonormal columns
+// and U = V_k R^{-1} satisfies A U = C (to the accuracy of the FP32
+// products).  A later solve of A d = r projects r onto the complement of C,
+// r0 = r - C (C^T r), runs Arnoldi on (I - C C^T) A, and returns
+// d = V y + U (C^T r - B y), B = C^T A V the coefficients of C in its
+// Gram-Schmidt; its least-squares problem and residual estimate are those
+// of plain GMRES on r0.
+// ---------------------------------------------------------------------------
+
+// One thread per row m: C_i[m] (the rotations applied to the row's basis
+// values, carrying one value: O(k) per row) and U_i[m] (forward substitution
+// through R's columns, reading back the row's own earlier U values).
+__global__ void k_recycle_build(const double *V, long ldv, int n, int k, const double *H,
+                                int ldh, const double *cs, const double *sn, double *C,
+                                double *U) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    double carry = V[m];
+    for (int i = 0; i < k; ++i) {
+        const double nx = V[(long)(i + 1) * ldv + m];
+        const double c = cs[i], s = sn[i];
+        C[(long)i * ldv + m] = c * carry + s * nx;
+        carry = -s * carry + c * nx;
+    }
+    for (int i = 0; i < k; ++i) {
+        const double *rc = H + (long)i * ldh;      // column i of R
+        double acc = V[(long)i * ldv + m];
+        for (int l = 0; l < i; ++l) acc -= rc[l] * U[(long)l * ldv + m];
+        U[(long)i * ldv + m] = acc / rc[i];
+    }
+}
+
+// Partial dots of r with C_0..C_{kc-1} (P[i*G + b]) and the partial squared
+// norm of r (P3[b]); runs whatever the state of the previous solve.
+__global__ __launch_bounds__(kT) void k_recycle_dots(const double *C, long ldv, const double *r,
+                                                     int n, int kc, double *P, double *P3,
+                                                     int G) {
+    __shared__ double sh[kT / 64];
+    int c0, c1;
+    chunk_of(n, G, blockIdx.x, c0, c1);
+    double nn = 0.0;
+    for (int m = c0 + threadIdx.x; m < c1; m += kT) nn += r[m] * r[m];
+    nn = block_sum(nn, sh);
+    if (threadIdx.x == 0) P3[blockIdx.x] = nn;
+    chunk_dots(C, ldv, r, c0, c1, kc - 1, P, G);
+}
+
+// h = C^T r (summed from P, every block in the same order; block 0 keeps it
+// in z), r0 = r - C h and the partial squared norms of r0 (P3).
+__global__ __launch_bounds__(kT) void k_recycle_project(const double *C, long ldv,
+                                                        const double *r, int n, int kc,
+                                                        const double *P, double *P3, int G,
+                                                        double *r0, double *z) {
+    __shared__ double h[WWBI_MAX_RESTART + 1];
+    __shared__ double sh[kT / 64];
+    reduce_coeffs(P, G, kc - 1, h);
+    __syncthreads();
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < kc; i += kT) z[i] = h[i];
+    int c0, c1;
+    chunk_of(n, G, blockIdx.x, c0, c1);
+    double nn = 0.0;
+    for (int m = c0 + threadIdx.x; m < c1; m += kT) {
+        const double v = minus_proj(r[m], h, C, ldv, m, kc - 1);
+        r0[m] = v;
+        nn += v * v;
+    }
+    nn = block_sum(nn, sh);
+    if (threadIdx.x == 0) P3[blockIdx.x] = nn;
+}
+
+// z <- z - B y over the jdone solved columns (one block, a thread per row of
+// B, columns in ascending order).
+__global__ void k_recycle_coef(double *z, const double *B, int ldb, const double *y, int kc,
+                               const GState *gs) {
+    const int k = gs->jdone;
+    for (int i = threadIdx.x; i < kc; i += blockDim.x) {
+        double acc = z[i];
+        for (int j = 0; j < k; ++j) acc -= B[(long)j * ldb + i] * y[j];
+        z[i] = acc;
+    }
+}
+
+// x = sum_{i<jdone} y_i V_i + sum_{i<kc} z_i U_i
+__global__ void k_xupdate_recycled(double *x, const double *V, long ldv, int n, const double *y,
+                                   const double *U, const double *z, int kc,
+                                   const GState *gs) {
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= n) return;
+    const int k = gs->jdone;
+    double acc = 0.0;
+    for (int i = 0; i < k; ++i) acc += y[i] * V[(long)i * ldv + m];
+    for (int i = 0; i < kc; ++i) acc += z[i] * U[(long)i * ldv + m];
+    x[m] = acc;
+}
+
 }  // namespace
 
 int gmres_nblocks(int n) {
@@ -456,10 +566,37 @@ void launch_cgs_first(const double *V, long ldv, double *w, int n, int j, const 
 void launch_cgs_final(const double *V, long ldv, const double *w, int n, int j,
                       const double *P2, const double *P3, int G, float *v32, double *H, int ldh,
                       bool add, double *cs, double *sn, double *g, int restart_len, GState *gs,
-                      int cyc, GState *mirror, hipStream_t st, const Bat &bt, int GP) {
+                      int cyc, GState *mirror, hipStream_t st, const Bat &bt, int GP, int kc,
+                      double *B, int ldb) {
     hipLaunchKernelGGL(k_cgs_final, dim3(G, bt.nsys), dim3(kT), 0, st, V, ldv, w, n, j, P2, P3, G,
                        GP > 0 ? GP : G, v32, H, ldh, add ? 1 : 0, cs, sn, g, restart_len, gs,
-                       cyc, mirror, bt);
+                       cyc, mirror, bt, kc, B, ldb);
+}
+void launch_recycle_build(const double *V, long ldv, int n, int k, const double *H, int ldh,
+                          const double *cs, const double *sn, double *C, double *U,
+                          hipStream_t st) {
+    hipLaunchKernelGGL(k_recycle_build, dim3(cdiv(n, 256)), dim3(256), 0, st, V, ldv, n, k, H,
+                       ldh, cs, sn, C, U);
+}
+void launch_recycle_dots(const double *C, long ldv, const double *r, int n, int kc, double *P,
+                         double *P3, int G, hipStream_t st) {
+    hipLaunchKernelGGL(k_recycle_dots, dim3(G), dim3(kT), 0, st, C, ldv, r, n, kc, P, P3, G);
+}
+void launch_recycle_project(const double *C, long ldv, const double *r, int n, int kc,
+                            const double *P, double *P3, int G, double *r0, double *z,
+                            hipStream_t st) {
+    hipLaunchKernelGGL(k_recycle_project, dim3(G), dim3(kT), 0, st, C, ldv, r, n, kc, P, P3, G,
+                       r0, z);
+}
+void launch_recycle_coef(double *z, const double *B, int ldb, const double *y, int kc,
+                         const GState *gs, hipStream_t st) {
+    hipLaunchKernelGGL(k_recycle_coef, dim3(1), dim3(64), 0, st, z, B, ldb, y, kc, gs);
+}
+void launch_xupdate_recycled(double *x, const double *V, long ldv, int n, const double *y,
+                             const double *U, const double *z, int kc, const GState *gs,
+                             hipStream_t st) {
+    hipLaunchKernelGGL(k_xupdate_recycled, dim3(cdiv(n, 256)), dim3(256), 0, st, x, V, ldv, n, y,
+                       U, z, kc, gs);
 }
 void launch_hsolve(const double *H, int ldh, const double *g, double *y, const GState *gs,
                    hipStream_t st, const Bat &bt) {

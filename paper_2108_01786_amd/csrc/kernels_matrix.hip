@@ -420,7 +420,7 @@ __device__ __forceinline__ bool discs_within(const double *a, const double *b, d
     return (sqrt(gx * gx + gy * gy) - a[2] - b[2]) * f < 1.001 * max(a[3], b[3]);
 }
 __device__ __forceinline__ bool discs_may_be_near(const double *a, const double *b) {
-    return discs_within(a, b, 64.0);
+    return discs_within(a, b, kNearCut);
 }
 
 // True when every pair of target nodes [pa, pb] and source nodes [qa, qb] is
@@ -460,7 +460,7 @@ __device__ __forceinline__ bool near_pair(int q, int mbase, int mloc, int mM, in
     if (l >= 0 && l < mM && cyc_dist(l, mloc, mM) <= nb) return false;
     const double dr = (qx - ex) + (qxl - exl);
     const double di = (qy - ey) + (qyl - eyl);
-    return (dr * dr + di * di) * 4096.0 < max(ex * ex + ey * ey, qx * qx + qy * qy);
+    return (dr * dr + di * di) * (kNearCut * kNearCut) < max(ex * ex + ey * ey, qx * qx + qy * qy);
 }
 
 // Ordered list, in LDS, of the cells of [c0, c0 + cn) whose discs come within

@@ -91,7 +91,8 @@ extern "C" int wwbi_solve_phi_noalloc(wwbi_ctx *ctx, const wwbi_geom *g, const d
     // the workspace of this solve, laid out in the array: the cycle state
     // first, then every buffer of the plan, each 256-byte aligned
     WsItem it[kMaxWsItems];
-    const int k = c->ws_plan((int)n, o->restart, it);
+    // (an on-the-fly FP64 solve: no room for a recycled space)
+    const int k = c->ws_plan((int)n, o->restart, it, false);
     size_t off[kMaxWsItems];
     size_t total = align_up(sizeof(GState));
     for (int i = 0; i < k; ++i) {
@@ -111,8 +112,10 @@ extern "C" int wwbi_solve_phi_noalloc(wwbi_ctx *ctx, const wwbi_geom *g, const d
     }
     GState *save_gs = c->gs;
     const int save_restart = c->restart_cap;
+    const int save_vpre = c->vpre;
     c->gs = reinterpret_cast<GState *>(base);
     c->restart_cap = o->restart;
+    c->vpre = 0;
     c->fixed_ws = true;
 
     // the array keeps the previous call's contents: start from zero, as a
@@ -123,6 +126,7 @@ extern "C" int wwbi_solve_phi_noalloc(wwbi_ctx *ctx, const wwbi_geom *g, const d
     if (hipStreamSynchronize(c->stream) != hipSuccess && rc >= 0) rc = WWBI_EHIP;
 
     c->fixed_ws = false;
+    c->vpre = save_vpre;
     c->restart_cap = save_restart;
     c->gs = save_gs;
     for (int i = 0; i < k; ++i) {

@@ -25,7 +25,7 @@ NOT_CONVERGED, STAGNATED, REFINE_STALLED, WARN_UNDERRESOLVED = 1, 2, 3, 4
 FP64, FP32_REFINED = 0, 1
 SURF_GRAPH, SURF_HLS = 0, 1
 MATVEC_AUTO, MATVEC_STORED, MATVEC_ON_THE_FLY = 0, 1, 2
-FLAG_PROFILE, FLAG_NO_CORRECTION = 1, 2
+FLAG_PROFILE, FLAG_NO_CORRECTION, FLAG_NO_RECYCLE = 1, 2, 4
 OP_D, OP_D2, OP_H, OP_ABSD = 0, 1, 2, 3
 MAT_A, MAT_WALL, MAT_T = 0, 1, 2
 
