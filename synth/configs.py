@@ -133,6 +133,21 @@ def _smooth_field(rng, M: int, K: int, decay: float) -> np.ndarray:
     return f
 
 
+def _smooth_field3(rng, M: int, K: int, decay: float):
+    """The field of _smooth_field (same draws) with its exact first and second
+    alpha-derivatives."""
+    al = grid(M)
+    ks = np.arange(1, K + 1)
+    cc = rng.standard_normal(K)
+    ss = rng.standard_normal(K)
+    w = np.exp(-ks / decay)
+    c, s = np.cos(np.outer(al, ks)), np.sin(np.outer(al, ks))
+    f = (w * (cc * c + ss * s)).sum(1)
+    f1 = (w * ks * (-cc * s + ss * c)).sum(1)
+    f2 = (w * ks * ks * (-cc * c - ss * s)).sum(1)
+    return f, f1, f2
+
+
 def _adjoint_draws(M0: int) -> Dict:
     """Weights w_m ~ U[0,1] and 32 smooth directions (x~, y, phi), max-norm 1."""
     rng = np.random.default_rng(178604)
@@ -151,17 +166,23 @@ def large_adjoint_draws(M0: int = 16384) -> Dict:
     """Weights and directions of J = sum w U^2 on the large cell: w_m ~ U[0, 1]
     from seed 178605, and 4 directions (x~, y, phi), each component
     sum_{k=1..32} e^{-k/8}(N cos k alpha + N sin k alpha) scaled to max-norm 1,
-    from seed 178615."""
+    from seed 178615.  `derivatives` holds, per direction and component, the
+    exact first and second alpha-derivatives (same scale), so that a
+    direction of the surface nodes (zeta, zeta', zeta'') needs no numerical
+    differentiation."""
     w = np.random.default_rng(178605).uniform(0.0, 1.0, M0)
     rng = np.random.default_rng(178615)
-    dirs = []
+    dirs, ders = [], []
     for _ in range(4):
-        comps = []
+        comps, cd = [], []
         for _c in range(3):
-            f = _smooth_field(rng, M0, 32, 8.0)
-            comps.append(f / np.abs(f).max())
+            f, f1, f2 = _smooth_field3(rng, M0, 32, 8.0)
+            sc = np.abs(f).max()
+            comps.append(f / sc)
+            cd.append(np.stack([f1 / sc, f2 / sc]))
         dirs.append(np.stack(comps))
-    return {"weights": w, "directions": np.stack(dirs)}
+        ders.append(np.stack(cd))
+    return {"weights": w, "directions": np.stack(dirs), "derivatives": np.stack(ders)}
 
 
 def _config5(rng) -> Dict:

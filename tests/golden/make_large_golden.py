@@ -12,7 +12,11 @@ Only oracle/ and synth/ are used.  The FP64 matrix of the collocated system
 
 It then evaluates J = sum w U^2 (weights of synth.large_adjoint_draws) and
 its derivatives along the 4 seeded directions by the tangent-linear model
-(tangent_J, with the LU factors as the solver).
+on the surface's node data (tangent_J_nodes, with the LU factors as the
+solver): each direction moves (x~, y, phi) and, with their exact
+derivatives, (x', y', x'', y''), so no spectral derivative of the surface or
+of the directions enters (at 16384 surface nodes the rounding of a spectral
+second derivative alone reaches 1e-9).
 
 Run from the repository root:  python tests/golden/make_large_golden.py
 (about 40 minutes on 8 cores; peaks near 35 GB of host memory).
@@ -90,13 +94,13 @@ def main():
     log(f"spread GMRES vs LU {meta['spread_gmres_vs_lu']}")
 
     adj = large_adjoint_draws(M0)
-    z0 = geom.curves[0].z
-    al = 2 * np.pi * np.arange(M0) / M0
-    xt, yt = z0.real - al, z0.imag
+    dirs = []
+    for d, dd in zip(adj["directions"], adj["derivatives"]):
+        # (x, y, x', y', x'', y'', phi): x~ and y move with their derivatives
+        dirs.append((d[0], d[1], dd[0][0], dd[1][0], dd[0][1], dd[1][1], d[2]))
     t = time.time()
-    J, U_t, _, dJ, _ = O.tangent_J(og, xt, yt, np.asarray(cfg["phi"]), adj["weights"],
-                                   [tuple(d) for d in adj["directions"]], lu_solve, omega=x,
-                                   chunk=512)
+    J, U_t, _, dJ, _ = O.tangent_J_nodes(og, np.asarray(cfg["phi"]), adj["weights"], dirs,
+                                         lu_solve, omega=x, chunk=512)
     meta["t_tangent_s"] = time.time() - t
     meta["U_tangent_vs_U"] = rel(U_t, U)
     log(f"J {J:.17g} dJ {dJ} in {meta['t_tangent_s']:.0f} s")

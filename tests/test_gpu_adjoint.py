@@ -1,6 +1,11 @@
 """Adjoint of the velocity-potential solve (hand-written transpose solve and
 kernel-derivative contractions) against torch.autograd.gradcheck, central
-differences of the GPU forward, and the oracle's autograd gradient."""
+differences of the GPU forward, and the oracle's autograd gradient: through
+the spectral surface on the small cells, and element by element on the
+surface's node data on the M = 4608 adjoint cell (config 4)."""
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -113,8 +118,7 @@ def test_adjoint_config4_directions(ww, ctx, prec):
         return float((wt * U * U).sum())
 
     worst = 0.0
-    ndir = 32 if prec == "fp64" else 8
-    for k in range(ndir):
+    for k in range(len(cfg["directions"])):
         d = cfg["directions"][k]
         fd = (Jat(h * d[0], h * d[1], h * d[2]) - Jat(-h * d[0], -h * d[1], -h * d[2])) / (2 * h)
         an = float(gx @ d[0] + gy @ d[1] + gp @ d[2])
@@ -132,3 +136,36 @@ def test_adjoint_refined_equals_fp64(ww, ctx):
     b = _gpu_J_grad(ctx, geom, phi, w, tol=1e-14, precision=ww.FP32_REFINED)
     for u, v in zip(a[1:4], b[1:4]):
         assert np.abs(u - v).max() <= 1e-9 * np.abs(u).max()
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_adjoint_config4_matches_oracle_gradient(ww, ctx, prec):
+    """Config 4 (M = 4608): the gradient of J = sum w U^2 with respect to the
+    surface's node data (x, y, x', y', x'', y'') and phi~ from
+    wwbi_adjoint_phi, on the cell's own node data, element by element against
+    the oracle's reverse-mode gradient through its dense solve
+    (tests/golden/adjoint_c4.npz, written by make_adjoint_golden.py).  Each
+    array is compared relative to its largest entry."""
+    say(f"case adjoint config4 vs oracle {prec}")
+    gd = np.load(os.path.join(GOLDEN, "adjoint_c4.npz"))
+    cfg = make_config(4)
+    geom, phi, w = cfg["geom"], cfg["phi"], cfg["weights"]
+    opts = dict(tol=1e-15 if prec == "fp64" else 1e-14,
+                precision=ww.FP64 if prec == "fp64" else ww.FP32_REFINED)
+    dg = ww.DeviceGeometry.from_synth(geom, DEV)
+    U, om, _, rf = ctx.solve_phi(dg, torch.as_tensor(phi, device=DEV), **opts)
+    wt = torch.as_tensor(w, device=DEV)
+    grads, ra = ctx.adjoint_phi(dg, om, 2.0 * wt * U, **opts)
+    J = float((wt * U * U).sum())
+    eJ = abs(J - float(gd["J"])) / abs(float(gd["J"]))
+    errs = {k: float(np.abs(grads[k].cpu().numpy() - gd[f"g_{k}"]).max()
+                     / np.abs(gd[f"g_{k}"]).max())
+            for k in ("x", "y", "dx", "dy", "ddx", "ddy", "phi")}
+    say(f"  forward iters {rf.iters} adjoint iters {ra.iters}  J {eJ:.1e}  "
+        + " ".join(f"{k} {v:.1e}" for k, v in errs.items()))
+    bar = 1e-11 if prec == "fp64" else 1e-10
+    assert eJ <= bar
+    assert max(errs.values()) <= 10 * bar

@@ -4,10 +4,27 @@ differences of the velocity-potential solution.
 
 gamma_t applies d/dalpha twice to the velocity-potential solution (gamma =
 -D omega_0, then D of the bracket), so rounding anywhere upstream reaches it
-amplified by about (M_0/2)^2.  The oracle itself moves by 3.9e-13 (M_0 = 256)
-and 3.7e-11 (M_0 = 2048) when phi~ alone is perturbed by 2e-16 relative noise.
-The bar is therefore max(base, 2e-16 M_0^2), base = 1e-11 for FP64 solves and
-1e-10 for refined ones; it equals the base up to M_0 = 256."""
+amplified by up to about (M_0/2)^2.  The oracle measures that floor itself
+(tests/golden/gamma_t_spread.json, written by gamma_t_spread.py), three ways:
+every kernel entry and spectral output moved by one unit of rounding (up to
+4.2e-13 at config 1, M_0 = 256, and 3.8e-11 at config 2, M_0 = 2048); omega
+alone moved by one unit of rounding (4.8e-13 and 1.8e-11); and both systems
+solved by GMRES to 1e-15 instead of dense LU (1.6e-12 and 5.6e-11).  The
+last is the spread between two correct FP64 solvers, and the device's own
+GMRES sits at about that distance (fed the device's omega, the oracle's
+gamma_t moves to within 1.5e-11 of the device's at config 2).  The bar is
+max(base, 4 x the largest of the three spreads), base = 1e-11 for FP64 solves
+and 1e-10 for refined ones; the tiny and ragged cells, with no measured
+spread, keep the base.
+
+Both solves run to the paper's GMRES tolerance, 1e-15 (Sec. 7.4): at 1e-13
+the truncation error GMRES leaves in omega, amplified by the two
+derivatives, moves gamma_t at config 2 by 2.3e-10, four times the spread
+above.
+"""
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -60,10 +77,23 @@ def _oracle(name, cfg, V, tau):
     return _REF[key]
 
 
+_SPREAD = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                      "gamma_t_spread.json")))
+
+
+def _bar(name, prec):
+    base = 1e-11 if prec == "fp64" else 1e-10
+    if name in _SPREAD:
+        sp = _SPREAD[name]
+        return max(base, 4.0 * max(sp["rel_change"] + sp["omega_rounding"] + [sp["gmres_vs_lu"]]))
+    return base
+
+
 @pytest.mark.parametrize("name,mode,prec", [("tiny", "stored", "fp64"), ("ragged", "stored", "fp64"),
                                             ("c1", "stored", "fp64"), ("c1", "otf", "fp64"),
                                             ("ragged", "stored", "fp32"), ("c1", "stored", "fp32"),
-                                            ("c1", "otf", "fp32"), ("c2", "stored", "fp32")])
+                                            ("c1", "otf", "fp32"), ("c2", "stored", "fp64"),
+                                            ("c2", "stored", "fp32")])
 def test_gamma_t_matches_oracle(ww, ctx, name, mode, prec):
     say(f"case gamma_t {name} {mode} {prec}")
     cfg = _cfg(name)
@@ -72,7 +102,7 @@ def test_gamma_t_matches_oracle(ww, ctx, name, mode, prec):
     dg = ww.DeviceGeometry.from_synth(geom, DEV)
     gt, U, r1, r2 = ctx.solve_gamma_t(
         dg, torch.as_tensor(cfg["phi"], device=DEV), torch.as_tensor(V, device=DEV), tau=0.1,
-        tol=1e-13 if prec == "fp64" else 1e-14,
+        tol=1e-15,
         matvec=ww.MATVEC_STORED if mode == "stored" else ww.MATVEC_ON_THE_FLY,
         precision=ww.FP64 if prec == "fp64" else ww.FP32_REFINED)
     ref = _oracle(name, cfg, V, 0.1)
@@ -81,7 +111,7 @@ def test_gamma_t_matches_oracle(ww, ctx, name, mode, prec):
     eU = np.abs(U.cpu().numpy() - ref["U"].numpy()).max() / np.abs(ref["U"].numpy()).max()
     say(f"  its phi {r1.iters} gamma_t {r2.iters}  err {err:.2e}  U err {eU:.2e}")
     assert r2.status == 0 and r2.rel_resid <= 1e-13
-    bar = max(1e-11 if prec == "fp64" else 1e-10, 2e-16 * geom.M[0] ** 2)
+    bar = _bar(name, prec)
     assert err <= bar, (err, bar)
     assert eU <= (1e-11 if prec == "fp64" else 1e-10)
 

@@ -11,7 +11,20 @@ Nyquist, not as discretization error.  So the closed form pins U to 1e-10 at
 1/16 resolution, and at full size the checks are: FP64 and refined FP32 agree,
 the oracle's own rows of A give a small residual for the GPU solution, and the
 closed form holds to the rounding-limited 1e-7.
+
+The seeded large cell itself (stage 0 of the bench) is compared element by
+element with the oracle's reference (tests/golden/large_M40960.npz: the FP64
+matrix solved by the oracle's GMRES to 6e-16, written by
+make_large_golden.py): omega and psi|_k at the bars of the solves (1e-11 FP64,
+1e-10 refined); U at max(bar, 4 x the oracle's own spread), where the spread
+is how far the oracle's U moves when every entry of its matrix moves by one
+unit of rounding (large_rounding_spread.py: 4.7e-12); and J = sum w U^2
+with its derivatives along four seeded directions of the surface's node data
+(the oracle's tangent-linear model) against the hand-written adjoint.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -127,3 +140,68 @@ def test_large_full_size(ww, ctx):
         r = bvec[rows] - Ar @ om
         say(f"  sampled residual {np.abs(r).max() / np.abs(bvec).max():.2e}")
         assert np.abs(r).max() <= 1e-11 * np.abs(bvec).max()
+
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden():
+    gd = np.load(os.path.join(GOLDEN, "large_M40960.npz"))
+    meta = json.load(open(os.path.join(GOLDEN, "large_M40960.json")))
+    return gd, meta
+
+
+def _opts(ww, prec):
+    # FP64 to the paper's tolerance (Sec. 7.4); refined in the large-stage
+    # bench's options
+    if prec == "fp64":
+        return dict(tol=1e-15, restart=120)
+    return dict(tol=1e-14, restart=120, precision=ww.FP32_REFINED)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_large_forward_matches_oracle(ww, ctx, prec):
+    say(f"case large forward vs oracle {prec}")
+    gd, meta = _golden()
+    cfg = make_config(5)
+    dg = ww.DeviceGeometry.from_synth(cfg["geom"], DEV)
+    U, om, psi, rep = ctx.solve_phi(dg, torch.as_tensor(cfg["phi"], device=DEV), **_opts(ww, prec))
+    eU, eo = _rel(U.cpu().numpy(), gd["U"]), _rel(om.cpu().numpy(), gd["omega"])
+    ep = _rel(psi, gd["psi_k"])
+    spread = meta["U_rounding_spread"]["entry_rounding"]["U"]
+    say(f"  status {rep.status} iters {rep.iters} resid {rep.rel_resid:.1e}  U {eU:.2e} "
+        f"omega {eo:.2e} psi {ep:.2e} (oracle U spread {spread:.1e})")
+    bar = 1e-11 if prec == "fp64" else 1e-10
+    assert rep.status == ww.OK
+    assert eo <= bar and ep <= bar
+    assert eU <= max(bar, 4.0 * spread)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_large_adjoint_matches_oracle(ww, ctx, prec):
+    """J and its derivatives along the four seeded directions of the surface's
+    node data (x~, y and phi~ move, x', y', x'', y'' with their exact
+    derivatives): the adjoint's gradient contracted with each direction
+    against the oracle's tangent-linear model, relative to the largest."""
+    from synth import large_adjoint_draws
+    say(f"case large adjoint vs oracle {prec}")
+    gd, _ = _golden()
+    cfg = make_config(5)
+    geom = cfg["geom"]
+    adj = large_adjoint_draws(geom.M[0])
+    dg = ww.DeviceGeometry.from_synth(geom, DEV)
+    opts = _opts(ww, prec)
+    U, om, _, rf = ctx.solve_phi(dg, torch.as_tensor(cfg["phi"], device=DEV), **opts)
+    wt = torch.as_tensor(adj["weights"], device=DEV)
+    grads, ra = ctx.adjoint_phi(dg, om, 2.0 * wt * U, **opts)
+    g = {k: v.cpu().numpy() for k, v in grads.items()}
+    J = float((wt * U * U).sum())
+    dJ = []
+    for d, dd in zip(adj["directions"], adj["derivatives"]):
+        dJ.append(float(g["x"] @ d[0] + g["y"] @ d[1] + g["dx"] @ dd[0][0] + g["dy"] @ dd[1][0]
+                        + g["ddx"] @ dd[0][1] + g["ddy"] @ dd[1][1] + g["phi"] @ d[2]))
+    eJ = abs(J - float(gd["J"])) / abs(float(gd["J"]))
+    edJ = float(np.abs(np.array(dJ) - gd["dJ"]).max() / np.abs(gd["dJ"]).max())
+    say(f"  forward iters {rf.iters} adjoint iters {ra.iters}  J {eJ:.2e}  dJ {edJ:.2e}")
+    bar = 1e-11 if prec == "fp64" else 1e-10
+    assert eJ <= bar and edJ <= 10 * bar
