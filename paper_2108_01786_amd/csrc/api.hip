@@ -66,6 +66,7 @@ int Ctx::ws_plan(int n, int restart, WsItem *it, bool recycle) {
     }
     D(part, cappart, 258 * nn + 64);   // up to 256 far slices + the near-band and near-fix slices
     D(pw, cappw, 65 * (size_t)gemv_partials(nn) + 64);   // 64 dot rows + the norms
+    D(hsum, caphsum, 128);
     I(bid, capbid, nn);
     I(loc, caploc, nn);
     I(Mk, capMk, nn);
@@ -142,6 +143,7 @@ void Ctx::release() {
     capA64 = 0;
     F(pw);
     cappw = 0;
+    F(hsum);
     F(V);
     F(Urec);
     F(Brec);
@@ -436,14 +438,17 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
                     apply(op, vj, x32, nullptr, w, &gs->active);
                 prof_end();
                 if (fuse32) {
+                    // the product's partials summed once (kc + j + 1 dots and the norm)
+                    launch_reduce_rows(pw, NB, pw + 64L * NB, kc + j + 2, hsum, gs, stream);
                     launch_cgs_final(Cb, ldv, w, n, j, pw, pw + 64L * NB, G, x32, H, restart + 1,
                                      false, cs, sn, gv, jmax, gs, cid, dmir, stream, kSingle, NB,
-                                     kc, Bm, kRecycleMax);
+                                     kc, Bm, kRecycleMax, hsum);
                     continue;
                 }
                 if (fuse64) {
+                    launch_reduce_rows(pw, NB, nullptr, j + 1, hsum, gs, stream);
                     launch_cgs_first(Vb, ldv, w, n, j, pw, P2, P3, G, H, restart + 1, gs, stream,
-                                     kSingle, NB);
+                                     kSingle, NB, hsum);
                     launch_cgs_final(Vb, ldv, w, n, j, P2, P3, G, x32, H, restart + 1, true, cs,
                                      sn, gv, jmax, gs, cid, dmir, stream);
                     continue;

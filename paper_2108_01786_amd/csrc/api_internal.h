@@ -63,10 +63,6 @@ constexpr int kStateSlotBytes = 8192;    // bytes per slot (up to kMaxMulti stat
 constexpr int kTailOffset = 24576;       // byte offset of the Fourier-tail energies in hst
 constexpr int kHostStaging = 32768;      // pinned host staging bytes
 constexpr int kMaxMulti = 32;            // right-hand sides per multi solve
-// Krylov vectors an FP32 inner solve may hand on to the later inner solves of
-// its refinement (recycled space); the basis array keeps room for them in
-// front of the Arnoldi basis.
-constexpr int kRecycleMax = 64;
 
 double inner_tolerance(const wwbi_opts &o, double bnorm, double rnorm);
 
@@ -122,6 +118,7 @@ struct Ctx {
     double *P = nullptr;    size_t capP = 0;
     double *part = nullptr; size_t cappart = 0;
     double *pw = nullptr;   size_t cappw = 0;     // partials of the fused Arnoldi product
+    double *hsum = nullptr; size_t caphsum = 0;   // their row sums
     int *bid = nullptr;     size_t capbid = 0;
     int *loc = nullptr;     size_t caploc = 0;
     int *Mk = nullptr;      size_t capMk = 0;

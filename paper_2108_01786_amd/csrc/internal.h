@@ -53,6 +53,11 @@ struct Nodes {
     int near;              // the geometry has near pairs outside the band (set-up)
 };
 
+// Krylov vectors an FP32 inner solve may hand on to the later inner solves of
+// its refinement (recycled space); the basis array keeps room for them in
+// front of the Arnoldi basis.
+constexpr int kRecycleMax = 64;
+
 constexpr int kCellNodes = 64;
 // Near-pair cut: a pair with |E_q - E_p| < max(|E_p|, |E_q|) / kNearCut takes
 // the exact-difference cotangent (kappa64 and the on-the-fly near-pair fix).
@@ -336,9 +341,15 @@ void launch_cgs_dot(const double *V, long ldv, const double *w, int n, int j, do
                     double *P3, int G, const GState *gs, hipStream_t st, const Bat &bt = kSingle);
 // first Gram-Schmidt pass (w -= V h; dots of V with w into P2, |w|^2 into P3)
 // GP: the number of partials in P1 (0: G, the chunk count)
+// hred (may be null): the coefficients already summed (launch_reduce_rows)
 void launch_cgs_first(const double *V, long ldv, double *w, int n, int j, const double *P1,
                       double *P2, double *P3, int G, double *H, int ldh, const GState *gs,
-                      hipStream_t st, const Bat &bt = kSingle, int GP = 0);
+                      hipStream_t st, const Bat &bt = kSingle, int GP = 0,
+                      const double *hred = nullptr);
+// out[r] = sum of row r of the GP per-block partials P (rows 0..nrows-1, the
+// last one taken from Px when Px is given); nothing once the cycle has ended
+void launch_reduce_rows(const double *P, int GP, const double *Px, int nrows, double *out,
+                        const GState *gs, hipStream_t st);
 // last pass fused with normalisation into V_{j+1} and the Givens step
 // (add: column j of H already holds a first pass)
 // GP: the number of partials in P2 and P3 (0: G, the chunk count)
@@ -348,7 +359,8 @@ void launch_cgs_final(const double *V, long ldv, const double *w, int n, int j,
                       const double *P2, const double *P3, int G, float *v32, double *H, int ldh,
                       bool add, double *cs, double *sn, double *g, int restart_len, GState *gs,
                       int cyc, GState *mirror, hipStream_t st, const Bat &bt = kSingle,
-                      int GP = 0, int kc = 0, double *B = nullptr, int ldb = 0);
+                      int GP = 0, int kc = 0, double *B = nullptr, int ldb = 0,
+                      const double *hred = nullptr);
 // Recycling of an inner solve's Krylov space (k steps, basis V, rotated
 // Hessenberg H, rotations cs/sn): C (k rows, orthonormal) and U with A U = C
 void launch_recycle_build(const double *V, long ldv, int n, int k, const double *H, int ldh,

@@ -159,18 +159,17 @@ __device__ __forceinline__ void chunk_dots(const double *V, long ldv, const doub
     }
 }
 
-// acc - sum_{i<=j} h_i V_i[m] in ascending i, eight loads in flight at a time
+// acc - sum_{i<=j} h_i V_i[m] in ascending i, sixteen loads in flight at a
+// time (the last group predicated, its missing terms exact zeros)
 __device__ __forceinline__ double minus_proj(double acc, const double *h, const double *V,
                                              long ldv, int m, int j) {
-    int i = 0;
-    for (; i + 8 <= j + 1; i += 8) {
-        double v[8];
+    for (int i = 0; i <= j; i += 16) {
+        double v[16];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v[u] = V[(long)(i + u) * ldv + m];
+        for (int u = 0; u < 16; ++u) v[u] = i + u <= j ? V[(long)(i + u) * ldv + m] : 0.0;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc -= h[i + u] * v[u];
+        for (int u = 0; u < 16; ++u) acc -= (i + u <= j ? h[i + u] : 0.0) * v[u];
     }
-    for (; i <= j; ++i) acc -= h[i] * V[(long)i * ldv + m];
     return acc;
 }
 
@@ -210,6 +209,30 @@ __device__ __forceinline__ void reduce_coeffs(const double *P, int G, int j, dou
     }
 }
 
+// Row sums of the per-block partials of a fused Arnoldi product (one block
+// per row): out[r] = sum_b P[r * GP + b] for the coefficient rows and, when
+// Px is given, out[nrows - 1] = sum_b Px[b] (the squared norm).  Each row in
+// one fixed order: thread t takes b = t, t + kT, ... (eight loads in flight),
+// then the waves' butterflies and the wave sums in order.  Summed once here,
+// the coefficients are then read by every block of the Gram-Schmidt kernel.
+__global__ __launch_bounds__(kT) void k_reduce_rows(const double *P, int GP, const double *Px,
+                                                    int nrows, double *out, const GState *gs) {
+    if (gs->active == 0) return;
+    __shared__ double sh[kT / 64];
+    const int r = blockIdx.x;
+    const double *row = (Px && r == nrows - 1) ? Px : P + (long)r * GP;
+    double a = 0.0;
+    for (int b0 = threadIdx.x; b0 < GP; b0 += 8 * kT) {
+        double t[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) t[k] = b0 + k * kT < GP ? row[b0 + k * kT] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) a += t[k];
+    }
+    a = block_sum(a, sh);
+    if (threadIdx.x == 0) out[r] = a;
+}
+
 // Partial dots of w with V_0..V_j (P[i*G + b]) and the partial squared norm
 // of w (P3[b]).
 __global__ __launch_bounds__(kT) void k_cgs_dot(const double *V, long ldv, const double *w,
@@ -238,7 +261,7 @@ __global__ __launch_bounds__(kT) void k_cgs_dot(const double *V, long ldv, const
 __global__ __launch_bounds__(kT) void k_cgs_first(const double *V, long ldv, double *w, int n,
                                                   int j, const double *P1, double *P2,
                                                   double *P3, int G, int GP, double *H, int ldh,
-                                                  const GState *gs, Bat bt) {
+                                                  const GState *gs, Bat bt, const double *hred) {
     gs += sys();
     if (gs->active == 0) return;
     V += sys() * bt.v;
@@ -249,7 +272,11 @@ __global__ __launch_bounds__(kT) void k_cgs_first(const double *V, long ldv, dou
     H += sys() * bt.h;
     __shared__ double h[WWBI_MAX_RESTART + 1];
     __shared__ double sh[kT / 64];
-    reduce_coeffs(P1, GP, j, h);
+    if (hred) {
+        for (int i = threadIdx.x; i <= j; i += kT) h[i] = hred[i];
+    } else {
+        reduce_coeffs(P1, GP, j, h);
+    }
     __syncthreads();
     if (blockIdx.x == 0)
         for (int i = threadIdx.x; i <= j; i += kT) H[(long)j * ldh + i] = h[i];
@@ -288,7 +315,8 @@ __global__ __launch_bounds__(kT) void k_cgs_final(const double *V_, long ldv, co
                                                   double *H, int ldh, int add, double *cs,
                                                   double *sn, double *g, int restart_len,
                                                   GState *gs, int cyc, GState *mirror,
-                                                  Bat bt, int kc, double *B, int ldb) {
+                                                  Bat bt, int kc, double *B, int ldb,
+                                                  const double *hred) {
     gs += sys();
     if (gs->active == 0) return;
     double *V = const_cast<double *>(V_) + sys() * bt.v;
@@ -304,8 +332,13 @@ __global__ __launch_bounds__(kT) void k_cgs_final(const double *V_, long ldv, co
     __shared__ double snrm;
     __shared__ double col[WWBI_MAX_RESTART + 2], lc[WWBI_MAX_RESTART], ls[WWBI_MAX_RESTART];
     const int jj = kc + j;     // last row orthogonalised against
-    // h[0..jj] from P2 and ||w'||^2 from P3 into h[jj + 1], in one pass
-    reduce_coeffs(P2, GP, jj, h, P3);
+    // h[0..jj] from P2 and ||w'||^2 from P3 into h[jj + 1], in one pass (or
+    // already summed into hred)
+    if (hred) {
+        for (int i = threadIdx.x; i <= jj + 1; i += kT) h[i] = hred[i];
+    } else {
+        reduce_coeffs(P2, GP, jj, h, P3);
+    }
     const bool b0 = blockIdx.x == 0;
     if (b0) {
         const double *hc = H + (long)j * ldh;
@@ -444,26 +477,44 @@ __global__ void k_to_f32(const double *src, float *dst, int n) {
 // of plain GMRES on r0.
 // ---------------------------------------------------------------------------
 
-// One thread per row m: C_i[m] (the rotations applied to the row's basis
-// values, carrying one value: O(k) per row) and U_i[m] (forward substitution
-// through R's columns, reading back the row's own earlier U values).
-__global__ void k_recycle_build(const double *V, long ldv, int n, int k, const double *H,
-                                int ldh, const double *cs, const double *sn, double *C,
-                                double *U) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= n) return;
-    double carry = V[m];
+// One thread per row m, one wave per block: the row's k + 1 basis values
+// are staged in the thread's own column of LDS (sixteen loads in flight),
+// then C_i[m] (the rotations applied along the row, carrying one value:
+// O(k)) and U_i[m] (forward substitution through R's columns, in place over
+// the staged values: O(k^2) LDS reads).  R and the rotations are uniform
+// across the wave.
+constexpr int kRecycleRows = 64;
+__global__ __launch_bounds__(kRecycleRows) void k_recycle_build(const double *V, long ldv, int n,
+                                                                int k, const double *H, int ldh,
+                                                                const double *cs,
+                                                                const double *sn, double *C,
+                                                                double *U) {
+    __shared__ double ws[kRecycleMax + 1][kRecycleRows];      // k <= kRecycleMax
+    const int t = threadIdx.x;
+    const int m = blockIdx.x * kRecycleRows + t;
+    if (m >= n) return;                  // no barrier below: each thread keeps to its column
+    for (int i0 = 0; i0 <= k; i0 += 16) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = i0 + u <= k ? V[(long)(i0 + u) * ldv + m] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            if (i0 + u <= k) ws[i0 + u][t] = v[u];
+    }
+    double carry = ws[0][t];
     for (int i = 0; i < k; ++i) {
-        const double nx = V[(long)(i + 1) * ldv + m];
+        const double nx = ws[i + 1][t];
         const double c = cs[i], s = sn[i];
         C[(long)i * ldv + m] = c * carry + s * nx;
         carry = -s * carry + c * nx;
     }
     for (int i = 0; i < k; ++i) {
         const double *rc = H + (long)i * ldh;      // column i of R
-        double acc = V[(long)i * ldv + m];
-        for (int l = 0; l < i; ++l) acc -= rc[l] * U[(long)l * ldv + m];
-        U[(long)i * ldv + m] = acc / rc[i];
+        double acc = ws[i][t];
+        for (int l = 0; l < i; ++l) acc -= rc[l] * ws[l][t];
+        acc /= rc[i];
+        ws[i][t] = acc;
+        U[(long)i * ldv + m] = acc;
     }
 }
 
@@ -559,24 +610,28 @@ void launch_cgs_dot(const double *V, long ldv, const double *w, int n, int j, do
 }
 void launch_cgs_first(const double *V, long ldv, double *w, int n, int j, const double *P1,
                       double *P2, double *P3, int G, double *H, int ldh, const GState *gs,
-                      hipStream_t st, const Bat &bt, int GP) {
+                      hipStream_t st, const Bat &bt, int GP, const double *hred) {
     hipLaunchKernelGGL(k_cgs_first, dim3(G, bt.nsys), dim3(kT), 0, st, V, ldv, w, n, j, P1, P2,
-                       P3, G, GP > 0 ? GP : G, H, ldh, gs, bt);
+                       P3, G, GP > 0 ? GP : G, H, ldh, gs, bt, hred);
+}
+void launch_reduce_rows(const double *P, int GP, const double *Px, int nrows, double *out,
+                        const GState *gs, hipStream_t st) {
+    hipLaunchKernelGGL(k_reduce_rows, dim3(nrows), dim3(kT), 0, st, P, GP, Px, nrows, out, gs);
 }
 void launch_cgs_final(const double *V, long ldv, const double *w, int n, int j,
                       const double *P2, const double *P3, int G, float *v32, double *H, int ldh,
                       bool add, double *cs, double *sn, double *g, int restart_len, GState *gs,
                       int cyc, GState *mirror, hipStream_t st, const Bat &bt, int GP, int kc,
-                      double *B, int ldb) {
+                      double *B, int ldb, const double *hred) {
     hipLaunchKernelGGL(k_cgs_final, dim3(G, bt.nsys), dim3(kT), 0, st, V, ldv, w, n, j, P2, P3, G,
                        GP > 0 ? GP : G, v32, H, ldh, add ? 1 : 0, cs, sn, g, restart_len, gs,
-                       cyc, mirror, bt, kc, B, ldb);
+                       cyc, mirror, bt, kc, B, ldb, hred);
 }
 void launch_recycle_build(const double *V, long ldv, int n, int k, const double *H, int ldh,
                           const double *cs, const double *sn, double *C, double *U,
                           hipStream_t st) {
-    hipLaunchKernelGGL(k_recycle_build, dim3(cdiv(n, 256)), dim3(256), 0, st, V, ldv, n, k, H,
-                       ldh, cs, sn, C, U);
+    hipLaunchKernelGGL(k_recycle_build, dim3(cdiv(n, kRecycleRows)), dim3(kRecycleRows), 0, st, V,
+                       ldv, n, k, H, ldh, cs, sn, C, U);
 }
 void launch_recycle_dots(const double *C, long ldv, const double *r, int n, int kc, double *P,
                          double *P3, int G, hipStream_t st) {
