@@ -111,7 +111,7 @@ def parse():
     ap.add_argument("--mode", default="stored", choices=["stored", "otf"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
-    ap.add_argument("--inner-tol", type=float, default=3e-7)
+    ap.add_argument("--inner-tol", type=float, default=1e-7)
     ap.add_argument("--poll", type=int, default=2)
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="after timing, run one device copy of this many MiB (counter calibration)")
@@ -306,7 +306,9 @@ def run_large(a):
     disp = cfg["stage_disp"]
     w = torch.as_tensor(np.random.default_rng(178605).uniform(0.0, 1.0, M0), device=dev)
     ctx.reserve(geom.Mtot, 120, wwbi.FP32_REFINED)
-    opts = dict(precision=wwbi.FP32_REFINED, tol=1e-14, inner_tol=a.inner_tol,
+    # the paper's tolerance (Sec. 7.4): U on this near-overturning surface
+    # amplifies what the solve leaves in omega by up to about 3e4
+    opts = dict(precision=wwbi.FP32_REFINED, tol=1e-15, inner_tol=a.inner_tol,
                 matvec=wwbi.MATVEC_STORED, restart=120, poll_every=a.poll)
     inputs = []
     for s in range(4):
@@ -357,7 +359,7 @@ def run_large(a):
         "adjoint_iters": [r["iters"] for r in ad],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(TRAFFIC_FILE_LARGE),
-                     "kernel": "k_gemv<float,float,float,2,4,true,4> (stored FP32 matvec with the first Gram-Schmidt dots)",
+                     "kernel": "k_gemv<float,float,double,2,4,true,4> (stored FP32 matvec, FP64 accumulation, with the first Gram-Schmidt dots)",
                      "avg_launch_ms": avg, "launches": p["n_matvec"],
                      "bytes_per_launch": p["bytes_matvec"]},
         "cpu_baseline": None,
@@ -431,7 +433,7 @@ def run_adjoint(a):
     achieved = bytes_mv / (avg * 1e-3) / 1e9 if avg > 0 else 0.0
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-            "kernel": "k_gemv<float,float,float,2,4,true,4> (stored FP32 matvec with the first Gram-Schmidt dots, A and A^T)",
+            "kernel": "k_gemv<float,float,double,2,4,true,4> (stored FP32 matvec, FP64 accumulation, with the first Gram-Schmidt dots, A and A^T)",
             "avg_launch_ms": avg, "launches": nmv, "bytes_per_launch": bytes_mv}
 
     res = {}
@@ -530,7 +532,7 @@ def main():
     traffic = measured_traffic() if (a.config == 3 and a.mode == "stored") else None
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-            "kernel": "k_gemv<float,float,float,2,4,true,4> (stored FP32 matvec with the first Gram-Schmidt dots)",
+            "kernel": "k_gemv<float,float,double,2,4,true,4> (stored FP32 matvec, FP64 accumulation, with the first Gram-Schmidt dots)",
             "avg_launch_ms": avg, "launches": nmv, "bytes_per_launch": bytes_mv}
 
     cpu = None

@@ -147,7 +147,7 @@ typedef struct {
                               for other entry points)                                   */
 } wwbi_report;
 
-/* Fill *o with defaults: tol 1e-13, inner_tol 3e-7, restart 100, max_iter 2000,
+/* Fill *o with defaults: tol 1e-13, inner_tol 1e-7, restart 100, max_iter 2000,
  * FP64, stored matvec, poll every 2 steps, max_refine 8, band 16, no flags. */
 void wwbi_default_opts(wwbi_opts *o);
 

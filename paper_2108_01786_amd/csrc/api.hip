@@ -50,9 +50,8 @@ int Ctx::ws_plan(int n, int restart, WsItem *it, bool recycle) {
     int k = 0;
     auto D = [&](double *&p, size_t &c, size_t w) { it[k++] = WsItem{(void **)&p, &c, w, 8}; };
     auto I = [&](int *&p, size_t &c, size_t w) { it[k++] = WsItem{(void **)&p, &c, w, 4}; };
-    auto Fl = [&](float *&p, size_t &c, size_t w) { it[k++] = WsItem{(void **)&p, &c, w, 4}; };
     D(V, capV, (pre + rr + 1) * nn);
-    Fl(v32, capv32, nn);
+    it[k++] = WsItem{(void **)&v32, &capv32, nn, 4};   // FP32 copy of the newest basis vector
     for (int i = 0; i < kNumVec; ++i) D(vec[i], capvec[i], nn);
     D(H, capH, (rr + 1) * (rr + 1));
     D(cs, capcs, rr + 1);
@@ -145,10 +144,10 @@ void Ctx::release() {
     cappw = 0;
     F(hsum);
     F(V);
+    F(v32);
     F(Urec);
     F(Brec);
     vpre = 0;
-    F(v32);
     for (int i = 0; i < kNumVec; ++i) F(vec[i]);
     F(H); F(cs); F(sn); F(gv); F(yv); F(P); F(part);
     F(bid); F(loc); F(Mk); F(wq); F(s); F(lre); F(lim); F(rowD); F(rowH); F(val); F(apart);
@@ -245,10 +244,12 @@ void Ctx::apply(const Op &op, const double *x, const float *x32, const double *c
     case OP_A_S32:
     case OP_GT_S32:
     case OP_W_S32:
-        if (x32)
-            launch_gemv32((const float *)A, ld, op.n, x32, c, y, active, stream);
-        else
-            launch_gemv32_x64((const float *)A, ld, op.n, x, c, y, active, stream);
+        // FP32 products read x in FP32 (the caller's copy, or one made here)
+        if (!x32) {
+            launch_to_f32(x, v32, op.n, stream);
+            x32 = v32;
+        }
+        launch_gemv32((const float *)A, ld, op.n, x32, c, y, active, stream);
         break;
     case OP_A_O64:
         launch_otf_matvec(L, N, op.flags, 0, op.band, 0, x, c, y, part, active, stream);
@@ -344,7 +345,7 @@ void Ctx::prof_end() {
 // memory: the host sees the end without a queued copy, and steps enqueued
 // after it return at once on the device flag.
 int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol, int restart,
-               int max_iter, int poll, bool fp32_basis, bool verify, SolveStats &st, int kc) {
+               int max_iter, int poll, bool verify, SolveStats &st, int kc) {
     const int n = op.n;
     const int G = gmres_nblocks(n);
     const int ldp = restart + 1 + vpre;    // rows of Gram-Schmidt partials (recycled ones too)
@@ -352,11 +353,13 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
     double *r = vec[VR], *w = vec[VW];
     double *P1 = P, *P2 = P + 64 * ldp, *P3 = P + 2 * 64 * ldp;   // P[i*G + b] layout
     const int NB = gemv_partials(n);
-    float *x32 = fp32_basis ? v32 : nullptr;
     // the Arnoldi basis, and in front of it the kc recycled vectors C
     double *Vb = V + (long)vpre * ldv;
     double *Cb = Vb - (long)kc * ldv;
     double *Bm = Brec, *zc = Brec + (long)kRecycleMax * (restart + 1);
+    // stored FP32 products read the newest basis vector's FP32 copy, written
+    // by the kernel that forms the vector
+    float *x32 = stored_fp32(op.kind) ? v32 : nullptr;
     // the inner solves of the refinement (the only callers without the
     // true-residual check) orthogonalise once; every other solve twice
     const bool single_pass = !verify;
@@ -425,7 +428,7 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
                 // steps on a stored matrix take the first Gram-Schmidt dots in the
                 // product's epilogue (one partial per product block), for up to
                 // 64 rows (the recycled ones included)
-                const bool fuse32 = single_pass && x32 && stored_fp32(op.kind) && kc + j < 64;
+                const bool fuse32 = single_pass && stored_fp32(op.kind) && kc + j < 64;
                 const bool fuse64 = !single_pass && stored_fp64(op.kind) && j < 64;
                 prof_begin();
                 if (fuse32)
@@ -492,9 +495,12 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
 }
 
 // Tolerance of an inner FP32 solve: o.inner_tol (the contraction the FP32
-// operator supports), loosened when the residual is already close to the
-// target -- a correction only needs to gain the remaining factor (with a 3x
-// margin), which keeps the last refinement step short.
+// operator supports: FP32 entries and vector, FP64 accumulation), loosened
+// when the residual is already close to the target -- a correction only needs
+// to gain the remaining factor (with a 3x margin), which keeps the last
+// refinement step short.
+constexpr double kMulti32Floor = 3e-7;
+
 double inner_tolerance(const wwbi_opts &o, double bnorm, double rnorm) {
     const double need = rnorm > 0 ? 0.3 * o.tol * bnorm / rnorm : 1.0;
     return std::min(0.1, std::max(o.inner_tol, need));
@@ -601,8 +607,7 @@ int Ctx::refine(const Op &op32, const Op &op64, const double *b, double *x, bool
         // for the cold step rn = ||b||, where the inner tolerance does not depend on ||b||
         const double itol = cold ? inner_tolerance(o, 1.0, 1.0) : inner_tolerance(o, bn, rn);
         const int rc = gmres(op32, cold ? b : r, cold ? x : d, true, itol, o.restart,
-                             o.max_iter - st.iters, o.poll_every, stored_fp32(op32.kind), false,
-                             in, kc);
+                             o.max_iter - st.iters, o.poll_every, false, in, kc);
         if (rc < 0) return rc;
         inner_pending = true;
         st.cycles += in.cycles;
@@ -917,8 +922,11 @@ int Ctx::refine_multi(int n, long ld, const double *B, double *X, int nr, const 
         for (int s = 0; s < nr; ++s)
             if (bnrm[s] > 0 && rn[s] > o.tol * bnrm[s])
                 itol = std::max(itol, inner_tolerance(o, bnrm[s], rn[s]));
-        rc = gmres_multi(OP_A_S32, n, ld, m.rr, m.d, nr, itol > 0 ? itol : o.inner_tol, o.restart,
-                         o.max_iter, o.poll_every, false, in);
+        // the matrix-core products accumulate in FP32, which holds their
+        // contraction near kMulti32Floor
+        itol = std::max(itol > 0 ? itol : o.inner_tol, kMulti32Floor);
+        rc = gmres_multi(OP_A_S32, n, ld, m.rr, m.d, nr, itol, o.restart, o.max_iter,
+                         o.poll_every, false, in);
         if (rc < 0) return rc;
         st.iters = in.iters;
         st.cycles += in.cycles;
@@ -940,7 +948,7 @@ void wwbi_default_opts(wwbi_opts *o) {
     if (!o) return;
     std::memset(o, 0, sizeof(*o));
     o->tol = 1e-13;
-    o->inner_tol = 3e-7;
+    o->inner_tol = 1e-7;
     o->restart = 100;
     o->max_iter = 2000;
     o->precision = WWBI_FP64;
@@ -1082,8 +1090,7 @@ int solve_phi_impl(Ctx *c, const wwbi_geom *g, const double *phi, const wwbi_opt
     int status;
     double bytes;
     if (!fp32) {
-        status = c->gmres(op64, b, x, xz, o->tol, o->restart, o->max_iter, o->poll_every, false,
-                          true, st);
+        status = c->gmres(op64, b, x, xz, o->tol, o->restart, o->max_iter, o->poll_every, true, st);
         bytes = c->op_bytes(op64);
     } else {
         Op op32{stored ? OP_A_S32 : OP_A_O32, n, ld, o->flags, o->band};
@@ -1196,7 +1203,7 @@ int wwbi_solve_gamma(wwbi_ctx *ctx, const wwbi_geom *g, const double *gamma0, co
         const Op op64{OP_W_O64, nw, ldw, o->flags, o->band};
         status = c->refine(op, op64, rhs, gw, xz, *o, st);
     } else {
-        status = c->gmres(op, rhs, gw, xz, o->tol, o->restart, o->max_iter, o->poll_every, false,
+        status = c->gmres(op, rhs, gw, xz, o->tol, o->restart, o->max_iter, o->poll_every,
                           true, st);
     }
     hipEventRecord(c->ev[3], c->stream);
@@ -1352,8 +1359,7 @@ int wwbi_solve_gamma_t(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi, con
         const Op op64{OP_GT_O64, n, ld, o->flags, o->band};
         status = c->refine(op, op64, b, x, true, *o, st);
     } else {
-        status = c->gmres(op, b, x, true, o->tol, o->restart, o->max_iter, o->poll_every, false,
-                          true, st);
+        status = c->gmres(op, b, x, true, o->tol, o->restart, o->max_iter, o->poll_every, true, st);
     }
     hipEventRecord(c->ev[3], sm);
     if (status < 0) { c->finish_report(rep, status, st, c->op_bytes(op)); return status; }
@@ -1704,7 +1710,7 @@ int wwbi_pressure(wwbi_ctx *ctx, const wwbi_geom *g, const double *phi, double t
     Op op64{stored ? OP_A_S64 : OP_A_O64, n, ld, o->flags, o->band};
     int status;
     if (!fp32) {
-        status = c->gmres(op64, b, x, true, o->tol, o->restart, o->max_iter, o->poll_every, false,
+        status = c->gmres(op64, b, x, true, o->tol, o->restart, o->max_iter, o->poll_every,
                           true, st);
     } else {
         Op op32{stored ? OP_A_S32 : OP_A_O32, n, ld, o->flags, o->band};
@@ -1813,7 +1819,7 @@ int wwbi_adjoint_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, con
     if (!fp32) {
         // the stored operator is A^T itself: the forward product applies it
         Op op{stored ? OP_A_S64 : OP_AT_O64, n, ld, o->flags, o->band};
-        status = c->gmres(op, mu, lam, xz, o->tol, o->restart, o->max_iter, o->poll_every, false,
+        status = c->gmres(op, mu, lam, xz, o->tol, o->restart, o->max_iter, o->poll_every,
                           true, st);
         bytes = c->op_bytes(op);
     } else {
@@ -2046,13 +2052,8 @@ int wwbi_matvec(wwbi_ctx *ctx, const wwbi_geom *g, const double *x, double *y, i
     else
         kind = transpose ? (fp32 ? OP_AT_O32 : OP_AT_O64) : (fp32 ? OP_A_O32 : OP_A_O64);
     Op op{kind, n, ld, 0, band};
-    float *x32 = nullptr;
-    if (kind == OP_A_S32) {
-        x32 = c->v32;
-        launch_to_f32(xw, x32, n, c->stream);
-    }
     c->prof_begin();
-    c->apply(op, xw, x32, nullptr, yw, nullptr);
+    c->apply(op, xw, nullptr, nullptr, yw, nullptr);
     c->prof_end();
     hipEventRecord(c->ev[3], c->stream);
     launch_copy(y, yw, n, c->stream);

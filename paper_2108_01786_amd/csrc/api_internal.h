@@ -106,9 +106,9 @@ struct Ctx {
     double *A64 = nullptr;  size_t capA64 = 0;   // FP64 copy beside an FP32 A (multi refine)
     double *V = nullptr;    size_t capV = 0;      // vpre recycled rows, then the basis
     int vpre = 0;
+    float *v32 = nullptr;   size_t capv32 = 0;
     double *Urec = nullptr; size_t capUrec = 0;   // U of the recycled space (A U = C)
     double *Brec = nullptr; size_t capBrec = 0;   // B (kRecycleMax x restart) | z
-    float *v32 = nullptr;   size_t capv32 = 0;
     double *vec[kNumVec] = {};  size_t capvec[kNumVec] = {};
     double *H = nullptr;    size_t capH = 0;
     double *cs = nullptr;   size_t capcs = 0;
@@ -184,6 +184,7 @@ struct Ctx {
     int ensure_matrix64(size_t bytes);
     void release();
     int setup(const wwbi_geom *g, const double *phi, int nphi);
+    // x32 (may be null): an FP32 copy of x for the stored FP32 operators
     void apply(const Op &op, const double *x, const float *x32, const double *c, double *y,
                const int *active);
     double op_bytes(const Op &op) const;
@@ -196,7 +197,7 @@ struct Ctx {
     // kc > 0: deflate the kc recycled vectors in front of the basis (one
     // cycle, no verification, x = the solution from zero)
     int gmres(const Op &op, const double *b, double *x, bool x_zero, double tol, int restart,
-              int max_iter, int poll, bool fp32_basis, bool verify, SolveStats &st, int kc = 0);
+              int max_iter, int poll, bool verify, SolveStats &st, int kc = 0);
     double device_norm(const double *v, int n);
     int refine(const Op &op32, const Op &op64, const double *b, double *x, bool x_zero,
                const wwbi_opts &o, SolveStats &st);

@@ -259,25 +259,24 @@ void launch_assemble_wall32(const Layout &L, const Nodes &N, const double *hrow,
 // the normal-velocity map T (surface rows, all columns), FP64
 void launch_assemble_T64(const Layout &L, const Nodes &N, const double *hrow, double *T, long ld,
                          hipStream_t st);
-// y = c - A x, or y = A x when c is null
+// y = c - A x, or y = A x when c is null, accumulated in FP64 for either
+// matrix type (FP32 entries and x widened one by one)
 void launch_gemv64(const double *A, long ld, int n, const double *x, const double *c, double *y,
                    const int *active, hipStream_t st);
 void launch_gemv32(const float *A, long ld, int n, const float *x, const double *c, double *y,
                    const int *active, hipStream_t st);
 // Number of per-block partials of the fused Arnoldi product below.
 int gemv_partials(int n);
-// y = A x (FP32 matrix and x, FP32 accumulation) fused with the first
+// y = A x (FP32 matrix and x, FP64 accumulation) fused with the first
 // Gram-Schmidt dots: P[i * gemv_partials(n) + b] (i <= j < 64) and the squared
 // norm partials P3[b] of y, per block b, summed later in a fixed order.
 void launch_gemv32_dots(const float *A, long ld, int n, const float *x, double *y,
                         const int *active, const double *V, long ldv, int j, double *P,
                         double *P3, hipStream_t st);
-// the same for an FP64 matrix (FP64 accumulation)
+// the same for an FP64 matrix
 void launch_gemv64_dots(const double *A, long ld, int n, const double *x, double *y,
                         const int *active, const double *V, long ldv, int j, double *P,
                         double *P3, hipStream_t st);
-void launch_gemv32_x64(const float *A, long ld, int n, const double *x, const double *c,
-                       double *y, const int *active, hipStream_t st);
 void launch_otf_matvec(const Layout &L, const Nodes &N, int flags, int fp32, int band,
                        int transpose, const double *x, const double *c, double *y, double *part,
                        const int *active, hipStream_t st);

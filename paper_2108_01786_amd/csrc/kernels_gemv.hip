@@ -60,7 +60,10 @@ struct GemvDots {
 };
 
 // y = c - A x (or A x): each wave owns R rows and walks them in steps of
-// 64 lanes x 16 bytes, U steps in flight; FP32 matrices accumulate in FP32.
+// 64 lanes x 16 bytes, U steps in flight, every product accumulated in TACC.
+// An FP32 matrix (and FP32 x) accumulates in FP64: the accumulation then adds
+// no error that grows with the row length, and a product's error is set by
+// the FP32 entries and vector alone.
 template <typename TA, typename TX, typename TACC, int R, int U, bool DOTS = false, int WPB = 4>
 __global__ __launch_bounds__(64 * WPB) void k_gemv(const TA *__restrict__ A, long ld, int n,
                                               const TX *__restrict__ x,
@@ -171,12 +174,6 @@ void launch_gemv64(const double *A, long ld, int n, const double *x, const doubl
                        dim3(gemv_blocks(n, kGemvR)), dim3(256), 0, st, A, ld, n, x, c, y, active);
 }
 
-void launch_gemv32(const float *A, long ld, int n, const float *x, const double *c, double *y,
-                   const int *active, hipStream_t st) {
-    hipLaunchKernelGGL((k_gemv<float, float, float, kGemvR, kGemvU>),
-                       dim3(gemv_blocks(n, kGemvR)), dim3(256), 0, st, A, ld, n, x, c, y, active);
-}
-
 // waves per block of the fused product (8, with half the partials, streamed
 // slower: 70.9 against 65 us per launch at n = 10240)
 constexpr int kDotsWaves = 4;
@@ -186,7 +183,7 @@ int gemv_partials(int n) { return cdiv(cdiv(n, kGemvR), kDotsWaves); }
 void launch_gemv32_dots(const float *A, long ld, int n, const float *x, double *y,
                         const int *active, const double *V, long ldv, int j, double *P,
                         double *P3, hipStream_t st) {
-    hipLaunchKernelGGL((k_gemv<float, float, float, kGemvR, kGemvU, true, kDotsWaves>),
+    hipLaunchKernelGGL((k_gemv<float, float, double, kGemvR, kGemvU, true, kDotsWaves>),
                        dim3(gemv_partials(n)), dim3(64 * kDotsWaves), 0, st, A, ld, n, x, nullptr,
                        y, active, GemvDots{V, ldv, j, P, P3});
 }
@@ -199,9 +196,9 @@ void launch_gemv64_dots(const double *A, long ld, int n, const double *x, double
                        nullptr, y, active, GemvDots{V, ldv, j, P, P3});
 }
 
-void launch_gemv32_x64(const float *A, long ld, int n, const double *x, const double *c,
-                       double *y, const int *active, hipStream_t st) {
-    hipLaunchKernelGGL((k_gemv<float, double, float, kGemvR, kGemvU>),
+void launch_gemv32(const float *A, long ld, int n, const float *x, const double *c, double *y,
+                   const int *active, hipStream_t st) {
+    hipLaunchKernelGGL((k_gemv<float, float, double, kGemvR, kGemvU>),
                        dim3(gemv_blocks(n, kGemvR)), dim3(256), 0, st, A, ld, n, x, c, y, active);
 }
 

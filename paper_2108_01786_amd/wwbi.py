@@ -230,7 +230,7 @@ class DeviceGeometry:
         return g
 
 
-def make_opts(tol=1e-13, inner_tol=3e-7, restart=100, max_iter=2000, precision=FP64,
+def make_opts(tol=1e-13, inner_tol=1e-7, restart=100, max_iter=2000, precision=FP64,
               matvec=MATVEC_AUTO, poll_every=2, max_refine=8, band=16, flags=0,
               x0: Optional[torch.Tensor] = None) -> _Opts:
     o = _Opts()

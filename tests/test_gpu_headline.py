@@ -50,7 +50,7 @@ def rel(a, b):
 def _opts(ww, prec, mode):
     mv = ww.MATVEC_STORED if mode == "stored" else ww.MATVEC_ON_THE_FLY
     if prec in ("refined", "refined-norecycle"):
-        return dict(precision=ww.FP32_REFINED, tol=1e-14, inner_tol=3e-7, matvec=mv, restart=100,
+        return dict(precision=ww.FP32_REFINED, tol=1e-14, inner_tol=1e-7, matvec=mv, restart=100,
                     poll_every=2, flags=ww.FLAG_NO_RECYCLE if prec == "refined-norecycle" else 0)
     return dict(precision=ww.FP64, tol=1e-13, matvec=mv, restart=100, poll_every=2)
 
