@@ -128,6 +128,7 @@ typedef struct {
 } wwbi_opts;
 
 #define WWBI_MAX_RESTART 256
+#define WWBI_HIST_MAX 32
 
 typedef struct {
     int32_t status;
@@ -145,6 +146,14 @@ typedef struct {
                               times the largest mean square of omega on any boundary
                               (Parseval: the tail's share at the solution's scale; 0
                               for other entry points)                                   */
+    int32_t n_hist;        /* entries of resid_hist written (at most WWBI_HIST_MAX)       */
+    int32_t pad1;
+    double resid_hist[WWBI_HIST_MAX];
+                           /* ||b - A x|| / ||b|| in the order measured: at the start of
+                              every restart cycle of an FP64 GMRES solve (the true
+                              residual) and after every step of an iterative refinement
+                              (the FP64 residual; the largest over the systems of a
+                              multi-RHS solve); the first WWBI_HIST_MAX values          */
 } wwbi_report;
 
 /* Fill *o with defaults: tol 1e-13, inner_tol 1e-7, restart 100, max_iter 2000,
@@ -167,8 +176,13 @@ int wwbi_destroy(wwbi_ctx *ctx);
 
 /* Pre-size the workspace for up to `max_unknowns` nodes, restart length
  * `max_restart`, and a stored matrix of the given precision (WWBI_FP64 or
- * WWBI_FP32_REFINED; -1 = no stored matrix).  Optional: solves grow the
- * workspace on demand. */
+ * WWBI_FP32_REFINED; -1 = no stored matrix).  Optional: a solve allocates
+ * (hipMalloc, after freeing a smaller buffer) every part of the workspace
+ * that is missing or too small for it, inside the call; after wwbi_reserve
+ * for the largest problem, solves of that size or smaller allocate nothing,
+ * except the FP64 matrix copy of a refined multi-RHS solve
+ * (wwbi_solve_phi_multi).  For no allocation at all, see
+ * wwbi_solve_phi_noalloc. */
 int wwbi_reserve(wwbi_ctx *ctx, int64_t max_unknowns, int32_t max_restart, int32_t precision);
 
 /* Velocity-potential solve (Sec. 3.2-3.4).
@@ -392,16 +406,18 @@ int wwbi_adjoint_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, con
 /* Several right-hand sides against one matrix: solves A omega_i = rhs_i,
  * i < n, with the matrix read once per Arnoldi step for all i (matrix-core
  * product).  rhs, omega: (device) sum(M) x n, column i at offset i*sum(M).
- * With WWBI_FP32_REFINED the context also holds an FP64 copy of the matrix
- * (8 bytes per entry beside the FP32 one), from which the residuals of all
- * systems are formed in one pass; when that copy cannot be allocated they are
- * formed on the fly, one system at a time.
+ * With WWBI_FP32_REFINED the context also allocates and assembles an FP64
+ * copy of the matrix (8 bytes per entry beside the FP32 one: 839 MB at 10240
+ * unknowns, 13.4 GB at 40960), kept until wwbi_destroy, from which the
+ * residuals of all systems are formed in one matrix-core pass; when that copy
+ * cannot be allocated they are formed on the fly, one system at a time.
+ * report.bytes_matvec counts the FP32 matrix of the inner products.
  * Errors: WWBI_EINVAL_OPTS for n outside 1..32, an on-the-fly matvec or a
  * warm start; WWBI_EINVAL_NONFINITE for a non-finite right-hand side entry
  * (omega untouched); the geometry is checked as for wwbi_solve_phi.
  * The lockstep path pays off from a few systems on; a single system solves
- * faster through wwbi_solve_phi (at 10240 unknowns, refined: 3.9 ms against
- * 5.9 ms here; 32 systems take 8.5 ms here). */
+ * faster through wwbi_solve_phi (at 10240 unknowns, refined: 3.3 ms against
+ * 5.9 ms here; 32 systems take 8.9 ms here). */
 int wwbi_solve_phi_multi(wwbi_ctx *ctx, const wwbi_geom *g, const double *rhs, int32_t n,
                          const wwbi_opts *o, double *omega, wwbi_report *rep);
 

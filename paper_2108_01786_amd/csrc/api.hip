@@ -404,6 +404,7 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
             its_seen = h.its;
             st.iters = its0 + h.its;
             st.rel_resid = h.bnorm > 0 ? h.beta / h.bnorm : 0.0;
+            note_resid(st.rel_resid);
             if (trace)
                 std::fprintf(stderr, "wwbi: op %d n %d cycle %d its %d beta/bnorm %.3e\n",
                              op.kind, n, st.cycles, st.iters, st.rel_resid);
@@ -592,6 +593,7 @@ int Ctx::refine(const Op &op32, const Op &op64, const double *b, double *x, bool
         }
         if (!cold) {
             st.rel_resid = bn > 0 ? rn / bn : 0.0;
+            note_resid(st.rel_resid);
             if (trace)
                 std::fprintf(stderr, "wwbi: refine step %d its %d rel_resid %.3e\n", k,
                              st.iters, st.rel_resid);
@@ -649,6 +651,7 @@ void Ctx::begin_report(bool prof) {
     profiling = prof;
     nprof = 0;
     cyc_done.clear();
+    hist.clear();
     cur_cycle = -1;
     cur_step = 0;
     hipEventRecord(ev[0], stream);
@@ -690,6 +693,8 @@ void Ctx::finish_report(wwbi_report *rep, int status, const SolveStats &st, doub
     rep->n_matvec = cnt;
     rep->ms_matvec = t;
     rep->bytes_matvec = bytes;
+    rep->n_hist = (int32_t)std::min<size_t>(hist.size(), WWBI_HIST_MAX);
+    for (int i = 0; i < rep->n_hist; ++i) rep->resid_hist[i] = hist[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -912,6 +917,7 @@ int Ctx::refine_multi(int n, long ld, const double *B, double *X, int nr, const 
                       (k > 0 && rel > o.tol && rn[s] > 0.5 * prev[s]);
         }
         st.rel_resid = worst;
+        note_resid(worst);
         if (done) { status = WWBI_OK; break; }
         if (stalled) { status = WWBI_REFINE_STALLED; break; }
         if (k >= o.max_refine || st.iters >= o.max_iter) { status = WWBI_NOT_CONVERGED; break; }
@@ -990,6 +996,7 @@ int wwbi_create(wwbi_ctx **out, int32_t device, void *stream) {
     c->stream = (hipStream_t)stream;
     // the per-cycle bookkeeping never grows inside a solve of up to 4096 cycles
     c->cyc_done.reserve(4096);
+    c->hist.reserve(WWBI_HIST_MAX);
     // device address of the allocation-free entry point's static scratch array
     scratch_init(device);
     int rc = WWBI_OK;

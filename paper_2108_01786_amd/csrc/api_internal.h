@@ -164,6 +164,12 @@ struct Ctx {
     int prof_cycle[kProfPairs] = {};
     int prof_step[kProfPairs] = {};
     std::vector<int> cyc_done;   // completed steps per cycle, -1 while unknown
+    // relative residuals for wwbi_report.resid_hist (capacity reserved at
+    // creation; values past it are dropped, never reallocated)
+    std::vector<double> hist;
+    void note_resid(double r) {
+        if (hist.size() < hist.capacity()) hist.push_back(r);
+    }
     int cur_cycle = -1;
     int cur_step = 0;
     int last_cycle = -1;

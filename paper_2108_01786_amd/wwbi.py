@@ -51,10 +51,19 @@ class Report(C.Structure):
                 ("ms_prep", C.c_double), ("ms_assemble", C.c_double), ("ms_solve", C.c_double),
                 ("ms_U", C.c_double), ("ms_total", C.c_double), ("n_matvec", C.c_int32),
                 ("pad0", C.c_int32), ("ms_matvec", C.c_double), ("bytes_matvec", C.c_double),
-                ("tail_ratio", C.c_double)]
+                ("tail_ratio", C.c_double), ("n_hist", C.c_int32), ("pad1", C.c_int32),
+                ("resid_hist", C.c_double * 32)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad0"}
+        d = {k: getattr(self, k) for k, _ in self._fields_
+             if k not in ("pad0", "pad1", "resid_hist")}
+        d["resid_hist"] = self.history()
+        return d
+
+    def history(self):
+        """The relative residuals the solve measured (cycle starts of an FP64
+        solve, refinement steps of a refined one), in order."""
+        return [self.resid_hist[i] for i in range(max(0, min(self.n_hist, 32)))]
 
 
 _SIGS = {

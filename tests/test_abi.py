@@ -52,4 +52,4 @@ def test_struct_layouts_match_header():
     """ctypes mirrors of the option and report structs have the C sizes."""
     from paper_2108_01786_amd import wwbi
     assert ctypes.sizeof(wwbi._Opts) == 8 + 8 + 4 * 8 + 8
-    assert ctypes.sizeof(wwbi.Report) == 4 * 4 + 8 * 6 + 4 * 2 + 8 * 3
+    assert ctypes.sizeof(wwbi.Report) == 4 * 4 + 8 * 6 + 4 * 2 + 8 * 3 + 4 * 2 + 8 * 32

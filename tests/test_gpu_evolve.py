@@ -1,6 +1,9 @@
 """One Runge-Kutta stage and one step of the free-surface evolution (graph
 and HLS surfaces, Sec. 2, 3.5, 5) on the device against the oracle, whose
 stage is pinned by energy conservation and the HLS kinematics."""
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -77,9 +80,10 @@ def _rk4():
 
 
 def _dop853():
-    from scipy.integrate._ivp import dop853_coefficients as d
-    n = d.N_STAGES
-    return np.array(d.A[:n, :n], dtype=np.float64), np.array(d.B[:n], dtype=np.float64)
+    """The DOP853 tableau stored as data (tests/golden/dop853_tableau.json)."""
+    d = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                    "dop853_tableau.json")))
+    return np.array(d["A"], dtype=np.float64), np.array(d["b"], dtype=np.float64)
 
 
 @pytest.mark.parametrize("mode,tab", [("graph", "rk4"), ("hls", "rk4"), ("hls", "dop853")])

@@ -446,3 +446,25 @@ def test_T_matrix_entrywise(ww, ctx, name):
     # T v for a seeded v against the oracle's product
     v = np.random.default_rng(3).standard_normal(geom.Mtot)
     assert rel(T @ v, Tr @ v) <= 1e-13
+
+
+def test_report_residual_history(ww, ctx):
+    """report.resid_hist: the true residual at every cycle start of an FP64
+    solve (restart 7: several cycles, decreasing, the last the reported
+    rel_resid) and the FP64 residual after every refinement step."""
+    say("case report residual history")
+    cfg = make_config(1)
+    dg = ww.DeviceGeometry.from_synth(cfg["geom"], DEV)
+    phi = torch.as_tensor(cfg["phi"], device=DEV)
+    _, _, _, rep = ctx.solve_phi(dg, phi, tol=1e-13, restart=7)
+    h = rep.history()
+    say(f"  fp64 restarts {rep.restarts}: {['%.1e' % v for v in h]}")
+    assert rep.status == 0 and len(h) == min(32, rep.restarts + 1)
+    assert h[0] == 1.0 and h[-1] == rep.rel_resid and h[-1] <= 1e-13
+    assert all(b < a for a, b in zip(h, h[1:]))
+    _, _, _, rep = ctx.solve_phi(dg, phi, tol=1e-14, precision=ww.FP32_REFINED)
+    h = rep.history()
+    say(f"  refined steps {rep.refine_steps}: {['%.1e' % v for v in h]}")
+    assert rep.status == 0 and len(h) == rep.refine_steps
+    assert h[-1] == rep.rel_resid and h[-1] <= 1e-14
+    assert all(b < a for a, b in zip(h, h[1:]))
