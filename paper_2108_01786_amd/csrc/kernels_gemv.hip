@@ -94,21 +94,23 @@ __global__ __launch_bounds__(64 * WPB) void k_gemv(const TA *__restrict__ A, lon
     for (int r = 0; r < R; ++r) acc[r] = (TACC)0;
     const int nbig = r0 < n ? (n / (STEP * U)) * (STEP * U) : 0;
     for (int c0 = 0; c0 < nbig; c0 += STEP * U) {
+        // every load of the U steps is issued before any value is converted
+        // or used, so that all of them are in flight together
         V a[U][R];
-        TACC xv[U][VW];
+        TX xv[U][VW];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int col = c0 + u * STEP + lane * VW;
 #pragma unroll
             for (int r = 0; r < R; ++r) a[u][r] = stream_load(rowp[r] + col);
-            load_x<TACC, TX, VW>(x, col, xv[u]);
+            load_x<TX, TX, VW>(x, col, xv[u]);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
 #pragma unroll
             for (int r = 0; r < R; ++r)
 #pragma unroll
-                for (int v = 0; v < VW; ++v) acc[r] += (TACC)a[u][r][v] * xv[u][v];
+                for (int v = 0; v < VW; ++v) acc[r] += (TACC)a[u][r][v] * (TACC)xv[u][v];
     }
     const int nstep = r0 < n ? (n / STEP) * STEP : 0;
     for (int c0 = nbig; c0 < nstep; c0 += STEP) {
