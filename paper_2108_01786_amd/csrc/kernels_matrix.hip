@@ -435,6 +435,88 @@ __device__ __forceinline__ bool cells_far(const Nodes &N, int pa, int pb, int qa
     return true;
 }
 
+// FP64 assembly of A.  One column per thread and kRowsPerAsm64 rows per
+// block, as in the FP32 far pass.  A wave whose live columns lie on one
+// boundary, in a block whose rows lie on one boundary, clear of the
+// same-boundary band and, by the 64-node cells' E discs, of every near pair,
+// takes the E quotient with one entry formula for the whole tile: the source
+// data pre-scaled (a = w dx / 2, b = w dy / 2), the reciprocal of |D|^2 from
+// the FP32 estimate refined twice, and E's trailing parts only where the
+// discs come within |E| / 4 (cells_far).  Every other wave takes a_val64,
+// the full entry (band, near pairs, diagonal limits).
+constexpr int kRowsPerAsm64 = 32;
+
+template <int KIND, bool LO>
+__device__ __forceinline__ double a_fast64(const Tgt &t, const Src &s, double fa, double fb,
+                                           double ec) {
+    const double dr = LO ? (s.ex - t.ex) + (s.exl - t.exl) : s.ex - t.ex;
+    const double di = LO ? (s.ey - t.ey) + (s.eyl - t.eyl) : s.ey - t.ey;
+    const double nr = s.ex + t.ex, ni = s.ey + t.ey;
+    const double inv = recip64_from32(dr * dr + di * di);
+    const double pr = nr * dr + ni * di;
+    const double pi = ni * dr - nr * di;
+    if (KIND == kFastReNeg) return -(fa * pi + fb * pr) * inv;
+    if (KIND == kFastRePos) return (fa * pi + fb * pr) * inv;
+    return (fa * pr - fb * pi) * inv - ec;
+}
+
+template <int KIND, bool LO>
+__device__ __forceinline__ void asm64_tile(const Tgt *tg, int rend, const Src &s, double fa,
+                                           double fb, double ec, bool live, double *o, long ld) {
+    for (int i = 0; i < rend; ++i)
+        __builtin_nontemporal_store(live ? a_fast64<KIND, LO>(tg[i], s, fa, fb, ec) : 0.0,
+                                    o + i * ld);
+}
+
+__global__ __launch_bounds__(256) void k_assemble64(Nodes N, int n, int corr, double *out,
+                                                    long ld) {
+    __shared__ Tgt tg[kRowsPerAsm64];
+    const int wb = wave_base();
+    const int col = blockIdx.x * 256 + threadIdx.x;
+    const int rbase = blockIdx.y * kRowsPerAsm64;
+    if (threadIdx.x < kRowsPerAsm64) {
+        const int r = rbase + threadIdx.x;
+        if (r < n) tg[threadIdx.x] = load_tgt(N, r);
+    }
+    __syncthreads();
+    if (col >= ld) return;
+    const bool live = col < n;
+    const Src s = load_src(N, live ? col : 0);
+    const int rend = min(kRowsPerAsm64, n - rbase);
+    double *o = out + (long)rbase * ld + col;
+    // the wave's live columns [ca, cb] and the block's rows, each on one
+    // boundary, clear of the band and of near pairs (wave-uniform tests)
+    const int ca = blockIdx.x * 256 + wb, cb = min(ca + 63, n - 1);
+    const int re = rbase + rend - 1;
+    int kq = -1, kr = -1;
+    if (ca < n) {
+        kq = range_boundary(N, ca, cb);
+        kr = range_boundary(N, rbase, re);
+    }
+    bool fast = kq >= 0 && kr >= 0 && ranges_apart(N, rbase, re, ca, cb, kNearBand);
+    for (int a = rbase / kCellNodes; fast && a <= re / kCellNodes; ++a)
+        for (int b = ca / kCellNodes; fast && b <= cb / kCellNodes; ++b)
+            fast = !discs_may_be_near(N.cell + 4 * a, N.cell + 4 * b);
+    if (fast) {
+        const double fa = 0.5 * s.w * s.dx, fb = 0.5 * s.w * s.dy;
+        const double ec = (corr && kr == kq && kr >= 2) ? s.w : 0.0;
+        const bool lo = !cells_far(N, rbase, re, ca, cb);
+        if ((kr == 0) == (kq == 0)) {
+            if (lo) asm64_tile<kFastIm, true>(tg, rend, s, fa, fb, ec, live, o, ld);
+            else asm64_tile<kFastIm, false>(tg, rend, s, fa, fb, ec, live, o, ld);
+        } else if (kr == 0) {
+            if (lo) asm64_tile<kFastReNeg, true>(tg, rend, s, fa, fb, 0.0, live, o, ld);
+            else asm64_tile<kFastReNeg, false>(tg, rend, s, fa, fb, 0.0, live, o, ld);
+        } else {
+            if (lo) asm64_tile<kFastRePos, true>(tg, rend, s, fa, fb, 0.0, live, o, ld);
+            else asm64_tile<kFastRePos, false>(tg, rend, s, fa, fb, 0.0, live, o, ld);
+        }
+        return;
+    }
+    for (int i = 0; i < rend; ++i)
+        __builtin_nontemporal_store(live ? a_val64(N, tg[i], s, corr != 0) : 0.0, o + i * ld);
+}
+
 // Near pairs outside the band.  The far loops of the on-the-fly products
 // take kappa from the E quotient for every pair outside the same-boundary
 // band; a pair closer than |E_q - E_p| < max(|E_p|, |E_q|) / 64 (kappa64's
@@ -1015,9 +1097,9 @@ static int fix_blocks(int o, int n) { return (o + n - 1) / kCellNodes - o / kCel
 void launch_assemble64(const Layout &L, const Nodes &N, int flags, double *A, long ld,
                        hipStream_t st) {
     const int n = L.n;
-    dim3 grid(cdiv(ld, 256), cdiv(n, kRowsPerAsmBlock));
+    dim3 grid(cdiv(ld, 256), cdiv(n, kRowsPerAsm64));
     const int corr = (flags & WWBI_FLAG_NO_CORRECTION) ? 0 : 1;
-    hipLaunchKernelGGL(k_assemble<0>, grid, dim3(256), 0, st, N, nullptr, 0, n, 0, n, corr, A, ld);
+    hipLaunchKernelGGL(k_assemble64, grid, dim3(256), 0, st, N, n, corr, A, ld);
 }
 
 void launch_assemble32(const Layout &L, const Nodes &N, int flags, int band, float *A, long ld,
