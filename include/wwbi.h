@@ -403,6 +403,31 @@ int wwbi_adjoint_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, con
                      const wwbi_opts *o, double *g_phi, double *g_x, double *g_y, double *g_dx,
                      double *g_dy, double *g_ddx, double *g_ddy, wwbi_report *rep);
 
+/* Tangent-linear model of the velocity-potential solve (Sec. 3.2-3.4
+ * differentiated; the forward-mode counterpart of wwbi_adjoint_phi), walls
+ * fixed.  For nd directions of the surface's node data and phi~, the
+ * directional derivatives of U:
+ *   d omega_i = A^{-1} (dphi~_i e_0 - (dA_i) omega),
+ *   dU_i = (d u_mv + (dT_i) gamma + T d gamma_i + H d gamma_0,i / 2 - U ds_i) / s,
+ * with gamma = (-D omega_0, D omega_j).  The nd systems share A and are
+ * solved together by the multi-RHS solver (wwbi_solve_phi_multi's, with the
+ * matrix read once per Arnoldi step for all of them).
+ *   omega  (device) sum(M): the solution at this geometry and phi~ (from
+ *          wwbi_solve_phi); phi~ itself enters only through its directions.
+ *   nd     1..32 directions.
+ *   dirs   (device) 7 x nd x M_0: component c of direction i at offset
+ *          (c * nd + i) * M_0, the components being x, y, x', y', x'', y''
+ *          of the surface nodes and phi~ (a displacement of the surface
+ *          comes with its own derivatives x', x'', ...).
+ *   dU     (device) nd x M_0, direction i at offset i * M_0.
+ *   domega (device) nd x sum(M), or NULL.
+ * Options as for wwbi_solve_phi_multi (a stored matrix, no warm start).
+ * Errors: WWBI_EINVAL_OPTS for nd outside 1..32, an on-the-fly matvec or a
+ * warm start; WWBI_EINVAL_NONFINITE for a non-finite direction entry. */
+int wwbi_tangent_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, int32_t nd,
+                     const double *dirs, const wwbi_opts *o, double *dU, double *domega,
+                     wwbi_report *rep);
+
 /* Several right-hand sides against one matrix: solves A omega_i = rhs_i,
  * i < n, with the matrix read once per Arnoldi step for all i (matrix-core
  * product).  rhs, omega: (device) sum(M) x n, column i at offset i*sum(M).

@@ -1850,6 +1850,89 @@ int wwbi_adjoint_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, con
     return status;
 }
 
+int wwbi_tangent_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, int32_t nd,
+                     const double *dirs, const wwbi_opts *o, double *dU, double *domega,
+                     wwbi_report *rep) {
+    if (!ctx) return WWBI_EINVAL_NULL;
+    Ctx *c = reinterpret_cast<Ctx *>(ctx);
+    SolveStats st{};
+    int rc = Ctx::check_opts(o);
+    if (!rc && (!omega || !dirs || !dU)) rc = WWBI_EINVAL_NULL;
+    if (!rc && (nd < 1 || nd > kMaxMulti)) rc = WWBI_EINVAL_OPTS;
+    if (!rc && (o->matvec == WWBI_MATVEC_ON_THE_FLY || o->x0)) rc = WWBI_EINVAL_OPTS;
+    if (!rc && (!g || !g->M)) rc = WWBI_EINVAL_NULL;
+    if (!rc && (g->nb < 2 || g->nb > kMaxB || g->M[0] < 8)) rc = WWBI_EINVAL_SIZE;
+    if (!rc) {
+        c->restart_cap = std::max(c->restart_cap, o->restart);
+        c->begin_report((o->flags & WWBI_FLAG_PROFILE) != 0);
+        // the directions are checked for finite values with the geometry
+        rc = c->setup(g, dirs, 7 * nd * g->M[0]);
+    }
+    const int n = rc ? 0 : c->L.n, n0 = rc ? 0 : c->L.off[1];
+    const int nsr = rc ? 0 : adjoint_nsplit(n), nsc = rc ? 0 : tlm_nsplit(n0);
+    if (!rc) rc = c->ensure_multi(n, nd, o->restart);
+    if (!rc)
+        rc = grow(c->apart, c->capapart,
+                  (size_t)6 * nsr * n0 + (size_t)nsc * nd * (n + n0) + (size_t)nd * n0 + 64);
+    if (rc) {
+        if (rep) { std::memset(rep, 0, sizeof(*rep)); rep->status = rc; }
+        return rc;
+    }
+    hipStream_t sm = c->stream;
+    const long ld = round_up(n, 64), ldv = ld;
+    double *gam = c->vec[VG], *U = c->vec[VTMP2], *dg = c->vec[VTMP], *hg = c->vec[VHG];
+    double *prow = c->apart, *pA = prow + (size_t)6 * nsr * n0, *pT = pA + (size_t)nsc * nd * n;
+    double *um = pT + (size_t)nsc * nd * n0;
+    launch_circulant_rows(c->L, WWBI_OP_D, c->rowD, sm);
+    launch_circulant_rows(c->L, WWBI_OP_H, c->rowH, sm);
+    // base state: gamma = (-D omega_0, D omega_j) and U
+    c->gamma_from_omega(omega, gam);
+    c->eval_U_from_gamma(gam, U);
+    // the terms of dA omega and dT gamma: row sums (per target node) and the
+    // source-moving column parts of every direction; then the right-hand sides
+    launch_adj_rows(c->N, c->hrow, n0, n, omega, gam, prow, sm);
+    launch_tlm_cols(c->N, n0, n, nd, dirs, omega, gam, pA, pT, sm);
+    launch_tlm_rhs(c->N, c->F, n0, n, nd, dirs, omega, gam, U, prow, pA, pT, c->mw.b, ldv, um,
+                   sm);
+    hipEventRecord(c->ev[1], sm);
+    // the nd systems share A: one multi-RHS solve (matrix read once per step)
+    const bool fp32 = o->precision == WWBI_FP32_REFINED;
+    rc = c->ensure_matrix((size_t)n * ld * (fp32 ? 4 : 8));
+    if (rc) { c->finish_report(rep, rc, st, 0); return rc; }
+    const bool stored64 = fp32 && c->ensure_matrix64((size_t)n * ld * 8) == WWBI_OK;
+    if (fp32) {
+        launch_assemble32(c->L, c->N, o->flags, o->band, (float *)c->A, ld, sm);
+        if (stored64) launch_assemble64(c->L, c->N, o->flags, c->A64, ld, sm);
+    } else {
+        launch_assemble64(c->L, c->N, o->flags, (double *)c->A, ld, sm);
+    }
+    hipEventRecord(c->ev[2], sm);
+    int status;
+    if (!fp32)
+        status = c->gmres_multi(OP_A_S64, n, ld, c->mw.b, c->mw.x, nd, o->tol, o->restart,
+                                o->max_iter, o->poll_every, true, st);
+    else
+        status = c->refine_multi(n, ld, c->mw.b, c->mw.x, nd, *o, stored64, st);
+    hipEventRecord(c->ev[3], sm);
+    if (status >= 0) {
+        // dU_i = (um_i + H d gamma_0 / 2 + T d gamma) / s, d gamma = Gamma d omega_i
+        const int nsu = rflavour_nsplit(c->N, n0, n, 0);
+        for (int i = 0; i < nd; ++i) {
+            c->gamma_from_omega(c->mw.x + (long)i * ldv, dg);
+            launch_circulant_apply(c->L, c->rowH, dg, hg, 1.0, 0.0, 0, 0, sm);
+            launch_rflavour(c->L, c->N, c->hrow, 2, 0, 0, n0, 0, n, dg, c->part, nullptr, sm);
+            launch_U_finalize(n0, c->s, um + (long)i * n0, hg, c->part, nsu,
+                              dU + (long)i * n0, sm);
+        }
+        if (domega) launch_copy_strided(c->mw.x, ldv, domega, n, n, nd, sm);
+    }
+    hipEventRecord(c->ev[4], sm);
+    const double bytes = (double)n * n * (fp32 ? 4.0 : 8.0);
+    c->finish_report(rep, status, st, bytes);
+    if (hipGetLastError() != hipSuccess) return WWBI_EHIP;
+    return status;
+}
+
 int wwbi_solve_phi_multi(wwbi_ctx *ctx, const wwbi_geom *g, const double *rhs, int32_t nr,
                          const wwbi_opts *o, double *omega, wwbi_report *rep) {
     if (!ctx) return WWBI_EINVAL_NULL;

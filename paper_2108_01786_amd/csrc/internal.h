@@ -298,6 +298,18 @@ int otf_nsplit(int n);
 
 // ---- kernels_adjoint.hip -----------------------------------------------------
 int adjoint_nsplit(int n);
+// Tangent-linear model of the velocity-potential solve (up to 32 directions
+// at once; dirs 7 x nd x M_0): the source-moving parts of dA omega (pA, n per
+// direction and slice) and of dT gamma (pT, M_0), then the right-hand sides
+// (rhs, ld ldb) and the surface terms of dU (um, nd x M_0).
+int tlm_nsplit(int n0);
+void launch_tlm_cols(const Nodes &N, int n0, int n, int nd, const double *dirs,
+                     const double *omega, const double *gamma, double *pA, double *pT,
+                     hipStream_t st);
+void launch_tlm_rhs(const Nodes &N, const Flow &F, int n0, int n, int nd, const double *dirs,
+                    const double *omega, const double *gamma, const double *U,
+                    const double *prow, const double *pA, const double *pT, double *rhs, long ldb,
+                    double *um, hipStream_t st);
 void launch_adj_c(int n0, const double *Ubar, const double *s, double *c, hipStream_t st);
 void launch_adj_rows(const Nodes &N, const double *hrow, int n0, int n, const double *omega,
                      const double *gamma, double *part, hipStream_t st);

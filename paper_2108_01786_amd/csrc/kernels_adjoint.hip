@@ -21,6 +21,9 @@ namespace {
 
 inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 constexpr int kStage = 256;
+constexpr int kTlmMax = 32;      // directions of one tangent-linear launch
+constexpr int kTlmStage = 16;    // sources staged per pass
+constexpr int kTlmChunk = 256;   // surface sources per slice
 
 struct Cx {
     double re, im;
@@ -214,6 +217,41 @@ __global__ __launch_bounds__(256) void k_adj_near(Nodes N, int n0, int nb,
     store6(part, st, (long)slice * n0 + r, a);
 }
 
+// Derivatives of u_mv = -(V1 + sum a / 2) y' + sum_j a_j Re{cot((z - z_j)/2) z' / 2}
+// with respect to x, y, x', y' of one surface node.
+__device__ __forceinline__ void umv_derivs(const Flow &F, double x, double y, double dx, double dy,
+                                           double &ux, double &uy, double &udx, double &udy) {
+    double asum = 0.0;
+    for (int j = 0; j < F.nobs; ++j) asum += F.a[j];
+    ux = 0.0;
+    uy = 0.0;
+    udx = 0.0;
+    udy = -(F.V1 + 0.5 * asum);
+    for (int j = 0; j < F.nobs; ++j) {
+        double cr, ci;
+        cot_half64(x - F.zx[j], y - F.zy[j], cr, ci);
+        const Cx kap{cr, ci};
+        const Cx Q{1.0 + cr * cr - ci * ci, 2.0 * cr * ci};
+        const Cx dz = cscale(cmul({dx, dy}, Q), -0.25 * F.a[j]);   // d/dz of a kappa z'/2
+        ux += dz.re;
+        uy += ctimes_i(dz).re;
+        udx += 0.5 * F.a[j] * kap.re;
+        udy += 0.5 * F.a[j] * ctimes_i(kap).re;
+    }
+}
+
+// The diagonal limit L = e / (2 d) (d = z', e = z'') of a surface node and its
+// complex derivatives dL/dd = -L / d and dL/de = 1 / (2 d); A_rr = -1/2 + w Im L
+// and T_rr = w Re L.
+__device__ __forceinline__ void diag_limit_derivs(double dx, double dy, double ex, double ey,
+                                                  Cx &dLdd, Cx &dLde) {
+    const double d2 = dx * dx + dy * dy;
+    const Cx inv_d{dx / d2, -dy / d2};                 // 1/d
+    const Cx L{(ex * dx + ey * dy) / (2.0 * d2), (ey * dx - ex * dy) / (2.0 * d2)};
+    dLdd = cscale(cmul(L, inv_d), -1.0);
+    dLde = cscale(inv_d, 0.5);
+}
+
 // Combine every term on the surface nodes.
 __global__ void k_adj_finalize(Nodes N, Flow F, int n0, const double *__restrict__ Ubar,
                                const double *__restrict__ U, const double *__restrict__ omega,
@@ -235,28 +273,12 @@ __global__ void k_adj_finalize(Nodes N, Flow F, int n0, const double *__restrict
     const double s = N.s[r], w = N.w[r];
     const double c = Ubar[r] / s;
     const double lr = lam[r], wr = omega[r], gr = gamma[r];
-    // u_mv = -(V1 + sum a / 2) y' + sum_j a_j Re{cot((z - z_j)/2) z' / 2}
-    double asum = 0.0;
-    for (int j = 0; j < F.nobs; ++j) asum += F.a[j];
-    double ux = 0, uy = 0, udx = 0, udy = -(F.V1 + 0.5 * asum);
-    for (int j = 0; j < F.nobs; ++j) {
-        double cr, ci;
-        cot_half64(x - F.zx[j], y - F.zy[j], cr, ci);
-        const Cx kap{cr, ci};
-        const Cx Q{1.0 + cr * cr - ci * ci, 2.0 * cr * ci};
-        const Cx dz = cscale(cmul({dx, dy}, Q), -0.25 * F.a[j]);   // d/dz of a kappa z'/2
-        ux += dz.re;
-        uy += ctimes_i(dz).re;
-        udx += 0.5 * F.a[j] * kap.re;
-        udy += 0.5 * F.a[j] * ctimes_i(kap).re;
-    }
+    double ux, uy, udx, udy;
+    umv_derivs(F, x, y, dx, dy, ux, uy, udx, udy);
     // diagonal limits L = e/(2d): A_rr = -1/2 + w Im L, T_rr = w Re L
-    const double d2 = dx * dx + dy * dy;
-    const Cx inv_d{dx / d2, -dy / d2};                 // 1/d
-    const Cx L{(ex * dx + ey * dy) / (2.0 * d2), (ey * dx - ex * dy) / (2.0 * d2)};
-    const Cx dLdd = cscale(cmul(L, inv_d), -1.0);      // -e/(2 d^2) = -L/d
+    Cx dLdd, dLde;
+    diag_limit_derivs(dx, dy, ex, ey, dLdd, dLde);
     const Cx dLdd_y = ctimes_i(dLdd);
-    const Cx dLde = cscale(inv_d, 0.5);                // 1/(2d)
     const Cx dLde_y = ctimes_i(dLde);
     const double la = -lr * wr * w, tc = c * gr * w;   // weights of Im (A) and Re (T) parts
     g_phi[r] = lr;
@@ -266,6 +288,128 @@ __global__ void k_adj_finalize(Nodes N, Flow F, int n0, const double *__restrict
     g_dy[r] = c * udy - c * U[r] * dy / s + c * R[5] - wr * Cc[3] + la * dLdd_y.im + tc * dLdd_y.re;
     g_ddx[r] = la * dLde.im + tc * dLde.re;
     g_ddy[r] = la * dLde_y.im + tc * dLde_y.re;
+}
+
+// ---------------------------------------------------------------------------
+// Tangent-linear model (forward mode) of the same chain, for up to kTlmMax
+// directions at once.  A direction moves the surface's node data (x, y, x',
+// y', x'', y'') and phi~; dirs holds 7 x nd x M_0 values, component c of
+// direction i at (c * nd + i) * M_0.  With d omega = A^{-1} (d phi~ e_0 -
+// dA omega) and dU = (d u_mv + dT gamma + T d gamma + H d gamma_0 / 2 - U ds) / s,
+// the terms of dA omega and dT gamma that move with the target node are the
+// adjoint's row sums (k_adj_rows) times the direction at that node; the terms
+// that move with the source node come from k_tlm_cols.
+// ---------------------------------------------------------------------------
+
+// Column part, one thread per target p, the surface sources q != p of one
+// slice (blockIdx.y) staged kTlmStage at a time with their direction weights:
+//   TPART = false: colA_i[p] = sum_q (dA_pq/dx_q dx_iq + dA_pq/dy_q dy_iq
+//                                    + dA_pq/dx'_q dx'_iq + dA_pq/dy'_q dy'_iq) omega_q,
+//   TPART = true (surface targets): colT_i[p] = sum_q (dT_pq/dx_q dx_iq + dT_pq/dy_q dy_iq) gamma_q,
+// with kappa from kappa64 (near pairs exact) and d kappa / d z_q = -(1 + kappa^2) / 2.
+template <bool TPART>
+__global__ __launch_bounds__(256) void k_tlm_cols(Nodes N, int n0, int nt, int nd, int chunk,
+                                                  const double *__restrict__ dirs,
+                                                  const double *__restrict__ wq,
+                                                  double *__restrict__ part) {
+    constexpr int NC = TPART ? 2 : 4;
+    __shared__ Src ss[kTlmStage];
+    __shared__ double sw[kTlmStage][NC][kTlmMax];
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    const bool live = p < nt;
+    const Tgt t = load_tgt(N, live ? p : 0);
+    const bool surf = t.k == 0;
+    double acc[kTlmMax];
+#pragma unroll
+    for (int i = 0; i < kTlmMax; ++i) acc[i] = 0.0;
+    const int q0 = blockIdx.y * chunk, q1 = min(n0, q0 + chunk);
+    for (int qq = q0; qq < q1; qq += kTlmStage) {
+        const int m = min(kTlmStage, q1 - qq);
+        for (int e = threadIdx.x; e < kTlmStage * NC * kTlmMax; e += 256) {
+            const int j = e / (NC * kTlmMax), c = (e / kTlmMax) % NC, i = e % kTlmMax;
+            double v = 0.0;
+            if (j < m && i < nd) v = dirs[((long)c * nd + i) * n0 + qq + j] * wq[qq + j];
+            sw[j][c][i] = v;
+        }
+        if (threadIdx.x < m) ss[threadIdx.x] = load_src(N, qq + threadIdx.x);
+        __syncthreads();
+        if (live) {
+            for (int j = 0; j < m; ++j) {
+                const Src &s = ss[j];
+                if (s.idx == p) continue;             // the diagonal limit is a node term
+                double cr, ci;
+                kappa64(N, t, s, cr, ci);
+                const Cx Q{1.0 + cr * cr - ci * ci, 2.0 * cr * ci};
+                if (!TPART) {
+                    // S = (w/2) z'_q kappa: dS/dz_q = -(w/4) z'_q Q, dS/dz'_q = (w/2) kappa;
+                    // surface rows take Im S, wall rows -Re S
+                    const Cx dz = cscale(cmul({s.dx, s.dy}, Q), -0.25 * s.w);
+                    const Cx dd = cscale({cr, ci}, 0.5 * s.w);
+                    const double ax = surf ? dz.im : -dz.re;
+                    const double ay = surf ? ctimes_i(dz).im : -ctimes_i(dz).re;
+                    const double adx = surf ? dd.im : -dd.re;
+                    const double ady = surf ? ctimes_i(dd).im : -ctimes_i(dd).re;
+#pragma unroll
+                    for (int i = 0; i < kTlmMax; ++i)
+                        acc[i] += ax * sw[j][0][i] + ay * sw[j][1][i] + adx * sw[j][2][i] +
+                                  ady * sw[j][3][i];
+                } else {
+                    // R = -(1/2) z'_p kappa: dR/dz_q = z'_p Q / 4 (surface sources: Re)
+                    const Cx dz = cscale(cmul({t.dx, t.dy}, Q), 0.25 * s.w);
+                    const double tx = dz.re, ty = ctimes_i(dz).re;
+#pragma unroll
+                    for (int i = 0; i < kTlmMax; ++i) acc[i] += tx * sw[j][0][i] + ty * sw[j][1][i];
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (live)
+        for (int i = 0; i < nd; ++i) part[((long)blockIdx.y * nd + i) * nt + p] = acc[i];
+}
+
+// Right-hand sides of the nd tangent systems (rhs, system i at i * ldb) and
+// the surface terms of dU (um, direction i at i * n0):
+//   rhs_i = [p on the surface] (dphi~_i - row terms of dA omega) - colA_i,
+//   um_i = d u_mv + row terms of dT gamma + colT_i - U ds,
+// the row terms being the adjoint's row sums times the direction at the node
+// plus the diagonal limits' derivatives.
+__global__ void k_tlm_rhs(Nodes N, Flow F, int n0, int n, int nd, const double *__restrict__ dirs,
+                          const double *__restrict__ omega, const double *__restrict__ gamma,
+                          const double *__restrict__ U, const double *__restrict__ prow, int nsr,
+                          const double *__restrict__ pA, const double *__restrict__ pT, int nsc,
+                          double *rhs, long ldb, double *um) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = blockIdx.y;
+    if (r >= n) return;
+    double colA = 0.0;
+    for (int b = 0; b < nsc; ++b) colA += pA[((long)b * nd + i) * n + r];
+    if (r >= n0) {
+        rhs[i * ldb + r] = -colA;
+        return;
+    }
+    double R[6] = {0, 0, 0, 0, 0, 0};
+    const long sr = (long)nsr * n0;
+    for (int k = 0; k < 6; ++k)
+        for (int b = 0; b < nsr; ++b) R[k] += prow[k * sr + (long)b * n0 + r];
+    double colT = 0.0;
+    for (int b = 0; b < nsc; ++b) colT += pT[((long)b * nd + i) * n0 + r];
+    double d[7];
+    for (int c = 0; c < 7; ++c) d[c] = dirs[((long)c * nd + i) * n0 + r];
+    const double x = N.x[r], y = N.y[r], dx = N.dx[r], dy = N.dy[r];
+    const double s = N.s[r], w = N.w[r];
+    Cx dLdd, dLde;
+    diag_limit_derivs(dx, dy, N.ddx[r], N.ddy[r], dLdd, dLde);
+    const Cx a = cmul(dLdd, {d[2], d[3]}), b2 = cmul(dLde, {d[4], d[5]});
+    const Cx dL{a.re + b2.re, a.im + b2.im};
+    double ux, uy, udx, udy;
+    umv_derivs(F, x, y, dx, dy, ux, uy, udx, udy);
+    const double dArow = R[0] * d[0] + R[1] * d[1] + w * omega[r] * dL.im;
+    rhs[i * ldb + r] = d[6] - dArow - colA;
+    const double dumv = ux * d[0] + uy * d[1] + udx * d[2] + udy * d[3];
+    const double dTrow = R[2] * d[0] + R[3] * d[1] + R[4] * d[2] + R[5] * d[3] + w * gamma[r] * dL.re;
+    const double ds = (dx * d[2] + dy * d[3]) / s;
+    um[(long)i * n0 + r] = dumv + dTrow + colT - U[r] * ds;
 }
 
 // c = Ubar / s on the surface
@@ -278,6 +422,28 @@ __global__ void k_adj_c(int n0, const double *Ubar, const double *s, double *c) 
 
 // partial slices per component: far chunks plus the near slice
 int adjoint_nsplit(int n) { return cdiv(n, otf_chunk(n)) + 1; }
+
+// slices of the tangent-linear column passes over the M_0 surface sources
+int tlm_nsplit(int n0) { return cdiv(n0, kTlmChunk); }
+
+void launch_tlm_cols(const Nodes &N, int n0, int n, int nd, const double *dirs,
+                     const double *omega, const double *gamma, double *pA, double *pT,
+                     hipStream_t st) {
+    const int ns = tlm_nsplit(n0);
+    hipLaunchKernelGGL((k_tlm_cols<false>), dim3(cdiv(n, 256), ns), dim3(256), 0, st, N, n0, n, nd,
+                       kTlmChunk, dirs, omega, pA);
+    hipLaunchKernelGGL((k_tlm_cols<true>), dim3(cdiv(n0, 256), ns), dim3(256), 0, st, N, n0, n0,
+                       nd, kTlmChunk, dirs, gamma, pT);
+}
+
+void launch_tlm_rhs(const Nodes &N, const Flow &F, int n0, int n, int nd, const double *dirs,
+                    const double *omega, const double *gamma, const double *U,
+                    const double *prow, const double *pA, const double *pT, double *rhs, long ldb,
+                    double *um, hipStream_t st) {
+    hipLaunchKernelGGL(k_tlm_rhs, dim3(cdiv(n, 256), nd), dim3(256), 0, st, N, F, n0, n, nd, dirs,
+                       omega, gamma, U, prow, adjoint_nsplit(n), pA, pT, tlm_nsplit(n0), rhs, ldb,
+                       um);
+}
 
 void launch_adj_c(int n0, const double *Ubar, const double *s, double *c, hipStream_t st) {
     hipLaunchKernelGGL(k_adj_c, dim3(cdiv(n0, 256)), dim3(256), 0, st, n0, Ubar, s, c);

@@ -108,6 +108,9 @@ _SIGS = {
                                    C.POINTER(_Opts)] + [C.c_void_p] * 7 + [C.POINTER(Report)]),
     "wwbi_solve_phi_multi": (C.c_int, [C.c_void_p, C.POINTER(_Geom), C.c_void_p, C.c_int32,
                                        C.POINTER(_Opts), C.c_void_p, C.POINTER(Report)]),
+    "wwbi_tangent_phi": (C.c_int, [C.c_void_p, C.POINTER(_Geom), C.c_void_p, C.c_int32,
+                                   C.c_void_p, C.POINTER(_Opts), C.c_void_p, C.c_void_p,
+                                   C.POINTER(Report)]),
     "wwbi_spectral": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_double,
                                 C.c_double, C.c_void_p]),
     "wwbi_surface_fill": (C.c_int, [C.c_void_p, C.c_int32] + [C.c_void_p] * 8),
@@ -507,6 +510,26 @@ class Context:
                                            _ptr(out), C.byref(rep))
         _check(rc, check, "wwbi_solve_phi_multi")
         return out, rep
+
+    def tangent_phi(self, geom: DeviceGeometry, omega: torch.Tensor, dirs: torch.Tensor,
+                    want_omega: bool = False, check: bool = True, **kw):
+        """wwbi_tangent_phi: dirs is a (7, nd, M_0) device tensor (x, y, x', y',
+        x'', y'', phi~ of the surface nodes for each direction); returns dU
+        (nd, M_0), d omega (nd, sum(M)) or None, and the report."""
+        self._stream()
+        dev = self._dev()
+        omega = _f64(omega, dev)
+        dirs = _f64(dirs, dev)
+        nd = dirs.shape[1]
+        dU = torch.empty((nd, geom.M[0]), dtype=torch.float64, device=dev)
+        dom = torch.empty((nd, geom.n), dtype=torch.float64, device=dev) if want_omega else None
+        rep = Report()
+        g = geom.c_struct()
+        o = make_opts(**kw)
+        rc = self.lib.wwbi_tangent_phi(self.h, C.byref(g), _ptr(omega), nd, _ptr(dirs),
+                                       C.byref(o), _ptr(dU), _ptr(dom), C.byref(rep))
+        _check(rc, check, "wwbi_tangent_phi")
+        return dU, dom, rep
 
     def spectral(self, f: torch.Tensor, op: int, alpha: float = 1.0, beta: float = 0.0,
                  out: Optional[torch.Tensor] = None) -> torch.Tensor:

@@ -20,7 +20,7 @@ def declared_functions():
 def test_header_declares_the_documented_entry_points():
     names = declared_functions()
     for must in ("wwbi_create", "wwbi_destroy", "wwbi_solve_phi", "wwbi_solve_gamma",
-                 "wwbi_adjoint_phi", "wwbi_solve_phi_multi", "wwbi_spectral",
+                 "wwbi_adjoint_phi", "wwbi_solve_phi_multi", "wwbi_tangent_phi", "wwbi_spectral",
                  "wwbi_debug_matrix", "wwbi_matvec", "wwbi_status_str", "wwbi_default_opts",
                  "wwbi_tangential_energy", "wwbi_solve_gamma_t", "wwbi_stage_rhs",
                  "wwbi_rk_step", "wwbi_boundary_velocity", "wwbi_interior_eval",

@@ -1,0 +1,150 @@
+"""Tangent-linear model of the velocity-potential solve on the device
+(wwbi_tangent_phi; Sec. 3.2-3.4 differentiated): the directional derivatives
+dU of up to 32 directions of the surface's node data and phi~, the systems
+A d omega_i = dphi~_i e_0 - dA_i omega solved together by the multi-RHS
+solver (the matrix read once per Arnoldi step for all directions).
+
+* Config 1 (M = 640), four seeded directions whose seven components (x, y,
+  x', y', x'', y'', phi~) are independent smooth fields: dU element by element
+  against the oracle's tangent-linear model (forward-mode autodiff through its
+  assembly and U map, around its refined dense solve).
+* Config 4 (M = 4608), its 32 seeded displacement directions (x~, y, phi~,
+  with x' = D x~ and so on): dJ_i = sum 2 w U dU_i against the oracle's
+  reverse-mode gradient contracted with each direction
+  (tests/golden/adjoint_c4.npz).
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from synth import make_config
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+@pytest.fixture(scope="module")
+def ww():
+    from paper_2108_01786_amd import wwbi
+    return wwbi
+
+
+@pytest.fixture(scope="module")
+def ctx(ww):
+    c = ww.Context(0)
+    yield c
+    c.close()
+
+
+def _opts(ww, prec):
+    if prec == "fp64":
+        return dict(tol=1e-13)
+    return dict(tol=1e-14, precision=ww.FP32_REFINED)
+
+
+def _smooth(rng, M, kmax=8):
+    a = 2 * np.pi * np.arange(M) / M
+    f = np.zeros(M)
+    for k in range(kmax + 1):
+        f += (rng.standard_normal() * np.cos(k * a) + rng.standard_normal() * np.sin(k * a)) / (1 + k)
+    return f / np.abs(f).max()
+
+
+def _spectral_d(f):
+    M = f.shape[0]
+    k = np.fft.fftfreq(M, d=1.0 / M)
+    k[M // 2] = 0.0
+    return np.fft.ifft(1j * k * np.fft.fft(f)).real
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tangent_matches_oracle_tlm(ww, ctx, prec):
+    say(f"case tangent c1 vs oracle tlm {prec}")
+    cfg = make_config(1)
+    geom, phi = cfg["geom"], cfg["phi"]
+    M0 = geom.M[0]
+    rng = np.random.default_rng(41)
+    w = rng.uniform(0.0, 1.0, M0)
+    dirs = np.array([[_smooth(rng, M0) for _ in range(7)] for _ in range(4)])  # (nd, 7, M0)
+    og = O.OGeom.from_synth(geom)
+    A = O.assemble_A(og)
+    J, Uo, om, dJo, dUo = O.tangent_J_nodes(og, phi, w, [tuple(d) for d in dirs],
+                                             lambda r: O.dense_solve(A, r))
+    dg = ww.DeviceGeometry.from_synth(geom, DEV)
+    U, omega, _, rep = ctx.solve_phi(dg, torch.as_tensor(phi, device=DEV), **_opts(ww, prec))
+    dU, dom, rt = ctx.tangent_phi(dg, omega, torch.as_tensor(dirs.transpose(1, 0, 2).copy(),
+                                                             device=DEV),
+                                  want_omega=True, **_opts(ww, prec))
+    dU = dU.cpu().numpy()
+    errs = [float(np.abs(dU[i] - dUo[i].numpy()).max() / np.abs(dUo[i].numpy()).max())
+            for i in range(len(dirs))]
+    dJ = [float((2.0 * w * U.cpu().numpy() * dU[i]).sum()) for i in range(len(dirs))]
+    eJ = max(abs(a - b) for a, b in zip(dJ, dJo)) / max(abs(b) for b in dJo)
+    say(f"  status {rt.status} iters {rt.iters} refine {rt.refine_steps}  dU err "
+        f"{max(errs):.2e}  dJ err {eJ:.2e}")
+    assert rt.status == 0
+    bar = 1e-11 if prec == "fp64" else 1e-10
+    assert max(errs) <= 10 * bar and eJ <= bar
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tangent_config4_directions(ww, ctx, prec):
+    say(f"case tangent config4 {prec}")
+    cfg = make_config(4)
+    geom, phi, w = cfg["geom"], cfg["phi"], cfg["weights"]
+    M0 = geom.M[0]
+    nodes = []
+    for d in cfg["directions"]:
+        dx1, dy1 = _spectral_d(d[0]), _spectral_d(d[1])
+        nodes.append([d[0], d[1], dx1, dy1, _spectral_d(dx1), _spectral_d(dy1), d[2]])
+    nodes = np.array(nodes)                                            # (32, 7, M0)
+    gd = np.load(os.path.join(GOLDEN, "adjoint_c4.npz"))
+    gr = [gd[f"g_{k}"] for k in ("x", "y", "dx", "dy", "ddx", "ddy", "phi")]
+    dJo = np.array([sum(float(gr[c] @ nd[c]) for c in range(7)) for nd in nodes])
+    dg = ww.DeviceGeometry.from_synth(geom, DEV)
+    U, omega, _, rep = ctx.solve_phi(dg, torch.as_tensor(phi, device=DEV), **_opts(ww, prec))
+    dU, _, rt = ctx.tangent_phi(dg, omega, torch.as_tensor(nodes.transpose(1, 0, 2).copy(),
+                                                          device=DEV), **_opts(ww, prec))
+    Ug = U.cpu().numpy()
+    dJ = np.array([float((2.0 * w * Ug * dU[i].cpu().numpy()).sum()) for i in range(len(nodes))])
+    eJ = float(np.abs(dJ - dJo).max() / np.abs(dJo).max())
+    # the device adjoint's gradient contracted with the same directions
+    grads, _ = ctx.adjoint_phi(dg, omega, 2.0 * torch.as_tensor(w, device=DEV) * U,
+                               **_opts(ww, prec))
+    ga = [grads[k].cpu().numpy() for k in ("x", "y", "dx", "dy", "ddx", "ddy", "phi")]
+    dJa = np.array([sum(float(ga[c] @ nd[c]) for c in range(7)) for nd in nodes])
+    eA = float(np.abs(dJ - dJa).max() / np.abs(dJa).max())
+    say(f"  status {rt.status} iters {rt.iters} refine {rt.refine_steps} ms {rt.ms_total:.2f}  "
+        f"dJ err {eJ:.2e} vs adjoint {eA:.2e} (32 directions)")
+    assert rt.status == 0
+    bar = 1e-11 if prec == "fp64" else 1e-10
+    assert eJ <= bar and eA <= bar
+
+
+def test_tangent_errors(ww, ctx):
+    say("case tangent errors")
+    cfg = make_config(1)
+    geom = cfg["geom"]
+    dg = ww.DeviceGeometry.from_synth(geom, DEV)
+    U, omega, _, _ = ctx.solve_phi(dg, torch.as_tensor(cfg["phi"], device=DEV))
+    good = torch.zeros((7, 2, geom.M[0]), dtype=torch.float64, device=DEV)
+    with pytest.raises(ww.WWBIError) as e:
+        ctx.tangent_phi(dg, omega, good, matvec=ww.MATVEC_ON_THE_FLY)
+    assert e.value.status == ww.EINVAL_OPTS
+    with pytest.raises(ww.WWBIError) as e:
+        ctx.tangent_phi(dg, omega, torch.zeros((7, 33, geom.M[0]), dtype=torch.float64,
+                                               device=DEV))
+    assert e.value.status == ww.EINVAL_OPTS
+    bad = good.clone()
+    bad[3, 1, 5] = float("nan")
+    with pytest.raises(ww.WWBIError) as e:
+        ctx.tangent_phi(dg, omega, bad)
+    assert e.value.status == ww.EINVAL_NONFINITE
