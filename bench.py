@@ -409,7 +409,9 @@ def run_adjoint(a):
     weights ~ U[0, 1]).  One step is the forward solve plus the adjoint: the
     transpose solve, the kernel-derivative contractions and the chain rule
     through the spectral derivatives.  Timed in refined FP32 (the value) and
-    in FP64."""
+    in FP64.  Beside it, the tangent-linear model along the cell's 32 seeded
+    directions in one call (32 systems sharing the matrix), with its dJ
+    checked against the adjoint's gradient along the same directions."""
     from paper_2108_01786_amd import wwbi
     from paper_2108_01786_amd.autograd import SurfaceProblem
     from synth import make_config
@@ -458,6 +460,53 @@ def run_adjoint(a):
     log(f"bench: refined fp32 forward+adjoint {1e3 * t32:.3f} ms")
     t64, out64, fw64, ad64, wall64 = timed(o64, a.steps, a.warmup)
     log(f"bench: fp64 forward+adjoint {1e3 * t64:.3f} ms")
+
+    # the tangent-linear model along the cell's 32 seeded displacement
+    # directions (x~, y~, phi~ with their spectral derivatives), one call: the
+    # 32 systems A d omega_i = r_i share the matrix
+    g = prob.fill(xt, yt)
+    U32, om32, _, _ = ctx.solve_phi(g, ph, **o32)
+    U64, om64, _, _ = ctx.solve_phi(g, ph, **o64)
+    comp = []
+    for d in cfg["directions"]:
+        d0, d1 = (torch.as_tensor(v, device=dev) for v in (d[0], d[1]))
+        d0p, d1p = ctx.spectral(d0, wwbi.OP_D), ctx.spectral(d1, wwbi.OP_D)
+        comp.append(torch.stack([d0, d1, d0p, d1p, ctx.spectral(d0p, wwbi.OP_D),
+                                 ctx.spectral(d1p, wwbi.OP_D), torch.as_tensor(d[2], device=dev)]))
+    tdirs = torch.stack(comp, dim=1).contiguous()                  # 7 x 32 x M_0
+
+    def tangent(om, opts, steps, warmup):
+        for _ in range(warmup):
+            ctx.tangent_phi(g, om, tdirs, **opts)
+        torch.cuda.synchronize()
+        reps, wall = [], []
+        for k in range(steps):
+            ts = time.perf_counter()
+            dU, _, rt = ctx.tangent_phi(g, om, tdirs, flags=wwbi.FLAG_PROFILE if k == 0 else 0,
+                                        **opts)
+            torch.cuda.synchronize()
+            wall.append({"ms_total": 1e3 * (time.perf_counter() - ts)})
+            reps.append(rt.as_dict())
+        return dU, reps, wall
+
+    dU32, tr32, tw32 = tangent(om32, o32, a.steps, a.warmup)
+    dU64, tr64, tw64 = tangent(om64, o64, a.steps, a.warmup)
+    log(f"bench: tangent 32 directions refined {stats_ms(tw32)['median']:.3f} ms, "
+        f"fp64 {stats_ms(tw64)['median']:.3f} ms")
+    # dJ_i from the tangent against the adjoint's gradient along the same directions
+    grads, _ = ctx.adjoint_phi(g, om64, 2.0 * wt * U64, **o64)
+    gv = torch.stack([grads[k] for k in ("x", "y", "dx", "dy", "ddx", "ddy", "phi")])
+    dJ_adj = (gv[:, None, :] * tdirs).sum(dim=(0, 2))
+    tangent_info = {"directions": len(cfg["directions"])}
+    for name, dU, tr, tw, U in (("refined", dU32, tr32, tw32, U32), ("fp64", dU64, tr64, tw64, U64)):
+        dJ = (2.0 * wt * U * dU).sum(dim=1)
+        mv = tr[0]["ms_matvec"] / max(1, tr[0]["n_matvec"])
+        tangent_info[name] = {
+            "ms_stats": stats_ms(tw), "iters": tr[-1]["iters"],
+            "refine_steps": tr[-1]["refine_steps"],
+            "multi_product_avg_ms": mv, "multi_product_launches": tr[0]["n_matvec"],
+            "multi_product_GBps": tr[0]["bytes_matvec"] / (mv * 1e-3) / 1e9 if mv > 0 else None,
+            "dJ_rel_diff_vs_adjoint": float((dJ - dJ_adj).abs().max() / dJ_adj.abs().max())}
 
     nmv = fw32[0]["n_matvec"] + ad32[0]["n_matvec"]
     msmv = fw32[0]["ms_matvec"] + ad32[0]["ms_matvec"]
@@ -510,6 +559,7 @@ def run_adjoint(a):
         "refine_steps": [fw32[-1]["refine_steps"], ad32[-1]["refine_steps"]],
         "fp64_gradients_per_s": 1.0 / t64, "fp64_ms_per_step_stats": s64,
         "fp64_forward_iters": fw64[-1]["iters"], "fp64_adjoint_iters": ad64[-1]["iters"],
+        "tangent_linear": tangent_info,
         "roofline": roof, "cpu_baseline": cpu,
     }
     line.update(res)
