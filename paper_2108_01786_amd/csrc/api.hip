@@ -1869,20 +1869,25 @@ int wwbi_tangent_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, int
         rc = c->setup(g, dirs, 7 * nd * g->M[0]);
     }
     const int n = rc ? 0 : c->L.n, n0 = rc ? 0 : c->L.off[1];
-    const int nsr = rc ? 0 : adjoint_nsplit(n), nsc = rc ? 0 : tlm_nsplit(n0);
+    const int nsr = rc ? 0 : adjoint_nsplit(n), nsc = rc ? 0 : tlm_nsplit(n, n0);
     if (!rc) rc = c->ensure_multi(n, nd, o->restart);
     if (!rc)
         rc = grow(c->apart, c->capapart,
-                  (size_t)6 * nsr * n0 + (size_t)nsc * nd * (n + n0) + (size_t)nd * n0 + 64);
+                  (size_t)6 * nsr * n0 + (size_t)nsc * nd * (n + n0) + (size_t)3 * nd * n0 +
+                      tlm_weights_size(n0) + 64);
+    // the partial sums of the multi-vector product with T (M_0 x n)
+    if (!rc)
+        rc = grow(c->mw.part, c->mw.cpart, (size_t)multi_part_size_rect64(n0, n, nd) + 64);
     if (rc) {
         if (rep) { std::memset(rep, 0, sizeof(*rep)); rep->status = rc; }
         return rc;
     }
     hipStream_t sm = c->stream;
     const long ld = round_up(n, 64), ldv = ld;
-    double *gam = c->vec[VG], *U = c->vec[VTMP2], *dg = c->vec[VTMP], *hg = c->vec[VHG];
+    double *gam = c->vec[VG], *U = c->vec[VTMP2];
     double *prow = c->apart, *pA = prow + (size_t)6 * nsr * n0, *pT = pA + (size_t)nsc * nd * n;
-    double *um = pT + (size_t)nsc * nd * n0;
+    double *um = pT + (size_t)nsc * nd * n0, *hgs = um + (size_t)nd * n0;
+    double *tgs = hgs + (size_t)nd * n0, *wts = tgs + (size_t)nd * n0;
     launch_circulant_rows(c->L, WWBI_OP_D, c->rowD, sm);
     launch_circulant_rows(c->L, WWBI_OP_H, c->rowH, sm);
     // base state: gamma = (-D omega_0, D omega_j) and U
@@ -1891,7 +1896,7 @@ int wwbi_tangent_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, int
     // the terms of dA omega and dT gamma: row sums (per target node) and the
     // source-moving column parts of every direction; then the right-hand sides
     launch_adj_rows(c->N, c->hrow, n0, n, omega, gam, prow, sm);
-    launch_tlm_cols(c->N, n0, n, nd, dirs, omega, gam, pA, pT, sm);
+    launch_tlm_cols(c->N, n0, n, nd, dirs, omega, gam, wts, pA, pT, sm);
     launch_tlm_rhs(c->N, c->F, n0, n, nd, dirs, omega, gam, U, prow, pA, pT, c->mw.b, ldv, um,
                    sm);
     hipEventRecord(c->ev[1], sm);
@@ -1915,14 +1920,34 @@ int wwbi_tangent_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, int
         status = c->refine_multi(n, ld, c->mw.b, c->mw.x, nd, *o, stored64, st);
     hipEventRecord(c->ev[3], sm);
     if (status >= 0) {
-        // dU_i = (um_i + H d gamma_0 / 2 + T d gamma) / s, d gamma = Gamma d omega_i
-        const int nsu = rflavour_nsplit(c->N, n0, n, 0);
-        for (int i = 0; i < nd; ++i) {
-            c->gamma_from_omega(c->mw.x + (long)i * ldv, dg);
-            launch_circulant_apply(c->L, c->rowH, dg, hg, 1.0, 0.0, 0, 0, sm);
-            launch_rflavour(c->L, c->N, c->hrow, 2, 0, 0, n0, 0, n, dg, c->part, nullptr, sm);
-            launch_U_finalize(n0, c->s, um + (long)i * n0, hg, c->part, nsu,
-                              dU + (long)i * n0, sm);
+        // dU_i = (um_i + H d gamma_0,i / 2 + T d gamma_i) / s, d gamma_i = Gamma d omega_i,
+        // for all directions at once: d gamma into the right-hand sides' buffer
+        // (free after the solve), and T assembled in FP64 over matrix storage
+        // the solve has finished with
+        double *dG = c->mw.b;
+        launch_circulant_batched(c->L, c->rowD, c->mw.x, ldv, dG, ldv, nd, -1.0, 1.0, 0.0, 0,
+                                 c->L.nb - 1, sm);
+        launch_circulant_batched(c->L, c->rowH, dG, ldv, hgs, n0, nd, 1.0, 1.0, 0.0, 0, 0, sm);
+        double *Tm = nullptr;
+        if (!fp32)
+            Tm = (double *)c->A;
+        else if (stored64)
+            Tm = c->A64;
+        else if (c->ensure_matrix((size_t)n0 * ld * 8) == WWBI_OK)
+            Tm = (double *)c->A;
+        if (Tm) {
+            launch_assemble_T64(c->L, c->N, c->hrow, Tm, ld, sm);
+            launch_mfma_rect64(Tm, ld, n0, n, dG, ldv, nd, tgs, n0, c->mw.part, sm);
+            launch_tlm_finalize(n0, nd, c->s, um, hgs, tgs, dU, sm);
+        } else {
+            // no room for T: its on-the-fly product, one direction at a time
+            const int nsu = rflavour_nsplit(c->N, n0, n, 0);
+            for (int i = 0; i < nd; ++i) {
+                launch_rflavour(c->L, c->N, c->hrow, 2, 0, 0, n0, 0, n, dG + (long)i * ldv,
+                                c->part, nullptr, sm);
+                launch_U_finalize(n0, c->s, um + (long)i * n0, hgs + (long)i * n0, c->part, nsu,
+                                  dU + (long)i * n0, sm);
+            }
         }
         if (domega) launch_copy_strided(c->mw.x, ldv, domega, n, n, nd, sm);
     }

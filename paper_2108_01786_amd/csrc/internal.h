@@ -162,6 +162,10 @@ void launch_circulant_apply(const Layout &L, const double *rows, const double *f
 void launch_circulant_apply2(const Layout &L, const double *rows, const double *f, double *out,
                              double alpha0, double alpha, double beta, int first_block,
                              int last_block, hipStream_t st);
+// the same for nv vectors at once: vector v reads f + v fs and writes out + v os
+void launch_circulant_batched(const Layout &L, const double *rows, const double *f, long fs,
+                              double *out, long os, int nv, double alpha0, double alpha,
+                              double beta, int first_block, int last_block, hipStream_t st);
 void launch_circ_row1(int M, int op, double *row, hipStream_t st);
 void launch_circ_apply1(int M, const double *row, const double *f, double *out, double alpha,
                         double beta, hipStream_t st);
@@ -300,16 +304,20 @@ int otf_nsplit(int n);
 int adjoint_nsplit(int n);
 // Tangent-linear model of the velocity-potential solve (up to 32 directions
 // at once; dirs 7 x nd x M_0): the source-moving parts of dA omega (pA, n per
-// direction and slice) and of dT gamma (pT, M_0), then the right-hand sides
-// (rhs, ld ldb) and the surface terms of dU (um, nd x M_0).
-int tlm_nsplit(int n0);
+// direction and slice) and of dT gamma (pT, M_0), from the weights W
+// (tlm_weights_size(M_0) doubles), then the right-hand sides (rhs, ld ldb) and
+// the surface terms of dU (um, nd x M_0).
+int tlm_nsplit(int n, int n0);
+size_t tlm_weights_size(int n0);
 void launch_tlm_cols(const Nodes &N, int n0, int n, int nd, const double *dirs,
-                     const double *omega, const double *gamma, double *pA, double *pT,
+                     const double *omega, const double *gamma, double *W, double *pA, double *pT,
                      hipStream_t st);
 void launch_tlm_rhs(const Nodes &N, const Flow &F, int n0, int n, int nd, const double *dirs,
                     const double *omega, const double *gamma, const double *U,
                     const double *prow, const double *pA, const double *pT, double *rhs, long ldb,
                     double *um, hipStream_t st);
+void launch_tlm_finalize(int n0, int nd, const double *s, const double *um, const double *hg,
+                         const double *tg, double *dU, hipStream_t st);
 void launch_adj_c(int n0, const double *Ubar, const double *s, double *c, hipStream_t st);
 void launch_adj_rows(const Nodes &N, const double *hrow, int n0, int n, const double *omega,
                      const double *gamma, double *part, hipStream_t st);
@@ -334,6 +342,11 @@ void launch_to_f32_batched(const double *src, long ss, float *dst, long ds, int 
 void launch_copy_strided(const double *src, long ss, double *dst, long ds, int n, int nr,
                          hipStream_t st);
 int multi_part_size(int n, int nr);
+// y_s = T X_s, s < nr, for an FP64 m x n matrix T (row stride ld, a multiple
+// of 64 columns readable past n); part needs multi_part_size_rect64(m, n, nr).
+void launch_mfma_rect64(const double *A, long ld, int m, int n, const double *X, long xs, int nr,
+                        double *y, long ys, double *part, hipStream_t st);
+int multi_part_size_rect64(int m, int n, int nr);
 
 // ---- kernels_gmres.hip -------------------------------------------------------
 int gmres_nblocks(int n);

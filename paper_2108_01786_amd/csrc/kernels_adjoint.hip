@@ -22,8 +22,7 @@ namespace {
 inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 constexpr int kStage = 256;
 constexpr int kTlmMax = 32;      // directions of one tangent-linear launch
-constexpr int kTlmStage = 16;    // sources staged per pass
-constexpr int kTlmChunk = 256;   // surface sources per slice
+constexpr int kTlmWaves = 2048;  // waves the column pass's source split aims at
 
 struct Cx {
     double re, im;
@@ -298,74 +297,107 @@ __global__ void k_adj_finalize(Nodes N, Flow F, int n0, const double *__restrict
 // dA omega) and dU = (d u_mv + dT gamma + T d gamma + H d gamma_0 / 2 - U ds) / s,
 // the terms of dA omega and dT gamma that move with the target node are the
 // adjoint's row sums (k_adj_rows) times the direction at that node; the terms
-// that move with the source node come from k_tlm_cols.
+// that move with the source node come from k_tlm_cols (matrix cores).
 // ---------------------------------------------------------------------------
 
-// Column part, one thread per target p, the surface sources q != p of one
-// slice (blockIdx.y) staged kTlmStage at a time with their direction weights:
-//   TPART = false: colA_i[p] = sum_q (dA_pq/dx_q dx_iq + dA_pq/dy_q dy_iq
-//                                    + dA_pq/dx'_q dx'_iq + dA_pq/dy'_q dy'_iq) omega_q,
-//   TPART = true (surface targets): colT_i[p] = sum_q (dT_pq/dx_q dx_iq + dT_pq/dy_q dy_iq) gamma_q,
-// with kappa from kappa64 (near pairs exact) and d kappa / d z_q = -(1 + kappa^2) / 2.
-template <bool TPART>
-__global__ __launch_bounds__(256) void k_tlm_cols(Nodes N, int n0, int nt, int nd, int chunk,
-                                                  const double *__restrict__ dirs,
-                                                  const double *__restrict__ wq,
-                                                  double *__restrict__ part) {
-    constexpr int NC = TPART ? 2 : 4;
-    __shared__ Src ss[kTlmStage];
-    __shared__ double sw[kTlmStage][NC][kTlmMax];
-    const int p = blockIdx.x * 256 + threadIdx.x;
-    const bool live = p < nt;
-    const Tgt t = load_tgt(N, live ? p : 0);
+// Weights of the column part: W[(q * 6 + c) * kTlmMax + i] is direction i's
+// change of source q's x, y, x', y' times omega_q (c = 0..3) and of its x, y
+// times gamma_q (c = 4, 5); zero for i >= nd.
+__global__ void k_tlm_weights(int n0, int nd, const double *__restrict__ dirs,
+                              const double *__restrict__ omega, const double *__restrict__ gamma,
+                              double *__restrict__ W) {
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)n0 * 6 * kTlmMax) return;
+    const int i = (int)(e % kTlmMax), c = (int)((e / kTlmMax) % 6), q = (int)(e / (6 * kTlmMax));
+    double v = 0.0;
+    if (i < nd) {
+        const int cc = c < 4 ? c : c - 4;
+        v = dirs[((long)cc * nd + i) * n0 + q] * (c < 4 ? omega[q] : gamma[q]);
+    }
+    W[e] = v;
+}
+
+// Column part on the matrix cores: for targets p and directions i,
+//   colA_i[p] = sum_{q != p on the surface} sum_c dA_pq/dc_q W_c(q, i)   (c = x, y, x', y')
+//   colT_i[p] = sum_{q != p on the surface} sum_c dT_pq/dc_q W_{4+c}(q, i) (c = x, y; p on the surface)
+// a contraction over (q, c) of the derivative coefficients with the weights.
+// A wave owns 16 targets and all directions (two 16-wide tiles when nd > 16)
+// over one chunk of sources (blockIdx.y), 4 sources per step: lane l takes
+// the pair (p0 + l % 16, q0 + l / 16), which is exactly the A operand it
+// supplies to v_mfma_f64_16x16x4f64 (row l % 16, k slot l / 16), forms kappa
+// once (kappa64: near pairs from the exact difference) and one coefficient
+// per component c, and the B operand is W_c(q0 + l / 16, 16 t + l % 16).
+// With S = (w/2) z'_q kappa and R = -(1/2) z'_p kappa:
+//   dS/dz_q = -(w/4) z'_q (1 + kappa^2), dS/dz'_q = (w/2) kappa (surface rows
+//   take Im S, wall rows -Re S), dR/dz_q = (w/4) z'_p (1 + kappa^2) (Re R).
+// Result element r of lane l is target p0 + l / 16 + 4 r, direction l % 16.
+__global__ __launch_bounds__(256) void k_tlm_cols(Nodes N, int n0, int n, int nd, int chunk,
+                                                  const double *__restrict__ W,
+                                                  double *__restrict__ pA,
+                                                  double *__restrict__ pT) {
+    typedef double v4d __attribute__((ext_vector_type(4)));
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int p0 = (blockIdx.x * 4 + wv) * 16;
+    if (p0 >= n) return;                        // whole waves; no barriers below
+    const int il = lane & 15, kq = lane >> 4;
+    const int p = p0 + il;
+    const bool live = p < n;
+    const Tgt t = load_tgt(N, live ? p : n - 1);
     const bool surf = t.k == 0;
-    double acc[kTlmMax];
-#pragma unroll
-    for (int i = 0; i < kTlmMax; ++i) acc[i] = 0.0;
-    const int q0 = blockIdx.y * chunk, q1 = min(n0, q0 + chunk);
-    for (int qq = q0; qq < q1; qq += kTlmStage) {
-        const int m = min(kTlmStage, q1 - qq);
-        for (int e = threadIdx.x; e < kTlmStage * NC * kTlmMax; e += 256) {
-            const int j = e / (NC * kTlmMax), c = (e / kTlmMax) % NC, i = e % kTlmMax;
-            double v = 0.0;
-            if (j < m && i < nd) v = dirs[((long)c * nd + i) * n0 + qq + j] * wq[qq + j];
-            sw[j][c][i] = v;
-        }
-        if (threadIdx.x < m) ss[threadIdx.x] = load_src(N, qq + threadIdx.x);
-        __syncthreads();
-        if (live) {
-            for (int j = 0; j < m; ++j) {
-                const Src &s = ss[j];
-                if (s.idx == p) continue;             // the diagonal limit is a node term
-                double cr, ci;
-                kappa64(N, t, s, cr, ci);
-                const Cx Q{1.0 + cr * cr - ci * ci, 2.0 * cr * ci};
-                if (!TPART) {
-                    // S = (w/2) z'_q kappa: dS/dz_q = -(w/4) z'_q Q, dS/dz'_q = (w/2) kappa;
-                    // surface rows take Im S, wall rows -Re S
-                    const Cx dz = cscale(cmul({s.dx, s.dy}, Q), -0.25 * s.w);
-                    const Cx dd = cscale({cr, ci}, 0.5 * s.w);
-                    const double ax = surf ? dz.im : -dz.re;
-                    const double ay = surf ? ctimes_i(dz).im : -ctimes_i(dz).re;
-                    const double adx = surf ? dd.im : -dd.re;
-                    const double ady = surf ? ctimes_i(dd).im : -ctimes_i(dd).re;
-#pragma unroll
-                    for (int i = 0; i < kTlmMax; ++i)
-                        acc[i] += ax * sw[j][0][i] + ay * sw[j][1][i] + adx * sw[j][2][i] +
-                                  ady * sw[j][3][i];
-                } else {
-                    // R = -(1/2) z'_p kappa: dR/dz_q = z'_p Q / 4 (surface sources: Re)
-                    const Cx dz = cscale(cmul({t.dx, t.dy}, Q), 0.25 * s.w);
-                    const double tx = dz.re, ty = ctimes_i(dz).re;
-#pragma unroll
-                    for (int i = 0; i < kTlmMax; ++i) acc[i] += tx * sw[j][0][i] + ty * sw[j][1][i];
-                }
+    const bool tpart = p0 < n0;                 // the tile holds surface targets
+    const bool two = nd > 16;
+    const int qb = blockIdx.y * chunk, qe = min(n0, qb + chunk);
+    v4d a0 = {0.0, 0.0, 0.0, 0.0}, a1 = a0, t0 = a0, t1 = a0;
+    for (int qs = qb; qs < qe; qs += 4) {
+        const int q = qs + kq;
+        const int qc = min(q, n0 - 1);
+        const Src s = load_src(N, qc);
+        double ca[4] = {0.0, 0.0, 0.0, 0.0}, ct[2] = {0.0, 0.0};
+        if (live && q < qe && q != p) {
+            double cr, ci;
+            kappa64(N, t, s, cr, ci);
+            const Cx Q{1.0 + cr * cr - ci * ci, 2.0 * cr * ci};
+            const Cx dz = cscale(cmul({s.dx, s.dy}, Q), -0.25 * s.w);
+            const Cx dd = cscale({cr, ci}, 0.5 * s.w);
+            if (surf) {
+                ca[0] = dz.im; ca[1] = dz.re; ca[2] = dd.im; ca[3] = dd.re;
+                const Cx dr = cscale(cmul({t.dx, t.dy}, Q), 0.25 * s.w);
+                ct[0] = dr.re; ct[1] = -dr.im;
+            } else {
+                ca[0] = -dz.re; ca[1] = dz.im; ca[2] = -dd.re; ca[3] = dd.im;
             }
         }
-        __syncthreads();
+        const double *w = W + (long)qc * 6 * kTlmMax + il;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[c], w[c * kTlmMax], a0, 0, 0, 0);
+            if (two)
+                a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[c], w[c * kTlmMax + 16], a1, 0, 0, 0);
+        }
+        if (tpart) {
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                t0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ct[c], w[(4 + c) * kTlmMax], t0, 0, 0,
+                                                          0);
+                if (two)
+                    t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ct[c], w[(4 + c) * kTlmMax + 16],
+                                                              t1, 0, 0, 0);
+            }
+        }
     }
-    if (live)
-        for (int i = 0; i < nd; ++i) part[((long)blockIdx.y * nd + i) * nt + p] = acc[i];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = p0 + kq + 4 * r;
+        const long sa = (long)blockIdx.y * nd;
+        if (row < n) {
+            if (il < nd) pA[(sa + il) * n + row] = a0[r];
+            if (two && il + 16 < nd) pA[(sa + il + 16) * n + row] = a1[r];
+        }
+        if (tpart && row < n0) {
+            if (il < nd) pT[(sa + il) * n0 + row] = t0[r];
+            if (two && il + 16 < nd) pT[(sa + il + 16) * n0 + row] = t1[r];
+        }
+    }
 }
 
 // Right-hand sides of the nd tangent systems (rhs, system i at i * ldb) and
@@ -412,6 +444,17 @@ __global__ void k_tlm_rhs(Nodes N, Flow F, int n0, int n, int nd, const double *
     um[(long)i * n0 + r] = dumv + dTrow + colT - U[r] * ds;
 }
 
+// dU_i = (um_i + H d gamma_0,i / 2 + T d gamma_i) / s for every direction
+// (blockIdx.y), all three terms at stride n0.
+__global__ void k_tlm_finalize(int n0, const double *__restrict__ s, const double *__restrict__ um,
+                               const double *__restrict__ hg, const double *__restrict__ tg,
+                               double *__restrict__ dU) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n0) return;
+    const long o = (long)blockIdx.y * n0 + r;
+    dU[o] = (um[o] + 0.5 * hg[o] + tg[o]) / s[r];
+}
+
 // c = Ubar / s on the surface
 __global__ void k_adj_c(int n0, const double *Ubar, const double *s, double *c) {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
@@ -423,17 +466,25 @@ __global__ void k_adj_c(int n0, const double *Ubar, const double *s, double *c) 
 // partial slices per component: far chunks plus the near slice
 int adjoint_nsplit(int n) { return cdiv(n, otf_chunk(n)) + 1; }
 
-// slices of the tangent-linear column passes over the M_0 surface sources
-int tlm_nsplit(int n0) { return cdiv(n0, kTlmChunk); }
+// slices of the tangent-linear column pass over the M_0 surface sources:
+// about kTlmWaves waves for n targets in tiles of 16, chunks of a multiple of
+// 4 sources
+static int tlm_chunk(int n, int n0) {
+    const int ks = std::max(1, std::min(16, cdiv(kTlmWaves, cdiv(n, 16))));
+    return cdiv(cdiv(n0, ks), 4) * 4;
+}
+int tlm_nsplit(int n, int n0) { return cdiv(n0, tlm_chunk(n, n0)); }
+size_t tlm_weights_size(int n0) { return (size_t)n0 * 6 * kTlmMax; }
 
 void launch_tlm_cols(const Nodes &N, int n0, int n, int nd, const double *dirs,
-                     const double *omega, const double *gamma, double *pA, double *pT,
+                     const double *omega, const double *gamma, double *W, double *pA, double *pT,
                      hipStream_t st) {
-    const int ns = tlm_nsplit(n0);
-    hipLaunchKernelGGL((k_tlm_cols<false>), dim3(cdiv(n, 256), ns), dim3(256), 0, st, N, n0, n, nd,
-                       kTlmChunk, dirs, omega, pA);
-    hipLaunchKernelGGL((k_tlm_cols<true>), dim3(cdiv(n0, 256), ns), dim3(256), 0, st, N, n0, n0,
-                       nd, kTlmChunk, dirs, gamma, pT);
+    const long nw = (long)tlm_weights_size(n0);
+    hipLaunchKernelGGL(k_tlm_weights, dim3(cdiv(nw, 256)), dim3(256), 0, st, n0, nd, dirs, omega,
+                       gamma, W);
+    const int chunk = tlm_chunk(n, n0);
+    hipLaunchKernelGGL(k_tlm_cols, dim3(cdiv(n, 64), cdiv(n0, chunk)), dim3(256), 0, st, N, n0, n,
+                       nd, chunk, W, pA, pT);
 }
 
 void launch_tlm_rhs(const Nodes &N, const Flow &F, int n0, int n, int nd, const double *dirs,
@@ -441,8 +492,14 @@ void launch_tlm_rhs(const Nodes &N, const Flow &F, int n0, int n, int nd, const 
                     const double *prow, const double *pA, const double *pT, double *rhs, long ldb,
                     double *um, hipStream_t st) {
     hipLaunchKernelGGL(k_tlm_rhs, dim3(cdiv(n, 256), nd), dim3(256), 0, st, N, F, n0, n, nd, dirs,
-                       omega, gamma, U, prow, adjoint_nsplit(n), pA, pT, tlm_nsplit(n0), rhs, ldb,
+                       omega, gamma, U, prow, adjoint_nsplit(n), pA, pT, tlm_nsplit(n, n0), rhs, ldb,
                        um);
+}
+
+void launch_tlm_finalize(int n0, int nd, const double *s, const double *um, const double *hg,
+                         const double *tg, double *dU, hipStream_t st) {
+    hipLaunchKernelGGL(k_tlm_finalize, dim3(cdiv(n0, 256), nd), dim3(256), 0, st, n0, s, um, hg,
+                       tg, dU);
 }
 
 void launch_adj_c(int n0, const double *Ubar, const double *s, double *c, hipStream_t st) {

@@ -245,12 +245,15 @@ __global__ __launch_bounds__(kCT * kCW) void k_circ_tile(int M, const double *__
 
 // The same for boundaries first..last of a layout in one launch (their tiles
 // run side by side): block b takes the tile of the boundary its index falls
-// in; alpha0 scales boundary 0, alpha every other one.
+// in; alpha0 scales boundary 0, alpha every other one.  blockIdx.y selects
+// one of several vectors, at strides fs (input) and os (output).
 __global__ __launch_bounds__(kCT * kCW) void k_circ_tiles(Layout L, int first, int last,
                                                           const double *__restrict__ rows,
-                                                          const double *__restrict__ f,
-                                                          double *out, double alpha0,
+                                                          const double *__restrict__ f, long fs,
+                                                          double *out, long os, double alpha0,
                                                           double alpha, double beta) {
+    f += blockIdx.y * fs;
+    out += blockIdx.y * os;
     int b = blockIdx.x, k = first;
     for (; k < last; ++k) {
         const int t = (L.off[k + 1] - L.off[k] + kCT - 1) / kCT;
@@ -542,14 +545,21 @@ void launch_circulant_rows(const Layout &L, int op, double *rows, hipStream_t st
     hipLaunchKernelGGL(k_circ_rows, dim3(cdiv(L.n, 256)), dim3(256), 0, st, L, op, rows);
 }
 
+void launch_circulant_batched(const Layout &L, const double *rows, const double *f, long fs,
+                              double *out, long os, int nv, double alpha0, double alpha,
+                              double beta, int first_block, int last_block, hipStream_t st) {
+    int tiles = 0;
+    for (int k = first_block; k <= last_block; ++k) tiles += cdiv(L.off[k + 1] - L.off[k], kCT);
+    if (tiles == 0 || nv < 1) return;
+    hipLaunchKernelGGL(k_circ_tiles, dim3(tiles, nv), dim3(kCT * kCW), 0, st, L, first_block,
+                       last_block, rows, f, fs, out, os, alpha0, alpha, beta);
+}
+
 void launch_circulant_apply2(const Layout &L, const double *rows, const double *f, double *out,
                              double alpha0, double alpha, double beta, int first_block,
                              int last_block, hipStream_t st) {
-    int tiles = 0;
-    for (int k = first_block; k <= last_block; ++k) tiles += cdiv(L.off[k + 1] - L.off[k], kCT);
-    if (tiles == 0) return;
-    hipLaunchKernelGGL(k_circ_tiles, dim3(tiles), dim3(kCT * kCW), 0, st, L, first_block,
-                       last_block, rows, f, out, alpha0, alpha, beta);
+    launch_circulant_batched(L, rows, f, 0, out, 0, 1, alpha0, alpha, beta, first_block,
+                             last_block, st);
 }
 
 void launch_circulant_apply(const Layout &L, const double *rows, const double *f, double *out,

@@ -1,4 +1,4 @@
-// One pass over the stored matrix for several right-hand sides:
+// One pass over a stored m x n matrix for several vectors:
 //   Y_s = A X_s,  s < nr,
 // on the matrix cores (v_mfma_f64_16x16x4_f64 for an FP64 matrix,
 // v_mfma_f32_16x16x4_f32 for FP32).  A wave owns RT tiles of 16 rows and ST
@@ -70,9 +70,10 @@ template <typename T, int ST> struct MultiShape {
 };
 
 template <typename T, int ST>
-__global__ __launch_bounds__(256) void k_mfma_multi(const T *__restrict__ A, long ld, int n,
-                                                    const T *__restrict__ X, long xs, int nr,
-                                                    int kchunk, double *__restrict__ part) {
+__global__ __launch_bounds__(256) void k_mfma_multi(const T *__restrict__ A, long ld, int m,
+                                                    int n, const T *__restrict__ X, long xs,
+                                                    int nr, int kchunk,
+                                                    double *__restrict__ part) {
     using M = Mfma<T>;
     using V = typename M::vec;
     constexpr int RT = MultiShape<T, ST>::RT;
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(256) void k_mfma_multi(const T *__restrict__ A, lon
     __shared__ float lds[4][R * SW];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int row0 = (blockIdx.x * 4 + wv) * R;
-    if (row0 >= n) return;
+    if (row0 >= m) return;
     const int kb = blockIdx.y * kchunk;
     const int ke = min(n, kb + kchunk);
     const int i = lane & 15, q = lane >> 4;
@@ -94,7 +95,7 @@ __global__ __launch_bounds__(256) void k_mfma_multi(const T *__restrict__ A, lon
     const V *ap[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        const int r = min(row0 + 4 * p + lr, n - 1);
+        const int r = min(row0 + 4 * p + lr, m - 1);
         ap[p] = reinterpret_cast<const V *>(A + (long)r * ld + kb + lc);
     }
     const V *xp[ST];
@@ -194,7 +195,7 @@ __global__ __launch_bounds__(256) void k_mfma_multi(const T *__restrict__ A, lon
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int rr = row0 + 16 * rt + M::row(q, r);
-                if (rr < n) part[((long)blockIdx.y * nr + s) * n + rr] = (double)c[rt][st][r];
+                if (rr < m) part[((long)blockIdx.y * nr + s) * m + rr] = (double)c[rt][st][r];
             }
         }
 }
@@ -206,11 +207,11 @@ __global__ __launch_bounds__(256) void k_mfma_multi(const T *__restrict__ A, lon
 // last read at step t - 2, and every wave has passed the barrier of step t - 1
 // (which follows its reads of step t - 2) before any wave writes it again.
 // Each wave keeps its own matrix tile in LDS as in k_mfma_multi.  Waves past
-// the last row load row n - 1, join every barrier and store nothing.
+// the last row load row m - 1, join every barrier and store nothing.
 template <typename T>
-__global__ __launch_bounds__(256) void k_mfma_multi_shared(const T *__restrict__ A, long ld, int n,
-                                                           const T *__restrict__ X, long xs,
-                                                           int nr, int kchunk,
+__global__ __launch_bounds__(256) void k_mfma_multi_shared(const T *__restrict__ A, long ld, int m,
+                                                           int n, const T *__restrict__ X,
+                                                           long xs, int nr, int kchunk,
                                                            double *__restrict__ part) {
     using M = Mfma<T>;
     using V = typename M::vec;
@@ -234,7 +235,7 @@ __global__ __launch_bounds__(256) void k_mfma_multi_shared(const T *__restrict__
     const V *ap[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        const int r = min(row0 + 4 * p + lr, n - 1);
+        const int r = min(row0 + 4 * p + lr, m - 1);
         ap[p] = reinterpret_cast<const V *>(A + (long)r * ld + kb + lc);
     }
     // B piece f = tid + 256 j: system f / 16, columns (f % 16) E ..
@@ -310,7 +311,7 @@ __global__ __launch_bounds__(256) void k_mfma_multi_shared(const T *__restrict__
     int k0 = kb;
     for (; k0 + KS < ke; k0 += KS) body(k0, true, false);
     body(k0, false, k0 + KS > ke);
-    if (row0 >= n) return;
+    if (row0 >= m) return;
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -320,21 +321,21 @@ __global__ __launch_bounds__(256) void k_mfma_multi_shared(const T *__restrict__
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int rr = row0 + 16 * rt + M::row(q, r);
-                if (rr < n) part[((long)blockIdx.y * nr + s) * n + rr] = (double)c[rt][st][r];
+                if (rr < m) part[((long)blockIdx.y * nr + s) * m + rr] = (double)c[rt][st][r];
             }
         }
 }
 
-// y_s = c_s - sum_k part[k][s] (or the plain sum when c is null)
-__global__ void k_reduce_multi(int n, int nr, const double *__restrict__ part, int ks,
+// y_s = c_s - sum_k part[k][s] (or the plain sum when c is null), m rows
+__global__ void k_reduce_multi(int m, int nr, const double *__restrict__ part, int ks,
                                const double *__restrict__ c, long cs, double *__restrict__ y,
                                long ys) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
     const int s = blockIdx.y;
-    if (m >= n || s >= nr) return;
+    if (r >= m || s >= nr) return;
     double acc = 0.0;
-    for (int k = 0; k < ks; ++k) acc += part[((long)k * nr + s) * n + m];
-    y[(long)s * ys + m] = c ? c[(long)s * cs + m] - acc : acc;
+    for (int k = 0; k < ks; ++k) acc += part[((long)k * nr + s) * m + r];
+    y[(long)s * ys + r] = c ? c[(long)s * cs + r] - acc : acc;
 }
 
 __global__ void k_copy_strided(const double *src, long ss, double *dst, long ds, int n) {
@@ -355,39 +356,40 @@ struct MultiGrid {
     int kchunk, ksn;
 };
 
-MultiGrid multi_grid(int n, int rt, int waves) {
-    const int tiles = cdiv(n, 16 * rt);
+MultiGrid multi_grid(int m, int n, int rt, int waves) {
+    const int tiles = cdiv(m, 16 * rt);
     const int ks = std::max(1, std::min(16, cdiv(waves, tiles)));
     const int kchunk = cdiv(cdiv(n, ks), 64) * 64;
     return {kchunk, cdiv(n, kchunk)};
 }
 
-template <typename T, int ST> MultiGrid multi_grid_for(int n) {
-    return multi_grid(n, MultiShape<T, ST>::RT, MultiShape<T, ST>::waves);
+template <typename T, int ST> MultiGrid multi_grid_for(int m, int n) {
+    return multi_grid(m, n, MultiShape<T, ST>::RT, MultiShape<T, ST>::waves);
 }
 
 template <typename T, int ST>
-void launch_mfma_st(const T *A, long ld, int n, const T *X, long xs, int nr, const double *c,
-                    long cs, double *y, long ys, double *part, hipStream_t st) {
-    const MultiGrid g = multi_grid_for<T, ST>(n);
-    const dim3 grid(cdiv(n, 4 * 16 * MultiShape<T, ST>::RT), g.ksn);
+void launch_mfma_st(const T *A, long ld, int m, int n, const T *X, long xs, int nr,
+                    const double *c, long cs, double *y, long ys, double *part, hipStream_t st) {
+    const MultiGrid g = multi_grid_for<T, ST>(m, n);
+    const dim3 grid(cdiv(m, 4 * 16 * MultiShape<T, ST>::RT), g.ksn);
     if (ST == 2)
-        hipLaunchKernelGGL((k_mfma_multi_shared<T>), grid, dim3(256), 0, st, A, ld, n, X, xs, nr,
-                           g.kchunk, part);
+        hipLaunchKernelGGL((k_mfma_multi_shared<T>), grid, dim3(256), 0, st, A, ld, m, n, X, xs,
+                           nr, g.kchunk, part);
     else
-        hipLaunchKernelGGL((k_mfma_multi<T, 1>), grid, dim3(256), 0, st, A, ld, n, X, xs, nr,
+        hipLaunchKernelGGL((k_mfma_multi<T, 1>), grid, dim3(256), 0, st, A, ld, m, n, X, xs, nr,
                            g.kchunk, part);
-    hipLaunchKernelGGL(k_reduce_multi, dim3(cdiv(n, 256), nr), dim3(256), 0, st, n, nr, part,
+    hipLaunchKernelGGL(k_reduce_multi, dim3(cdiv(m, 256), nr), dim3(256), 0, st, m, nr, part,
                        g.ksn, c, cs, y, ys);
 }
 
 template <typename T>
-void launch_mfma_multi(const T *A, long ld, int n, const T *X, long xs, int nr, const double *c,
-                       long cs, double *y, long ys, double *part, hipStream_t st) {
+void launch_mfma_multi(const T *A, long ld, int m, int n, const T *X, long xs, int nr,
+                       const double *c, long cs, double *y, long ys, double *part,
+                       hipStream_t st) {
     if (nr > 16)
-        launch_mfma_st<T, 2>(A, ld, n, X, xs, nr, c, cs, y, ys, part, st);
+        launch_mfma_st<T, 2>(A, ld, m, n, X, xs, nr, c, cs, y, ys, part, st);
     else
-        launch_mfma_st<T, 1>(A, ld, n, X, xs, nr, c, cs, y, ys, part, st);
+        launch_mfma_st<T, 1>(A, ld, m, n, X, xs, nr, c, cs, y, ys, part, st);
 }
 
 }  // namespace
@@ -395,13 +397,18 @@ void launch_mfma_multi(const T *A, long ld, int n, const T *X, long xs, int nr, 
 void launch_mfma_multi64(const double *A, long ld, int n, const double *X, long xs, int nr,
                          const double *c, long cs, double *y, long ys, double *part,
                          hipStream_t st) {
-    launch_mfma_multi<double>(A, ld, n, X, xs, nr, c, cs, y, ys, part, st);
+    launch_mfma_multi<double>(A, ld, n, n, X, xs, nr, c, cs, y, ys, part, st);
 }
 
 void launch_mfma_multi32(const float *A, long ld, int n, const float *X, long xs, int nr,
                          const double *c, long cs, double *y, long ys, double *part,
                          hipStream_t st) {
-    launch_mfma_multi<float>(A, ld, n, X, xs, nr, c, cs, y, ys, part, st);
+    launch_mfma_multi<float>(A, ld, n, n, X, xs, nr, c, cs, y, ys, part, st);
+}
+
+void launch_mfma_rect64(const double *A, long ld, int m, int n, const double *X, long xs, int nr,
+                        double *y, long ys, double *part, hipStream_t st) {
+    launch_mfma_multi<double>(A, ld, m, n, X, xs, nr, nullptr, 0, y, ys, part, st);
 }
 
 void launch_to_f32_batched(const double *src, long ss, float *dst, long ds, int n, int nr,
@@ -419,10 +426,18 @@ void launch_copy_strided(const double *src, long ss, double *dst, long ds, int n
 // the largest partial-sum buffer any shape and precision needs for nr systems
 int multi_part_size(int n, int nr) {
     int ks = 0;
-    for (const MultiGrid g : {multi_grid_for<float, 1>(n), multi_grid_for<float, 2>(n),
-                              multi_grid_for<double, 1>(n), multi_grid_for<double, 2>(n)})
+    for (const MultiGrid g : {multi_grid_for<float, 1>(n, n), multi_grid_for<float, 2>(n, n),
+                              multi_grid_for<double, 1>(n, n), multi_grid_for<double, 2>(n, n)})
         ks = std::max(ks, g.ksn);
     return ks * nr * n;
+}
+
+// the same for the FP64 product of an m x n matrix
+int multi_part_size_rect64(int m, int n, int nr) {
+    int ks = 0;
+    for (const MultiGrid g : {multi_grid_for<double, 1>(m, n), multi_grid_for<double, 2>(m, n)})
+        ks = std::max(ks, g.ksn);
+    return ks * nr * m;
 }
 
 }  // namespace wwbi
