@@ -799,6 +799,46 @@ __device__ __forceinline__ void rows_tile_a64(const Tgt (&t)[kTPT], const SrcA *
     }
 }
 
+// Far entries of the normal-velocity map T (targets on the surface) for a
+// tile whose sources all lie on one boundary, with no near-band pair.  With
+// the same quotient and the target data halved (a = dx_p / 2, b = dy_p / 2),
+// the entry times x_q is w_q x_q times
+//   surface source: (a PI + b PR) / |D|^2 + h((alpha_q - alpha_p)),
+//   wall source:   -(a PR - b PI) / |D|^2,
+// h read from the surface's table (for one source, the wave's consecutive
+// targets read consecutive entries).
+struct SrcT {
+    double ex, ey, exl, eyl, wx;
+    int loc;
+};
+
+template <bool SURF, bool LO>
+__device__ __forceinline__ void rows_tile_t64(const Tgt (&t)[kTPT], const SrcT *sv, int m,
+                                              const double *hrow, double (&acc)[kTPT]) {
+    double ta[kTPT], tb[kTPT];
+#pragma unroll
+    for (int u = 0; u < kTPT; ++u) { ta[u] = 0.5 * t[u].dx; tb[u] = 0.5 * t[u].dy; }
+    for (int i = 0; i < m; ++i) {
+        const SrcT q = sv[i];
+#pragma unroll
+        for (int u = 0; u < kTPT; ++u) {
+            const double dr = LO ? (q.ex - t[u].ex) + (q.exl - t[u].exl) : q.ex - t[u].ex;
+            const double di = LO ? (q.ey - t[u].ey) + (q.eyl - t[u].eyl) : q.ey - t[u].ey;
+            const double nr = q.ex + t[u].ex, ni = q.ey + t[u].ey;
+            const double inv = recip64_from32(dr * dr + di * di);
+            const double pr = nr * dr + ni * di;
+            const double pi = ni * dr - nr * di;
+            if (SURF) {
+                int d = q.loc - t[u].loc;
+                if (d < 0) d += t[u].M;
+                acc[u] += q.wx * ((ta[u] * pi + tb[u] * pr) * inv + hrow[d]);
+            } else {
+                acc[u] -= q.wx * ((ta[u] * pr - tb[u] * pi) * inv);
+            }
+        }
+    }
+}
+
 template <int MODE, bool ACC32>
 __global__ __launch_bounds__(256) void k_otf_rows(Nodes N, const double *hrow, int r0, int nr,
                                                   int c0, int nc,
@@ -807,12 +847,15 @@ __global__ __launch_bounds__(256) void k_otf_rows(Nodes N, const double *hrow, i
                                                   double *__restrict__ part,
                                                   const int *active) {
     if (active && *active == 0) return;
-    constexpr bool FAST = MODE == 0 && !ACC32;        // specialised far tiles of A
-    constexpr int kFastStage = FAST ? kOtfStage : 1;
+    // specialised far tiles of A and of T
+    constexpr bool FAST = (MODE == 0 || MODE == 2) && !ACC32;
+    constexpr int kStageA = FAST && MODE == 0 ? kOtfStage : 1;
+    constexpr int kStageT = FAST && MODE == 2 ? kOtfStage : 1;
     __shared__ Src ss[kOtfStage];
     __shared__ double sx[kOtfStage];
-    __shared__ SrcA sa[kFastStage];
-    __shared__ double swx[kFastStage];
+    __shared__ SrcA sa[kStageA];
+    __shared__ double swx[kStageA];
+    __shared__ SrcT stt[kStageT];
     const int wb = wave_base();
     Tgt t[kTPT];
     bool live[kTPT];
@@ -835,11 +878,13 @@ __global__ __launch_bounds__(256) void k_otf_rows(Nodes N, const double *hrow, i
             const double xv = x[q];
             ss[threadIdx.x] = sv;
             sx[threadIdx.x] = xv;
-            if (FAST) {
+            if constexpr (FAST && MODE == 0) {
                 const double hw = 0.5 * sv.w * xv;
                 sa[threadIdx.x] = SrcA{sv.ex, sv.ey, sv.exl, sv.eyl, hw * sv.dx, hw * sv.dy};
                 swx[threadIdx.x] = sv.w * xv;
             }
+            if constexpr (FAST && MODE == 2)
+                stt[threadIdx.x] = SrcT{sv.ex, sv.ey, sv.exl, sv.eyl, sv.w * xv, sv.loc};
         }
         __syncthreads();
         const int m = min(kOtfStage, ce - cc);
@@ -855,13 +900,21 @@ __global__ __launch_bounds__(256) void k_otf_rows(Nodes N, const double *hrow, i
             }
         }
         const int kq = FAST ? range_boundary(N, c0 + cc, c0 + cc + m - 1) : -1;
-        if (FAST && apart && kp >= 0 && kq >= 0) {
+        if (FAST && apart && kp >= 0 && kq >= 0 && (MODE == 0 || kp == 0)) {
             const bool ec = corr != 0 && kp == kq && kp >= 2;
             const int o0 = blockIdx.x * 256 * kTPT + wb;
             const bool lo = o0 >= nr || !cells_far(N, r0 + o0, r0 + min(o0 + 256 * (kTPT - 1) + 63,
                                                                          nr - 1),
                                                    c0 + cc, c0 + cc + m - 1);
-            if (lo) {
+            if constexpr (MODE == 2) {
+                if (kq == 0) {
+                    if (lo) rows_tile_t64<true, true>(t, stt, m, hrow, acc);
+                    else rows_tile_t64<true, false>(t, stt, m, hrow, acc);
+                } else {
+                    if (lo) rows_tile_t64<false, true>(t, stt, m, hrow, acc);
+                    else rows_tile_t64<false, false>(t, stt, m, hrow, acc);
+                }
+            } else if (lo) {
                 if ((kp == 0) == (kq == 0)) {
                     if (ec) rows_tile_a64<kFastIm, true, true>(t, sa, swx, m, acc);
                     else rows_tile_a64<kFastIm, false, true>(t, sa, swx, m, acc);
