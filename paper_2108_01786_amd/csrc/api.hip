@@ -173,7 +173,7 @@ void Ctx::release() {
 // geometry set-up and validation
 // ---------------------------------------------------------------------------
 
-int Ctx::setup(const wwbi_geom *g, const double *phi, int nphi) {
+int Ctx::setup(const wwbi_geom *g, const double *phi, int nphi, bool check) {
     if (!g || !g->M || !g->x || !g->y || !g->dx || !g->dy || !g->ddx || !g->ddy)
         return WWBI_EINVAL_NULL;
     if (g->nb < 2 || g->nb > kMaxB) return WWBI_EINVAL_SIZE;
@@ -214,7 +214,15 @@ int Ctx::setup(const wwbi_geom *g, const double *phi, int nphi) {
     if (hipMemcpyAsync(hst, val, sizeof(double) * (4 * L.nb + 2), hipMemcpyDeviceToHost,
                        stream) != hipSuccess)
         return WWBI_EHIP;
-    if (hipStreamSynchronize(stream) != hipSuccess) return WWBI_EHIP;
+    if (hipEventRecord(pollev[2], stream) != hipSuccess) return WWBI_EHIP;
+    return check ? setup_check() : WWBI_OK;
+}
+
+// The device-side checks of setup(): finite samples and data, even counts in
+// range, the orientation of every boundary, and the near-pair count.
+int Ctx::setup_check() {
+    // wait for the copy of the checks only: work queued after it keeps running
+    if (hipEventSynchronize(pollev[2]) != hipSuccess) return WWBI_EHIP;
     const double *h = (const double *)hst;
     for (int k = 0; k < L.nb; ++k)
         if (h[4 * k] != 0.0) return WWBI_EINVAL_NONFINITE;
@@ -1067,7 +1075,7 @@ int solve_phi_impl(Ctx *c, const wwbi_geom *g, const double *phi, const wwbi_opt
     if (!rc) {
         c->restart_cap = std::max(c->restart_cap, o->restart);
         c->begin_report((o->flags & WWBI_FLAG_PROFILE) != 0);
-        rc = c->setup(g, phi, g ? g->M[0] : 0);
+        rc = c->setup(g, phi, g ? g->M[0] : 0, false);
     }
     if (rc) {
         if (rep) { std::memset(rep, 0, sizeof(*rep)); rep->status = rc; }
@@ -1076,6 +1084,8 @@ int solve_phi_impl(Ctx *c, const wwbi_geom *g, const double *phi, const wwbi_opt
     const int n = c->L.n;
     const long ld = round_up(n, 64);
     double *b = c->vec[VB], *x = c->vec[VX];
+    // the right-hand side, circulant rows and matrix go into internal buffers
+    // only, so they are queued before the input checks are read back
     launch_rhs_phi(c->L, c->N, c->F, phi, c->psi_wall, b, c->stream);
     launch_circulant_rows(c->L, WWBI_OP_D, c->rowD, c->stream);
     launch_circulant_rows(c->L, WWBI_OP_H, c->rowH, c->stream);
@@ -1091,6 +1101,11 @@ int solve_phi_impl(Ctx *c, const wwbi_geom *g, const double *phi, const wwbi_opt
             launch_assemble64(c->L, c->N, o->flags, (double *)c->A, ld, c->stream);
     }
     hipEventRecord(c->ev[2], c->stream);
+    rc = c->setup_check();
+    if (rc) {
+        if (rep) { std::memset(rep, 0, sizeof(*rep)); rep->status = rc; }
+        return rc;
+    }
     const bool xz = o->x0 == nullptr;
     if (!xz) launch_copy(x, o->x0, n, c->stream);
     Op op64{stored ? OP_A_S64 : OP_A_O64, n, ld, o->flags, o->band};

@@ -156,7 +156,7 @@ struct Ctx {
     int cyc_id = 0;            // id of the latest GMRES cycle enqueued on gs
 
     hipEvent_t ev[5] = {};
-    hipEvent_t pollev[2] = {};
+    hipEvent_t pollev[3] = {};   // two convergence polls and the input checks' copy
     hipEvent_t prof[2 * kProfPairs] = {};
     bool profiling = false;
     // launch -> (cycle, step) of every profiled matvec; steps at or beyond a
@@ -189,7 +189,10 @@ struct Ctx {
     int ensure_matrix(size_t bytes);
     int ensure_matrix64(size_t bytes);
     void release();
-    int setup(const wwbi_geom *g, const double *phi, int nphi);
+    // check = false leaves the device-side input checks to setup_check(), so
+    // that work which writes only internal buffers can be queued meanwhile
+    int setup(const wwbi_geom *g, const double *phi, int nphi, bool check = true);
+    int setup_check();
     // x32 (may be null): an FP32 copy of x for the stored FP32 operators
     void apply(const Op &op, const double *x, const float *x32, const double *c, double *y,
                const int *active);
