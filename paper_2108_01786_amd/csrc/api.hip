@@ -1792,7 +1792,7 @@ int wwbi_adjoint_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, con
     if (!rc) {
         c->restart_cap = std::max(c->restart_cap, o->restart);
         c->begin_report((o->flags & WWBI_FLAG_PROFILE) != 0);
-        rc = c->setup(g, dJdU, g ? g->M[0] : 0);
+        rc = c->setup(g, dJdU, g ? g->M[0] : 0, false);
     }
     const int n = rc ? 0 : c->L.n, n0 = rc ? 0 : c->L.off[1];
     if (!rc) {
@@ -1809,20 +1809,11 @@ int wwbi_adjoint_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, con
     double *mu = c->vec[VMU], *lam = c->vec[VLAM];
     launch_circulant_rows(c->L, WWBI_OP_D, c->rowD, sm);
     launch_circulant_rows(c->L, WWBI_OP_H, c->rowH, sm);
-    // forward quantities: gamma = (-D omega_0, D omega_j) and U
-    c->gamma_from_omega(omega, gam);
-    c->eval_U_from_gamma(gam, U);
-    // c = Ubar / s;  gammabar = T^T c - H c / 2 (surface block);  mu = Gamma^T gammabar
-    launch_adj_c(n0, dJdU, c->s, cv, sm);
-    launch_rflavour(c->L, c->N, c->hrow, 2, 1, 0, n0, 0, n, cv, c->part, nullptr, sm);
-    launch_reduce_partials(n, c->part, rflavour_nsplit(c->N, n0, n, 1), nullptr, 1.0, gbar,
-                           nullptr, sm);
-    launch_circulant_apply(c->L, c->rowH, cv, gbar, -0.5, 1.0, 0, 0, sm);
-    launch_circulant_apply2(c->L, c->rowD, gbar, mu, 1.0, -1.0, 0.0, 0, c->L.nb - 1, sm);
     hipEventRecord(c->ev[1], sm);
-    // transpose solve A^T lambda = mu; the stored path assembles A^T itself, so
-    // that its products stream rows (the forward matvec, about 6% faster at
-    // large n than the column-split transpose product)
+    // the transpose solve A^T lambda = mu; the stored path assembles A^T itself,
+    // so that its products stream rows (the forward matvec, about 6% faster at
+    // large n than the column-split transpose product).  The matrix goes into
+    // internal memory only, so it is queued before the input checks are read.
     const bool stored = o->matvec != WWBI_MATVEC_ON_THE_FLY;
     const bool fp32 = o->precision == WWBI_FP32_REFINED;
     if (stored) {
@@ -1834,6 +1825,21 @@ int wwbi_adjoint_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, con
             launch_assemble64_T(c->L, c->N, o->flags, (double *)c->A, ld, sm);
     }
     hipEventRecord(c->ev[2], sm);
+    rc = c->setup_check();
+    if (rc) {
+        if (rep) { std::memset(rep, 0, sizeof(*rep)); rep->status = rc; }
+        return rc;
+    }
+    // forward quantities: gamma = (-D omega_0, D omega_j) and U
+    c->gamma_from_omega(omega, gam);
+    c->eval_U_from_gamma(gam, U);
+    // c = Ubar / s;  gammabar = T^T c - H c / 2 (surface block);  mu = Gamma^T gammabar
+    launch_adj_c(n0, dJdU, c->s, cv, sm);
+    launch_rflavour(c->L, c->N, c->hrow, 2, 1, 0, n0, 0, n, cv, c->part, nullptr, sm);
+    launch_reduce_partials(n, c->part, rflavour_nsplit(c->N, n0, n, 1), nullptr, 1.0, gbar,
+                           nullptr, sm);
+    launch_circulant_apply(c->L, c->rowH, cv, gbar, -0.5, 1.0, 0, 0, sm);
+    launch_circulant_apply2(c->L, c->rowD, gbar, mu, 1.0, -1.0, 0.0, 0, c->L.nb - 1, sm);
     int status;
     double bytes;
     const bool xz = o->x0 == nullptr;
@@ -1881,7 +1887,7 @@ int wwbi_tangent_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, int
         c->restart_cap = std::max(c->restart_cap, o->restart);
         c->begin_report((o->flags & WWBI_FLAG_PROFILE) != 0);
         // the directions are checked for finite values with the geometry
-        rc = c->setup(g, dirs, 7 * nd * g->M[0]);
+        rc = c->setup(g, dirs, 7 * nd * g->M[0], false);
     }
     const int n = rc ? 0 : c->L.n, n0 = rc ? 0 : c->L.off[1];
     const int nsr = rc ? 0 : adjoint_nsplit(n), nsc = rc ? 0 : tlm_nsplit(n, n0);
@@ -1905,17 +1911,10 @@ int wwbi_tangent_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, int
     double *tgs = hgs + (size_t)nd * n0, *wts = tgs + (size_t)nd * n0;
     launch_circulant_rows(c->L, WWBI_OP_D, c->rowD, sm);
     launch_circulant_rows(c->L, WWBI_OP_H, c->rowH, sm);
-    // base state: gamma = (-D omega_0, D omega_j) and U
-    c->gamma_from_omega(omega, gam);
-    c->eval_U_from_gamma(gam, U);
-    // the terms of dA omega and dT gamma: row sums (per target node) and the
-    // source-moving column parts of every direction; then the right-hand sides
-    launch_adj_rows(c->N, c->hrow, n0, n, omega, gam, prow, sm);
-    launch_tlm_cols(c->N, n0, n, nd, dirs, omega, gam, wts, pA, pT, sm);
-    launch_tlm_rhs(c->N, c->F, n0, n, nd, dirs, omega, gam, U, prow, pA, pT, c->mw.b, ldv, um,
-                   sm);
     hipEventRecord(c->ev[1], sm);
-    // the nd systems share A: one multi-RHS solve (matrix read once per step)
+    // the nd systems share A: one multi-RHS solve (matrix read once per step).
+    // The matrix goes into internal memory only, so it is queued before the
+    // input checks are read back.
     const bool fp32 = o->precision == WWBI_FP32_REFINED;
     rc = c->ensure_matrix((size_t)n * ld * (fp32 ? 4 : 8));
     if (rc) { c->finish_report(rep, rc, st, 0); return rc; }
@@ -1927,6 +1926,20 @@ int wwbi_tangent_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, int
         launch_assemble64(c->L, c->N, o->flags, (double *)c->A, ld, sm);
     }
     hipEventRecord(c->ev[2], sm);
+    rc = c->setup_check();
+    if (rc) {
+        if (rep) { std::memset(rep, 0, sizeof(*rep)); rep->status = rc; }
+        return rc;
+    }
+    // base state: gamma = (-D omega_0, D omega_j) and U
+    c->gamma_from_omega(omega, gam);
+    c->eval_U_from_gamma(gam, U);
+    // the terms of dA omega and dT gamma: row sums (per target node) and the
+    // source-moving column parts of every direction; then the right-hand sides
+    launch_adj_rows(c->N, c->hrow, n0, n, omega, gam, prow, sm);
+    launch_tlm_cols(c->N, n0, n, nd, dirs, omega, gam, wts, pA, pT, sm);
+    launch_tlm_rhs(c->N, c->F, n0, n, nd, dirs, omega, gam, U, prow, pA, pT, c->mw.b, ldv, um,
+                   sm);
     int status;
     if (!fp32)
         status = c->gmres_multi(OP_A_S64, n, ld, c->mw.b, c->mw.x, nd, o->tol, o->restart,
