@@ -82,7 +82,7 @@ int Ctx::ws_plan(int n, int restart, WsItem *it, bool recycle) {
     D(eIl, capeIl, nn);
     D(cell, capcell, 4 * (nn / kCellNodes) + 4);
     I(nlist, capnlist, (size_t)kNearStride * (nn / kCellNodes));
-    D(val, capval, 4 * kMaxB + 8);
+    D(val, capval, 4 * kMaxB + 8 + kValidateBlocks);
     return k;
 }
 
@@ -209,10 +209,11 @@ int Ctx::setup(const wwbi_geom *g, const double *phi, int nphi, bool check) {
     launch_cells(N, cell, stream);
     launch_circulant_rows(L, kOpHalfCot, hrow, stream);
     N.near = 0;
+    val_blocks = validate_data_blocks(phi ? nphi : 0);
     launch_validate(L, N, phi, phi ? nphi : 0, val, stream);   // also zeroes val[4 nb + 1]
     launch_near_cells(N, nlist, val + 4 * L.nb + 1, stream);
-    if (hipMemcpyAsync(hst, val, sizeof(double) * (4 * L.nb + 2), hipMemcpyDeviceToHost,
-                       stream) != hipSuccess)
+    if (hipMemcpyAsync(hst, val, sizeof(double) * (4 * L.nb + 2 + val_blocks),
+                       hipMemcpyDeviceToHost, stream) != hipSuccess)
         return WWBI_EHIP;
     if (hipEventRecord(pollev[2], stream) != hipSuccess) return WWBI_EHIP;
     return check ? setup_check() : WWBI_OK;
@@ -226,7 +227,8 @@ int Ctx::setup_check() {
     const double *h = (const double *)hst;
     for (int k = 0; k < L.nb; ++k)
         if (h[4 * k] != 0.0) return WWBI_EINVAL_NONFINITE;
-    if (h[4 * L.nb] != 0.0) return WWBI_EINVAL_NONFINITE;
+    for (int b = 0; b < val_blocks; ++b)
+        if (h[4 * L.nb + 2 + b] != 0.0) return WWBI_EINVAL_NONFINITE;
     for (int k = 0; k < L.nb; ++k)
         if (h[4 * k + 3] != 0.0) return WWBI_EINVAL_RANGE;
     N.near = h[4 * L.nb + 1] > 0.0 ? 1 : 0;

@@ -177,6 +177,7 @@ struct Ctx {
     int nprof = 0;
 
     long near_pairs = 0;       // near pairs outside the band of the last geometry
+    int val_blocks = 1;        // blocks of the data check of the last setup
     // workspace carved from a fixed region for one call (the allocation-free
     // entry point): ensure() then checks capacities and never allocates
     bool fixed_ws = false;

@@ -122,8 +122,14 @@ void launch_prep_nodes(const Layout &L, const double *x, const double *y, const 
                        double *ex, double *ey, double *exl, double *eyl, hipStream_t st);
 void launch_cells(const Nodes &N, double *cell, hipStream_t st);
 void launch_near_cells(const Nodes &N, int *lists, double *count, hipStream_t st);
+// Input checks: per boundary k, out[4k..4k+3] = (non-finite samples, signed
+// area, mean x', samples beyond the height limit); out[4 nb + 1] = 0 (the
+// near-pair count, added by launch_near_cells); out[4 nb + 2 + b] for
+// b < validate_data_blocks(nphi): non-finite entries of the data array.
+constexpr int kValidateBlocks = 64;
+int validate_data_blocks(int nphi);
 void launch_validate(const Layout &L, const Nodes &N, const double *phi, int nphi,
-                     double *out /* 3*nb+1 */, hipStream_t st);
+                     double *out, hipStream_t st);
 void launch_rhs_phi(const Layout &L, const Nodes &N, const Flow &F, const double *phi,
                     const double *psi_wall, double *b, hipStream_t st);
 void launch_umv(const Nodes &N, const Flow &F, int first, int count, double *out,

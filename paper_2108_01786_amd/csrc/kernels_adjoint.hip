@@ -22,7 +22,7 @@ namespace {
 inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 constexpr int kStage = 256;
 constexpr int kTlmMax = 32;      // directions of one tangent-linear launch
-constexpr int kTlmWaves = 2048;  // waves the column pass's source split aims at
+constexpr int kTlmWaves = 4608;  // waves the column pass's source split aims at
 
 struct Cx {
     double re, im;
@@ -348,10 +348,24 @@ __global__ __launch_bounds__(256) void k_tlm_cols(Nodes N, int n0, int n, int nd
     const bool two = nd > 16;
     const int qb = blockIdx.y * chunk, qe = min(n0, qb + chunk);
     v4d a0 = {0.0, 0.0, 0.0, 0.0}, a1 = a0, t0 = a0, t1 = a0;
+    // the step's source and weights, loaded one step ahead
+    auto weights = [&](int qc, double (&wo)[12]) __attribute__((always_inline)) {
+        const double *w = W + (long)qc * 6 * kTlmMax + il;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            wo[2 * c] = w[c * kTlmMax];
+            wo[2 * c + 1] = w[c * kTlmMax + 16];
+        }
+    };
+    Src s = load_src(N, min(qb + kq, n0 - 1));
+    double wc[12];
+    weights(min(qb + kq, n0 - 1), wc);
     for (int qs = qb; qs < qe; qs += 4) {
         const int q = qs + kq;
-        const int qc = min(q, n0 - 1);
-        const Src s = load_src(N, qc);
+        const int qn = min(qs + 4 + kq, n0 - 1);
+        const Src sn = load_src(N, qn);
+        double wn[12];
+        weights(qn, wn);
         double ca[4] = {0.0, 0.0, 0.0, 0.0}, ct[2] = {0.0, 0.0};
         if (live && q < qe && q != p) {
             double cr, ci;
@@ -367,23 +381,22 @@ __global__ __launch_bounds__(256) void k_tlm_cols(Nodes N, int n0, int n, int nd
                 ca[0] = -dz.re; ca[1] = dz.im; ca[2] = -dd.re; ca[3] = dd.im;
             }
         }
-        const double *w = W + (long)qc * 6 * kTlmMax + il;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-            a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[c], w[c * kTlmMax], a0, 0, 0, 0);
-            if (two)
-                a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[c], w[c * kTlmMax + 16], a1, 0, 0, 0);
+            a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[c], wc[2 * c], a0, 0, 0, 0);
+            if (two) a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ca[c], wc[2 * c + 1], a1, 0, 0, 0);
         }
         if (tpart) {
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-                t0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ct[c], w[(4 + c) * kTlmMax], t0, 0, 0,
-                                                          0);
+                t0 = __builtin_amdgcn_mfma_f64_16x16x4f64(ct[c], wc[8 + 2 * c], t0, 0, 0, 0);
                 if (two)
-                    t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ct[c], w[(4 + c) * kTlmMax + 16],
-                                                              t1, 0, 0, 0);
+                    t1 = __builtin_amdgcn_mfma_f64_16x16x4f64(ct[c], wc[9 + 2 * c], t1, 0, 0, 0);
             }
         }
+        s = sn;
+#pragma unroll
+        for (int e = 0; e < 12; ++e) wc[e] = wn[e];
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {

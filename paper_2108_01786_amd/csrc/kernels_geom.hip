@@ -1,5 +1,7 @@
 // Node preparation, validation, right-hand side, multi-valued terms, spectral
 // circulants and the final assembly of the normal velocity.
+#include <algorithm>
+
 #include "ddmath.h"
 #include "entries.h"
 #include "internal.h"
@@ -60,17 +62,20 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
 // One block per boundary: count of non-finite samples, signed area
 // (1/2) sum (x y' - y x') 2pi/M (negative = clockwise) and the mean of x'.
 // Block nb checks the potential.
-__global__ void k_validate(Layout L, Nodes N, const double *phi, int nphi, double *out) {
+__global__ void k_validate(Layout L, Nodes N, const double *phi, int nphi, int pb, double *out) {
     __shared__ double sh[16];
     const int k = blockIdx.x;
-    if (k == L.nb) {
+    if (k >= L.nb) {
+        // the data array: block b of pb counts its share (grid-stride) into
+        // out[4 nb + 2 + b], for the host to add
+        const int b = k - L.nb;
         double bad = 0.0;
-        for (int i = threadIdx.x; i < nphi; i += blockDim.x)
+        for (long i = (long)b * blockDim.x + threadIdx.x; i < nphi; i += (long)pb * blockDim.x)
             bad += isfinite(phi[i]) ? 0.0 : 1.0;
         bad = block_sum(bad, sh);
         if (threadIdx.x == 0) {
-            out[4 * L.nb] = bad;
-            out[4 * L.nb + 1] = 0.0;      // the near-pair count, added next
+            out[4 * L.nb + 2 + b] = bad;
+            if (b == 0) out[4 * L.nb + 1] = 0.0;   // the near-pair count, added next
         }
         return;
     }
@@ -489,9 +494,14 @@ void launch_prep_nodes(const Layout &L, const double *x, const double *y, const 
                        ddy, bid, loc, Mk, w, s, lre, lim, ex, ey, exl, eyl);
 }
 
+int validate_data_blocks(int nphi) {
+    return std::max(1, std::min(kValidateBlocks, cdiv(nphi, 8192)));
+}
+
 void launch_validate(const Layout &L, const Nodes &N, const double *phi, int nphi, double *out,
                      hipStream_t st) {
-    hipLaunchKernelGGL(k_validate, dim3(L.nb + 1), dim3(256), 0, st, L, N, phi, nphi, out);
+    const int pb = validate_data_blocks(nphi);
+    hipLaunchKernelGGL(k_validate, dim3(L.nb + pb), dim3(256), 0, st, L, N, phi, nphi, pb, out);
 }
 
 void launch_rhs_phi(const Layout &L, const Nodes &N, const Flow &F, const double *phi,
