@@ -829,9 +829,16 @@ int Ctx::gmres_multi(int kind, int n, long ld, const double *B, double *X, int n
                             m.w);
                 prof_end();
                 launch_cgs_dot(m.V, ldv, m.w, n, j, P1, P3, G, m.gs, stream, bt);
-                launch_cgs_first(m.V, ldv, m.w, n, j, P1, P2, P3, G, m.H, ldp, m.gs, stream, bt);
-                launch_cgs_final(m.V, ldv, m.w, n, j, P2, P3, G, x32, m.H, ldp, true, m.cs, m.sn,
-                                 m.g, jmax, m.gs, 0, nullptr, stream, bt);
+                if (x32) {
+                    // FP32 inner solves: one Gram-Schmidt pass, as for one system
+                    launch_cgs_final(m.V, ldv, m.w, n, j, P1, P3, G, x32, m.H, ldp, false, m.cs,
+                                     m.sn, m.g, jmax, m.gs, 0, nullptr, stream, bt);
+                } else {
+                    launch_cgs_first(m.V, ldv, m.w, n, j, P1, P2, P3, G, m.H, ldp, m.gs, stream,
+                                     bt);
+                    launch_cgs_final(m.V, ldv, m.w, n, j, P2, P3, G, x32, m.H, ldp, true, m.cs,
+                                     m.sn, m.g, jmax, m.gs, 0, nullptr, stream, bt);
+                }
             }
             const int cur = (j0 / poll) & 1;
             GState *dst = reinterpret_cast<GState *>((char *)slot + cur * kStateSlotBytes);
