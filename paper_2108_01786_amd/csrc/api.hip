@@ -824,11 +824,16 @@ int Ctx::gmres_multi(int kind, int n, long ld, const double *B, double *X, int n
         for (int j0 = 0; j0 < jmax && !ended; j0 += poll) {
             const int j1 = std::min(jmax, j0 + poll);
             for (int j = j0; j < j1; ++j) {
+                // the product's K-split slices are summed by the first Gram-Schmidt kernel
                 prof_begin();
-                apply_multi(kind, n, ld, m.V + (long)j * ldv, x32, x32 ? ldv : bt.v, nr, nullptr,
-                            m.w);
+                const int ks =
+                    kind == OP_A_S64
+                        ? launch_mfma_parts64((const double *)A, ld, n, m.V + (long)j * ldv,
+                                              bt.v, nr, m.part, stream)
+                        : launch_mfma_parts32((const float *)A, ld, n, x32, ldv, nr, m.part,
+                                              stream);
                 prof_end();
-                launch_cgs_dot(m.V, ldv, m.w, n, j, P1, P3, G, m.gs, stream, bt);
+                launch_cgs_dot(m.V, ldv, m.w, n, j, P1, P3, G, m.gs, stream, bt, m.part, ks, nr);
                 if (x32) {
                     // FP32 inner solves: one Gram-Schmidt pass, as for one system
                     launch_cgs_final(m.V, ldv, m.w, n, j, P1, P3, G, x32, m.H, ldp, false, m.cs,

@@ -348,6 +348,12 @@ void launch_to_f32_batched(const double *src, long ss, float *dst, long ds, int 
 void launch_copy_strided(const double *src, long ss, double *dst, long ds, int n, int nr,
                          hipStream_t st);
 int multi_part_size(int n, int nr);
+// the product alone: system s of slice k at part + (k * nr + s) * n, for the
+// caller to sum in slice order; returns the slice count
+int launch_mfma_parts64(const double *A, long ld, int n, const double *X, long xs, int nr,
+                        double *part, hipStream_t st);
+int launch_mfma_parts32(const float *A, long ld, int n, const float *X, long xs, int nr,
+                        double *part, hipStream_t st);
 // y_s = T X_s, s < nr, for an FP64 m x n matrix T (row stride ld, a multiple
 // of 64 columns readable past n); part needs multi_part_size_rect64(m, n, nr).
 void launch_mfma_rect64(const double *A, long ld, int m, int n, const double *X, long xs, int nr,
@@ -367,8 +373,11 @@ void launch_cycle_start(const double *r, int n, const double *P, int G, double *
                         double *g, int ldg, GState *gs, int cyc, GState *mirror, hipStream_t st,
                         const Bat &bt = kSingle);
 // partial dots of w with V_0..V_j into P, partial |w|^2 into P3
-void launch_cgs_dot(const double *V, long ldv, const double *w, int n, int j, double *P,
-                    double *P3, int G, const GState *gs, hipStream_t st, const Bat &bt = kSingle);
+// With part (ks slices of nr systems, as launch_mfma_parts* leave them), w is
+// first written as their sum in slice order.
+void launch_cgs_dot(const double *V, long ldv, double *w, int n, int j, double *P,
+                    double *P3, int G, const GState *gs, hipStream_t st, const Bat &bt = kSingle,
+                    const double *part = nullptr, int ks = 0, int nr = 0);
 // first Gram-Schmidt pass (w -= V h; dots of V with w into P2, |w|^2 into P3)
 // GP: the number of partials in P1 (0: G, the chunk count)
 // hred (may be null): the coefficients already summed (launch_reduce_rows)

@@ -235,20 +235,33 @@ __global__ __launch_bounds__(kT) void k_reduce_rows(const double *P, int GP, con
 
 // Partial dots of w with V_0..V_j (P[i*G + b]) and the partial squared norm
 // of w (P3[b]).
-__global__ __launch_bounds__(kT) void k_cgs_dot(const double *V, long ldv, const double *w,
-                                                int n, int j, double *P, double *P3, int G,
-                                                const GState *gs, Bat bt) {
-    gs += sys();
+__global__ __launch_bounds__(kT) void k_cgs_dot(const double *V, long ldv, double *w, int n,
+                                                int j, double *P, double *P3, int G,
+                                                const GState *gs, Bat bt, const double *part,
+                                                int ks, int nr) {
+    const int s = sys();
+    gs += s;
     if (gs->active == 0) return;
-    V += sys() * bt.v;
-    w += sys() * bt.vec;
-    P += sys() * bt.p;
-    P3 += sys() * bt.p;
+    V += s * bt.v;
+    w += s * bt.vec;
+    P += s * bt.p;
+    P3 += s * bt.p;
     __shared__ double sh[kT / 64];
     int c0, c1;
     chunk_of(n, G, blockIdx.x, c0, c1);
     double nn = 0.0;
-    for (int m = c0 + threadIdx.x; m < c1; m += kT) nn += w[m] * w[m];
+    if (part) {
+        // w = the product's slices summed in order, on this block's chunk
+        for (int m = c0 + threadIdx.x; m < c1; m += kT) {
+            double a = 0.0;
+            for (int k = 0; k < ks; ++k) a += part[((long)k * nr + s) * n + m];
+            w[m] = a;
+            nn += a * a;
+        }
+        __syncthreads();    // the chunk's w, written by this block, read below
+    } else {
+        for (int m = c0 + threadIdx.x; m < c1; m += kT) nn += w[m] * w[m];
+    }
     nn = block_sum(nn, sh);
     if (threadIdx.x == 0) P3[blockIdx.x] = nn;
     chunk_dots(V, ldv, w, c0, c1, j, P, G);
@@ -603,10 +616,11 @@ void launch_cycle_start(const double *r, int n, const double *P, int G, double *
     hipLaunchKernelGGL(k_cycle_start, dim3(G, bt.nsys), dim3(kT), 0, st, r, n, P, G, V, v32, g,
                        ldg, gs, cyc, mirror, bt);
 }
-void launch_cgs_dot(const double *V, long ldv, const double *w, int n, int j, double *P,
-                    double *P3, int G, const GState *gs, hipStream_t st, const Bat &bt) {
+void launch_cgs_dot(const double *V, long ldv, double *w, int n, int j, double *P,
+                    double *P3, int G, const GState *gs, hipStream_t st, const Bat &bt,
+                    const double *part, int ks, int nr) {
     hipLaunchKernelGGL(k_cgs_dot, dim3(G, bt.nsys), dim3(kT), 0, st, V, ldv, w, n, j, P, P3, G,
-                       gs, bt);
+                       gs, bt, part, ks, nr);
 }
 void launch_cgs_first(const double *V, long ldv, double *w, int n, int j, const double *P1,
                       double *P2, double *P3, int G, double *H, int ldh, const GState *gs,

@@ -367,9 +367,11 @@ template <typename T, int ST> MultiGrid multi_grid_for(int m, int n) {
     return multi_grid(m, n, MultiShape<T, ST>::RT, MultiShape<T, ST>::waves);
 }
 
+// the product into K-split partial slices, then (y non-null) their sum;
+// returns the slice count
 template <typename T, int ST>
-void launch_mfma_st(const T *A, long ld, int m, int n, const T *X, long xs, int nr,
-                    const double *c, long cs, double *y, long ys, double *part, hipStream_t st) {
+int launch_mfma_st(const T *A, long ld, int m, int n, const T *X, long xs, int nr,
+                   const double *c, long cs, double *y, long ys, double *part, hipStream_t st) {
     const MultiGrid g = multi_grid_for<T, ST>(m, n);
     const dim3 grid(cdiv(m, 4 * 16 * MultiShape<T, ST>::RT), g.ksn);
     if (ST == 2)
@@ -378,18 +380,18 @@ void launch_mfma_st(const T *A, long ld, int m, int n, const T *X, long xs, int 
     else
         hipLaunchKernelGGL((k_mfma_multi<T, 1>), grid, dim3(256), 0, st, A, ld, m, n, X, xs, nr,
                            g.kchunk, part);
-    hipLaunchKernelGGL(k_reduce_multi, dim3(cdiv(m, 256), nr), dim3(256), 0, st, m, nr, part,
-                       g.ksn, c, cs, y, ys);
+    if (y)
+        hipLaunchKernelGGL(k_reduce_multi, dim3(cdiv(m, 256), nr), dim3(256), 0, st, m, nr, part,
+                           g.ksn, c, cs, y, ys);
+    return g.ksn;
 }
 
 template <typename T>
-void launch_mfma_multi(const T *A, long ld, int m, int n, const T *X, long xs, int nr,
-                       const double *c, long cs, double *y, long ys, double *part,
-                       hipStream_t st) {
-    if (nr > 16)
-        launch_mfma_st<T, 2>(A, ld, m, n, X, xs, nr, c, cs, y, ys, part, st);
-    else
-        launch_mfma_st<T, 1>(A, ld, m, n, X, xs, nr, c, cs, y, ys, part, st);
+int launch_mfma_multi(const T *A, long ld, int m, int n, const T *X, long xs, int nr,
+                      const double *c, long cs, double *y, long ys, double *part,
+                      hipStream_t st) {
+    if (nr > 16) return launch_mfma_st<T, 2>(A, ld, m, n, X, xs, nr, c, cs, y, ys, part, st);
+    return launch_mfma_st<T, 1>(A, ld, m, n, X, xs, nr, c, cs, y, ys, part, st);
 }
 
 }  // namespace
@@ -404,6 +406,16 @@ void launch_mfma_multi32(const float *A, long ld, int n, const float *X, long xs
                          const double *c, long cs, double *y, long ys, double *part,
                          hipStream_t st) {
     launch_mfma_multi<float>(A, ld, n, n, X, xs, nr, c, cs, y, ys, part, st);
+}
+
+int launch_mfma_parts64(const double *A, long ld, int n, const double *X, long xs, int nr,
+                        double *part, hipStream_t st) {
+    return launch_mfma_multi<double>(A, ld, n, n, X, xs, nr, nullptr, 0, nullptr, 0, part, st);
+}
+
+int launch_mfma_parts32(const float *A, long ld, int n, const float *X, long xs, int nr,
+                        double *part, hipStream_t st) {
+    return launch_mfma_multi<float>(A, ld, n, n, X, xs, nr, nullptr, 0, nullptr, 0, part, st);
 }
 
 void launch_mfma_rect64(const double *A, long ld, int m, int n, const double *X, long xs, int nr,
