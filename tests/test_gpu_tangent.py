@@ -11,7 +11,10 @@ solver (the matrix read once per Arnoldi step for all directions).
 * Config 4 (M = 4608), its 32 seeded displacement directions (x~, y, phi~,
   with x' = D x~ and so on): dJ_i = sum 2 w U dU_i against the oracle's
   reverse-mode gradient contracted with each direction
-  (tests/golden/adjoint_c4.npz).
+  (tests/golden/adjoint_c4.npz) and against the device adjoint.
+* Config 4, 8 seeded directions with independent components: dU element by
+  element against the oracle's tangent-linear model
+  (tests/golden/tangent_c4.npz).
 """
 import os
 
@@ -127,6 +130,29 @@ def test_tangent_config4_directions(ww, ctx, prec):
     assert rt.status == 0
     bar = 1e-11 if prec == "fp64" else 1e-10
     assert eJ <= bar and eA <= bar
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tangent_config4_matches_oracle_golden(ww, ctx, prec):
+    """Config 4: dU element by element along 8 seeded directions of the node
+    data and phi~, against the oracle's tangent-linear model stored by
+    tests/golden/make_tangent_golden.py (its directions stored with it)."""
+    say(f"case tangent config4 vs oracle golden {prec}")
+    gd = np.load(os.path.join(GOLDEN, "tangent_c4.npz"))
+    cfg = make_config(4)
+    geom, phi = cfg["geom"], cfg["phi"]
+    dg = ww.DeviceGeometry.from_synth(geom, DEV)
+    U, omega, _, _ = ctx.solve_phi(dg, torch.as_tensor(phi, device=DEV), **_opts(ww, prec))
+    dirs = torch.as_tensor(gd["dirs"].transpose(1, 0, 2).copy(), device=DEV)   # 7 x 8 x M0
+    dU, _, rt = ctx.tangent_phi(dg, omega, dirs, **_opts(ww, prec))
+    dU = dU.cpu().numpy()
+    ref = gd["dU"]
+    errs = [float(np.abs(dU[i] - ref[i]).max() / np.abs(ref[i]).max()) for i in range(ref.shape[0])]
+    eU = float(np.abs(U.cpu().numpy() - gd["U"]).max() / np.abs(gd["U"]).max())
+    say(f"  status {rt.status} iters {rt.iters}  U err {eU:.2e}  dU err max {max(errs):.2e} "
+        f"(per direction {' '.join(f'{e:.1e}' for e in errs)})")
+    assert rt.status == 0
+    assert max(errs) <= (1e-10 if prec == "fp64" else 1e-9)
 
 
 def test_tangent_errors(ww, ctx):
