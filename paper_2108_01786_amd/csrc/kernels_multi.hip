@@ -61,11 +61,12 @@ template <> struct Mfma<float> {
 };
 
 // rows per wave (in tiles of 16) and the wave count the K split aims at,
-// measured at n = 10240: for up to 16 systems, 32 rows (FP32) or 64 rows
-// (FP64) per wave; for more, 32 rows per wave with the B tile shared by the
-// block (k_mfma_multi_shared), on a grid that runs in one round
+// measured at n = 4608 and 10240: for up to 16 systems, 32 rows (FP32) or 64
+// rows (FP64) per wave; for more, the B tile shared by the block
+// (k_mfma_multi_shared) and 16 rows (FP32; its LDS then admits four blocks
+// per CU) or 32 rows (FP64) per wave, on a grid that runs in one round
 template <typename T, int ST> struct MultiShape {
-    static constexpr int RT = (ST == 2 || sizeof(T) == 4) ? 2 : 4;
+    static constexpr int RT = ST == 2 ? (sizeof(T) == 4 ? 1 : 2) : (sizeof(T) == 4 ? 2 : 4);
     static constexpr int waves = ST == 2 ? 2304 : (RT == 2 ? 4096 : 1920);
 };
 
