@@ -23,7 +23,7 @@ import pytest
 import torch
 
 import oracle as O
-from synth import make_config
+from synth import make_config, ragged_config
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
@@ -96,6 +96,35 @@ def test_tangent_matches_oracle_tlm(ww, ctx, prec):
     assert rt.status == 0
     bar = 1e-11 if prec == "fp64" else 1e-10
     assert max(errs) <= 10 * bar and eJ <= bar
+
+
+@pytest.mark.parametrize("nd", [1, 17])
+def test_tangent_ragged_matches_oracle_tlm(ww, ctx, nd):
+    """The ragged cell (250/126/66/58: no size a multiple of a tile), with 1
+    direction and with 17 (one past a 16-wide tile of directions): dU element
+    by element against the oracle's tangent-linear model, FP64."""
+    say(f"case tangent ragged nd={nd}")
+    cfg = ragged_config()
+    geom, phi = cfg["geom"], cfg["phi"]
+    M0 = geom.M[0]
+    rng = np.random.default_rng(100 + nd)
+    w = rng.uniform(0.0, 1.0, M0)
+    dirs = np.array([[_smooth(rng, M0) for _ in range(7)] for _ in range(nd)])
+    og = O.OGeom.from_synth(geom)
+    A = O.assemble_A(og)
+    _, _, _, dJo, dUo = O.tangent_J_nodes(og, phi, w, [tuple(d) for d in dirs],
+                                           lambda r: O.dense_solve(A, r))
+    dg = ww.DeviceGeometry.from_synth(geom, DEV)
+    U, omega, _, _ = ctx.solve_phi(dg, torch.as_tensor(phi, device=DEV), tol=1e-13)
+    dU, dom, rt = ctx.tangent_phi(dg, omega, torch.as_tensor(dirs.transpose(1, 0, 2).copy(),
+                                                             device=DEV),
+                                  want_omega=True, tol=1e-13)
+    dU = dU.cpu().numpy()
+    errs = [float(np.abs(dU[i] - dUo[i].numpy()).max() / np.abs(dUo[i].numpy()).max())
+            for i in range(nd)]
+    say(f"  status {rt.status} iters {rt.iters}  dU err max {max(errs):.2e}")
+    assert rt.status == 0 and tuple(dom.shape) == (nd, geom.Mtot)
+    assert max(errs) <= 1e-10
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
