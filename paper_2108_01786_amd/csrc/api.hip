@@ -803,21 +803,27 @@ int Ctx::gmres_multi(int kind, int n, long ld, const double *B, double *X, int n
         launch_norm_partial(m.r, n, P3, G, stream, bt);
         launch_cycle_start(m.r, n, P3, G, m.V, x32, m.g, restart + 1, m.gs, 0, nullptr,
                            stream, bt);
-        int rc = read_states(h.data(), nr);
-        if (rc) return rc;
-        bool any = false;
-        double worst = 0.0, bsum = 0.0;
-        for (int s = 0; s < nr; ++s) {
-            any = any || h[s].active;
-            worst = std::max(worst, h[s].bnorm > 0 ? h[s].beta / h[s].bnorm : 0.0);
-            bsum += h[s].beta;
+        int rc;
+        double worst = 0.0;
+        // an inner solve (one cycle, no verification) leaves the per-system
+        // flags to the device and reads the states once, after its cycle
+        if (verify || !first) {
+            rc = read_states(h.data(), nr);
+            if (rc) return rc;
+            bool any = false;
+            double bsum = 0.0;
+            for (int s = 0; s < nr; ++s) {
+                any = any || h[s].active;
+                worst = std::max(worst, h[s].bnorm > 0 ? h[s].beta / h[s].bnorm : 0.0);
+                bsum += h[s].beta;
+            }
+            st.rel_resid = worst;
+            if (!any) { status = WWBI_OK; break; }
+            if (!std::isfinite(bsum)) { status = WWBI_STAGNATED; break; }
+            if (st.iters >= max_iter) { status = WWBI_NOT_CONVERGED; break; }
+            if (!first && bsum > 0.99 * prev) { status = WWBI_STAGNATED; break; }
+            prev = bsum;
         }
-        st.rel_resid = worst;
-        if (!any) { status = WWBI_OK; break; }
-        if (!std::isfinite(bsum)) { status = WWBI_STAGNATED; break; }
-        if (st.iters >= max_iter) { status = WWBI_NOT_CONVERGED; break; }
-        if (!first && bsum > 0.99 * prev) { status = WWBI_STAGNATED; break; }
-        prev = bsum;
         const int jmax = std::min(restart, max_iter - st.iters);
         int pending = -1;
         bool ended = false;
@@ -861,7 +867,7 @@ int Ctx::gmres_multi(int kind, int n, long ld, const double *B, double *X, int n
             }
             pending = cur;
         }
-        if (hipEventSynchronize(pollev[pending]) != hipSuccess) return WWBI_EHIP;
+        // the states are read after the update (a full synchronisation)
         launch_hsolve(m.H, ldp, m.g, m.y, m.gs, stream, bt);
         launch_xupdate(X, m.V, ldv, n, m.y, false, m.gs, stream, bt);
         rc = read_states(h.data(), nr);
