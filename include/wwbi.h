@@ -423,7 +423,8 @@ int wwbi_adjoint_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, con
  *   domega (device) nd x sum(M), or NULL.
  * Options as for wwbi_solve_phi_multi (a stored matrix, no warm start).
  * Errors: WWBI_EINVAL_OPTS for nd outside 1..32, an on-the-fly matvec or a
- * warm start; WWBI_EINVAL_NONFINITE for a non-finite direction entry. */
+ * warm start; WWBI_EINVAL_NONFINITE for a non-finite direction entry;
+ * WWBI_EINVAL_SIZE when 7 * nd * M_0 exceeds 2^31 - 1. */
 int wwbi_tangent_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, int32_t nd,
                      const double *dirs, const wwbi_opts *o, double *dU, double *domega,
                      wwbi_report *rep);

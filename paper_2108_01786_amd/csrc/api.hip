@@ -1903,11 +1903,12 @@ int wwbi_tangent_phi(wwbi_ctx *ctx, const wwbi_geom *g, const double *omega, int
     if (!rc && (o->matvec == WWBI_MATVEC_ON_THE_FLY || o->x0)) rc = WWBI_EINVAL_OPTS;
     if (!rc && (!g || !g->M)) rc = WWBI_EINVAL_NULL;
     if (!rc && (g->nb < 2 || g->nb > kMaxB || g->M[0] < 8)) rc = WWBI_EINVAL_SIZE;
+    if (!rc && 7L * nd * g->M[0] > INT32_MAX) rc = WWBI_EINVAL_SIZE;
     if (!rc) {
         c->restart_cap = std::max(c->restart_cap, o->restart);
         c->begin_report((o->flags & WWBI_FLAG_PROFILE) != 0);
         // the directions are checked for finite values with the geometry
-        rc = c->setup(g, dirs, 7 * nd * g->M[0], false);
+        rc = c->setup(g, dirs, (int)(7L * nd * g->M[0]), false);
     }
     const int n = rc ? 0 : c->L.n, n0 = rc ? 0 : c->L.off[1];
     const int nsr = rc ? 0 : adjoint_nsplit(n), nsc = rc ? 0 : tlm_nsplit(n, n0);
