@@ -437,6 +437,42 @@ __global__ __launch_bounds__(kT) void k_hsolve(const double *H, int ldh, const d
     }
 }
 
+// The same back substitution with the triangle staged first: the whole
+// block copies columns 0..k-1 of R (rows 0..l of column l, at l (l + 1) / 2 + i
+// of the dynamic LDS) in parallel, then one wave solves from LDS with no block
+// barrier: one wave's LDS operations complete in issue order.
+__global__ __launch_bounds__(kT) void k_hsolve_lds(const double *H, int ldh, const double *g,
+                                                   double *y, const GState *gs, Bat bt) {
+    extern __shared__ double tri[];
+    __shared__ double sr[WWBI_MAX_RESTART + 1];
+    H += sys() * bt.h;
+    g += sys() * bt.rot;
+    y += sys() * bt.rot;
+    gs += sys();
+    const int k = gs->jdone;
+    const int nt = k * (k + 1) / 2;
+    for (int e = threadIdx.x; e < nt; e += kT) {
+        int l = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+        while (l * (l + 1) / 2 > e) --l;
+        while ((l + 1) * (l + 2) / 2 <= e) ++l;
+        tri[e] = H[(long)l * ldh + (e - l * (l + 1) / 2)];
+    }
+    for (int i = threadIdx.x; i < k; i += kT) sr[i] = g[i];
+    __syncthreads();
+    if (threadIdx.x >= 64) return;
+    for (int l = k - 1; l >= 0; --l) {
+        const double *col = tri + l * (l + 1) / 2;
+        const double rl = col[l];
+        const double yl = rl != 0.0 ? sr[l] / rl : 0.0;
+        if (threadIdx.x == 0) y[l] = yl;
+        for (int i = threadIdx.x; i < l; i += 64) sr[i] -= col[i] * yl;
+        // keep the compiler from reordering or forwarding LDS accesses across steps
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
+}
+
 // x += sum_{i<k} y_i V_i (x = ... when overwrite is set)
 __global__ void k_xupdate(double *x, const double *V, long ldv, int n, const double *y,
                           int overwrite, const GState *gs, Bat bt) {
@@ -669,7 +705,14 @@ void launch_xupdate_recycled(double *x, const double *V, long ldv, int n, const 
 }
 void launch_hsolve(const double *H, int ldh, const double *g, double *y, const GState *gs,
                    hipStream_t st, const Bat &bt) {
-    hipLaunchKernelGGL(k_hsolve, dim3(1, bt.nsys), dim3(kT), 0, st, H, ldh, g, y, gs, bt);
+    // the staged form while the triangle of the largest k (ldh - 1) fits the default
+    // 64 KB launch limit beside the static right-hand side
+    const size_t tri = (size_t)ldh * (ldh - 1) / 2 * sizeof(double);
+    if (tri <= 60 * 1024)
+        hipLaunchKernelGGL(k_hsolve_lds, dim3(1, bt.nsys), dim3(kT), tri, st, H, ldh, g, y, gs,
+                           bt);
+    else
+        hipLaunchKernelGGL(k_hsolve, dim3(1, bt.nsys), dim3(kT), 0, st, H, ldh, g, y, gs, bt);
 }
 void launch_xupdate(double *x, const double *V, long ldv, int n, const double *y,
                     bool overwrite, const GState *gs, hipStream_t st, const Bat &bt) {
