@@ -162,6 +162,7 @@ void Ctx::release() {
     for (auto &e : ev) if (e) hipEventDestroy(e);
     for (auto &e : prof) if (e) hipEventDestroy(e);
     for (auto &e : pollev) if (e) hipEventDestroy(e);
+    for (auto &e : stepev) if (e) hipEventDestroy(e);
     {
         MultiWS &m = mw;
         F(m.V); F(m.v32); F(m.x32); F(m.w); F(m.r); F(m.x); F(m.b); F(m.d); F(m.rr); F(m.P); F(m.H);
@@ -349,8 +350,9 @@ void Ctx::prof_end() {
 // reads after its next synchronisation (inner solves of the refinement).
 //
 // The host enqueues `poll` Arnoldi steps at a time.  After each batch it
-// records an event, enqueues the next batch and only then waits for the
-// previous event, so the device never idles on the host.  The kernel that
+// records an event (one without the system-scope fence, 1% of a refined solve
+// on the 10240-unknown cell), enqueues the next batch and only then waits for
+// the previous event, so the device never idles on the host.  The kernel that
 // ends a cycle publishes the cycle's state, with its id, into host-mapped
 // memory: the host sees the end without a queued copy, and steps enqueued
 // after it return at once on the device flag.
@@ -479,9 +481,11 @@ int Ctx::gmres(const Op &op, const double *b, double *x, bool x_zero, double tol
                 }
             }
             const int cur = (j0 / poll) & 1;
-            if (hipEventRecord(pollev[cur], stream) != hipSuccess) return WWBI_EHIP;
+            if (hipEventRecord(stepev[cur], stream) != hipSuccess) return WWBI_EHIP;
             if (pending >= 0) {
-                if (hipEventSynchronize(pollev[pending]) != hipSuccess) return WWBI_EHIP;
+                if (hipEventSynchronize(stepev[pending]) != hipSuccess) return WWBI_EHIP;
+                // a mirror that still lags only delays the end by a batch of
+                // no-op steps: the id is new for every cycle
                 if (static_cast<const volatile GState *>(hmir)->cyc == cid) ended = true;
             }
             pending = cur;
@@ -1043,6 +1047,10 @@ int wwbi_create(wwbi_ctx **out, int32_t device, void *stream) {
         if (!rc && hipEventCreate(&e) != hipSuccess) rc = WWBI_EHIP;
     for (auto &e : c->pollev)
         if (!rc && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) rc = WWBI_EHIP;
+    for (auto &e : c->stepev)
+        if (!rc && hipEventCreateWithFlags(&e, hipEventDisableTiming | hipEventDisableSystemFence) !=
+                       hipSuccess)
+            rc = WWBI_EHIP;
     if (rc) {
         c->release();
         delete c;

@@ -157,6 +157,9 @@ struct Ctx {
 
     hipEvent_t ev[5] = {};
     hipEvent_t pollev[3] = {};   // two convergence polls and the input checks' copy
+    // the single-system solve's two step polls: they only pace the host, which
+    // then reads the coherent host mirror, so they skip the system-scope fence
+    hipEvent_t stepev[2] = {};
     hipEvent_t prof[2 * kProfPairs] = {};
     bool profiling = false;
     // launch -> (cycle, step) of every profiled matvec; steps at or beyond a
