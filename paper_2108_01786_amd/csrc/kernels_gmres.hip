@@ -8,6 +8,8 @@
 // per reduction.  Kernels of an iteration return at once when the cycle has
 // ended (gs->active == 0), so the host may enqueue several steps between
 // reads of the flag.
+#include <cstddef>
+
 #include "internal.h"
 
 namespace wwbi {
@@ -43,6 +45,25 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
     double t = 0.0;
     for (int i = 0; i < kT / 64; ++i) t += sh[i];
     return t;
+}
+
+// (active, jdone) of a cycle state as one 8-byte word.  The Hessenberg block
+// of k_cgs_final may end the cycle while vector blocks of the same launch
+// still read the flag: a block of step j runs when the cycle is active or was
+// ended by step j itself (jdone = j + 1 only then), whichever word it sees.
+static_assert(offsetof(GState, active) == 0 && offsetof(GState, jdone) == 4,
+              "active and jdone share one aligned 8-byte word");
+__device__ __forceinline__ bool step_runs(const GState *gs, int j) {
+    const unsigned long long v =
+        __hip_atomic_load(reinterpret_cast<unsigned long long *>(const_cast<GState *>(gs)),
+                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return (unsigned)(v & 0xffffffffu) != 0u || (int)(unsigned)(v >> 32) == j + 1;
+}
+__device__ __forceinline__ void store_step(GState *gs, int active, int jdone) {
+    const unsigned long long v =
+        (unsigned long long)(unsigned)active | ((unsigned long long)(unsigned)jdone << 32);
+    __hip_atomic_store(reinterpret_cast<unsigned long long *>(gs), v, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Copy of the state at the end of cycle `cyc` into host-visible memory (m may
@@ -314,9 +335,13 @@ __global__ __launch_bounds__(kT) void k_cgs_first(const double *V, long ldv, dou
 // rounding level, so the difference loses nothing; as the only pass (add = 0)
 // the difference is exact to about eps (||w|| / ||w''||)^2, ample for the
 // inner solves of the refinement, whose outer FP64 residual corrects them.
-// Block 0 adds h to (add = 1) or stores it into (add = 0) column j of H,
-// applies the previous rotations, forms the new one and updates the residual
-// estimate, with the column and the rotations staged in LDS.
+//
+// Blocks 0..G-1 form V_{j+1} on their chunks.  Block G, beside them, adds h
+// to (add = 1) or stores it into (add = 0) column j of H, applies the
+// previous rotations, forms the new one and updates the residual estimate, so
+// the serial rotation chain overlaps the vector update instead of following
+// it.  V_{j+1} is written also by the step that ends the cycle (the recycled
+// space of the refinement reads it).
 //
 // With kc > 0 recycled vectors C_0..C_{kc-1} sit in front of the Arnoldi
 // basis (V_ points at C_0, the basis vector v_i at row kc + i): w is
@@ -331,19 +356,11 @@ __global__ __launch_bounds__(kT) void k_cgs_final(const double *V_, long ldv, co
                                                   Bat bt, int kc, double *B, int ldb,
                                                   const double *hred) {
     gs += sys();
-    if (gs->active == 0) return;
-    double *V = const_cast<double *>(V_) + sys() * bt.v;
-    w += sys() * bt.vec;
+    if (!step_runs(gs, j)) return;
     P2 += sys() * bt.p;
     P3 += sys() * bt.p;
-    if (v32) v32 += sys() * bt.v32;
-    H += sys() * bt.h;
-    cs += sys() * bt.rot;
-    sn += sys() * bt.rot;
-    g += sys() * bt.rot;
     __shared__ double h[WWBI_MAX_RESTART + 1];
-    __shared__ double snrm;
-    __shared__ double col[WWBI_MAX_RESTART + 2], lc[WWBI_MAX_RESTART], ls[WWBI_MAX_RESTART];
+    __shared__ double sh[kT / 64];
     const int jj = kc + j;     // last row orthogonalised against
     // h[0..jj] from P2 and ||w'||^2 from P3 into h[jj + 1], in one pass (or
     // already summed into hred)
@@ -352,44 +369,51 @@ __global__ __launch_bounds__(kT) void k_cgs_final(const double *V_, long ldv, co
     } else {
         reduce_coeffs(P2, GP, jj, h, P3);
     }
-    const bool b0 = blockIdx.x == 0;
-    if (b0) {
-        const double *hc = H + (long)j * ldh;
-        for (int i = threadIdx.x; i <= j; i += kT) col[i] = add ? hc[i] : 0.0;
-        for (int i = threadIdx.x; i < j; i += kT) { lc[i] = cs[i]; ls[i] = sn[i]; }
-    }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        double s2 = 0.0;
-        for (int i = 0; i <= jj; ++i) s2 += h[i] * h[i];
-        const double q = h[jj + 1] - s2;
-        snrm = q > 0.0 ? sqrt(q) : 0.0;
+    // ||h||^2 in one fixed order (the same in every block)
+    double s2 = 0.0;
+    for (int i = threadIdx.x; i <= jj; i += kT) s2 += h[i] * h[i];
+    s2 = block_sum(s2, sh);
+    const double q = h[jj + 1] - s2;
+    const double nrm = q > 0.0 ? sqrt(q) : 0.0;
+    if ((int)blockIdx.x < G) {
+        double *V = const_cast<double *>(V_) + sys() * bt.v;
+        w += sys() * bt.vec;
+        if (v32) v32 += sys() * bt.v32;
+        const double sc = nrm > 0.0 ? 1.0 / nrm : 0.0;
+        int c0, c1;
+        chunk_of(n, G, blockIdx.x, c0, c1);
+        double *vn = V + (long)(jj + 1) * ldv;
+        for (int m = c0 + threadIdx.x; m < c1; m += kT) {
+            const double v = minus_proj(w[m], h, V, ldv, m, jj) * sc;
+            vn[m] = v;
+            if (v32) v32[m] = (float)v;
+        }
+        return;
     }
-    __syncthreads();
-    const double nrm = snrm;
-    const double sc = nrm > 0.0 ? 1.0 / nrm : 0.0;
-    int c0, c1;
-    chunk_of(n, G, blockIdx.x, c0, c1);
-    double *vn = V + (long)(jj + 1) * ldv;
-    for (int m = c0 + threadIdx.x; m < c1; m += kT) {
-        const double v = minus_proj(w[m], h, V, ldv, m, jj) * sc;
-        vn[m] = v;
-        if (v32) v32[m] = (float)v;
-    }
-    if (!b0) return;
+    H += sys() * bt.h;
+    cs += sys() * bt.rot;
+    sn += sys() * bt.rot;
+    g += sys() * bt.rot;
+    __shared__ double col[WWBI_MAX_RESTART + 2], lc[WWBI_MAX_RESTART], ls[WWBI_MAX_RESTART];
+    double *hc = H + (long)j * ldh;
+    for (int i = threadIdx.x; i <= j; i += kT) col[i] = (add ? hc[i] : 0.0) + h[kc + i];
+    for (int i = threadIdx.x; i < j; i += kT) { lc[i] = cs[i]; ls[i] = sn[i]; }
     if (kc > 0) {
         double *bc = B + (long)j * ldb;
         for (int i = threadIdx.x; i < kc; i += kT) bc[i] = (add ? bc[i] : 0.0) + h[i];
     }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        for (int i = 0; i <= j; ++i) col[i] += h[kc + i];
-        col[j + 1] = nrm;
+        // rotation i mixes entries i and i + 1; the rotated entry i + 1 is
+        // carried in a register into the next rotation
+        double a = col[0];
         for (int i = 0; i < j; ++i) {
-            const double a = col[i], b = col[i + 1];
+            const double b = col[i + 1];
             col[i] = lc[i] * a + ls[i] * b;
-            col[i + 1] = -ls[i] * a + lc[i] * b;
+            a = -ls[i] * a + lc[i] * b;
         }
-        const double a = col[j], b = col[j + 1];
+        const double b = nrm;
         const double r = hypot(a, b);
         double c = 1.0, s = 0.0;
         if (r > 0.0) { c = a / r; s = b / r; }
@@ -402,17 +426,14 @@ __global__ __launch_bounds__(kT) void k_cgs_final(const double *V_, long ldv, co
         g[j + 1] = -s * gj;
         const double res = fabs(g[j + 1]);
         gs->resid = res;
-        gs->jdone = j + 1;
         gs->its += 1;
         const bool brk = !(nrm > 0.0);           // exact invariant subspace, or NaN
         gs->breakdown = brk ? 1 : 0;
-        if (res <= gs->tol_abs || brk || j + 1 >= restart_len) {
-            gs->active = 0;
-            publish(mirror, gs, cyc);
-        }
+        const bool end = res <= gs->tol_abs || brk || j + 1 >= restart_len;
+        store_step(gs, end ? 0 : 1, j + 1);
+        if (end) publish(mirror, gs, cyc);
     }
     __syncthreads();
-    double *hc = H + (long)j * ldh;
     for (int i = threadIdx.x; i <= j + 1; i += kT) hc[i] = col[i];
 }
 
@@ -673,7 +694,9 @@ void launch_cgs_final(const double *V, long ldv, const double *w, int n, int j,
                       bool add, double *cs, double *sn, double *g, int restart_len, GState *gs,
                       int cyc, GState *mirror, hipStream_t st, const Bat &bt, int GP, int kc,
                       double *B, int ldb, const double *hred) {
-    hipLaunchKernelGGL(k_cgs_final, dim3(G, bt.nsys), dim3(kT), 0, st, V, ldv, w, n, j, P2, P3, G,
+    // G vector blocks and one Hessenberg block
+    hipLaunchKernelGGL(k_cgs_final, dim3(G + 1, bt.nsys), dim3(kT), 0, st, V, ldv, w, n, j, P2,
+                       P3, G,
                        GP > 0 ? GP : G, v32, H, ldh, add ? 1 : 0, cs, sn, g, restart_len, gs,
                        cyc, mirror, bt, kc, B, ldb, hred);
 }
