@@ -397,6 +397,27 @@ def test_poll_interval_does_not_change_results(ww, ctx, prec):
             assert torch.equal(om, om0) and torch.equal(U, U0)
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_back_substitution_forms_agree(ww, ctx, prec):
+    """A cycle's triangle is solved from LDS by one wave while it fits 60 KB
+    (restart <= 123) and from global memory beyond.  Both forms take the same
+    operations in the same order, so solves that end within their first
+    cycle give bitwise the same result at restart 123, 124 and 256."""
+    say(f"case back substitution forms {prec}")
+    cfg = make_config(1)
+    dg = ww.DeviceGeometry.from_synth(cfg["geom"], DEV)
+    phi = torch.as_tensor(cfg["phi"], device=DEV)
+    kw = dict(tol=1e-13 if prec == "fp64" else 1e-14,
+              precision=ww.FP64 if prec == "fp64" else ww.FP32_REFINED)
+    U0, om0, _, r0 = ctx.solve_phi(dg, phi, restart=123, **kw)
+    assert r0.status == 0 and r0.iters < 123    # one cycle per (inner) solve
+    for restart in (124, 256):
+        U, om, _, r = ctx.solve_phi(dg, phi, restart=restart, **kw)
+        say(f"  restart {restart}: iters {r.iters} (123: {r0.iters})")
+        assert r.status == 0 and r.iters == r0.iters
+        assert torch.equal(om, om0) and torch.equal(U, U0)
+
+
 @pytest.mark.parametrize("gap", [0.3, 0.03, 0.01])
 def test_underresolved_warning(ww, ctx, gap):
     """An ellipse `gap` below the flat surface (256/256/128 nodes): far away its
