@@ -1043,8 +1043,11 @@ int wwbi_create(wwbi_ctx **out, int32_t device, void *stream) {
     }
     for (auto &e : c->ev)
         if (!rc && hipEventCreate(&e) != hipSuccess) rc = WWBI_EHIP;
+    // the matvec timing pairs: timing only, so no system-scope fence (its
+    // cache write-back would be timed with the kernel)
     for (auto &e : c->prof)
-        if (!rc && hipEventCreate(&e) != hipSuccess) rc = WWBI_EHIP;
+        if (!rc && hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess)
+            rc = WWBI_EHIP;
     for (auto &e : c->pollev)
         if (!rc && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) rc = WWBI_EHIP;
     for (auto &e : c->stepev)
