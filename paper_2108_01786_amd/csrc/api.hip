@@ -1041,10 +1041,12 @@ int wwbi_create(wwbi_ctx **out, int32_t device, void *stream) {
         std::memset(c->hmir, 0, sizeof(GState));
         if (hipHostGetDevicePointer((void **)&c->dmir, c->hmir, 0) != hipSuccess) rc = WWBI_EHIP;
     }
+    // the phase markers and the matvec timing pairs only time (the report is
+    // read after a full synchronisation of the stream), so they skip the
+    // system-scope fence, whose cache write-back would be timed with the work
     for (auto &e : c->ev)
-        if (!rc && hipEventCreate(&e) != hipSuccess) rc = WWBI_EHIP;
-    // the matvec timing pairs: timing only, so no system-scope fence (its
-    // cache write-back would be timed with the kernel)
+        if (!rc && hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess)
+            rc = WWBI_EHIP;
     for (auto &e : c->prof)
         if (!rc && hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess)
             rc = WWBI_EHIP;
