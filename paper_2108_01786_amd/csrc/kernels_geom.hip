@@ -191,12 +191,27 @@ __global__ void k_circ_row1(int M, int op, double *row) {
 // Circulant product on one periodic grid of M points:
 //   out_m = alpha sum_l c((m - l) mod M) f_l + beta out_m.
 // A block owns 64 outputs; its 16 waves split the sources into interleaved
-// tiles of 64, each wave staging its tile of f and the 127 row entries the
-// tile needs in a private LDS region.  All waves run the same number of
-// rounds (so every barrier is reached), and the 16 partial sums are added in
-// a fixed order at the end.
+// tiles of 64.  Each wave stages its tile of f and the 127 row entries the
+// tile needs in a private LDS region (no block barrier: one wave's LDS
+// operations complete in issue order), loads the next tile's values into
+// registers while it sums the current one, and keeps four partial sums to
+// shorten the dependent chain.  The 16 waves' sums are added in a fixed
+// order at the end.
 constexpr int kCT = 64;
 constexpr int kCW = 16;
+
+// keeps the compiler from moving one wave's LDS accesses across this point
+__device__ __forceinline__ void wave_lds_order() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ int wrap_index(int d, int M) {
+    d %= M;
+    return d < 0 ? d + M : d;
+}
+
 // out[m0 .. m0+63] of one boundary of M nodes (see above).
 __device__ __forceinline__ void circ_tile(int M, int m0, const double *__restrict__ row,
                                           const double *__restrict__ f, double *out,
@@ -206,32 +221,36 @@ __device__ __forceinline__ void circ_tile(int M, int m0, const double *__restric
     __shared__ double red[kCW][kCT];
     const int lane = threadIdx.x % kCT, wv = threadIdx.x / kCT;
     const int ntiles = (M + kCT - 1) / kCT;
-    const int rounds = (ntiles + kCW - 1) / kCW;
-    double acc = 0.0;
-    for (int rd = 0; rd < rounds; ++rd) {
-        const int tile = rd * kCW + wv;
-        const int l0 = tile * kCT;
-        const bool live = tile < ntiles;
-        if (live) {
-            const int l = l0 + lane;
-            fs[wv][lane] = l < M ? f[l] : 0.0;
-            // row index (m - l) for m in [m0, m0+63], l in [l0, l0+63], stored
-            // at (m - l) - (m0 - l0 - 63) in [0, 126]
-            const long base = (long)m0 - l0 - (kCT - 1);
-            for (int t = lane; t < 2 * kCT - 1; t += kCT) {
-                long d = (base + t) % M;
-                if (d < 0) d += M;
-                rs[wv][t] = row[d];
-            }
+    // tile values: f_l (zero past M) and the row entries c(d) for
+    // d = m0 - l0 - 63 + t, t in [0, 126], at t = lane and t = 64 + lane
+    double fv = 0.0, r0 = 0.0, r1 = 0.0;
+    auto load = [&](int tile) {
+        const int l0 = tile * kCT, l = l0 + lane;
+        fv = l < M ? f[l] : 0.0;
+        const int base = m0 - l0 - (kCT - 1);
+        r0 = row[wrap_index(base + lane, M)];
+        r1 = lane < kCT - 1 ? row[wrap_index(base + kCT + lane, M)] : 0.0;
+    };
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (wv < ntiles) load(wv);
+    for (int tile = wv; tile < ntiles; tile += kCW) {
+        wave_lds_order();          // the previous tile's reads come first
+        fs[wv][lane] = fv;
+        rs[wv][lane] = r0;
+        rs[wv][kCT + lane] = r1;
+        wave_lds_order();
+        if (tile + kCW < ntiles) load(tile + kCW);
+        // c(m - l) for output m = m0 + lane and l = l0 + i sits at t = lane + 63 - i
+        const double *rw = &rs[wv][lane + kCT - 1];
+#pragma unroll
+        for (int i = 0; i < kCT; i += 4) {
+            a0 += rw[-i] * fs[wv][i];
+            a1 += rw[-i - 1] * fs[wv][i + 1];
+            a2 += rw[-i - 2] * fs[wv][i + 2];
+            a3 += rw[-i - 3] * fs[wv][i + 3];
         }
-        __syncthreads();
-        if (live) {
-            const int cnt = min(kCT, M - l0);
-            for (int i = 0; i < cnt; ++i) acc += rs[wv][lane - i + kCT - 1] * fs[wv][i];
-        }
-        __syncthreads();
     }
-    red[wv][lane] = acc;
+    red[wv][lane] = (a0 + a1) + (a2 + a3);
     __syncthreads();
     if (wv == 0) {
         double s = 0.0;
