@@ -83,6 +83,25 @@ __device__ __forceinline__ double sum_slices(const double *part, int ns, long st
     return acc;
 }
 
+// The same sum over the W waves of a block whose 64 lanes are 64 outputs:
+// wave w sums slices [ns w / W, ns (w + 1) / W) in increasing k, and the W
+// sums are added in wave order.  Every thread of the block calls it (it holds
+// a barrier); the result is valid in wave 0.  One lane alone would sum all ns
+// slices in dependent rounds of loads.
+template <int W>
+__device__ __forceinline__ double sum_slices_waves(const double *part, int ns, long stride,
+                                                   long i, bool live, double (*red)[64]) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int k0 = (int)((long)ns * wv / W), k1 = (int)((long)ns * (wv + 1) / W);
+    red[wv][lane] = live ? sum_slices(part + (long)k0 * stride, k1 - k0, stride, i) : 0.0;
+    __syncthreads();
+    double s = 0.0;
+    if (wv == 0)
+        for (int w = 0; w < W; ++w) s += red[w][lane];
+    return s;
+}
+constexpr int kSliceWaves = 8;
+
 // Device-resident GMRES cycle state (one per Krylov solve in flight).
 struct GState {
     int active;        // 1 while the current restart cycle runs

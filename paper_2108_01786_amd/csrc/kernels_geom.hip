@@ -384,11 +384,16 @@ __global__ __launch_bounds__(256) void k_tail_finish(Layout L, const double *__r
 }
 
 // U_m = (u_mv + (1/2) H gamma_0 + sum over split partials of T gamma) / s_m
-__global__ void k_U_finalize(int n0, const double *s, const double *umv, const double *hg,
-                             const double *part, int nsplit, double *U) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= n0) return;
-    const double acc = sum_slices(part, nsplit, n0, m);
+// (64 targets per block, the slices shared by kSliceWaves waves)
+__global__ __launch_bounds__(64 * kSliceWaves) void k_U_finalize(int n0, const double *s,
+                                                                 const double *umv,
+                                                                 const double *hg,
+                                                                 const double *part, int nsplit,
+                                                                 double *U) {
+    __shared__ double red[kSliceWaves][64];
+    const int m = blockIdx.x * 64 + (threadIdx.x & 63);
+    const double acc = sum_slices_waves<kSliceWaves>(part, nsplit, n0, m, m < n0, red);
+    if (threadIdx.x >= 64 || m >= n0) return;
     U[m] = (umv[m] + 0.5 * hg[m] + acc) / s[m];
 }
 
@@ -628,8 +633,8 @@ void launch_block_means(const Layout &L, const double *v, double *out, hipStream
 
 void launch_U_finalize(int n0, const double *s, const double *umv, const double *hg,
                        const double *part, int nsplit, double *U, hipStream_t st) {
-    hipLaunchKernelGGL(k_U_finalize, dim3(cdiv(n0, 64)), dim3(64), 0, st, n0, s, umv, hg, part,
-                       nsplit, U);
+    hipLaunchKernelGGL(k_U_finalize, dim3(cdiv(n0, 64)), dim3(64 * kSliceWaves), 0, st, n0, s,
+                       umv, hg, part, nsplit, U);
 }
 
 void launch_wall_rhs_finalize(int nw, const double *umv_w, const double *part, int nsplit,
