@@ -398,11 +398,14 @@ __global__ __launch_bounds__(64 * kSliceWaves) void k_U_finalize(int n0, const d
 }
 
 // wall rhs = -(sum of G_0k^dagger gamma_0 partials) - s dphi_mv/dn
-__global__ void k_wall_rhs_finalize(int nw, const double *umv_w, const double *part, int nsplit,
-                                    double *rhs) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nw) return;
-    const double acc = sum_slices(part, nsplit, nw, i);
+__global__ __launch_bounds__(64 * kSliceWaves) void k_wall_rhs_finalize(int nw,
+                                                                        const double *umv_w,
+                                                                        const double *part,
+                                                                        int nsplit, double *rhs) {
+    __shared__ double red[kSliceWaves][64];
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const double acc = sum_slices_waves<kSliceWaves>(part, nsplit, nw, i, i < nw, red);
+    if (threadIdx.x >= 64 || i >= nw) return;
     rhs[i] = -acc - umv_w[i];
 }
 
@@ -427,12 +430,13 @@ __global__ void k_tmv(Nodes N, Flow F, int first, int count, double *out) {
 // dphi/ds = (s dphi_mv/ds + local + sum of the split partials of Q gamma) / s
 // (s dphi/ds when s is null),
 // local = gamma_0 / 2 on the surface and -(H gamma_k)/2 on wall k.
-__global__ void k_tangential_finalize(int n, int n0, const double *s, const double *tmv,
-                                      const double *gamma, const double *hg, const double *part,
-                                      int nsplit, double *out) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const double acc = sum_slices(part, nsplit, n, p);
+__global__ __launch_bounds__(64 * kSliceWaves) void k_tangential_finalize(
+    int n, int n0, const double *s, const double *tmv, const double *gamma, const double *hg,
+    const double *part, int nsplit, double *out) {
+    __shared__ double red[kSliceWaves][64];
+    const int p = blockIdx.x * 64 + (threadIdx.x & 63);
+    const double acc = sum_slices_waves<kSliceWaves>(part, nsplit, n, p, p < n, red);
+    if (threadIdx.x >= 64 || p >= n) return;
     const double loc = p < n0 ? 0.5 * gamma[p] : -0.5 * hg[p];
     out[p] = s ? (tmv[p] + loc + acc) / s[p] : tmv[p] + loc + acc;
 }
@@ -452,13 +456,14 @@ __global__ void k_gt_vectors(int n0, const double *V, const double *U, const dou
 // W.t = (s dphi_mv/ds + sum_q Q gamma)/s (the principal value, without the
 // jump), W.n = U, theta_a = Im(zeta''/zeta') = 2 Im L,
 // F_00 = -H(fU)/2 + KS fV + GS fU.
-__global__ void k_gt_surface(int n0, Nodes N, double tau, double grav, const double *V,
-                             const double *U, const double *gamma, const double *tmv,
-                             const double *pq, int nsq, const double *hfu, const double *kfv,
-                             const double *gfu, double *e) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= n0) return;
-    const double acc = sum_slices(pq, nsq, n0, m);
+__global__ __launch_bounds__(64 * kSliceWaves) void k_gt_surface(
+    int n0, Nodes N, double tau, double grav, const double *V, const double *U,
+    const double *gamma, const double *tmv, const double *pq, int nsq, const double *hfu,
+    const double *kfv, const double *gfu, double *e) {
+    __shared__ double red[kSliceWaves][64];
+    const int m = blockIdx.x * 64 + (threadIdx.x & 63);
+    const double acc = sum_slices_waves<kSliceWaves>(pq, nsq, n0, m, m < n0, red);
+    if (threadIdx.x >= 64 || m >= n0) return;
     const double s = N.s[m], g0 = gamma[m], u = U[m];
     const double wt = (tmv[m] + acc) / s;
     const double F00 = -0.5 * hfu[m] + kfv[m] + gfu[m];
@@ -470,12 +475,13 @@ __global__ void k_gt_surface(int n0, Nodes N, double tau, double grav, const dou
 //   e = tau s + g y^2 x' / 2 + psi phi_alpha / 2,
 //   psi = psi_mv + (H omega_0)/2 + sum of the split partials of P omega,
 //   phi_alpha = D phi~ + s dphi_mv/ds.
-__global__ void k_energy_terms(int n0, Nodes N, Flow F, double tau, double grav,
-                               const double *hw, const double *part, int nsplit,
-                               const double *dphi, const double *tmv, double *e) {
-    const int m = blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= n0) return;
-    const double acc = sum_slices(part, nsplit, n0, m);
+__global__ __launch_bounds__(64 * kSliceWaves) void k_energy_terms(
+    int n0, Nodes N, Flow F, double tau, double grav, const double *hw, const double *part,
+    int nsplit, const double *dphi, const double *tmv, double *e) {
+    __shared__ double red[kSliceWaves][64];
+    const int m = blockIdx.x * 64 + (threadIdx.x & 63);
+    const double acc = sum_slices_waves<kSliceWaves>(part, nsplit, n0, m, m < n0, red);
+    if (threadIdx.x >= 64 || m >= n0) return;
     const double x = N.x[m], y = N.y[m];
     const double psi = psi_mv(F, x, y) + 0.5 * hw[m] + acc;
     const double pa = dphi[m] + tmv[m];
@@ -549,8 +555,8 @@ void launch_tmv(const Nodes &N, const Flow &F, int first, int count, double *out
 void launch_tangential_finalize(int n, int n0, const double *s, const double *tmv,
                                 const double *gamma, const double *hg, const double *part,
                                 int nsplit, double *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_tangential_finalize, dim3(cdiv(n, 64)), dim3(64), 0, st, n, n0, s, tmv,
-                       gamma, hg, part, nsplit, out);
+    hipLaunchKernelGGL(k_tangential_finalize, dim3(cdiv(n, 64)), dim3(64 * kSliceWaves), 0, st,
+                       n, n0, s, tmv, gamma, hg, part, nsplit, out);
 }
 
 void launch_gt_vectors(int n0, const double *V, const double *U, const double *gamma,
@@ -563,15 +569,15 @@ void launch_gt_surface(int n0, const Nodes &N, double tau, double grav, const do
                        const double *U, const double *gamma, const double *tmv,
                        const double *pq, int nsq, const double *hfu, const double *kfv,
                        const double *gfu, double *e, hipStream_t st) {
-    hipLaunchKernelGGL(k_gt_surface, dim3(cdiv(n0, 64)), dim3(64), 0, st, n0, N, tau, grav, V, U,
-                       gamma, tmv, pq, nsq, hfu, kfv, gfu, e);
+    hipLaunchKernelGGL(k_gt_surface, dim3(cdiv(n0, 64)), dim3(64 * kSliceWaves), 0, st, n0, N,
+                       tau, grav, V, U, gamma, tmv, pq, nsq, hfu, kfv, gfu, e);
 }
 
 void launch_energy(int n0, const Nodes &N, const Flow &F, double tau, double grav,
                    const double *hw, const double *part, int nsplit, const double *dphi,
                    const double *tmv, const double *psi_k, double *e, double *E, hipStream_t st) {
-    hipLaunchKernelGGL(k_energy_terms, dim3(cdiv(n0, 64)), dim3(64), 0, st, n0, N, F, tau, grav,
-                       hw, part, nsplit, dphi, tmv, e);
+    hipLaunchKernelGGL(k_energy_terms, dim3(cdiv(n0, 64)), dim3(64 * kSliceWaves), 0, st, n0, N,
+                       F, tau, grav, hw, part, nsplit, dphi, tmv, e);
     hipLaunchKernelGGL(k_energy_final, dim3(1), dim3(1024), 0, st, n0, e, F, psi_k, E);
 }
 
@@ -639,8 +645,8 @@ void launch_U_finalize(int n0, const double *s, const double *umv, const double 
 
 void launch_wall_rhs_finalize(int nw, const double *umv_w, const double *part, int nsplit,
                               double *rhs, hipStream_t st) {
-    hipLaunchKernelGGL(k_wall_rhs_finalize, dim3(cdiv(nw, 64)), dim3(64), 0, st, nw, umv_w, part,
-                       nsplit, rhs);
+    hipLaunchKernelGGL(k_wall_rhs_finalize, dim3(cdiv(nw, 64)), dim3(64 * kSliceWaves), 0, st,
+                       nw, umv_w, part, nsplit, rhs);
 }
 
 void launch_surface_base(int n, const double *xt, const double *yt, double *x, double *y,

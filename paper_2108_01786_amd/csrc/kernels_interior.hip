@@ -152,12 +152,13 @@ __global__ void k_boundary_velocity(int n, const double *dx, const double *dy, c
 
 // s dphi/dn = s dphi_mv/dn + local + sum of the split partials of T gamma,
 // local = H gamma_0 / 2 on the surface and -gamma_k / 2 on wall k
-__global__ void k_normal_finalize(int n, int n0, const double *umv, const double *gamma,
-                                  const double *hg, const double *part, int nsplit,
-                                  double *out) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const double acc = sum_slices(part, nsplit, n, p);
+__global__ __launch_bounds__(64 * kSliceWaves) void k_normal_finalize(
+    int n, int n0, const double *umv, const double *gamma, const double *hg, const double *part,
+    int nsplit, double *out) {
+    __shared__ double red[kSliceWaves][64];
+    const int p = blockIdx.x * 64 + (threadIdx.x & 63);
+    const double acc = sum_slices_waves<kSliceWaves>(part, nsplit, n, p, p < n, red);
+    if (threadIdx.x >= 64 || p >= n) return;
     const double loc = p < n0 ? 0.5 * hg[p] : -0.5 * gamma[p];
     out[p] = umv[p] + loc + acc;
 }
@@ -293,8 +294,8 @@ void launch_boundary_velocity(int n, const double *dx, const double *dy, const d
 void launch_normal_finalize(int n, int n0, const double *umv, const double *gamma,
                             const double *hg, const double *part, int nsplit, double *out,
                             hipStream_t st) {
-    hipLaunchKernelGGL(k_normal_finalize, dim3(cdiv(n, 64)), dim3(64), 0, st, n, n0, umv, gamma, hg,
-                       part, nsplit, out);
+    hipLaunchKernelGGL(k_normal_finalize, dim3(cdiv(n, 64)), dim3(64 * kSliceWaves), 0, st, n,
+                       n0, umv, gamma, hg, part, nsplit, out);
 }
 
 }  // namespace wwbi
