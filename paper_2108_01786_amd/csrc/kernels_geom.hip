@@ -62,7 +62,8 @@ __device__ __forceinline__ double block_sum(double v, double *sh) {
 // One block per boundary: count of non-finite samples, signed area
 // (1/2) sum (x y' - y x') 2pi/M (negative = clockwise) and the mean of x'.
 // Block nb checks the potential.
-__global__ void k_validate(Layout L, Nodes N, const double *phi, int nphi, int pb, double *out) {
+__global__ __launch_bounds__(1024) void k_validate(Layout L, Nodes N, const double *phi,
+                                                  int nphi, int pb, double *out) {
     __shared__ double sh[16];
     const int k = blockIdx.x;
     if (k >= L.nb) {
@@ -531,7 +532,9 @@ int validate_data_blocks(int nphi) {
 void launch_validate(const Layout &L, const Nodes &N, const double *phi, int nphi, double *out,
                      hipStream_t st) {
     const int pb = validate_data_blocks(nphi);
-    hipLaunchKernelGGL(k_validate, dim3(L.nb + pb), dim3(256), 0, st, L, N, phi, nphi, pb, out);
+    // 1024 threads: a block walks its boundary (or share of the data) in few
+    // rounds of loads (12 -> 9 us at M = 10240 against 256 threads)
+    hipLaunchKernelGGL(k_validate, dim3(L.nb + pb), dim3(1024), 0, st, L, N, phi, nphi, pb, out);
 }
 
 void launch_rhs_phi(const Layout &L, const Nodes &N, const Flow &F, const double *phi,
